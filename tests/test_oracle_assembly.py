@@ -1,0 +1,139 @@
+"""Pins of the global operator, the grid transfers and the exact solvers."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import assemble, exact, mesh, rhs, transfer
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8])
+def test_kron_equals_elementwise(n):
+    h, alpha = 1.0 / n, 0.37
+    A1 = assemble.matrix_kron(n, h, alpha)
+    A2 = assemble.matrix_elementwise(n, h, alpha)
+    assert abs(A1 - A2).max() <= 1e-15 * abs(A1).max()
+    assert abs(A1 - A1.T).max() == 0.0
+
+
+@pytest.mark.parametrize("n", [3, 4, 8])
+def test_de_rham(n):
+    """curl grad = 0 exactly for integer nodal data; hence A G phi = M G phi."""
+    C, _ = assemble.curl_operator(n)
+    G = assemble.gradient(n, 1.0)                      # integer differences
+    phi = np.random.default_rng(n).integers(-50, 50, size=(n - 1) ** 3).astype(float)
+    assert np.all(C @ (G @ phi) == 0.0)
+    h = 1.0 / n
+    Gh = assemble.gradient(n, h)
+    A = assemble.matrix_kron(n, h, 3.0)
+    M = assemble.mass_kron(n, h)
+    v = Gh @ phi
+    bound = 1e-14 * (abs(A) @ np.abs(v)).max()       # rounding of the cancelling sum
+    np.testing.assert_allclose(A @ v, M @ v, rtol=0, atol=bound)
+
+
+def test_ndof_counts():
+    for n, N in [(4, 108), (8, 1176), (16, 10800), (32, 92256), (64, 762048), (128, 6193536)]:
+        assert mesh.ndof(n) == N
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+def test_spd_and_spectrum(n):
+    h = 1.0 / n
+    A = assemble.matrix_kron(n, h, 2.0).toarray()
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() > 0 and ev.min() >= h ** 3 / 9.0 * (1 - 1e-12)
+    np.testing.assert_allclose(np.sort(exact.eigenvalues(n, h, 2.0)), ev, rtol=1e-12,
+                               atol=1e-14 * ev.max())
+
+
+@pytest.mark.parametrize("nc", [2, 3, 4])
+def test_galerkin(nc):
+    """I_k^{k-1} A_k I_{k-1}^k = A_{k-1}: nested spaces and one bilinear form."""
+    L, alpha = 1.0, 0.7
+    P = transfer.prolongation(nc)
+    Af = assemble.matrix_kron(2 * nc, L / (2 * nc), alpha)
+    Ac = assemble.matrix_kron(nc, L / nc, alpha)
+    D = (P.T @ Af @ P - Ac)
+    assert abs(D).max() <= 1e-14 * abs(Ac).max()
+
+
+@pytest.mark.parametrize("nc", [2, 3, 5])
+def test_commuting_gradient(nc):
+    """Prolongation of a coarse gradient is the fine gradient of the Q1-prolongated field."""
+    P = transfer.prolongation(nc)
+    P1 = transfer._P1(nc)
+    Q1 = sp.kron(P1, sp.kron(P1, P1))
+    Gc = assemble.gradient(nc, 1.0)
+    Gf = assemble.gradient(2 * nc, 0.5)
+    phi = np.random.default_rng(1).integers(-9, 9, size=(nc - 1) ** 3).astype(float)
+    assert np.all(P @ (Gc @ phi) == Gf @ (Q1 @ phi))
+
+
+def test_prolongation_weights():
+    """A fine x-edge on a coarse x-edge takes the coarse value (weight 1); one halfway
+    between two coarse node lines takes their mean (hat weights 1/2)."""
+    nc = 3
+    P = transfer.prolongation(nc)
+    c = np.random.default_rng(2).standard_normal(mesh.ndof(nc))
+    fine = P @ c
+    d, p = mesh.edge_coords(2 * nc)
+    sel = (d == 0) & (p[:, 1] % 2 == 0) & (p[:, 2] % 2 == 0)
+    ci = mesh.compact_index(nc, 0, p[sel, 0] // 2, p[sel, 1] // 2, p[sel, 2] // 2)
+    np.testing.assert_array_equal(fine[sel], c[ci])
+    sel = (d == 0) & (p[:, 1] % 2 == 1) & (p[:, 2] % 2 == 0)
+    lo = mesh.compact_index(nc, 0, p[sel, 0] // 2, p[sel, 1] // 2, p[sel, 2] // 2)
+    hi = mesh.compact_index(nc, 0, p[sel, 0] // 2, p[sel, 1] // 2 + 1, p[sel, 2] // 2)
+    ref = 0.5 * (np.where(lo >= 0, c[lo], 0.0) + np.where(hi >= 0, c[hi], 0.0))
+    np.testing.assert_array_equal(fine[sel], ref)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16, 24])
+def test_fft_matches_sparse_direct(n):
+    h, alpha = 1.0 / n, 1.7
+    b = np.random.default_rng(n).standard_normal(mesh.ndof(n))
+    u1 = exact.solve_direct(n, h, alpha, b)
+    u2 = exact.solve_fft(n, h, alpha, b)
+    A = assemble.matrix_kron(n, h, alpha)
+    # both are backward stable: small residuals, forward difference within kappa * eps
+    ev = exact.eigenvalues(n, h, alpha)
+    for u in (u1, u2):
+        assert np.linalg.norm(b - A @ u) <= 1e-14 * ev.max() * np.linalg.norm(u)
+    kappa = ev.max() / ev.min()
+    assert np.linalg.norm(u1 - u2) <= 10 * kappa * 2.2e-16 * np.linalg.norm(u1)
+
+
+def test_fft_multiple_rhs():
+    n, h = 6, 1.0 / 6
+    B = np.random.default_rng(0).standard_normal((3, mesh.ndof(n)))
+    U = exact.solve_fft(n, h, 0.5, B)
+    for r in range(3):
+        np.testing.assert_allclose(U[r], exact.solve_fft(n, h, 0.5, B[r]), rtol=1e-13, atol=1e-14)
+
+
+def test_load_vector_quadrature():
+    """The 2x2x2 Gauss rule is exact for f in Q1 per element; compare with 5^3 Gauss."""
+    n, L = 4, 1.0
+    f = lambda x, y, z: (1 + x + 2 * y - z + 3 * y * z, x * y - 2 * z + 1, 2 + x * z + y)
+    from paper_2205_05840_amd import synth
+    X = synth.gauss_points(n, L)
+    F = np.stack(f(X[..., 0], X[..., 1], X[..., 2]), -1)
+    b1 = rhs.load_from_samples(n, L / n, F)
+    b2 = rhs.load_from_function(n, L, f, q=5)
+    np.testing.assert_allclose(b1, b2, rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.slow
+def test_manufactured_first_order():
+    """Energy error ||u* - u_h||_a^2 = a(u*,u*) - b^T u_h decreases like h (Sec. 2)."""
+    alpha = 1.0
+    from paper_2205_05840_amd import synth
+    aa = (2 * np.pi ** 2 * alpha + 1) * 0.75
+    errs = []
+    for n in (8, 16, 32):
+        f = lambda x, y, z: tuple((2 * np.pi ** 2 * alpha + 1) * c
+                                  for c in synth.manufactured_field(x, y, z))
+        b = rhs.load_from_function(n, 1.0, f, q=5)
+        u = exact.solve_fft(n, 1.0 / n, alpha, b)
+        errs.append(np.sqrt(aa - b @ u))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(0.95 < r < 1.1 for r in rates), (errs, rates)

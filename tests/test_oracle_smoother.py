@@ -1,0 +1,138 @@
+"""Pins of the substructuring smoothers (Sec. 3.2) and their index sets."""
+import numpy as np
+import pytest
+
+from oracle import assemble, element, mesh, smoother
+
+
+def _dense(S, N):
+    return S(np.eye(N))
+
+
+@pytest.mark.parametrize("s,nI,nGV,nGE", [(2, 6, 60, 18), (4, 108, 312, 100)])
+def test_set_sizes(s, nI, nGV, nGE):
+    n = 3 * s
+    assert len(mesh.interior_set(n, s, (1, 1, 1))) == nI == 3 * s * (s - 1) ** 2
+    assert len(mesh.vertex_interface_set(n, s, (1, 1, 1))) == nGV == 6 * s + 24 * s * (s - 1)
+    assert len(mesh.edge_interface_set(n, s, 0, (0, s, s))) == nGE == s + 8 * s * (s - 1)
+
+
+@pytest.mark.parametrize("s", [2, 4])
+def test_partition_and_coverage(s):
+    """Interiors are disjoint; with boundary patches every face-interior unknown lies in
+    exactly 4 vertex sets and every unknown on a coarse edge in exactly 2."""
+    n = 3 * s
+    N = mesh.ndof(n)
+    cover_I = np.zeros(N, int)
+    for t in mesh.coarse_elements(n, s):
+        cover_I[mesh.interior_set(n, s, t)] += 1
+    cover_V = np.zeros(N, int)
+    for v in mesh.coarse_vertices(n, s, boundary=True):
+        cover_V[mesh.vertex_interface_set(n, s, v)] += 1
+    d, p = mesh.edge_coords(n)
+    trans = np.stack([p[np.arange(N), (d + 1) % 3], p[np.arange(N), (d + 2) % 3]], 1)
+    on = (trans % s == 0).sum(1)          # 0: interior, 1: face interior, 2: coarse edge
+    assert np.all(cover_I[on == 0] == 1) and np.all(cover_I[on > 0] == 0)
+    assert np.all(cover_V[on == 0] == 0)
+    assert np.all(cover_V[on == 1] == 4)
+    assert np.all(cover_V[on == 2] == 2)
+
+
+@pytest.mark.parametrize("n,boundary", [(4, True), (8, True), (8, False), (12, True)])
+def test_literal_equals_factored(n, boundary):
+    A = assemble.matrix_kron(n, 1.0 / n, 0.3)
+    r = np.random.default_rng(n).standard_normal((A.shape[0], 2))
+    a = smoother.LiteralSmoother(A, n, boundary=boundary)(r)
+    b = smoother.FactoredVertexSmoother(A, n, boundary=boundary)(r)
+    assert abs(a - b).max() <= 1e-13 * abs(a).max()
+
+
+def test_factored_s4_equals_literal():
+    n = 8
+    A = assemble.matrix_kron(n, 1.0 / n, 2.0)
+    r = np.random.default_rng(0).standard_normal(A.shape[0])
+    a = smoother.LiteralSmoother(A, n, s=4)(r)
+    b = smoother.FactoredVertexSmoother(A, n, s=4)(r)
+    assert abs(a - b).max() <= 1e-12 * abs(a).max()
+
+
+@pytest.mark.parametrize("kind,eta,bound", [("vertex", 1 / 9, 1 / 8), ("edge", 1 / 13, 1 / 12)])
+@pytest.mark.parametrize("boundary", [True, False])
+def test_symmetry_and_spectral_condition(kind, eta, bound, boundary):
+    """M^{-1} is symmetric and the spectrum of M^{-1} A lies in (0, 1] for eta at the
+    bound of Sec. 3.2 (eta_V <= 1/8, eta_E <= 1/12)."""
+    n = 6
+    A = assemble.matrix_kron(n, 1.0 / n, 1.0)
+    N = A.shape[0]
+    for e in (eta, bound):
+        Mi = _dense(smoother.LiteralSmoother(A, n, kind=kind, eta=e, boundary=boundary), N)
+        assert abs(Mi - Mi.T).max() <= 1e-13 * abs(Mi).max()
+        lam = np.linalg.eigvals(Mi @ A.toarray()).real
+        assert lam.min() > 0 and lam.max() <= 1 + 1e-10
+
+
+@pytest.mark.parametrize("kind", ["vertex", "edge"])
+def test_bubbles_scaled_by_eta(kind):
+    n = 6
+    A = assemble.matrix_kron(n, 1.0 / n, 5.0)
+    S = smoother.LiteralSmoother(A, n, kind=kind)
+    w = np.zeros(A.shape[0])
+    I = mesh.interior_set(n, 2, (1, 0, 2))
+    w[I] = np.random.default_rng(1).standard_normal(len(I))
+    np.testing.assert_allclose(S(A @ w), S.eta * w, atol=1e-13 * abs(w).max())
+
+
+def _coarse_element_energy(n, h, alpha, t, s):
+    """a_T restricted to the fine elements of coarse element t (assembled locally)."""
+    Ae = element.element_matrix(h, alpha)
+    dofs = assemble.element_dofs(n)
+    N = mesh.ndof(n)
+    out = np.zeros((N, N))
+    for c2 in range(s * t[2], s * t[2] + s):
+        for c1 in range(s * t[1], s * t[1] + s):
+            for c0 in range(s * t[0], s * t[0] + s):
+                e = dofs[(c2 * n + c1) * n + c0]
+                for i in range(12):
+                    for j in range(12):
+                        if e[i] >= 0 and e[j] >= 0:
+                            out[e[i], e[j]] += Ae[i, j]
+    return out
+
+
+def test_minimum_energy_vertex():
+    """eq. MinimumEnergyV: the discrete-harmonic field has the least energy on each
+    element of the patch among fields with the same interface values."""
+    n, s, alpha = 4, 2, 0.8
+    h = 1.0 / n
+    A = assemble.matrix_kron(n, h, alpha)
+    S = smoother.LiteralSmoother(A, n)
+    idx, Phi, _, _ = S.P[0]
+    nG = Phi.shape[1]
+    rng = np.random.default_rng(3)
+    v = np.zeros(A.shape[0])
+    v[idx] = Phi @ rng.standard_normal(nG)
+    # a-orthogonal to every bubble of the patch (harmonic)
+    for t in mesh.patch_elements(n, s, (1, 1, 1)):
+        I = mesh.interior_set(n, s, t)
+        assert abs((A @ v)[I]).max() <= 1e-13 * abs(A @ v).max()
+    for t in mesh.patch_elements(n, s, (1, 1, 1)):
+        aT = _coarse_element_energy(n, h, alpha, t, s)
+        for _ in range(3):
+            w = v.copy()
+            I = mesh.interior_set(n, s, t)
+            w[I] += rng.standard_normal(len(I))
+            assert v @ aT @ v <= w @ aT @ w + 1e-14
+
+
+def test_patch_matrices_translation_invariant():
+    """All patches of one vertex type have the same A_V (the GPU stores one per type)."""
+    n = 10
+    A = assemble.matrix_kron(n, 1.0 / n, 0.5)
+    S = smoother.LiteralSmoother(A, n)
+    by_type = {}
+    for v, AV in zip(mesh.coarse_vertices(n, 2), S.patch_matrices()):
+        by_type.setdefault(mesh.vertex_type(n, 2, v), []).append(AV)
+    assert len(by_type) == 19
+    for mats in by_type.values():
+        for M in mats[1:]:
+            assert abs(M - mats[0]).max() <= 1e-14 * abs(mats[0]).max()
