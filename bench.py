@@ -1,0 +1,192 @@
+"""Benchmark: V-cycle-preconditioned CG at 128^3 on one MI355X, mixed precision vs FP64.
+
+A step is one complete ndmg_pcg_solve (u0 = 0 to ||b - A u|| <= 1e-10 ||b||) of the
+128^3 unit-cube problem (6,193,536 interior-edge unknowns, alpha = 1, f ~ N(0, 1) at
+the 2x2x2 Gauss points, seed 2), with the right-hand side already resident in HBM and
+the setup done before the timed region.  The headline leg runs the V-cycle in FP32
+inside FP64 flexible CG; the FP64 leg (V-cycle in FP64) is reported next to it, and
+both are repeated at alpha = 1e-3.
+
+Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K, --warmup W,
+--no-cpu-baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_ELEM = 128
+SEED = 2
+RTOL = 1e-10
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2205_05840_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, prec):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}:{prec}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def run_leg(torch, Solver, f, alpha, precision, steps, warmup):
+    S = Solver(N_ELEM, alpha, precision=precision)
+    b = S.assemble_rhs(f)
+    u = S.zeros()
+    for _ in range(warmup):
+        S.solve(b, rtol=RTOL, u=u)
+    torch.cuda.synchronize()
+    times, iters, rels = [], [], []
+    t_all0 = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, it, rel = S.solve(b, rtol=RTOL, u=u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(it)
+        rels.append(rel)
+    t_all = time.perf_counter() - t_all0
+    # true residual in FP64
+    r = b - S.apply(u)
+    true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    return S, b, u, {"s_per_solve_total": t_all / steps, "s_per_solve_median": sorted(times)[len(times) // 2],
+                     "iters": iters[-1], "relres": rels[-1], "true_relres": true_rel}
+
+
+def time_apply(torch, S, reps=40, nbuf=8):
+    """Average duration of the operator-apply kernel (one launch per ndmg_apply), timed
+    with HIP events on the library's stream, rotating over nbuf input/output pairs so that
+    the 256 MB last-level cache cannot hold them."""
+    xs = [torch.randn(S.vec_len, dtype=torch.float64, device=S.device) for _ in range(nbuf)]
+    mask = S.apply(torch.ones(S.vec_len, dtype=torch.float64, device=S.device)) != 0
+    xs = [x * mask for x in xs]
+    ys = [S.zeros() for _ in range(nbuf)]
+    for i in range(nbuf):
+        S.apply(xs[i], ys[i])
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(reps):
+        S.apply(xs[i % nbuf], ys[i % nbuf])
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(f, iters_expected, sample_iters=3):
+    """The FP64 CPU oracle (assembled sparse matrices, factored vertex smoother) on a
+    bounded sample of the same 128^3 solve: setup untimed, then `sample_iters` PCG
+    iterations timed and scaled to a full solve of `iters_expected` iterations."""
+    from oracle import pcg, rhs, vcycle
+    h = 1.0 / N_ELEM
+    b = rhs.load_from_samples(N_ELEM, h, f)
+    t0 = time.perf_counter()
+    H = vcycle.Hierarchy(N_ELEM, 1.0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pcg.pcg(H.A[-1], b, H.precondition, rtol=RTOL, maxit=sample_iters)
+    t = time.perf_counter() - t0
+    per_iter = t / sample_iters
+    s_solve = per_iter * iters_expected
+    ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
+    return {"value": ndof / s_solve, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{sample_iters} V-cycle-PCG iterations of the 128^3 alpha=1 solve "
+                       f"({t:.1f} s, setup {t_setup:.1f} s untimed), scaled to "
+                       f"{iters_expected} iterations; SciPy SpMV single-threaded"),
+            "s_per_solve_est": s_solve,
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2205_05840_amd import Solver, synth
+    from paper_2205_05840_amd import _lib
+    _lib.lib()   # fail loudly if the HIP library is missing
+
+    f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
+    ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
+    legs = {}
+    sols = {}
+    for alpha in (1.0, 1e-3):
+        for prec in ("fp32", "fp64"):
+            S, b, u, res = run_leg(torch, Solver, f, alpha, prec, args.steps, args.warmup)
+            res["dof_per_s"] = ndof / res["s_per_solve_total"]
+            legs[f"{prec}@alpha={alpha:g}"] = res
+            sols[(alpha, prec)] = u.clone()
+            if alpha == 1.0 and prec == "fp64":
+                t_apply = time_apply(torch, S)
+            del S, b, u
+            torch.cuda.empty_cache()
+    for alpha in (1.0, 1e-3):
+        u32, u64 = sols[(alpha, "fp32")], sols[(alpha, "fp64")]
+        legs[f"fp32@alpha={alpha:g}"]["rel_diff_vs_fp64"] = float(
+            torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+
+    head = legs["fp32@alpha=1"]
+    fp64 = legs["fp64@alpha=1"]
+    bytes_apply = 2 * ndof * 8
+    achieved = bytes_apply / t_apply / 1e9
+    traffic = load_traffic("apply", "fp64")
+    roofline = {"kernel": "k_apply<double,0> (operator apply y = A x, 128^3, FP64)",
+                "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": achieved / 8000.0, "traffic": traffic,
+                "avg_launch_us": t_apply * 1e6, "algorithmic_bytes_per_launch": bytes_apply}
+    out = {
+        "metric": "DOF/s and s/solve to 1e-10 rel. residual at 128^3, mixed vs FP64 V-cycle-PCG",
+        "value": head["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["s_per_solve_total"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 CG + f32 V-cycle", "data": "synthetic",
+        "config": {"workload": ("128^3 unit-cube hex mesh, lowest-order Nedelec, alpha=1, f~N(0,1) "
+                                "at 2x2x2 Gauss points (seed 2), vertex-smoother V(1,1)-PCG to "
+                                "1e-10, FP32 V-cycle in FP64 flexible CG"),
+                   "n": N_ELEM, "ndof": ndof, "levels": 7, "parallelism": "single GPU"},
+        "s_per_solve": head["s_per_solve_total"], "iters": head["iters"],
+        "relres": head["relres"], "true_relres": head["true_relres"],
+        "fp64": {"value": fp64["dof_per_s"], "s_per_solve": fp64["s_per_solve_total"],
+                 "iters": fp64["iters"], "true_relres": fp64["true_relres"]},
+        "speedup_mixed_vs_fp64": fp64["s_per_solve_total"] / head["s_per_solve_total"],
+        "legs": legs, "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"])
+    print(json.dumps(out), flush=True)
+    del np
+
+
+if __name__ == "__main__":
+    main()

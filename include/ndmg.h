@@ -1,0 +1,168 @@
+/*
+ * ndmg: V-cycle multigrid for the lowest-order hexahedral Nedelec discretisation of
+ *        curl(alpha curl u) + u = f in a cube, u x n = 0 on its boundary,
+ *        with the nonoverlapping substructuring smoothers of Oh, "Multigrid methods for
+ *        3D H(curl) problems with nonoverlapping domain decomposition smoothers"
+ *        (arXiv 2205.05840), used as a preconditioner inside conjugate gradients.
+ *
+ * C ABI.  Every pointer argument named d_* is a device (HIP, gfx950) pointer owned by
+ * the caller; every other pointer is a host pointer owned by the caller.  Nothing
+ * here allocates device memory except ndmg_setup's per-context host metadata: the
+ * caller passes a device workspace of the size ndmg_plan reports.  All device work
+ * is enqueued on the stream given to ndmg_setup.  A context must not be used from two
+ * threads at once.  Functions return NDMG_OK or one of the error codes below and
+ * never abort or throw; ndmg_last_error() then describes the failure (per thread).
+ *
+ * Vector layout ("padded edge layout").  The mesh has n^3 cubes of side h = length/n.
+ * An edge of direction d (0 = x, 1 = y, 2 = z) is addressed by (i, j, k): along axis
+ * d a cell index in [0, n), along the other two axes a node index in [0, n].  A
+ * vector holds one value per edge (the edge average of the tangential component,
+ * Sec. 2, eq. NDdof) at offset
+ *        d * B + (k * (n + 1) + j) * P + i,    P = pitch, B = (n + 1)^2 * P,
+ * total length 3 * B (ndmg_layout reports n, P, B).  Only interior edges (transverse
+ * node indices in [1, n-1]) are unknowns (zero tangential trace, Sec. 1).  Every other
+ * entry (boundary edges, the unused i = n of x-edges etc., the row padding) must be 0
+ * on input and is written as 0 (or left untouched, where stated) on output.
+ * Floating-point vectors at the boundary are always double (FP64).
+ */
+#ifndef NDMG_H
+#define NDMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define NDMG_OK 0
+#define NDMG_EINVAL 1      /* invalid argument (sizes, alpha <= 0, null pointer, ...) */
+#define NDMG_EHIP 2        /* a HIP runtime call failed                               */
+#define NDMG_ENOCONV 3     /* PCG reached maxit; u, iters and relres are still written */
+#define NDMG_EBREAKDOWN 4  /* PCG breakdown: p^T A p <= 0 or a non-finite scalar        */
+#define NDMG_EWORKSPACE 5  /* workspace too small or misaligned                         */
+
+/* ---- options ----------------------------------------------------------------------- */
+#define NDMG_SMOOTHER_VERTEX 0   /* vertex-based smoother, eq. (Preconditioner P)       */
+#define NDMG_PREC_FP64 0         /* V-cycle in FP64                                     */
+#define NDMG_PREC_FP32 1         /* V-cycle in FP32 inside FP64 CG (mixed precision)    */
+
+typedef struct ndmg_opts {
+  int smoother;         /* NDMG_SMOOTHER_VERTEX                                       */
+  int m;                /* smoothing steps m of MG(k, g, z0, m) (Fig. 1); default 1   */
+  double eta;           /* damping eta_V; <= 0 selects 1/9 (Sec. 5)                   */
+  int precision;        /* NDMG_PREC_FP64 or NDMG_PREC_FP32                           */
+  int subdomain;        /* s: subdomains are s x s x s fine cells; 2 (= T_{k-1}) or 4 */
+  int boundary_patches; /* 1: vertex spaces also at coarse vertices on the boundary,
+                           cut to the domain (default; reproduces Table 2);
+                           0: interior coarse vertices only                          */
+  int flexible;         /* 1: Polak-Ribiere beta in PCG (default for FP32)          */
+} ndmg_opts;
+
+/* Fill *o with the defaults above. */
+void ndmg_default_opts(ndmg_opts* o);
+
+/* ---- planning and setup ---------------------------------------------------------------
+ * ndmg_plan: validate a problem and report the device workspace size in bytes and the
+ * vector length (in elements) of the padded edge layout of the finest level.
+ * n: elements per axis (>= 2); length: cube side (> 0); alpha: the constant of
+ * eq. (model problem) (> 0).  The levels are n, n/2, ... while a level is even and its
+ * half is >= 2 (Sec. 3.1, h_k = h_{k-1}/2); the coarsest is solved exactly.  Every
+ * smoothed level must be divisible by min(s, n_k / 2).  Either output pointer may be
+ * NULL.  Errors: NDMG_EINVAL.
+ */
+int ndmg_plan(int n, double length, double alpha, const ndmg_opts* opts,
+              size_t* workspace_bytes, size_t* vec_len);
+
+/* Opaque solver context. */
+typedef struct ndmg_ctx ndmg_ctx;
+
+/* ndmg_setup: build the level hierarchy and the local factors of every level (the
+ * subdomain matrices A_T of eq. ATDef and the vertex-space matrices A_V of eq. AVDef,
+ * inverted in FP64 on the host), lay out the caller's workspace (d_workspace, at
+ * least the planned size, 256-byte aligned), clear it and upload the factors.
+ * stream: a hipStream_t (NULL = default stream).  opts may be NULL (defaults).
+ * On success *out owns host metadata only; release it with ndmg_destroy.
+ * Errors: NDMG_EINVAL, NDMG_EWORKSPACE, NDMG_EHIP.
+ */
+int ndmg_setup(ndmg_ctx** out, int n, double length, double alpha, const ndmg_opts* opts,
+               void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* ndmg_layout: describe the padded edge layout of a level (level 0 = coarsest,
+ * level -1 = finest).  info[0] = n, info[1] = P (row pitch), info[2] = B (block
+ * length), info[3] = vector length 3 B, info[4] = number of levels,
+ * info[5] = number of unknowns 3 n (n-1)^2.  Errors: NDMG_EINVAL.
+ */
+int ndmg_layout(const ndmg_ctx* ctx, int level, int64_t info[6]);
+
+/* ---- operations (all FP64 vectors in the padded layout of the finest level) -------- */
+
+/* y = A x with A the matrix of a(., .) on N_h (eq. def bilinear form, eq. fem):
+ * y = alpha K x + M x.  d_x and d_y must not overlap.  Errors: NDMG_EINVAL, NDMG_EHIP. */
+int ndmg_apply(ndmg_ctx* ctx, const double* d_x, double* d_y);
+
+/* z = MG(J, g, 0, m): one symmetric V-cycle (Fig. 1) with the vertex-based smoother of
+ * eq. (Preconditioner P) and the grid transfers of eq. (F2C), in the context's
+ * precision.  d_g and d_z must not overlap.  Errors: NDMG_EINVAL, NDMG_EHIP. */
+int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
+
+/* Solve A u = b (eq. fem) by conjugate gradients preconditioned with the V-cycle,
+ * from u = 0, until ||b - A u||_2 <= rtol ||b||_2 (recursive residual) or maxit
+ * iterations.  iters and relres (host pointers, may be NULL) receive the iteration
+ * count and the final relative residual.  The stream is synchronised once per
+ * iteration for the convergence test.
+ * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (u still written), NDMG_EBREAKDOWN. */
+int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
+                   int* iters, double* relres);
+
+/* Load vector b_e = (f, phi_e) (Sec. 2, the functional f_h) from f sampled at the
+ * 2x2x2 Gauss-Legendre points of every element: d_f is [n^3][8][3] doubles, element
+ * (c0, c1, c2) at row (c2 n + c1) n + c0, point q = q0 + 2 q1 + 4 q2 at local
+ * coordinates (x_{q0}, x_{q1}, x_{q2}), x = (1 -+ 1/sqrt 3) / 2, components x, y, z.
+ * d_b receives the padded layout.  Errors: NDMG_EINVAL, NDMG_EHIP. */
+int ndmg_assemble_rhs(ndmg_ctx* ctx, const double* d_f, double* d_b);
+
+/* out = sum_r lam_r^T K u_r for nrhs vector pairs stored back to back (each of the
+ * padded vector length), K = dA/dalpha the curl-curl matrix of eq. (def bilinear
+ * form).  out is a host pointer.  Used for dL/dalpha = -sum_r lam_r^T K u_r.
+ * Errors: NDMG_EINVAL, NDMG_EHIP. */
+int ndmg_curlcurl_form(ndmg_ctx* ctx, const double* d_lam, const double* d_u, int nrhs,
+                       double* out);
+
+/* Debug export of the FP64 local factors of a level (level as in ndmg_layout, >= 1):
+ * which = 0: A_T^{-1} (nI x nI, row-major), which = 1: the padded inverse Schur
+ * complement of the vertex type `type` (0..26, per axis 0 low face, 1 inside, 2 high
+ * face; 13 = interior), npad x npad row-major with zero rows/columns for slots that do
+ * not exist for that type.  dims[0] receives the row count.  buf (host) must hold
+ * dims[0]^2 doubles, or be NULL to query dims only.  Errors: NDMG_EINVAL. */
+int ndmg_export_factor(const ndmg_ctx* ctx, int level, int which, int type, double* buf,
+                       int* dims);
+
+/* ---- single steps of one level (FP64 contexts; for tests and diagnostics) ----------
+ * Vectors use the padded layout of the level(s) named (ndmg_layout).  level as in
+ * ndmg_layout.
+ *   NDMG_OP_APPLY     out = A_k in                                  (any level)
+ *   NDMG_OP_SMOOTH    out = M_k^{-1} in, the vertex-based smoother of
+ *                     eq. (Preconditioner P) including its damping eta   (level >= 1)
+ *   NDMG_OP_RESTRICT  out (level k-1) = I_k^{k-1} in (level k), eq. (F2C)  (level >= 1)
+ *   NDMG_OP_PROLONG   out (level k) += I_{k-1}^k in (level k-1)           (level >= 1)
+ *   NDMG_OP_COARSE    out = A_0^{-1} in                               (level 0)
+ * Errors: NDMG_EINVAL (FP32 context, bad level or op), NDMG_EHIP. */
+#define NDMG_OP_APPLY 0
+#define NDMG_OP_SMOOTH 1
+#define NDMG_OP_RESTRICT 2
+#define NDMG_OP_PROLONG 3
+#define NDMG_OP_COARSE 4
+int ndmg_level_op(ndmg_ctx* ctx, int level, int op, const double* d_in, double* d_out);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+int ndmg_destroy(ndmg_ctx* ctx);
+
+/* Description of the last error on this thread ("" if none). */
+const char* ndmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NDMG_H */

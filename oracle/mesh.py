@@ -43,20 +43,33 @@ def block_offset(n, d):
     return d * n * (n - 1) ** 2
 
 
-def compact_index(n, d, p0, p1, p2):
-    """Compact index of the edge of direction d at p; -1 where it is a boundary edge."""
+def compact_index(n, dd, p0, p1, p2, d=None):
+    """Compact index of the edge of direction dd at p; -1 where it is a boundary edge.
+
+    dd may be None with an array ``d`` of per-entry directions instead."""
     p = [np.asarray(p0), np.asarray(p1), np.asarray(p2)]
-    ok = np.ones(np.broadcast(*p).shape, dtype=bool)
-    q = []
-    for ax in range(3):
-        if ax == d:
-            ok &= (p[ax] >= 0) & (p[ax] < n)
-            q.append(p[ax])
-        else:
-            ok &= (p[ax] >= 1) & (p[ax] <= n - 1)
-            q.append(p[ax] - 1)
-    s = block_shape(n, d)
-    idx = block_offset(n, d) + (q[2] * s[1] + q[1]) * s[2] + q[0]
+    dirs = np.asarray(dd if dd is not None else d)
+    shape = np.broadcast(*p, dirs).shape
+    ok = np.ones(shape, dtype=bool)
+    idx = np.full(shape, -1, dtype=np.int64)
+    for dv in range(3):
+        sel = np.broadcast_to(dirs == dv, shape)
+        if not np.any(sel):
+            continue
+        q = []
+        okd = np.ones(shape, dtype=bool)
+        for ax in range(3):
+            pa = np.broadcast_to(p[ax], shape)
+            if ax == dv:
+                okd &= (pa >= 0) & (pa < n)
+                q.append(pa)
+            else:
+                okd &= (pa >= 1) & (pa <= n - 1)
+                q.append(pa - 1)
+        sh = block_shape(n, dv)
+        val = block_offset(n, dv) + (q[2] * sh[1] + q[1]) * sh[2] + q[0]
+        idx = np.where(sel, val, idx)
+        ok = np.where(sel, okd, ok)
     return np.where(ok, idx, -1)
 
 
@@ -250,3 +263,33 @@ def edge_patch_elements(n, s, axis, c):
             if all(0 <= x < m for x in t):
                 out.append(tuple(t))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Whole-level index arrays (the same sets as above, built for all subdomains or
+# vertices at once; compact indices are affine in the edge coordinates within each
+# direction block, so translating a set keeps its sorted order).
+# ---------------------------------------------------------------------------
+
+def _shifted(n, rel_d, rel_p, shifts):
+    """Compact indices of the edges (rel_d, rel_p + shift) for every shift (rows)."""
+    P = shifts[:, None, :] + rel_p[None, :, :]
+    return compact_index(n, None, P[..., 0], P[..., 1], P[..., 2], d=rel_d[None, :])
+
+
+def interior_sets(n, s):
+    """[n_subdomains, 3 s (s-1)^2] array; row r is interior_set(n, s, coarse_elements()[r])."""
+    elems = np.array(coarse_elements(n, s))
+    ref = interior_set(n, s, (0, 0, 0))
+    d, p = edge_coords(n)
+    rel_d, rel_p = d[ref], p[ref]
+    return _shifted(n, rel_d, rel_p, s * elems)
+
+
+def vertex_interface_sets(n, s, verts):
+    """[len(verts), |Gamma|] for vertices of one type; rows equal vertex_interface_set."""
+    verts = np.asarray(verts)
+    ref = vertex_interface_set(n, s, tuple(verts[0]))
+    d, p = edge_coords(n)
+    rel_d, rel_p = d[ref], p[ref] - s * verts[0][None, :]
+    return _shifted(n, rel_d, rel_p, s * verts)

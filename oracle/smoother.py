@@ -101,30 +101,42 @@ class FactoredVertexSmoother:
     vertex lies on), taken from the first patch of that type.
     """
 
-    def __init__(self, A, n, s=2, eta=1.0 / 9.0, boundary=True):
+    def __init__(self, A, n, s=2, eta=1.0 / 9.0, boundary=True, inverse="lu"):
+        """inverse: 'lu' (numpy inverse, LAPACK solve for the Schur complement) or
+        'cholesky' (explicit Cholesky inverses); two FP64 routes to the same factors whose
+        difference measures how far rounding in the setup moves the result."""
         if n % s or n // s < 2:
             raise ValueError("need n divisible by s with at least 2 subdomains per axis")
         self.A, self.n, self.s, self.eta = A.tocsr(), n, s, eta
-        elems = mesh.coarse_elements(n, s)
-        self.Iidx = np.stack([mesh.interior_set(n, s, t) for t in elems])
+        self.Iidx = mesh.interior_sets(n, s)
         I0 = self.Iidx[0]
         self.AT = _sub(self.A, I0, I0)
-        self.ATinv = np.linalg.inv(self.AT)
+
+        def inv(M):
+            if inverse == "cholesky":
+                return sla.cho_solve(sla.cho_factor(M), np.eye(M.shape[0]))
+            return np.linalg.inv(M)
+
+        self.ATinv = inv(self.AT)
         groups = {}
         for v in mesh.coarse_vertices(n, s, boundary):
             groups.setdefault(mesh.vertex_type(n, s, v), []).append(v)
         self.groups = []
         for typ in sorted(groups):
             verts = groups[typ]
-            Gidx = np.stack([mesh.vertex_interface_set(n, s, v) for v in verts])
+            Gidx = mesh.vertex_interface_sets(n, s, verts)
             v0 = verts[0]
             G0 = Gidx[0]
             Ip = np.sort(np.concatenate([mesh.interior_set(n, s, t)
                                          for t in mesh.patch_elements(n, s, v0)]))
             App = _sub(self.A, Ip, Ip)
             ApG = _sub(self.A, Ip, G0)
-            S = _sub(self.A, G0, G0) - ApG.T @ np.linalg.solve(App, ApG)
-            self.groups.append((typ, Gidx, S, sla.inv(S)))
+            if inverse == "cholesky":
+                X = inv(App) @ ApG
+            else:
+                X = np.linalg.solve(App, ApG)
+            S = _sub(self.A, G0, G0) - ApG.T @ X
+            self.groups.append((typ, Gidx, S, inv(S)))
 
     def schur(self, typ=13):
         for t, _, S, _ in self.groups:

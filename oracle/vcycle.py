@@ -16,7 +16,7 @@ class Hierarchy:
     """All levels of the V-cycle for n elements per axis on a cube of side L."""
 
     def __init__(self, n, alpha, L=1.0, s=2, m=1, kind="vertex", eta=None,
-                 factored=None, damp_interior=True, boundary=True):
+                 factored=None, damp_interior=True, boundary=True, inverse="lu"):
         self.sizes = mesh.level_sizes(n)          # coarsest first
         self.alpha, self.L, self.m = alpha, L, m
         self.A, self.M, self.P = [], [], [None]
@@ -34,7 +34,7 @@ class Hierarchy:
             use_f = factored if factored is not None else (nk >= 24)
             if kind == "vertex" and use_f and damp_interior:
                 e = 1.0 / 9.0 if eta is None else eta
-                self.M.append(sm.FactoredVertexSmoother(A, nk, sk, e, boundary))
+                self.M.append(sm.FactoredVertexSmoother(A, nk, sk, e, boundary, inverse))
             else:
                 self.M.append(sm.LiteralSmoother(A, nk, sk, kind, eta, damp_interior, boundary))
             self.P.append(transfer.prolongation(self.sizes[k - 1]))

@@ -1,0 +1,153 @@
+"""ctypes binding of libndmg.so (the C ABI declared in include/ndmg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  The
+functions keep the C names; device pointers are passed as integers (for example
+``tensor.data_ptr()``) and the stream as ``torch.cuda.Stream.cuda_stream``.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libndmg.so")
+
+NDMG_OK = 0
+NDMG_EINVAL = 1
+NDMG_EHIP = 2
+NDMG_ENOCONV = 3
+NDMG_EBREAKDOWN = 4
+NDMG_EWORKSPACE = 5
+
+EXPORTED = [
+    "ndmg_default_opts", "ndmg_plan", "ndmg_setup", "ndmg_layout", "ndmg_apply",
+    "ndmg_vcycle", "ndmg_pcg_solve", "ndmg_assemble_rhs", "ndmg_curlcurl_form",
+    "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
+]
+
+NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE = range(5)
+
+
+class ndmg_opts(ctypes.Structure):
+    _fields_ = [
+        ("smoother", ctypes.c_int),
+        ("m", ctypes.c_int),
+        ("eta", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("subdomain", ctypes.c_int),
+        ("boundary_patches", ctypes.c_int),
+        ("flexible", ctypes.c_int),
+    ]
+
+
+class NdmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ndmg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libndmg.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, d, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    L.ndmg_default_opts.argtypes = [P(ndmg_opts)]
+    L.ndmg_default_opts.restype = None
+    L.ndmg_plan.argtypes = [i, d, d, P(ndmg_opts), P(sz), P(sz)]
+    L.ndmg_setup.argtypes = [P(vp), i, d, d, P(ndmg_opts), vp, sz, vp]
+    L.ndmg_layout.argtypes = [vp, i, P(ctypes.c_int64)]
+    L.ndmg_apply.argtypes = [vp, vp, vp]
+    L.ndmg_vcycle.argtypes = [vp, vp, vp]
+    L.ndmg_pcg_solve.argtypes = [vp, vp, vp, d, i, P(i), P(d)]
+    L.ndmg_assemble_rhs.argtypes = [vp, vp, vp]
+    L.ndmg_curlcurl_form.argtypes = [vp, vp, vp, i, P(d)]
+    L.ndmg_export_factor.argtypes = [vp, i, i, i, P(d), P(i)]
+    L.ndmg_level_op.argtypes = [vp, i, i, vp, vp]
+    L.ndmg_destroy.argtypes = [vp]
+    L.ndmg_last_error.argtypes = []
+    L.ndmg_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("ndmg_default_opts", "ndmg_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != NDMG_OK:
+        raise NdmgError(code, lib().ndmg_last_error().decode())
+    return code
+
+
+def ndmg_default_opts():
+    o = ndmg_opts()
+    lib().ndmg_default_opts(ctypes.byref(o))
+    return o
+
+
+def ndmg_plan(n, length, alpha, opts):
+    ws, vl = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().ndmg_plan(n, length, alpha, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(vl)))
+    return ws.value, vl.value
+
+
+def ndmg_setup(n, length, alpha, opts, d_workspace, workspace_bytes, stream):
+    ctx = ctypes.c_void_p()
+    check(lib().ndmg_setup(ctypes.byref(ctx), n, length, alpha, ctypes.byref(opts), d_workspace,
+                           workspace_bytes, stream))
+    return ctx
+
+
+def ndmg_layout(ctx, level=-1):
+    info = (ctypes.c_int64 * 6)()
+    check(lib().ndmg_layout(ctx, level, info))
+    return list(info)
+
+
+def ndmg_apply(ctx, d_x, d_y):
+    return check(lib().ndmg_apply(ctx, d_x, d_y))
+
+
+def ndmg_vcycle(ctx, d_g, d_z):
+    return check(lib().ndmg_vcycle(ctx, d_g, d_z))
+
+
+def ndmg_pcg_solve(ctx, d_b, d_u, rtol, maxit, raise_on_noconv=True):
+    it, rel = ctypes.c_int(), ctypes.c_double()
+    code = lib().ndmg_pcg_solve(ctx, d_b, d_u, rtol, maxit, ctypes.byref(it), ctypes.byref(rel))
+    if code != NDMG_OK and (raise_on_noconv or code != NDMG_ENOCONV):
+        check(code)
+    return code, it.value, rel.value
+
+
+def ndmg_assemble_rhs(ctx, d_f, d_b):
+    return check(lib().ndmg_assemble_rhs(ctx, d_f, d_b))
+
+
+def ndmg_curlcurl_form(ctx, d_lam, d_u, nrhs):
+    out = ctypes.c_double()
+    check(lib().ndmg_curlcurl_form(ctx, d_lam, d_u, nrhs, ctypes.byref(out)))
+    return out.value
+
+
+def ndmg_export_factor(ctx, level, which, typ=13):
+    dims = ctypes.c_int()
+    check(lib().ndmg_export_factor(ctx, level, which, typ, None, ctypes.byref(dims)))
+    buf = (ctypes.c_double * (dims.value * dims.value))()
+    check(lib().ndmg_export_factor(ctx, level, which, typ, buf, ctypes.byref(dims)))
+    return list(buf), dims.value
+
+
+def ndmg_level_op(ctx, level, op, d_in, d_out):
+    return check(lib().ndmg_level_op(ctx, level, op, d_in, d_out))
+
+
+def ndmg_destroy(ctx):
+    return check(lib().ndmg_destroy(ctx))

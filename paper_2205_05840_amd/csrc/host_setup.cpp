@@ -1,0 +1,443 @@
+// Host-side setup of the ndmg library: level geometry, the 12x12 Nedelec element
+// matrices, local subdomain and vertex-patch matrices, and their FP64 inverses.
+//
+// Element matrices (Sec. 2): on a cube of side h the lowest-order Nedelec basis
+// function of the x-edge at transverse offsets (a, b) is (psi_a(y) psi_b(z), 0, 0) in
+// local coordinates, psi_0(t) = 1 - t, psi_1(t) = t.  Its mass matrix is h^3 times the
+// tensor product of the 1-D hat mass [[1/3, 1/6], [1/6, 1/3]] over the two transverse
+// axes.  The curl of the element field is a Raviart-Thomas face field whose flux through
+// a face is h times the circulation of the edge values around it; the face mass along
+// the face normal is the same 1-D matrix, so K_T = h C^T blockdiag(m, m, m) C with C the
+// 6x12 circulation matrix.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "ndmg_internal.hpp"
+
+namespace ndmg {
+
+Geom make_geom(int n, double length) {
+  Geom g;
+  g.n = n;
+  g.P = ((n + 1) + 7) / 8 * 8;
+  g.plane = (int64_t)(n + 1) * g.P;
+  g.B = (int64_t)(n + 1) * g.plane;
+  g.len = 3 * g.B;
+  g.h = length / n;
+  return g;
+}
+
+SubInfo make_sub(int s, int n) {
+  SubInfo si;
+  si.s = s;
+  si.nH = n / s;
+  si.nI = 3 * s * (s - 1) * (s - 1);
+  si.nG = 6 * s * (4 * s - 3);
+  si.npad = (si.nG + 15) / 16 * 16;
+  si.lut_w = 2 * s + 1;
+  return si;
+}
+
+std::vector<Slot> vertex_slots(int s) {
+  // For direction d with transverse axes (a, b): cell offset in [-s, s-1];
+  // (off_a == 0 and |off_b| < s) or (off_b == 0 and 0 < |off_a| < s).
+  std::vector<Slot> out;
+  for (int d = 0; d < 3; ++d) {
+    for (int dz = -s; dz <= s; ++dz)
+      for (int dy = -s; dy <= s; ++dy)
+        for (int dx = -s; dx <= s; ++dx) {
+          int o[3] = {dx, dy, dz};
+          if (o[d] < -s || o[d] > s - 1) continue;
+          int a = (d + 1) % 3, b = (d + 2) % 3;
+          int oa = o[a], ob = o[b];
+          bool ok = (oa == 0 && std::abs(ob) < s) || (ob == 0 && oa != 0 && std::abs(oa) < s);
+          if (ok) out.push_back({d, dx, dy, dz});
+        }
+  }
+  return out;
+}
+
+std::vector<int> slot_lookup(int s) {
+  int w = 2 * s + 1;
+  std::vector<int> lut(3 * w * w * w, -1);
+  auto slots = vertex_slots(s);
+  for (size_t i = 0; i < slots.size(); ++i) {
+    const Slot& q = slots[i];
+    lut[((q.d * w + (q.dx + s)) * w + (q.dy + s)) * w + (q.dz + s)] = (int)i;
+  }
+  return lut;
+}
+
+std::vector<Slot> interior_dofs(int s) {
+  std::vector<Slot> out;
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z <= s; ++z)
+      for (int y = 0; y <= s; ++y)
+        for (int x = 0; x <= s; ++x) {
+          int o[3] = {x, y, z};
+          bool ok = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) ok &= (o[ax] >= 0 && o[ax] < s);
+            else ok &= (o[ax] >= 1 && o[ax] <= s - 1);
+          }
+          if (ok) out.push_back({d, x, y, z});
+        }
+  return out;
+}
+
+std::vector<Segment> vertex_segments(int nH, bool boundary_patches) {
+  std::vector<Segment> out;
+  for (int tz = 0; tz < 3; ++tz)
+    for (int ty = 0; ty < 3; ++ty)
+      for (int tx = 0; tx < 3; ++tx) {
+        int t[3] = {tx, ty, tz};
+        int nb = (tx != 1) + (ty != 1) + (tz != 1);
+        if (nb == 3) continue;                 // box corners: empty interface
+        if (!boundary_patches && nb > 0) continue;
+        Segment sg;
+        sg.type = tx + 3 * ty + 9 * tz;
+        sg.count = 1;
+        for (int ax = 0; ax < 3; ++ax) {
+          if (t[ax] == 0) { sg.lo[ax] = 0; sg.dims[ax] = 1; }
+          else if (t[ax] == 2) { sg.lo[ax] = nH; sg.dims[ax] = 1; }
+          else { sg.lo[ax] = 1; sg.dims[ax] = nH - 1; }
+          sg.count *= sg.dims[ax];
+        }
+        if (sg.count > 0) out.push_back(sg);
+      }
+  return out;
+}
+
+// ---------------------------------------------------------------------------------
+// Element matrix
+// ---------------------------------------------------------------------------------
+static inline int ledge(int d, int a, int b) { return 4 * d + a + 2 * b; }
+
+void element_matrix(double h, double alpha, double curl_scale, double* E) {
+  const double m[2][2] = {{1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 3.0}};
+  for (int i = 0; i < 144; ++i) E[i] = 0.0;
+  // mass: per direction, tensor product over the transverse (a, b) offsets
+  const double h3 = h * h * h;
+  for (int d = 0; d < 3; ++d)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a)
+        for (int b2 = 0; b2 < 2; ++b2)
+          for (int a2 = 0; a2 < 2; ++a2)
+            E[ledge(d, a, b) * 12 + ledge(d, a2, b2)] += h3 * m[a][a2] * m[b][b2];
+  // circulation matrix C (6 faces x 12 edges): face of normal ax at local node f.
+  // Right-hand rule around +ax with (p, q) the next two axes cyclically:
+  //   + e_q(at p = 1) - e_q(at p = 0) - e_p(at q = 1) + e_p(at q = 0)
+  // where e_q is the edge of direction q and e_p of direction p on that face.
+  double C[6][12] = {{0}};
+  for (int ax = 0; ax < 3; ++ax) {
+    int p = (ax + 1) % 3, q = (ax + 2) % 3;
+    for (int f = 0; f < 2; ++f) {
+      // edge of direction dir (p or q) on this face, at node c along the third axis
+      auto edge_at = [&](int dir, int c) {
+        int o[3] = {0, 0, 0};
+        o[ax] = f;
+        o[3 - dir - ax] = c;
+        int t0 = (dir == 0) ? 1 : 0;   // transverse axes of dir, ascending
+        int t1 = (dir == 2) ? 1 : 2;
+        return ledge(dir, o[t0], o[t1]);
+      };
+      int row = 2 * ax + f;
+      C[row][edge_at(q, 1)] += 1.0;   // edge of direction q at p-node 1
+      C[row][edge_at(q, 0)] -= 1.0;   // edge of direction q at p-node 0
+      C[row][edge_at(p, 1)] -= 1.0;   // edge of direction p at q-node 1
+      C[row][edge_at(p, 0)] += 1.0;   // edge of direction p at q-node 0
+    }
+  }
+  const double kh = alpha * curl_scale * h;
+  for (int ax = 0; ax < 3; ++ax)
+    for (int f = 0; f < 2; ++f)
+      for (int f2 = 0; f2 < 2; ++f2) {
+        double w = kh * m[f][f2];
+        const double* ci = C[2 * ax + f];
+        const double* cj = C[2 * ax + f2];
+        for (int i = 0; i < 12; ++i) {
+          if (ci[i] == 0.0) continue;
+          for (int j = 0; j < 12; ++j)
+            if (cj[j] != 0.0) E[i * 12 + j] += w * ci[i] * cj[j];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------------
+// Dense SPD inverse (Cholesky)
+// ---------------------------------------------------------------------------------
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double d = L[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = L[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / d;
+    }
+  }
+  // inverse of L (lower), then A^{-1} = L^{-T} L^{-1}
+  std::vector<double> Li(n * (size_t)n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Li[j * n + j] = 1.0 / L[j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double v = 0.0;
+      for (int k = j; k < i; ++k) v -= L[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = v / L[i * n + i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+      for (int k = i; k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
+      A[i * n + j] = v;
+      A[j * n + i] = v;
+    }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------
+// Local assembly over a set of fine cells (relative integer coordinates)
+// ---------------------------------------------------------------------------------
+namespace {
+
+using Key = std::tuple<int, int, int, int>;   // direction, x, y, z
+
+struct LocalSystem {
+  std::map<Key, int> index;
+  std::vector<Key> keys;
+  std::vector<double> A;   // dense, size N x N, filled after assembly
+  int N = 0;
+};
+
+// Edge of direction d of the cell with lower corner c at transverse offsets (a, b).
+Key cell_edge(const int c[3], int d, int a, int b) {
+  int t0 = (d == 0) ? 1 : 0;
+  int t1 = (d == 2) ? 1 : 2;
+  int o[3] = {c[0], c[1], c[2]};
+  o[t0] += a;
+  o[t1] += b;
+  return Key(d, o[0], o[1], o[2]);
+}
+
+void assemble_cells(const std::vector<std::array<int, 3>>& cells, double h, double alpha,
+                    LocalSystem* sys) {
+  for (auto& c : cells)
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          Key k = cell_edge(c.data(), d, a, b);
+          if (!sys->index.count(k)) {
+            sys->index[k] = (int)sys->keys.size();
+            sys->keys.push_back(k);
+          }
+        }
+  sys->N = (int)sys->keys.size();
+  sys->A.assign((size_t)sys->N * sys->N, 0.0);
+  double E[144];
+  element_matrix(h, alpha, 1.0, E);
+  for (auto& c : cells) {
+    int loc[12];
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) loc[ledge(d, a, b)] = sys->index[cell_edge(c.data(), d, a, b)];
+    for (int i = 0; i < 12; ++i)
+      for (int j = 0; j < 12; ++j) sys->A[(size_t)loc[i] * sys->N + loc[j]] += E[i * 12 + j];
+  }
+}
+
+std::vector<double> submatrix(const LocalSystem& sys, const std::vector<int>& r,
+                              const std::vector<int>& c) {
+  std::vector<double> out(r.size() * c.size());
+  for (size_t i = 0; i < r.size(); ++i)
+    for (size_t j = 0; j < c.size(); ++j) out[i * c.size() + j] = sys.A[(size_t)r[i] * sys.N + c[j]];
+  return out;
+}
+
+}  // namespace
+
+bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
+                         LevelFactors* out, std::string* err) {
+  const int s = sub.s;
+  // ---- subdomain interior: cells [0, s)^3 ------------------------------------------
+  {
+    std::vector<std::array<int, 3>> cells;
+    for (int z = 0; z < s; ++z)
+      for (int y = 0; y < s; ++y)
+        for (int x = 0; x < s; ++x) cells.push_back({x, y, z});
+    LocalSystem sys;
+    assemble_cells(cells, h, alpha, &sys);
+    auto dofs = interior_dofs(s);
+    std::vector<int> I;
+    for (auto& q : dofs) I.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+    out->ATinv = submatrix(sys, I, I);
+    if (!spd_inverse(out->ATinv, (int)I.size())) {
+      *err = "subdomain matrix A_T is not positive definite";
+      return false;
+    }
+  }
+  // ---- vertex patches, one per type ---------------------------------------------------
+  const int np = sub.npad;
+  out->Sinv.assign((size_t)27 * np * np, 0.0);
+  out->S27.assign((size_t)27 * np * np, 0.0);
+  auto slots = vertex_slots(s);
+  for (int tz = 0; tz < 3; ++tz)
+    for (int ty = 0; ty < 3; ++ty)
+      for (int tx = 0; tx < 3; ++tx) {
+        int t[3] = {tx, ty, tz};
+        int nb = (tx != 1) + (ty != 1) + (tz != 1);
+        if (nb == 3) continue;
+        if (!boundary_patches && nb > 0) continue;
+        int type = tx + 3 * ty + 9 * tz;
+        int lo[3], hi[3];   // present cells [lo, hi) relative to the vertex node
+        for (int ax = 0; ax < 3; ++ax) {
+          lo[ax] = (t[ax] == 0) ? 0 : -s;
+          hi[ax] = (t[ax] == 2) ? 0 : s;
+        }
+        std::vector<std::array<int, 3>> cells;
+        for (int z = lo[2]; z < hi[2]; ++z)
+          for (int y = lo[1]; y < hi[1]; ++y)
+            for (int x = lo[0]; x < hi[0]; ++x) cells.push_back({x, y, z});
+        LocalSystem sys;
+        assemble_cells(cells, h, alpha, &sys);
+        // an edge is Dirichlet if it lies in a boundary plane (node coordinate 0 along a
+        // boundary axis, for an axis other than its direction)
+        auto dirichlet = [&](const Key& k) {
+          int d = std::get<0>(k);
+          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+          for (int ax = 0; ax < 3; ++ax)
+            if (ax != d && t[ax] != 1 && o[ax] == 0) return true;
+          return false;
+        };
+        auto inside_cells = [&](const Key& k) {
+          int d = std::get<0>(k);
+          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) { if (o[ax] < lo[ax] || o[ax] >= hi[ax]) return false; }
+            else { if (o[ax] < lo[ax] || o[ax] > hi[ax]) return false; }
+          }
+          return true;
+        };
+        std::vector<int> G, Gslot, I;
+        for (size_t si = 0; si < slots.size(); ++si) {
+          Key k(slots[si].d, slots[si].dx, slots[si].dy, slots[si].dz);
+          if (!inside_cells(k) || dirichlet(k)) continue;
+          G.push_back(sys.index.at(k));
+          Gslot.push_back((int)si);
+        }
+        for (int e = 0; e < sys.N; ++e) {
+          const Key& k = sys.keys[e];
+          int d = std::get<0>(k);
+          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+          bool interior = true;
+          for (int ax = 0; ax < 3; ++ax)
+            if (ax != d) {
+              int r = ((o[ax] % s) + s) % s;
+              if (r == 0) interior = false;
+            }
+          if (interior && !dirichlet(k)) I.push_back(e);
+        }
+        if (G.empty()) continue;
+        const int nG = (int)G.size(), nIp = (int)I.size();
+        std::vector<double> S = submatrix(sys, G, G);
+        if (nIp > 0) {
+          std::vector<double> AII = submatrix(sys, I, I);
+          std::vector<double> AIG = submatrix(sys, I, G);
+          if (!spd_inverse(AII, nIp)) {
+            *err = "patch interior matrix is not positive definite";
+            return false;
+          }
+          // X = AII^{-1} AIG, S -= AIG^T X
+          std::vector<double> X((size_t)nIp * nG, 0.0);
+          for (int i = 0; i < nIp; ++i)
+            for (int k = 0; k < nIp; ++k) {
+              double a = AII[(size_t)i * nIp + k];
+              if (a == 0.0) continue;
+              for (int j = 0; j < nG; ++j) X[(size_t)i * nG + j] += a * AIG[(size_t)k * nG + j];
+            }
+          for (int i = 0; i < nG; ++i)
+            for (int k = 0; k < nIp; ++k) {
+              double a = AIG[(size_t)k * nG + i];
+              if (a == 0.0) continue;
+              for (int j = 0; j < nG; ++j) S[(size_t)i * nG + j] -= a * X[(size_t)k * nG + j];
+            }
+        }
+        for (int i = 0; i < nG; ++i)     // symmetrise against rounding
+          for (int j = 0; j < i; ++j) {
+            double v = 0.5 * (S[(size_t)i * nG + j] + S[(size_t)j * nG + i]);
+            S[(size_t)i * nG + j] = S[(size_t)j * nG + i] = v;
+          }
+        std::vector<double> Si = S;
+        if (!spd_inverse(Si, nG)) {
+          *err = "vertex Schur complement is not positive definite";
+          return false;
+        }
+        double* dst = &out->Sinv[(size_t)type * np * np];
+        double* dsS = &out->S27[(size_t)type * np * np];
+        for (int i = 0; i < nG; ++i)
+          for (int j = 0; j < nG; ++j) {
+            dst[(size_t)Gslot[i] * np + Gslot[j]] = Si[(size_t)i * nG + j];
+            dsS[(size_t)Gslot[i] * np + Gslot[j]] = S[(size_t)i * nG + j];
+          }
+      }
+  return true;
+}
+
+bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
+                  std::vector<int64_t>* map, std::string* err) {
+  const int n = g.n;
+  // unknowns: interior edges in padded-layout order
+  std::map<Key, int> idx;
+  map->clear();
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z <= n; ++z)
+      for (int y = 0; y <= n; ++y)
+        for (int x = 0; x <= n; ++x) {
+          int o[3] = {x, y, z};
+          bool ok = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) ok &= (o[ax] < n);
+            else ok &= (o[ax] >= 1 && o[ax] <= n - 1);
+          }
+          if (!ok) continue;
+          idx[Key(d, x, y, z)] = (int)map->size();
+          map->push_back(d * g.B + (int64_t)z * g.plane + (int64_t)y * g.P + x);
+        }
+  const int N = (int)map->size();
+  if (N > 1024) {
+    *err = "coarsest level too large for the dense solve (over 1024 unknowns)";
+    return false;
+  }
+  A0inv->assign((size_t)N * N, 0.0);
+  double E[144];
+  element_matrix(g.h, alpha, 1.0, E);
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        int c[3] = {x, y, z};
+        int loc[12];
+        for (int d = 0; d < 3; ++d)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+              auto it = idx.find(cell_edge(c, d, a, b));
+              loc[ledge(d, a, b)] = (it == idx.end()) ? -1 : it->second;
+            }
+        for (int i = 0; i < 12; ++i)
+          for (int j = 0; j < 12; ++j)
+            if (loc[i] >= 0 && loc[j] >= 0) (*A0inv)[(size_t)loc[i] * N + loc[j]] += E[i * 12 + j];
+      }
+  if (!spd_inverse(*A0inv, N)) {
+    *err = "coarsest matrix is not positive definite";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace ndmg

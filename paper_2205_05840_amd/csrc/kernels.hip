@@ -1,0 +1,690 @@
+// Device kernels of the ndmg library (gfx950).
+//
+// Operator (Sec. 2, eq. def bilinear form): A = alpha K + M on interior edges with
+//   K = h C^T M_F C,  M = h^3 M_E,
+// C the face circulation of edge values (right-hand rule), M_F the Raviart-Thomas face
+// mass = tridiag(1/6, 2/3, 1/6) along each face normal, M_E = the tensor product of the
+// same 1-D matrix across each edge direction.  For an edge of direction a with (b, c)
+// the next two axes cyclically:
+//   F_b(q) = u_a(q + e_c) - u_a(q) - u_c(q + e_a) + u_c(q)       (faces of normal b)
+//   F_c(q) = u_b(q + e_a) - u_b(q) - u_a(q + e_b) + u_a(q)       (faces of normal c)
+//   G_b = M_F F_b along b,  G_c = M_F F_c along c,
+//   (C^T G)_a(p) = G_b(p - e_c) - G_b(p) - G_c(p - e_b) + G_c(p).
+// All reads of an interior edge's stencil stay inside [0, n]^3 of the padded layout and
+// boundary entries are zero, so no bounds checks are needed inside the stencil.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace ndmg {
+
+namespace {
+
+__device__ __forceinline__ int64_t lin(const DGeom& g, int i, int j, int k) {
+  return (int64_t)k * g.plane + (int64_t)j * g.P + i;
+}
+
+// Edge of direction d at (i, j, k) is an unknown: cell index along d in [0, n),
+// node indices across in [1, n-1].
+__device__ __forceinline__ bool is_unknown(const DGeom& g, int d, int i, int j, int k) {
+  const int o[3] = {i, j, k};
+  bool ok = true;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax == d) ok = ok && (o[ax] < g.n);
+    else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
+  }
+  return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
+                                      T ah, T h3) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
+  const int64_t sa = st[a], sb = st[b], sc = st[c];
+  const T* __restrict__ ua = u + a * g.B;
+  const T* __restrict__ ub = u + b * g.B;
+  const T* __restrict__ uc = u + c * g.B;
+  const T t6 = T(1) / T(6), t23 = T(2) / T(3);
+  auto Fb = [&](int64_t q) { return (ua[q + sc] - ua[q]) - (uc[q + sa] - uc[q]); };
+  auto Fc = [&](int64_t q) { return (ub[q + sa] - ub[q]) - (ua[q + sb] - ua[q]); };
+  auto Gb = [&](int64_t q) { return t6 * (Fb(q - sb) + Fb(q + sb)) + t23 * Fb(q); };
+  auto Gc = [&](int64_t q) { return t6 * (Fc(q - sc) + Fc(q + sc)) + t23 * Fc(q); };
+  const T curl = (Gb(p - sc) - Gb(p)) - (Gc(p - sb) - Gc(p));
+  auto row = [&](int64_t q) { return t6 * (ua[q - sc] + ua[q + sc]) + t23 * ua[q]; };
+  const T mass = t6 * (row(p - sb) + row(p + sb)) + t23 * row(p);
+  return ah * curl + h3 * mass;
+}
+
+// ---------------------------------------------------------------------------------
+// operator apply / residual
+// ---------------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y, DGeom g, T ah, T h3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > g.n) return;
+  const int64_t p = lin(g, i, j, k);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T v = T(0);
+    if (is_unknown(g, d, i, j, k)) {
+      const T ax = apply_at(x, g, d, p, ah, h3);
+      v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
+    }
+    y[d * g.B + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// grid transfers (Sec. 3.1): per direction P0 (x) P1 (x) P1
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
+                                                 DGeom f, DGeom c) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y, K = blockIdx.z;
+  if (I > c.n) return;
+  const int64_t stf[3] = {1, (int64_t)f.P, f.plane};
+  const int64_t pc = lin(c, I, J, K);
+  const int64_t pf = lin(f, 2 * I, 2 * J, 2 * K);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T v = T(0);
+    if (is_unknown(c, a, I, J, K)) {
+      const int b = (a + 1) % 3, cc = (a + 2) % 3;
+      const T* __restrict__ r = rf + a * f.B + pf;
+      T acc = T(0);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t q = e * stf[a];
+        const T mid = T(0.5) * (r[q - stf[cc]] + r[q + stf[cc]]) + r[q];
+        const T lo = T(0.5) * (r[q - stf[b] - stf[cc]] + r[q - stf[b] + stf[cc]]) + r[q - stf[b]];
+        const T hi = T(0.5) * (r[q + stf[b] - stf[cc]] + r[q + stf[b] + stf[cc]]) + r[q + stf[b]];
+        acc += T(0.5) * (lo + hi) + mid;
+      }
+      v = acc;
+    }
+    gc[a * c.B + pc] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
+                                                    DGeom f, DGeom c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > f.n) return;
+  const int o[3] = {i, j, k};
+  const int64_t stc[3] = {1, (int64_t)c.P, c.plane};
+  const int64_t pf = lin(f, i, j, k);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!is_unknown(f, a, i, j, k)) continue;
+    const int b = (a + 1) % 3, cc = (a + 2) % 3;
+    int C[3];
+    C[a] = o[a] >> 1;
+    C[b] = o[b] >> 1;
+    C[cc] = o[cc] >> 1;
+    const T* __restrict__ e = ec + a * c.B + lin(c, C[0], C[1], C[2]);
+    const bool ob = o[b] & 1, oc = o[cc] & 1;
+    T v;
+    if (!ob && !oc) v = e[0];
+    else if (ob && !oc) v = T(0.5) * (e[0] + e[stc[b]]);
+    else if (!ob && oc) v = T(0.5) * (e[0] + e[stc[cc]]);
+    else v = T(0.25) * ((e[0] + e[stc[b]]) + (e[stc[cc]] + e[stc[b] + stc[cc]]));
+    zf[a * f.B + pf] += v;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// vertex-based smoother (Sec. 3.2.2), s = 2
+// ---------------------------------------------------------------------------------
+// Interior unknowns of the subdomain with lower fine node (2a, 2b, 2c), in the order of
+// interior_dofs(2): x-edges (0,1,1), (1,1,1); y-edges (1,0,1), (1,1,1);
+// z-edges (1,1,0), (1,1,1).
+__device__ __forceinline__ void interior_offsets_s2(const DGeom& g, int64_t base, int64_t off[6],
+                                                    int dir[6]) {
+  const int64_t sx = 1, sy = g.P, sz = g.plane;
+  off[0] = 0 * g.B + base + sy + sz;           dir[0] = 0;
+  off[1] = 0 * g.B + base + sx + sy + sz;      dir[1] = 0;
+  off[2] = 1 * g.B + base + sx + sz;           dir[2] = 1;
+  off[3] = 1 * g.B + base + sx + sy + sz;      dir[3] = 1;
+  off[4] = 2 * g.B + base + sx + sy;           dir[4] = 2;
+  off[5] = 2 * g.B + base + sx + sy + sz;      dir[5] = 2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, T* __restrict__ zi,
+                                                       const T* __restrict__ ATinv, DGeom g,
+                                                       int nH) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH) return;
+  int64_t off[6];
+  int dir[6];
+  interior_offsets_s2(g, lin(g, 2 * a, 2 * b, 2 * c), off, dir);
+  T rv[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) rv[q] = r[off[q]];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) s += ATinv[q * 6 + t] * rv[t];
+    zi[off[q]] = s;
+  }
+}
+
+// gg = r - A zi on interface unknowns (zi vanishes off subdomain interiors).
+template <typename T, int S>
+__global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, const T* __restrict__ zi,
+                                                    T* __restrict__ gg, DGeom g, T ah, T h3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > g.n) return;
+  const int o[3] = {i, j, k};
+  const int64_t p = lin(g, i, j, k);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!is_unknown(g, d, i, j, k)) continue;
+    const int b = (d + 1) % 3, c = (d + 2) % 3;
+    if ((o[b] % S) != 0 && (o[c] % S) != 0) continue;   // subdomain interior
+    gg[d * g.B + p] = r[d * g.B + p] - apply_at(zi, g, d, p, ah, h3);
+  }
+}
+
+// Vertex patch solves y_V = S_type^{-1} g|Gamma_V on MFMA.  A workgroup (4 waves) takes
+// NCOL = 64 vertices of one segment (one patch type); wave w owns columns
+// [16 w, 16 w + 16) and all npad rows.  Gathered g values are staged in LDS as
+// Gs[slot][col]; S^{-1} (row-major npad x npad) is read from global memory (L2).
+template <typename T>
+struct Mfma;
+
+// Operands of the 16x16x4 MFMAs: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result register q of lane l holds D[row(l / 16, q)][l % 16], where (measured on
+// gfx950) row = 4 q + l / 16 for the f64 instruction and 4 (l / 16) + q for f32.
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * q + lk; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
+};
+
+template <typename T, int S>
+__global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* __restrict__ Y,
+                                                  const T* __restrict__ Sinv, DGeom g, DSub sub) {
+  constexpr int NG = 6 * S * (4 * S - 3);
+  constexpr int NPAD = (NG + 15) / 16 * 16;
+  constexpr int NCOL = 64;
+  __shared__ T Gs[NPAD * NCOL];
+  __shared__ int64_t cbase[NCOL];   // linear position of the vertex's fine node
+  __shared__ int cvx[NCOL], cvy[NCOL], cvz[NCOL];
+  __shared__ int64_t crow[NCOL];    // Y row, -1 for an unused column
+
+  const int tid = threadIdx.x;
+  const int chunk = blockIdx.x;
+  const int seg = sub.chunks[2 * chunk];
+  const int first = sub.chunks[2 * chunk + 1];
+  const int* sg = sub.segs + 8 * seg;
+  const int type = sg[0];
+  const int nv = sub.nH + 1;
+  if (tid < NCOL) {
+    const int v = first + tid;
+    if (v < sg[7]) {
+      const int vx = sg[1] + v % sg[4];
+      const int vy = sg[2] + (v / sg[4]) % sg[5];
+      const int vz = sg[3] + v / (sg[4] * sg[5]);
+      cvx[tid] = vx; cvy[tid] = vy; cvz[tid] = vz;
+      cbase[tid] = lin(g, S * vx, S * vy, S * vz);
+      crow[tid] = ((int64_t)vz * nv + vy) * nv + vx;
+    } else {
+      cvx[tid] = cvy[tid] = cvz[tid] = 0;
+      cbase[tid] = 0;
+      crow[tid] = -1;
+    }
+  }
+  __syncthreads();
+  // gather
+  for (int e = tid; e < NPAD * NCOL; e += 256) {
+    const int slot = e / NCOL, col = e % NCOL;
+    T v = T(0);
+    if (slot < NG && crow[col] >= 0) {
+      const int* sl = sub.slots + 4 * slot;
+      const int d = sl[0];
+      const int px = S * cvx[col] + sl[1], py = S * cvy[col] + sl[2], pz = S * cvz[col] + sl[3];
+      // an edge exists if its cell index along d is in [0, n) and node indices across
+      // are in [1, n-1]; absent slots of boundary patches read as zero
+      const int o[3] = {px, py, pz};
+      bool ok = true;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax == d) ok = ok && (o[ax] >= 0 && o[ax] < g.n);
+        else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
+      }
+      if (ok) v = gg[d * g.B + lin(g, px, py, pz)];
+    }
+    Gs[slot * NCOL + col] = v;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int col = wave * 16 + lr;
+  const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
+  const int64_t row = crow[col];
+  for (int mb = 0; mb < NPAD / 16; ++mb) {
+    typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+    const T* __restrict__ Arow = Sm + (int64_t)(16 * mb + lr) * NPAD;
+    for (int ks = 0; ks < NPAD / 4; ++ks) {
+      const T av = Arow[4 * ks + lk];
+      const T bv = Gs[(4 * ks + lk) * NCOL + col];
+      acc = Mfma<T>::mma(av, bv, acc);
+    }
+    if (row >= 0) {
+      T* __restrict__ yr = Y + row * NPAD + 16 * mb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yr[Mfma<T>::row(lk, q)] = acc[q];
+    }
+  }
+}
+
+// w = sum_V R_V^T y_V on interface unknowns; z (assign ? =, +=) eta w there.
+template <typename T, int S>
+__global__ void __launch_bounds__(64) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
+                                                T* __restrict__ z, DGeom g, DSub sub, T eta,
+                                                int assign) {
+  constexpr int NG = 6 * S * (4 * S - 3);
+  constexpr int NPAD = (NG + 15) / 16 * 16;
+  constexpr int W = 2 * S + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > g.n) return;
+  const int o[3] = {i, j, k};
+  const int64_t p = lin(g, i, j, k);
+  const int nv = sub.nH + 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!is_unknown(g, d, i, j, k)) continue;
+    const int b = (d + 1) % 3, c = (d + 2) % 3;
+    const int rb = o[b] % S, rc = o[c] % S;
+    if (rb != 0 && rc != 0) continue;
+    // candidate vertices: along d two, across as dictated by the residues
+    int vb0, vb1, vc0, vc1;
+    if (rb == 0) { vb0 = vb1 = o[b] / S; } else { vb0 = o[b] / S; vb1 = vb0 + 1; }
+    if (rc == 0) { vc0 = vc1 = o[c] / S; } else { vc0 = o[c] / S; vc1 = vc0 + 1; }
+    T acc = T(0);
+    const int vd0 = o[d] / S;
+#pragma unroll
+    for (int ed = 0; ed < 2; ++ed)
+      for (int vb = vb0; vb <= vb1; ++vb)
+        for (int vc = vc0; vc <= vc1; ++vc) {
+          int V[3];
+          V[d] = vd0 + ed;
+          V[b] = vb;
+          V[c] = vc;
+          const int dx = o[0] - S * V[0], dy = o[1] - S * V[1], dz = o[2] - S * V[2];
+          const int slot = sub.lut[((d * W + (dx + S)) * W + (dy + S)) * W + (dz + S)];
+          const int64_t row = ((int64_t)V[2] * nv + V[1]) * nv + V[0];
+          if (slot >= 0) acc += Y[row * NPAD + slot];
+        }
+    w[d * g.B + p] = acc;
+    const T old = assign ? T(0) : z[d * g.B + p];
+    z[d * g.B + p] = old + eta * acc;
+  }
+}
+
+// Harmonic extension into subdomain interiors and the final interior update:
+// z_I (assign ? =, +=) eta (zi_I - A_T^{-1} (A w)_I).
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
+                                                     T* __restrict__ z, const T* __restrict__ ATinv,
+                                                     DGeom g, int nH, T ah, T h3, T eta,
+                                                     int assign) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH) return;
+  int64_t off[6];
+  int dir[6];
+  const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
+  interior_offsets_s2(g, base, off, dir);
+  T q[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) q[t] = apply_at(w, g, dir[t], off[t] - dir[t] * g.B, ah, h3);
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    T s = T(0);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) s += ATinv[t * 6 + u] * q[u];
+    const T old = assign ? T(0) : z[off[t]];
+    z[off[t]] = old + eta * (zi[off[t]] - s);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// coarsest level: dense inverse
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __restrict__ z,
+                                                const T* __restrict__ A0inv,
+                                                const int64_t* __restrict__ map, int N0) {
+  __shared__ T gl[1024];
+  for (int i = threadIdx.x; i < N0; i += blockDim.x) gl[i] = g[map[i]];
+  __syncthreads();
+  for (int i = threadIdx.x; i < N0; i += blockDim.x) {
+    T s = T(0);
+    for (int j = 0; j < N0; ++j) s += A0inv[(int64_t)i * N0 + j] * gl[j];
+    z[map[i]] = s;
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (Tout)in[e];
+}
+
+// ---------------------------------------------------------------------------------
+// reductions (FP64)
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // wavefront reduction by shuffles, then across the 4 waves of a 256-thread block
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  }
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                             const double* __restrict__ c, double* __restrict__ part,
+                                             int64_t len) {
+  __shared__ double sh[8];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double av = a[e];
+    s1 += av * b[e];
+    if (c) s2 += av * c[e];
+  }
+  s1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s1;
+  if (c) {
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_final(const double* __restrict__ part, int nparts,
+                                               int nout, double* __restrict__ out) {
+  __shared__ double sh[8];
+  for (int o = 0; o < nout; ++o) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < nparts; e += blockDim.x) s += part[o * nparts + e];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[o] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ q,
+                                                   const double* __restrict__ scal, int i_num,
+                                                   int i_den, double* __restrict__ part,
+                                                   int64_t len) {
+  __shared__ double sh[8];
+  const double alpha = scal[i_num] / scal[i_den];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    u[e] += alpha * p[e];
+    const double rv = r[e] - alpha * q[e];
+    r[e] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const double* __restrict__ z,
+                                                      const double* __restrict__ scal, int i_num,
+                                                      int i_den, int flexible, int i_zq, int i_an,
+                                                      int i_ad, int64_t len) {
+  double beta;
+  if (flexible) beta = -(scal[i_an] / scal[i_ad]) * scal[i_zq] / scal[i_den];
+  else beta = scal[i_num] / scal[i_den];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = z[e] + beta * p[e];
+}
+
+__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = x[e];
+}
+
+__global__ void k_zero(double* __restrict__ y, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = 0.0;
+}
+
+// ---------------------------------------------------------------------------------
+// load vector from 2x2x2 Gauss samples
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_assemble_rhs(const double* __restrict__ f, double* __restrict__ bv,
+                                                     DGeom g, double w8) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > g.n) return;
+  const double x0 = 0.5 - 0.5 / 1.7320508075688772935;   // (1 - 1/sqrt 3) / 2
+  const double x1 = 0.5 + 0.5 / 1.7320508075688772935;
+  const double gx[2] = {x0, x1};
+  const int o[3] = {i, j, k};
+  const int64_t p = lin(g, i, j, k);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double v = 0.0;
+    if (is_unknown(g, d, i, j, k)) {
+      const int b = (d + 1) % 3, c = (d + 2) % 3;
+      // the four elements sharing the edge: cell o[d] along d, o[b]-1+eb, o[c]-1+ec across
+      for (int ec = 0; ec < 2; ++ec)
+        for (int eb = 0; eb < 2; ++eb) {
+          int cell[3];
+          cell[d] = o[d];
+          cell[b] = o[b] - 1 + eb;
+          cell[c] = o[c] - 1 + ec;
+          const int lb = o[b] - cell[b];   // local node offset (0 or 1) along b
+          const int lc = o[c] - cell[c];
+          const int64_t e = ((int64_t)cell[2] * g.n + cell[1]) * g.n + cell[0];
+          const double* fe = f + e * 24;
+          for (int q = 0; q < 8; ++q) {
+            const int qa[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+            const double tb = gx[qa[b]], tc = gx[qa[c]];
+            const double pb = lb ? tb : 1.0 - tb;
+            const double pc = lc ? tc : 1.0 - tc;
+            v += fe[q * 3 + d] * pb * pc;
+          }
+        }
+      v *= w8;
+    }
+    bv[d * g.B + p] = v;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_curlcurl_form(const double* __restrict__ lam,
+                                                      const double* __restrict__ u,
+                                                      double* __restrict__ part, DGeom g, double h) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  double s = 0.0;
+  if (i <= g.n) {
+    const int64_t p = lin(g, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (is_unknown(g, d, i, j, k)) s += lam[d * g.B + p] * apply_at(u, g, d, p, h, 0.0);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0)
+    part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+}
+
+inline dim3 node_grid(const Geom& g) {
+  return dim3((unsigned)((g.n + 1 + 63) / 64), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
+                        hipStream_t st) {
+  const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_apply<T, 0>), node_grid(g), dim3(64), 0, st, x, b, y, dgeom(g), ah, h3);
+  else
+    hipLaunchKernelGGL((k_apply<T, 1>), node_grid(g), dim3(64), 0, st, x, b, y, dgeom(g), ah, h3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, hipStream_t st) {
+  hipLaunchKernelGGL((k_restrict<T>), node_grid(c), dim3(64), 0, st, rf, gc, dgeom(f), dgeom(c));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong_add<T>), node_grid(f), dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
+                         const Geom& g, double alpha, double eta, int assign, hipStream_t st) {
+  if (sub.s != 2) return hipErrorInvalidValue;
+  const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
+  const DGeom dg = dgeom(g);
+  const dim3 eg((unsigned)((sub.nH + 63) / 64), (unsigned)sub.nH, (unsigned)sub.nH);
+  hipLaunchKernelGGL((k_sm_interior_s2<T>), eg, dim3(64), 0, st, r, L.zi, L.ATinv, dg, sub.nH);
+  hipLaunchKernelGGL((k_sm_condense<T, 2>), node_grid(g), dim3(64), 0, st, r, L.zi, L.gg, dg, ah, h3);
+  if (sub.nchunks > 0)
+    hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks), dim3(256), 0, st, L.gg, L.Y,
+                       L.Sinv, dg, sub);
+  hipLaunchKernelGGL((k_sm_pull<T, 2>), node_grid(g), dim3(64), 0, st, L.Y, L.w, z, dg, sub, (T)eta,
+                     assign);
+  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.ATinv, dg, sub.nH, ah,
+                     h3, (T)eta, assign);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,
+                         hipStream_t st) {
+  if (N0 > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, st, g, z, A0inv, map, N0);
+  return hipGetLastError();
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(2048), dim3(256), 0, st, in, out, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const double* a, const double* b, const double* c, double* partial,
+                      double* out, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(256), 0, st, a, b, c, partial, len);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, kRedBlocks, c ? 2 : 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q,
+                            const double* scal, int i_num, int i_den, double* partial,
+                            double* out, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(256), 0, st, u, r, p, q, scal, i_num, i_den,
+                     partial, len);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, kRedBlocks, 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(double* p, const double* z, const double* scal, int i_num,
+                               int i_den, int flexible, int i_zq, int i_an, int i_ad,
+                               int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(2048), dim3(256), 0, st, p, z, scal, i_num, i_den, flexible,
+                     i_zq, i_an, i_ad, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* x, double* y, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, st, x, y, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* y, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, y, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st) {
+  const double w8 = g.h * g.h * g.h / 8.0;
+  hipLaunchKernelGGL(k_assemble_rhs, node_grid(g), dim3(64), 0, st, f, b, dgeom(g), w8);
+  return hipGetLastError();
+}
+
+hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,
+                                double* partial, double* out, hipStream_t st) {
+  const dim3 grid = node_grid(g);
+  const int nparts = (int)(grid.x * grid.y * grid.z);
+  hipLaunchKernelGGL(k_curlcurl_form, grid, dim3(64), 0, st, lam, u, partial, dgeom(g), g.h);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, nparts, 1, out);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t launch_apply<double>(const double*, const double*, double*, const Geom&, double,
+                                         int, hipStream_t);
+template hipError_t launch_apply<float>(const float*, const float*, float*, const Geom&, double, int,
+                                        hipStream_t);
+template hipError_t launch_restrict<double>(const double*, double*, const Geom&, const Geom&,
+                                            hipStream_t);
+template hipError_t launch_restrict<float>(const float*, float*, const Geom&, const Geom&, hipStream_t);
+template hipError_t launch_prolong_add<double>(const double*, double*, const Geom&, const Geom&,
+                                               hipStream_t);
+template hipError_t launch_prolong_add<float>(const float*, float*, const Geom&, const Geom&,
+                                              hipStream_t);
+template hipError_t launch_smooth<double>(const double*, double*, const LevelPtrs<double>&,
+                                          const DSub&, const Geom&, double, double, int, hipStream_t);
+template hipError_t launch_smooth<float>(const float*, float*, const LevelPtrs<float>&, const DSub&,
+                                         const Geom&, double, double, int, hipStream_t);
+template hipError_t launch_coarse<double>(const double*, double*, const double*, const int64_t*, int,
+                                          hipStream_t);
+template hipError_t launch_coarse<float>(const float*, float*, const float*, const int64_t*, int,
+                                         hipStream_t);
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+
+}  // namespace ndmg

@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol, and
+plans / validates problems without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2205_05840_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ndmg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ndmg_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    L = lib.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(lib.EXPORTED) == names
+
+
+def test_default_opts(lib):
+    o = lib.ndmg_default_opts()
+    assert o.m == 1 and abs(o.eta - 1 / 9) < 1e-15 and o.subdomain == 2
+    assert o.boundary_patches == 1 and o.precision == 0
+
+
+@pytest.mark.parametrize("n,nl", [(2, 1), (3, 1), (4, 2), (6, 2), (8, 3), (12, 3), (64, 6),
+                                  (96, 6), (128, 7)])
+def test_plan_sizes(lib, n, nl):
+    o = lib.ndmg_default_opts()
+    ws, vl = lib.ndmg_plan(n, 1.0, 1.0, o)
+    P = ((n + 1) + 7) // 8 * 8
+    assert vl == 3 * (n + 1) ** 2 * P
+    assert ws % 256 == 0 and ws > 4 * vl * 8
+
+
+@pytest.mark.parametrize("args,code", [
+    ((1, 1.0, 1.0), 1), ((8, 1.0, 0.0), 1), ((8, 1.0, -1.0), 1), ((8, 0.0, 1.0), 1),
+    ((8, 1.0, float("nan")), 1), ((22, 1.0, 1.0), 1),   # coarsest 11^3 is too large
+])
+def test_plan_rejects(lib, args, code):
+    o = lib.ndmg_default_opts()
+    with pytest.raises(lib.NdmgError) as e:
+        lib.ndmg_plan(*args, o)
+    assert e.value.code == code
+    assert lib.lib().ndmg_last_error().decode()
+
+
+def test_plan_rejects_bad_options(lib):
+    for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5)):
+        o = lib.ndmg_default_opts()
+        setattr(o, field, val)
+        with pytest.raises(lib.NdmgError):
+            lib.ndmg_plan(8, 1.0, 1.0, o)
+
+
+def test_null_arguments(lib):
+    L = lib.lib()
+    assert L.ndmg_apply(None, None, None) == lib.NDMG_EINVAL
+    assert L.ndmg_layout(None, 0, None) == lib.NDMG_EINVAL
+    ctx = ctypes.c_void_p()
+    o = lib.ndmg_default_opts()
+    assert L.ndmg_setup(ctypes.byref(ctx), 8, 1.0, 1.0, ctypes.byref(o), None, 0, None) == \
+        lib.NDMG_EINVAL
+    assert L.ndmg_destroy(None) == 0
+
+
+def test_product_path_does_not_import_oracle():
+    """The package never imports the oracle (parity would be void otherwise)."""
+    pkg = os.path.join(ROOT, "paper_2205_05840_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f

@@ -136,3 +136,17 @@ def test_patch_matrices_translation_invariant():
     for mats in by_type.values():
         for M in mats[1:]:
             assert abs(M - mats[0]).max() <= 1e-14 * abs(mats[0]).max()
+
+
+@pytest.mark.parametrize("n,s", [(8, 2), (12, 2), (8, 4)])
+def test_vectorized_sets_equal_per_item_sets(n, s):
+    I = mesh.interior_sets(n, s)
+    I2 = np.stack([mesh.interior_set(n, s, t) for t in mesh.coarse_elements(n, s)])
+    assert np.array_equal(I, I2)
+    groups = {}
+    for v in mesh.coarse_vertices(n, s):
+        groups.setdefault(mesh.vertex_type(n, s, v), []).append(v)
+    for verts in groups.values():
+        G = mesh.vertex_interface_sets(n, s, verts)
+        G2 = np.stack([mesh.vertex_interface_set(n, s, v) for v in verts])
+        assert np.array_equal(G, G2)
