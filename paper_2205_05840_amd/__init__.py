@@ -6,11 +6,14 @@ solver does, and fails loudly if it has not been built.
 """
 from . import synth  # noqa: F401
 
-__all__ = ["Solver", "synth"]
+__all__ = ["Solver", "solve", "synth"]
 
 
 def __getattr__(name):
     if name == "Solver":
         from .solver import Solver
         return Solver
+    if name == "solve":
+        from .autograd import solve
+        return solve
     raise AttributeError(name)

@@ -48,6 +48,8 @@ struct LevelHost {
   // offsets into the workspace
   size_t o_z = 0, o_r = 0, o_zi = 0, o_gg = 0, o_w = 0, o_g = 0, o_Y = 0;
   size_t o_ATinv = 0, o_Sinv = 0, o_lut = 0, o_slots = 0, o_segs = 0, o_chunks = 0;
+  size_t o_XT = 0, o_bofs = 0;
+  int nB = 0;
   size_t o_A0 = 0, o_map = 0;
   size_t nY = 0;
 };
@@ -125,7 +127,7 @@ int make_plan(int n, double length, double alpha, const ndmg_opts* o_in, Plan* p
       L.segs = ndmg::vertex_segments(L.sub.nH, o.boundary_patches != 0);
       L.chunks.clear();
       for (size_t si = 0; si < L.segs.size(); ++si)
-        for (int f = 0; f < L.segs[si].count; f += 64) {
+        for (int f = 0; f < L.segs[si].count; f += 64 * ndmg::patch_groups(L.sub.nH)) {
           L.chunks.push_back((int)si);
           L.chunks.push_back(f);
         }
@@ -137,6 +139,9 @@ int make_plan(int n, double length, double alpha, const ndmg_opts* o_in, Plan* p
       L.nY = nv * nv * nv * (size_t)L.sub.npad;
       L.o_Y = take(L.nY * pl->elem);
       L.o_ATinv = take((size_t)L.sub.nI * L.sub.nI * pl->elem);
+      L.nB = (int)ndmg::boundary_dofs(L.sub.s).size();
+      L.o_XT = take((size_t)L.sub.nI * L.nB * pl->elem);
+      L.o_bofs = take((size_t)L.nB * sizeof(int64_t));
       L.o_Sinv = take((size_t)27 * L.sub.npad * L.sub.npad * pl->elem);
       L.o_lut = take((size_t)3 * L.sub.lut_w * L.sub.lut_w * L.sub.lut_w * sizeof(int));
       L.o_slots = take((size_t)L.sub.nG * 4 * sizeof(int));
@@ -152,7 +157,8 @@ int make_plan(int n, double length, double alpha, const ndmg_opts* o_in, Plan* p
   pl->o_pp = take(v8);
   pl->o_pq = take(v8);
   const size_t cc_parts = (size_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
-  pl->npart = std::max<size_t>(2 * ndmg::kRedBlocks, cc_parts);
+  pl->npart = std::max<size_t>(std::max<size_t>(2 * ndmg::kRedBlocks, cc_parts),
+                               (size_t)ndmg::stencil_blocks(gf));
   pl->o_part = take(pl->npart * sizeof(double));
   pl->o_scal = take(S_N * sizeof(double));
   pl->bytes = off;
@@ -175,6 +181,8 @@ ndmg::LevelPtrs<T> level_ptrs(ndmg_ctx* c, const LevelHost& L) {
   p.Y = at<T>(c, L.o_Y);
   p.ATinv = at<T>(c, L.o_ATinv);
   p.Sinv = at<T>(c, L.o_Sinv);
+  p.XT = at<T>(c, L.o_XT);
+  p.bofs = at<int64_t>(c, L.o_bofs);
   return p;
 }
 
@@ -191,6 +199,7 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.segs = at<int>(c, L.o_segs);
   d.chunks = at<int>(c, L.o_chunks);
   d.nchunks = (int)(L.chunks.size() / 2);
+  d.gpw = ndmg::patch_groups(L.sub.nH);
   return d;
 }
 
@@ -219,7 +228,16 @@ int upload_factors(ndmg_ctx* c) {
     }
     auto at_ = cast_vec<T>(L.fac.ATinv);
     auto si = cast_vec<T>(L.fac.Sinv);
+    auto xt = cast_vec<T>(L.fac.XT);
     if ((rc = put(L.o_ATinv, at_.data(), at_.size() * sizeof(T)))) return rc;
+    if ((rc = put(L.o_XT, xt.data(), xt.size() * sizeof(T)))) return rc;
+    {
+      auto bd = ndmg::boundary_dofs(L.sub.s);
+      std::vector<int64_t> bo;
+      for (auto& q : bd)
+        bo.push_back(q.d * L.g.B + (int64_t)q.dz * L.g.plane + (int64_t)q.dy * L.g.P + q.dx);
+      if ((rc = put(L.o_bofs, bo.data(), bo.size() * sizeof(int64_t)))) return rc;
+    }
     if ((rc = put(L.o_Sinv, si.data(), si.size() * sizeof(T)))) return rc;
     auto lut = ndmg::slot_lookup(L.sub.s);
     if ((rc = put(L.o_lut, lut.data(), lut.size() * sizeof(int)))) return rc;
@@ -431,8 +449,15 @@ int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int max
   NDMG_HIP(ndmg::launch_copy(z, p, len, c->st));
   double rel = 1.0;
   for (int it = 1; it <= maxit; ++it) {
-    NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, pl.alpha, 0, c->st));
-    NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, sc + S_PQ, len, c->st));
+    if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
+      // q = A p with p^T q accumulated by the same kernel
+      int np = 0;
+      NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, pl.alpha, 2, part, &np, c->st));
+      NDMG_HIP(ndmg::launch_final(part, np, 1, sc + S_PQ, c->st));
+    } else {
+      NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, pl.alpha, 0, c->st));
+      NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, sc + S_PQ, len, c->st));
+    }
     NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, cur, S_PQ, part, sc + S_RR, len, c->st));
     NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, S_N * sizeof(double), hipMemcpyDeviceToHost, c->st));
     NDMG_HIP(hipStreamSynchronize(c->st));

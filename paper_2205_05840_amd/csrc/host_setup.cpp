@@ -88,6 +88,23 @@ std::vector<Slot> interior_dofs(int s) {
   return out;
 }
 
+std::vector<Slot> boundary_dofs(int s) {
+  std::vector<Slot> out;
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z <= s; ++z)
+      for (int y = 0; y <= s; ++y)
+        for (int x = 0; x <= s; ++x) {
+          int o[3] = {x, y, z};
+          bool edge = true, interior = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) edge &= (o[ax] >= 0 && o[ax] < s);
+            else interior &= (o[ax] >= 1 && o[ax] <= s - 1);
+          }
+          if (edge && !interior) out.push_back({d, x, y, z});
+        }
+  return out;
+}
+
 std::vector<Segment> vertex_segments(int nH, bool boundary_patches) {
   std::vector<Segment> out;
   for (int tz = 0; tz < 3; ++tz)
@@ -282,6 +299,19 @@ bool build_level_factors(double h, double alpha, const SubInfo& sub, bool bounda
       *err = "subdomain matrix A_T is not positive definite";
       return false;
     }
+    // X_T = A_T^{-1} A_{I, dT}: maps the boundary values of T to (minus) the
+    // discrete-harmonic extension into its interior
+    auto bd = boundary_dofs(s);
+    std::vector<int> Bd;
+    for (auto& q : bd) Bd.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+    std::vector<double> AIB = submatrix(sys, I, Bd);
+    const int nI = (int)I.size(), nB = (int)Bd.size();
+    out->XT.assign((size_t)nI * nB, 0.0);
+    for (int i = 0; i < nI; ++i)
+      for (int k = 0; k < nI; ++k) {
+        const double a = out->ATinv[(size_t)i * nI + k];
+        for (int j = 0; j < nB; ++j) out->XT[(size_t)i * nB + j] += a * AIB[(size_t)k * nB + j];
+      }
   }
   // ---- vertex patches, one per type ---------------------------------------------------
   const int np = sub.npad;

@@ -285,6 +285,7 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   const int col = wave * 16 + lr;
   const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
   const int64_t row = crow[col];
+  const int64_t NV = (int64_t)nv * nv * nv;
   for (int mb = 0; mb < NPAD / 16; ++mb) {
     typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
     const T* __restrict__ Arow = Sm + (int64_t)(16 * mb + lr) * NPAD;
@@ -293,28 +294,135 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
       const T bv = Gs[(4 * ks + lk) * NCOL + col];
       acc = Mfma<T>::mma(av, bv, acc);
     }
+    // Y is slot-major: Y[slot * NV + vertex]
     if (row >= 0) {
-      T* __restrict__ yr = Y + row * NPAD + 16 * mb;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yr[Mfma<T>::row(lk, q)] = acc[q];
+      for (int q = 0; q < 4; ++q) Y[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV + row] = acc[q];
     }
+  }
+}
+
+// Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
+// segment (one patch type).  S_type^{-1} is staged in LDS; wave w then walks its gpw
+// groups of 16 vertices: lane l gathers the B-operand column values g[slot = 4 ks + l / 16]
+// of vertex l % 16 straight from memory (prefetching the next group), reads the A-operand
+// fragment S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and accumulates the 16 x 16
+// output tile per mb; results go to the slot-major Y.
+template <typename T, int S>
+__global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, T* __restrict__ Y,
+                                                      const T* __restrict__ Sinv, DGeom g, DSub sub,
+                                                      int gpw) {
+  constexpr int NG = 6 * S * (4 * S - 3);
+  constexpr int NPAD = (NG + 15) / 16 * 16;
+  constexpr int NKS = NPAD / 4, NMB = NPAD / 16;
+  __shared__ T sA[NPAD * NPAD];
+  __shared__ int sslot[NPAD][4];
+  __shared__ int64_t soff[NPAD];
+  const int tid = threadIdx.x;
+  const int chunk = blockIdx.x;
+  const int seg = sub.chunks[2 * chunk];
+  const int first = sub.chunks[2 * chunk + 1];
+  const int* sg = sub.segs + 8 * seg;
+  const int type = sg[0], count = sg[7];
+  const bool inner = (type == 13);
+  const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
+  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[e] = Sm[e];
+  for (int e = tid; e < NPAD; e += blockDim.x) {
+    if (e < NG) {
+      const int* sl = sub.slots + 4 * e;
+      sslot[e][0] = sl[0]; sslot[e][1] = sl[1]; sslot[e][2] = sl[2]; sslot[e][3] = sl[3];
+      soff[e] = sl[0] * g.B + (int64_t)sl[3] * g.plane + (int64_t)sl[2] * g.P + sl[1];
+    } else {
+      sslot[e][0] = -1; sslot[e][1] = sslot[e][2] = sslot[e][3] = 0;
+      soff[e] = 0;
+    }
+  }
+  __syncthreads();
+  const int nv = sub.nH + 1;
+  const int64_t NV = (int64_t)nv * nv * nv;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int wfirst = first + wave * gpw * 16;
+
+  auto gather = [&](int c, T (&bcol)[NKS], int64_t& vrow, bool& vok) {
+    const int v = wfirst + 16 * c + lr;
+    vok = v < count;
+    int vx = 0, vy = 0, vz = 0;
+    if (vok) {
+      vx = sg[1] + v % sg[4];
+      vy = sg[2] + (v / sg[4]) % sg[5];
+      vz = sg[3] + v / (sg[4] * sg[5]);
+    }
+    vrow = ((int64_t)vz * nv + vy) * nv + vx;
+    const int64_t base = lin(g, S * vx, S * vy, S * vz);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int slot = 4 * ks + lk;
+      T val = T(0);
+      if (vok && slot < NG) {
+        bool ok = true;
+        if (!inner) {
+          // absent slots of boundary patches (outside the domain or on its boundary)
+          const int d = sslot[slot][0];
+          const int o[3] = {S * vx + sslot[slot][1], S * vy + sslot[slot][2], S * vz + sslot[slot][3]};
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) ok = ok && (o[ax] >= 0 && o[ax] < g.n);
+            else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
+          }
+        }
+        if (ok) val = gg[base + soff[slot]];
+      }
+      bcol[ks] = val;
+    }
+  };
+
+  int ngroups = 0;
+  for (int c = 0; c < gpw; ++c)
+    if (wfirst + 16 * c < count) ngroups = c + 1;
+  if (ngroups == 0) return;   // no barrier below
+  T bcur[NKS], bnext[NKS];
+  int64_t vrow, vrow_n = 0;
+  bool vok, vok_n = false;
+  gather(0, bcur, vrow, vok);
+  for (int c = 0; c < ngroups; ++c) {
+    if (c + 1 < ngroups) gather(c + 1, bnext, vrow_n, vok_n);
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+      // keep the A fragments in LDS (read per use) instead of registers: occupancy
+      __asm__ volatile("" ::: "memory");
+      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+        acc = Mfma<T>::mma(sA[(16 * mb + lr) * NPAD + 4 * ks + lk], bcur[ks], acc);
+      if (vok) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV + vrow] = acc[q];
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bnext[ks];
+    vrow = vrow_n;
+    vok = vok_n;
   }
 }
 
 // w = sum_V R_V^T y_V on interface unknowns; z (assign ? =, +=) eta w there.
 template <typename T, int S>
-__global__ void __launch_bounds__(64) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
-                                                T* __restrict__ z, DGeom g, DSub sub, T eta,
-                                                int assign) {
-  constexpr int NG = 6 * S * (4 * S - 3);
-  constexpr int NPAD = (NG + 15) / 16 * 16;
+__global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
+                                                 T* __restrict__ z, DGeom g, DSub sub, T eta,
+                                                 int assign) {
   constexpr int W = 2 * S + 1;
+  __shared__ int slut[3 * W * W * W];
+  for (int e = threadIdx.x; e < 3 * W * W * W; e += blockDim.x) slut[e] = sub.lut[e];
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
-  if (i > g.n) return;
+  if (i >= g.n) return;   // i = n is never an unknown
   const int o[3] = {i, j, k};
   const int64_t p = lin(g, i, j, k);
   const int nv = sub.nH + 1;
+  const int64_t NV = (int64_t)nv * nv * nv;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (!is_unknown(g, d, i, j, k)) continue;
@@ -336,9 +444,9 @@ __global__ void __launch_bounds__(64) k_sm_pull(const T* __restrict__ Y, T* __re
           V[b] = vb;
           V[c] = vc;
           const int dx = o[0] - S * V[0], dy = o[1] - S * V[1], dz = o[2] - S * V[2];
-          const int slot = sub.lut[((d * W + (dx + S)) * W + (dy + S)) * W + (dz + S)];
+          const int slot = slut[((d * W + (dx + S)) * W + (dy + S)) * W + (dz + S)];
           const int64_t row = ((int64_t)V[2] * nv + V[1]) * nv + V[0];
-          if (slot >= 0) acc += Y[row * NPAD + slot];
+          if (slot >= 0) acc += Y[(int64_t)slot * NV + row];
         }
     w[d * g.B + p] = acc;
     const T old = assign ? T(0) : z[d * g.B + p];
@@ -347,29 +455,39 @@ __global__ void __launch_bounds__(64) k_sm_pull(const T* __restrict__ Y, T* __re
 }
 
 // Harmonic extension into subdomain interiors and the final interior update:
-// z_I (assign ? =, +=) eta (zi_I - A_T^{-1} (A w)_I).
+// z_I (assign ? =, +=) eta (zi_I - X_T w_dT), X_T = A_T^{-1} A_{I, dT} (6 x 48 for s = 2),
+// w_dT the interface correction on the 48 edges of the subdomain's boundary (zero where
+// they lie on the boundary of the domain).
 template <typename T>
 __global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
-                                                     T* __restrict__ z, const T* __restrict__ ATinv,
-                                                     DGeom g, int nH, T ah, T h3, T eta,
-                                                     int assign) {
+                                                     T* __restrict__ z, const T* __restrict__ XT,
+                                                     const int64_t* __restrict__ bofs, DGeom g,
+                                                     int nH, T eta, int assign) {
+  __shared__ T sX[6 * 48];
+  __shared__ int64_t sofs[48];
+  for (int e = threadIdx.x; e < 6 * 48; e += blockDim.x) sX[e] = XT[e];
+  for (int e = threadIdx.x; e < 48; e += blockDim.x) sofs[e] = bofs[e];
+  __syncthreads();
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, c = blockIdx.z;
   if (a >= nH) return;
-  int64_t off[6];
-  int dir[6];
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
-  interior_offsets_s2(g, base, off, dir);
-  T q[6];
+  T wv[48];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) q[t] = apply_at(w, g, dir[t], off[t] - dir[t] * g.B, ah, h3);
-#pragma unroll
+  for (int e = 0; e < 48; ++e) wv[e] = w[base + sofs[e]];
+  // interior unknown t: direction d = t / 2 at offset 1 across d and (t & 1) along d
+  // (the order of interior_offsets_s2)
+  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
+  const int64_t all1 = st[0] + st[1] + st[2];
+#pragma unroll 1
   for (int t = 0; t < 6; ++t) {
-    T s = T(0);
+    const int d = t >> 1;
+    const int64_t off = d * g.B + base + all1 - (1 - (t & 1)) * (d == 0 ? st[0] : (d == 1 ? st[1] : st[2]));
+    T q = T(0);
 #pragma unroll
-    for (int u = 0; u < 6; ++u) s += ATinv[t * 6 + u] * q[u];
-    const T old = assign ? T(0) : z[off[t]];
-    z[off[t]] = old + eta * (zi[off[t]] - s);
+    for (int e = 0; e < 48; ++e) q += sX[t * 48 + e] * wv[e];
+    const T old = assign ? T(0) : z[off];
+    z[off] = old + eta * (zi[off] - q);
   }
 }
 
@@ -562,6 +680,8 @@ inline dim3 node_grid(const Geom& g) {
 template <typename T>
 hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
                         hipStream_t st) {
+  if (g.n > stencil_min_n() && g.n <= stencil_max_n())
+    return launch_stencil<T>(x, b, y, g, alpha, mode, nullptr, nullptr, st);
   const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
   if (mode == 0)
     hipLaunchKernelGGL((k_apply<T, 0>), node_grid(g), dim3(64), 0, st, x, b, y, dgeom(g), ah, h3);
@@ -586,18 +706,23 @@ template <typename T>
 hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
                          const Geom& g, double alpha, double eta, int assign, hipStream_t st) {
   if (sub.s != 2) return hipErrorInvalidValue;
-  const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
   const DGeom dg = dgeom(g);
   const dim3 eg((unsigned)((sub.nH + 63) / 64), (unsigned)sub.nH, (unsigned)sub.nH);
   hipLaunchKernelGGL((k_sm_interior_s2<T>), eg, dim3(64), 0, st, r, L.zi, L.ATinv, dg, sub.nH);
-  hipLaunchKernelGGL((k_sm_condense<T, 2>), node_grid(g), dim3(64), 0, st, r, L.zi, L.gg, dg, ah, h3);
+  // condensed interface residual gg = r - A zi (zi vanishes off subdomain interiors;
+  // the interior entries of gg come out as rounding-level values and are never read)
+  hipError_t e = launch_apply<T>(L.zi, r, L.gg, g, alpha, 1, st);
+  if (e != hipSuccess) return e;
   if (sub.nchunks > 0)
-    hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks), dim3(256), 0, st, L.gg, L.Y,
-                       L.Sinv, dg, sub);
-  hipLaunchKernelGGL((k_sm_pull<T, 2>), node_grid(g), dim3(64), 0, st, L.Y, L.w, z, dg, sub, (T)eta,
-                     assign);
-  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.ATinv, dg, sub.nH, ah,
-                     h3, (T)eta, assign);
+    hipLaunchKernelGGL((k_sm_patch_reg<T, 2>), dim3((unsigned)sub.nchunks), dim3(256), 0, st, L.gg, L.Y,
+                       L.Sinv, dg, sub, sub.gpw);
+  {
+    const int bx = (g.n <= 64) ? 64 : 128;
+    const dim3 pg((unsigned)((g.n + bx - 1) / bx), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
+    hipLaunchKernelGGL((k_sm_pull<T, 2>), pg, dim3(bx), 0, st, L.Y, L.w, z, dg, sub, (T)eta, assign);
+  }
+  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.XT, L.bofs, dg, sub.nH,
+                     (T)eta, assign);
   return hipGetLastError();
 }
 
@@ -619,6 +744,11 @@ hipError_t launch_dot(const double* a, const double* b, const double* c, double*
                       double* out, int64_t len, hipStream_t st) {
   hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(256), 0, st, a, b, c, partial, len);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, kRedBlocks, c ? 2 : 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(const double* part, int nparts, int nout, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, part, nparts, nout, out);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct DSub {
   const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, d2, count
   const int* chunks;    // [nchunks][2]: segment, first vertex
   int nchunks;
+  int gpw;              // 16-vertex groups per wave in the patch kernel
 };
 
 template <typename T>
@@ -36,10 +37,25 @@ struct LevelPtrs {
   T* zi;      // interior solves (only interior-of-subdomain entries ever written)
   T* gg;      // condensed interface residual
   T* w;       // interface correction (only interface entries ever written)
-  T* Y;       // vertex patch results [(nH+1)^3][npad]
+  T* Y;       // vertex patch results, slot-major [npad][(nH+1)^3]
   const T* ATinv;   // nI x nI
   const T* Sinv;    // 27 x npad x npad
+  const T* XT;      // nI x nB
+  const int64_t* bofs;   // nB offsets of the subdomain boundary edges from its lower node
 };
+
+// Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
+// part[block] = partial sums of x . y (then k_final over stencil_blocks(g) partials).
+template <typename T>
+hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
+                          double* part, int* nparts, hipStream_t st);
+int stencil_max_n();
+int stencil_min_n();   // the plane-marching kernel serves stencil_min_n() < n <= stencil_max_n()
+// groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
+// S^{-1} stagings), one on small levels (more workgroups)
+inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
+int stencil_blocks(const Geom& g);
+hipError_t launch_final(const double* part, int nparts, int nout, double* out, hipStream_t st);
 
 // y = A x (mode 0) or y = b - A x (mode 1); all entries of y written.
 template <typename T>

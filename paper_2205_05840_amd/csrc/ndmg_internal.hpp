@@ -50,6 +50,10 @@ std::vector<int> slot_lookup(int s);
 // (x fastest); offsets from the subdomain's lower fine node.
 std::vector<Slot> interior_dofs(int s);
 
+// Edges on the boundary of a subdomain (cell offset in [0, s) along the direction,
+// node offsets in [0, s] across, not interior), same ordering: 3 (s+1)^2 s - nI of them.
+std::vector<Slot> boundary_dofs(int s);
+
 // Segment of vertices sharing a patch type: a box of the vertex grid (0..nH)^3.
 struct Segment {
   int type;        // tx + 3 ty + 9 tz, t = 0 low face, 1 inside, 2 high face
@@ -63,6 +67,7 @@ std::vector<Segment> vertex_segments(int nH, bool boundary_patches);
 // Host FP64 factors of one smoothed level.
 struct LevelFactors {
   std::vector<double> ATinv;   // nI x nI
+  std::vector<double> XT;      // nI x nB: A_T^{-1} A_{I, boundary of T}
   std::vector<double> Sinv;    // 27 x npad x npad (zero for absent types/slots)
   std::vector<double> S27;     // same layout, the Schur complements themselves
 };

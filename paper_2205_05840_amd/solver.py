@@ -52,6 +52,21 @@ class Solver:
     def layout(self, level=-1):
         return _lib.ndmg_layout(self.ctx, level)
 
+    def unknown_mask(self):
+        """1.0 at the entries of the padded layout that are unknowns (interior edges), else 0."""
+        if getattr(self, "_mask", None) is None:
+            n = self.n
+            r = torch.arange(n + 1, device=self.device)
+            k, j, i = torch.meshgrid(r, r, r, indexing="ij")
+            node = (r >= 1) & (r <= n - 1)
+            cell = r < n
+            m = torch.zeros(3, n + 1, n + 1, self.P, dtype=torch.float64, device=self.device)
+            m[0, :, :, :n + 1] = (cell[i] & node[j] & node[k]).double()
+            m[1, :, :, :n + 1] = (node[i] & cell[j] & node[k]).double()
+            m[2, :, :, :n + 1] = (node[i] & node[j] & cell[k]).double()
+            self._mask = m.reshape(-1)
+        return self._mask
+
     # ---- operations -----------------------------------------------------------------
     def apply(self, x, y=None):
         y = self.zeros() if y is None else y
