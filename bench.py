@@ -84,7 +84,9 @@ def time_apply(torch, S, reps=40, nbuf=8):
     ys = [S.zeros() for _ in range(nbuf)]
     for i in range(nbuf):
         S.apply(xs[i], ys[i])
-    st = torch.cuda.current_stream()
+    # events on the library's own stream (the one the kernel runs on)
+    torch.cuda.synchronize()
+    st = S.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for i in range(reps):
@@ -118,12 +120,32 @@ def cpu_baseline(f, iters_expected, sample_iters=3):
             "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
+def kernel_probe(torch, Solver, precision, reps):
+    """For hardware-counter runs: a device copy of 256 MiB (calibration of the byte
+    counters against a kernel of known traffic), then `reps` operator applies at 128^3."""
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    S = Solver(N_ELEM, 1.0, precision=precision)
+    t = time_apply(torch, S, reps=reps)
+    # a few fine-level smoother applications (interior, condensation, patch, pull, extend)
+    r = torch.randn(S.vec_len, dtype=torch.float64, device=S.device) * S.unknown_mask()
+    for _ in range(4):
+        S.level_op(-1, "smooth", r)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "apply+smooth", "n": N_ELEM, "reps": reps, "avg_launch_us": t * 1e6,
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only run the calibration copy and the apply kernel (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -137,6 +159,9 @@ def main():
     from paper_2205_05840_amd import _lib
     _lib.lib()   # fail loudly if the HIP library is missing
 
+    if args.kernel_probe:
+        kernel_probe(torch, Solver, "fp64", 10)
+        return
     f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
     ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
     legs = {}

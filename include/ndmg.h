@@ -58,6 +58,8 @@ typedef struct ndmg_opts {
                            cut to the domain (default; reproduces Table 2);
                            0: interior coarse vertices only                          */
   int flexible;         /* 1: Polak-Ribiere beta in PCG (default for FP32)          */
+  int use_graphs;       /* 1 (default): replay each CG iteration from a captured HIP
+                           graph when the stream is not the null stream; 0: eager   */
 } ndmg_opts;
 
 /* Fill *o with the defaults above. */
@@ -111,7 +113,10 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
  * from u = 0, until ||b - A u||_2 <= rtol ||b||_2 (recursive residual) or maxit
  * iterations.  iters and relres (host pointers, may be NULL) receive the iteration
  * count and the final relative residual.  The stream is synchronised once per
- * iteration for the convergence test.
+ * iteration for the convergence test.  With use_graphs, the iterations after the first
+ * are replayed from two HIP graphs captured on first use (and again whenever d_u
+ * changes); the stream must then not be the null stream and must not be captured by
+ * the caller.
  * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (u still written), NDMG_EBREAKDOWN. */
 int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
                    int* iters, double* relres);

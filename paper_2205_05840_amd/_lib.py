@@ -35,6 +35,7 @@ class ndmg_opts(ctypes.Structure):
         ("subdomain", ctypes.c_int),
         ("boundary_patches", ctypes.c_int),
         ("flexible", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
     ]
 
 

@@ -72,6 +72,8 @@ struct ndmg_ctx {
   char* ws = nullptr;
   hipStream_t st = nullptr;
   double* host_scal = nullptr;   // pinned
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};   // CG iteration body, by scalar-slot parity
+  double* graph_u = nullptr;                       // solution pointer the graphs were captured with
 };
 
 namespace {
@@ -322,6 +324,85 @@ int precondition(ndmg_ctx* c, const double* g, double* z) {
   return NDMG_OK;
 }
 
+// q = A p with p^T q (slot S_PQ), then u += alpha p, r -= alpha q (alpha = s[num] / s[PQ])
+// and r . r (slot S_RR).
+int cg_apply_update(ndmg_ctx* c, double* u, int num) {
+  Plan& pl = c->plan;
+  const ndmg::Geom& g = pl.lv.back().g;
+  const int64_t len = g.len;
+  double* r = at<double>(c, pl.o_pr);
+  double* p = at<double>(c, pl.o_pp);
+  double* q = at<double>(c, pl.o_pq);
+  double* part = at<double>(c, pl.o_part);
+  double* sc = at<double>(c, pl.o_scal);
+  if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
+    int np = 0;
+    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, pl.alpha, 2, part, &np, c->st));
+    NDMG_HIP(ndmg::launch_final(part, np, 1, sc + S_PQ, c->st));
+  } else {
+    NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, pl.alpha, 0, c->st));
+    NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, sc + S_PQ, len, c->st));
+  }
+  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, S_PQ, part, sc + S_RR, len, c->st));
+  return NDMG_OK;
+}
+
+// One CG iteration after the first: z = B r; s[nxt] = r . z (and s[nxt+1] = z . q for the
+// flexible beta); p = z + beta p; then cg_apply_update with alpha = s[nxt] / p^T A p.
+int cg_body_eager(ndmg_ctx* c, double* u, int cur, int nxt) {
+  Plan& pl = c->plan;
+  const int64_t len = pl.lv.back().g.len;
+  double* r = at<double>(c, pl.o_pr);
+  double* z = at<double>(c, pl.o_pz);
+  double* p = at<double>(c, pl.o_pp);
+  double* q = at<double>(c, pl.o_pq);
+  double* part = at<double>(c, pl.o_part);
+  double* sc = at<double>(c, pl.o_scal);
+  const bool flexible =
+      pl.opts.flexible > 0 || (pl.opts.flexible < 0 && pl.opts.precision == NDMG_PREC_FP32);
+  int rc = precondition(c, r, z);
+  if (rc) return rc;
+  NDMG_HIP(ndmg::launch_dot(z, r, flexible ? q : nullptr, part, sc + nxt, len, c->st));
+  NDMG_HIP(ndmg::launch_cg_direction(p, z, sc, nxt, cur, flexible ? 1 : 0, nxt + 1, cur, S_PQ, len,
+                                     c->st));
+  return cg_apply_update(c, u, nxt);
+}
+
+void drop_graphs(ndmg_ctx* c) {
+  for (int i = 0; i < 2; ++i)
+    if (c->gexec[i]) {
+      (void)hipGraphExecDestroy(c->gexec[i]);
+      c->gexec[i] = nullptr;
+    }
+  c->graph_u = nullptr;
+}
+
+int cg_body(ndmg_ctx* c, double* u, int cur, int nxt) {
+  if (!c->plan.opts.use_graphs || c->st == nullptr) return cg_body_eager(c, u, cur, nxt);
+  if (c->graph_u != u) drop_graphs(c);
+  const int par = (cur == S_RZA) ? 0 : 1;
+  if (!c->gexec[par]) {
+    hipGraph_t graph = nullptr;
+    NDMG_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    int rc = cg_body_eager(c, u, cur, nxt);
+    hipError_t e = hipStreamEndCapture(c->st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(NDMG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[par], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c->gexec[par] = nullptr;
+      return fail(NDMG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    c->graph_u = u;
+  }
+  NDMG_HIP(hipGraphLaunch(c->gexec[par], c->st));
+  return NDMG_OK;
+}
+
 int check_ctx(const ndmg_ctx* c) {
   if (!c) return fail(NDMG_EINVAL, "null context");
   return NDMG_OK;
@@ -340,6 +421,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->subdomain = 2;
   o->boundary_patches = 1;
   o->flexible = -1;
+  o->use_graphs = 1;
 }
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }
@@ -426,11 +508,8 @@ int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int max
   double* r = at<double>(c, pl.o_pr);
   double* z = at<double>(c, pl.o_pz);
   double* p = at<double>(c, pl.o_pp);
-  double* q = at<double>(c, pl.o_pq);
   double* part = at<double>(c, pl.o_part);
   double* sc = at<double>(c, pl.o_scal);
-  const bool flexible =
-      pl.opts.flexible > 0 || (pl.opts.flexible < 0 && pl.opts.precision == NDMG_PREC_FP32);
   if (iters) *iters = 0;
   if (relres) *relres = 0.0;
   NDMG_HIP(ndmg::launch_copy(b, r, len, c->st));
@@ -447,18 +526,14 @@ int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int max
   int cur = S_RZA, nxt = S_RZB;
   NDMG_HIP(ndmg::launch_dot(r, z, nullptr, part, sc + cur, len, c->st));
   NDMG_HIP(ndmg::launch_copy(z, p, len, c->st));
-  double rel = 1.0;
+  if ((rc = cg_apply_update(c, u, cur))) return rc;
   for (int it = 1; it <= maxit; ++it) {
-    if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
-      // q = A p with p^T q accumulated by the same kernel
-      int np = 0;
-      NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, pl.alpha, 2, part, &np, c->st));
-      NDMG_HIP(ndmg::launch_final(part, np, 1, sc + S_PQ, c->st));
-    } else {
-      NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, pl.alpha, 0, c->st));
-      NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, sc + S_PQ, len, c->st));
+    if (it > 1) {
+      // z = B r, rz_new, p = z + beta p, q = A p, u += alpha p, r -= alpha q, r . r:
+      // replayed from a captured graph when the stream allows it
+      if ((rc = cg_body(c, u, cur, nxt))) return rc;
+      std::swap(cur, nxt);
     }
-    NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, cur, S_PQ, part, sc + S_RR, len, c->st));
     NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, S_N * sizeof(double), hipMemcpyDeviceToHost, c->st));
     NDMG_HIP(hipStreamSynchronize(c->st));
     const double pq = c->host_scal[S_PQ], rr = c->host_scal[S_RR], rz = c->host_scal[cur];
@@ -467,18 +542,10 @@ int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int max
       if (relres) *relres = std::sqrt(rr) / bnorm;
       return fail(NDMG_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite scalar)");
     }
-    rel = std::sqrt(rr) / bnorm;
+    const double rel = std::sqrt(rr) / bnorm;
     if (iters) *iters = it;
     if (relres) *relres = rel;
     if (rel <= rtol) return NDMG_OK;
-    if (it == maxit) break;
-    rc = precondition(c, r, z);
-    if (rc) return rc;
-    // rz_next = r . z (and z . q for the flexible beta)
-    NDMG_HIP(ndmg::launch_dot(z, r, flexible ? q : nullptr, part, sc + nxt, len, c->st));
-    NDMG_HIP(ndmg::launch_cg_direction(p, z, sc, nxt, cur, flexible ? 1 : 0, nxt + 1, cur, S_PQ, len,
-                                       c->st));
-    std::swap(cur, nxt);
   }
   return fail(NDMG_ENOCONV, "PCG reached maxit");
 }
@@ -572,6 +639,7 @@ int ndmg_level_op(ndmg_ctx* c, int level, int op, const double* in, double* out)
 
 int ndmg_destroy(ndmg_ctx* c) {
   if (!c) return NDMG_OK;
+  drop_graphs(c);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   delete c;
   return NDMG_OK;

@@ -315,7 +315,8 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
   constexpr int NG = 6 * S * (4 * S - 3);
   constexpr int NPAD = (NG + 15) / 16 * 16;
   constexpr int NKS = NPAD / 4, NMB = NPAD / 16;
-  __shared__ T sA[NPAD * NPAD];
+  constexpr int LDA = NPAD + 1;   // odd row stride: the 16 rows a wave reads hit distinct banks
+  __shared__ T sA[NPAD * LDA];
   __shared__ int sslot[NPAD][4];
   __shared__ int64_t soff[NPAD];
   const int tid = threadIdx.x;
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
   const int type = sg[0], count = sg[7];
   const bool inner = (type == 13);
   const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
-  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[e] = Sm[e];
+  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[(e / NPAD) * LDA + e % NPAD] = Sm[e];
   for (int e = tid; e < NPAD; e += blockDim.x) {
     if (e < NG) {
       const int* sl = sub.slots + 4 * e;
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
       typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks)
-        acc = Mfma<T>::mma(sA[(16 * mb + lr) * NPAD + 4 * ks + lk], bcur[ks], acc);
+        acc = Mfma<T>::mma(sA[(16 * mb + lr) * LDA + 4 * ks + lk], bcur[ks], acc);
       if (vok) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV + vrow] = acc[q];

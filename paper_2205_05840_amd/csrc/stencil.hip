@@ -129,14 +129,47 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   load_row<T, R>(X, g, i0, j, kstart, xp[2]);
   load_row<T, R>(Yc, g, i0, j, kstart, yp[2]);
   load_row<T, R>(Zc, g, i0, j, kstart, zp[1]);
+  // software pipeline: plane s + 2 (and b of plane s) is requested during step s
+  T xn[R], yn[R], zn[R], bn[3][R];
+  load_row<T, R>(X, g, i0, j, kstart + 1, xn);
+  load_row<T, R>(Yc, g, i0, j, kstart + 1, yn);
+  load_row<T, R>(Zc, g, i0, j, kstart + 1, zn);
+#pragma unroll
+  for (int r = 0; r < R; ++r) bn[0][r] = bn[1][r] = bn[2][r] = T(0);
   double dot = 0.0;
   const int kend = min(k0 + KZ, g.n + 1);   // output planes [k0, kend)
 
   for (int s = kstart; s <= kend; ++s) {
-    load_row<T, R>(X, g, i0, j, s + 1, xp[3]);
-    load_row<T, R>(Yc, g, i0, j, s + 1, yp[3]);
     T znew[R];
-    load_row<T, R>(Zc, g, i0, j, s + 1, znew);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xp[3][r] = xn[r];
+      yp[3][r] = yn[r];
+      znew[r] = zn[r];
+    }
+    T bcur[3][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bcur[0][r] = bn[0][r];
+      bcur[1][r] = bn[1][r];
+      bcur[2][r] = bn[2][r];
+    }
+    if (s + 1 <= kend) {
+      load_row<T, R>(X, g, i0, j, s + 2, xn);
+      load_row<T, R>(Yc, g, i0, j, s + 2, yn);
+      load_row<T, R>(Zc, g, i0, j, s + 2, zn);
+    }
+    if (MODE == 1 && out_row && s >= k0 && s < kend) {
+      // b of output plane s, used in step s + 1 (rows and planes up to n are in the array)
+      const T* pb = bv + (int64_t)s * g.plane + (int64_t)j * g.P + i0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool ok = i0 + r <= g.n;
+        bn[0][r] = ok ? pb[r] : T(0);
+        bn[1][r] = ok ? pb[g.B + r] : T(0);
+        bn[2][r] = ok ? pb[2 * g.B + r] : T(0);
+      }
+    }
     // ---- phase A: x(s), z(s) across rows
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -214,9 +247,9 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
         const bool uz = iin && jin && (ko < g.n);
         if (i <= g.n) {
           if (MODE == 1) {
-            ox = ux ? bv[rowoff + r] - ox : T(0);
-            oy = uy ? bv[g.B + rowoff + r] - oy : T(0);
-            oz = uz ? bv[2 * g.B + rowoff + r] - oz : T(0);
+            ox = ux ? bcur[0][r] - ox : T(0);
+            oy = uy ? bcur[1][r] - oy : T(0);
+            oz = uz ? bcur[2][r] - oz : T(0);
           } else {
             ox = ux ? ox : T(0);
             oy = uy ? oy : T(0);

@@ -16,7 +16,7 @@ class Solver:
     n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace."""
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
-                 boundary_patches=True, flexible=None, device="cuda:0"):
+                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0"):
         self.n, self.alpha, self.length = int(n), float(alpha), float(length)
         self.device = torch.device(device)
         o = _lib.ndmg_default_opts()
@@ -26,15 +26,21 @@ class Solver:
         o.precision = PRECISIONS[precision]
         o.boundary_patches = 1 if boundary_patches else 0
         o.flexible = -1 if flexible is None else int(bool(flexible))
+        o.use_graphs = 1 if use_graphs else 0
         self.opts = o
         self.precision = precision
         self.ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
+        # the library works on a stream of its own (default priority; graph capture needs a
+        # non-null stream); calls are ordered after the caller's current stream and the
+        # caller's stream waits for them
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self.ctx = _lib.ndmg_setup(self.n, self.length, self.alpha, o, self._ws_ptr,
                                    self.ws_bytes, self.stream.cuda_stream)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
         info = _lib.ndmg_layout(self.ctx, -1)
         self.P, self.B, self.levels, self.ndof = info[1], info[2], info[4], info[5]
 
@@ -68,20 +74,28 @@ class Solver:
         return self._mask
 
     # ---- operations -----------------------------------------------------------------
+    def _run(self, fn, *args):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        try:
+            return fn(self.ctx, *args)
+        finally:
+            cur.wait_stream(self.stream)
+
     def apply(self, x, y=None):
         y = self.zeros() if y is None else y
-        _lib.ndmg_apply(self.ctx, self._check(x), self._check(y))
+        self._run(_lib.ndmg_apply, self._check(x), self._check(y))
         return y
 
     def vcycle(self, g, z=None):
         z = self.zeros() if z is None else z
-        _lib.ndmg_vcycle(self.ctx, self._check(g), self._check(z))
+        self._run(_lib.ndmg_vcycle, self._check(g), self._check(z))
         return z
 
     def solve(self, b, rtol=1e-10, maxit=500, u=None, raise_on_noconv=True):
         u = self.zeros() if u is None else u
-        code, it, rel = _lib.ndmg_pcg_solve(self.ctx, self._check(b), self._check(u), rtol, maxit,
-                                            raise_on_noconv)
+        code, it, rel = self._run(_lib.ndmg_pcg_solve, self._check(b), self._check(u), rtol, maxit,
+                                  raise_on_noconv)
         return u, it, rel
 
     def assemble_rhs(self, f):
@@ -90,14 +104,14 @@ class Solver:
         if f.numel() != self.n ** 3 * 24:
             raise ValueError("f must hold n^3 x 8 x 3 values")
         b = self.zeros()
-        _lib.ndmg_assemble_rhs(self.ctx, f.data_ptr(), self._check(b))
+        self._run(_lib.ndmg_assemble_rhs, f.data_ptr(), self._check(b))
         return b
 
     def curlcurl_form(self, lam, u):
         """sum_r lam_r^T K u_r for stacked vectors [nrhs, vec_len]."""
-        lam = lam.reshape(-1, self.vec_len)
-        u = u.reshape(-1, self.vec_len)
-        return _lib.ndmg_curlcurl_form(self.ctx, self._check(lam), self._check(u), lam.shape[0])
+        lam = lam.reshape(-1, self.vec_len).contiguous()
+        u = u.reshape(-1, self.vec_len).contiguous()
+        return self._run(_lib.ndmg_curlcurl_form, self._check(lam), self._check(u), lam.shape[0])
 
     def level_op(self, level, op, x, out=None):
         """One step on one level (FP64 solvers): op in 'apply', 'smooth', 'restrict',
@@ -115,7 +129,7 @@ class Solver:
             out = torch.zeros(ln_out, dtype=torch.float64, device=self.device)
         if out.numel() != ln_out:
             raise ValueError("output has the wrong length")
-        _lib.ndmg_level_op(self.ctx, lvl, ops[op], x.data_ptr(), out.data_ptr())
+        self._run(_lib.ndmg_level_op, lvl, ops[op], x.data_ptr(), out.data_ptr())
         return out
 
     def export_factor(self, level, which, typ=13):
@@ -124,7 +138,7 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
-            torch.cuda.synchronize(self.device)
+            self.stream.synchronize()
             _lib.ndmg_destroy(self.ctx)
             self.ctx = None
 

@@ -232,3 +232,27 @@ def test_mixed_precision_pcg():
     err32 = _rel(from_padded(n, S32.P, S32.B, z), ref)
     print(f"FP32 V-cycle vs FP64 oracle: {err32:.2e} (tolerance {tol:.2e})")
     assert err32 <= tol
+
+
+def test_graph_replays_match_eager():
+    """The CG iterations replayed from captured graphs give bitwise the same iterates as
+    the eager launches; several solves in a row (replays with eager work and host
+    synchronisation in between), then a solve into a different output (re-capture)."""
+    from paper_2205_05840_amd import synth
+    n = 16
+    Sg = _solver(n, 1.0, use_graphs=True)
+    Se = _solver(n, 1.0, use_graphs=False)
+    b = Sg.assemble_rhs(torch.from_numpy(synth.normal_samples(n, 5)))
+    ue, ite, rele = Se.solve(b)
+    ue = _host(ue)
+    u = Sg.zeros()
+    for rep in range(3):
+        u.fill_(7.0)                     # eager work between replays
+        _, it, rel = Sg.solve(b, u=u)
+        assert it == ite and rel == rele
+        assert np.array_equal(_host(u), ue), rep
+    u2, it, rel = Sg.solve(b)
+    assert np.array_equal(_host(u2), ue)
+    S32 = _solver(n, 1.0, precision="fp32")
+    S32e = _solver(n, 1.0, precision="fp32", use_graphs=False)
+    assert np.array_equal(_host(S32.solve(b)[0]), _host(S32e.solve(b)[0]))
