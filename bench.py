@@ -7,8 +7,16 @@ the setup done before the timed region.  The headline leg runs the V-cycle in FP
 inside FP64 flexible CG; the FP64 leg (V-cycle in FP64) is reported next to it, and
 both are repeated at alpha = 1e-3.
 
+Two more forms are measured next to the plain FP64 path and reported under "forms":
+batched (512 problems with n drawn from {8, 12, 16, 24, 32} and alpha log-uniform in
+[1e-2, 1e2], 4 right-hand sides each, FP32 V-cycle in FP64 CG, one batched solve per
+step; against single FP64 solves of a sample of the same problems) and differentiated
+(96^3, 16 right-hand sides, loss sum_k ||u_k - t_k||^2 with t_k the alpha = 2
+solutions, forward and adjoint solves plus dL/dalpha per step; against the same
+gradient through single-right-hand-side solves).
+
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K, --warmup W,
---no-cpu-baseline.
+--no-cpu-baseline, --no-forms.
 """
 import argparse
 import hashlib
@@ -23,6 +31,14 @@ sys.path.insert(0, ROOT)
 N_ELEM = 128
 SEED = 2
 RTOL = 1e-10
+BATCH_NPROB, BATCH_NRHS, BATCH_SEED = 512, 4, 3
+BATCH_SAMPLE = 16          # problems of the sequential FP64 comparison
+DIFF_N, DIFF_NRHS, DIFF_SEED = 96, 16, 4
+
+
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -77,23 +93,146 @@ def run_leg(torch, Solver, f, alpha, precision, steps, warmup):
 def time_apply(torch, S, reps=40, nbuf=8):
     """Average duration of the operator-apply kernel (one launch per ndmg_apply), timed
     with HIP events on the library's stream, rotating over nbuf input/output pairs so that
-    the 256 MB last-level cache cannot hold them."""
+    the 256 MB last-level cache cannot hold them.  The loop calls the C ABI directly (a
+    few microseconds per call) so that the launches queue up ahead of the GPU and the
+    events measure the kernels, not the host."""
+    from paper_2205_05840_amd import _lib
     xs = [torch.randn(S.vec_len, dtype=torch.float64, device=S.device) for _ in range(nbuf)]
-    mask = S.apply(torch.ones(S.vec_len, dtype=torch.float64, device=S.device)) != 0
-    xs = [x * mask for x in xs]
+    mask = S.unknown_mask()
+    xs = [(x * mask).contiguous() for x in xs]
     ys = [S.zeros() for _ in range(nbuf)]
     for i in range(nbuf):
         S.apply(xs[i], ys[i])
-    # events on the library's own stream (the one the kernel runs on)
+    ptrs = [(xs[i].data_ptr(), ys[i].data_ptr()) for i in range(nbuf)]
+    L = _lib.lib()
     torch.cuda.synchronize()
     st = S.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # a first batch of launches keeps the GPU busy while the timed ones are queued
+    for i in range(nbuf):
+        _lib.check(L.ndmg_apply(S.ctx, *ptrs[i]))
     e0.record(st)
     for i in range(reps):
-        S.apply(xs[i % nbuf], ys[i % nbuf])
+        _lib.check(L.ndmg_apply(S.ctx, *ptrs[i % nbuf]))
     e1.record(st)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def batched_leg(torch, steps, warmup):
+    """512 uneven problems x 4 right-hand sides in one batched solve per step (FP32
+    V-cycle in FP64 CG); the same batch with the FP64 V-cycle; and single FP64 solves of
+    the first BATCH_SAMPLE problems one after another."""
+    from paper_2205_05840_amd import BatchedSolver, Solver, synth
+    ns, alphas = synth.batched_problems(BATCH_NPROB, seed=BATCH_SEED)
+    dof = [3 * int(n) * (int(n) - 1) ** 2 for n in ns]
+    out = {"nprob": BATCH_NPROB, "nrhs": BATCH_NRHS, "sizes": sorted(set(int(n) for n in ns)),
+           "dof_rhs_total": sum(dof) * BATCH_NRHS}
+    B = None
+    for prec in ("fp32", "fp64"):
+        t0 = time.perf_counter()
+        BS = BatchedSolver(ns, alphas, nrhs=BATCH_NRHS, precision=prec)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        if B is None:
+            g = torch.Generator(device=BS.device)
+            g.manual_seed(BATCH_SEED)
+            f = torch.randn(BS.sample_len(), generator=g, dtype=torch.float64, device=BS.device)
+            B = BS.assemble_rhs(f)
+            del f
+        U = BS.zeros()
+        for _ in range(warmup):
+            BS.solve(B, rtol=RTOL, U=U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, it, rel = BS.solve(B, rtol=RTOL, U=U)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        npairs = BATCH_NPROB * BATCH_NRHS
+        log(f"batched {prec}: setup {setup:.1f} s, {t * 1e3:.1f} ms per batch of {npairs} solves")
+        out[prec] = {"s_per_batch": t, "solves_per_s": npairs / t,
+                     "dof_rhs_per_s": out["dof_rhs_total"] / t, "setup_s": setup,
+                     "iters_max": int(it.max()), "iters_mean": float(it.mean()),
+                     "relres_max": float(rel.max())}
+        if prec == "fp32":
+            U32 = U.clone()
+        else:
+            out["fp32"]["rel_diff_vs_fp64_max"] = max(
+                float(torch.linalg.norm(BS.view(U32, p) - BS.view(U, p)) /
+                      torch.linalg.norm(BS.view(U, p))) for p in range(BATCH_NPROB))
+            # single FP64 solves of a sample, one after another (setup untimed)
+            sample = []
+            for p in range(BATCH_SAMPLE):
+                S = Solver(int(ns[p]), float(alphas[p]))
+                Bp = BS.view(B, p).clone()
+                Up = S.zeros()
+                S.solve(Bp[0].contiguous(), rtol=RTOL, u=Up)     # warm-up (graph capture)
+                sample.append((S, Bp, Up))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for S, Bp, Up in sample:
+                for r in range(BATCH_NRHS):
+                    S.solve(Bp[r].contiguous(), rtol=RTOL, u=Up)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            nsol = BATCH_SAMPLE * BATCH_NRHS
+            sdof = sum(dof[:BATCH_SAMPLE]) * BATCH_NRHS
+            out["sequential_fp64_sample"] = {"problems": BATCH_SAMPLE, "solves": nsol,
+                                             "solves_per_s": nsol / t, "dof_rhs_per_s": sdof / t}
+            del sample
+        del BS, U
+        torch.cuda.empty_cache()
+    out["speedup_batched_fp32_vs_sequential_fp64_dof_rate"] = (
+        out["fp32"]["dof_rhs_per_s"] / out["sequential_fp64_sample"]["dof_rhs_per_s"])
+    return out
+
+
+def diff_leg(torch, steps, warmup):
+    """dL/dB and dL/dalpha for L = sum_k ||u_k - t_k||^2 at 96^3 with 16 right-hand sides:
+    all right-hand sides in one batched solve (forward and adjoint), against the same
+    gradient through one solve per right-hand side.  FP64 V-cycle."""
+    from paper_2205_05840_amd import Solver, solve
+    n, k = DIFF_N, DIFF_NRHS
+    Sk = Solver(n, 1.0, nrhs=k)
+    S2 = Solver(n, 2.0, nrhs=k)
+    S1 = Solver(n, 1.0)
+    g = torch.Generator(device=Sk.device)
+    g.manual_seed(DIFF_SEED)
+    f = torch.randn(k * n ** 3 * 24, generator=g, dtype=torch.float64, device=Sk.device)
+    B = Sk.assemble_rhs(f)
+    del f
+    T, _, _ = S2.solve(B, rtol=1e-12)
+    del S2
+    res = {"n": n, "nrhs": k, "ndof": 3 * n * (n - 1) ** 2}
+
+    def grad(S):
+        Bg = B.clone().requires_grad_(True)
+        a = torch.tensor(1.0, dtype=torch.float64, device=B.device, requires_grad=True)
+        L = ((solve(Bg, a, S, rtol=RTOL) - T) ** 2).sum()
+        L.backward()
+        return float(L.detach()), Bg.grad, float(a.grad)
+
+    for name, S in (("batched_rhs", Sk), ("single_rhs", S1)):
+        for _ in range(warmup):
+            grad(S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            L, gB, ga = grad(S)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"s_per_gradient": t, "loss": L, "dL_dalpha": ga}
+        log(f"differentiation {name}: {t:.3f} s per gradient")
+        if name == "batched_rhs":
+            gB0 = gB
+        else:
+            res["batched_vs_single_grad_rel_diff"] = {
+                "dL_dB": float(torch.linalg.norm(gB - gB0) / torch.linalg.norm(gB)),
+                "dL_dalpha": abs(res["batched_rhs"]["dL_dalpha"] - ga) / abs(ga)}
+    res["speedup_batched_vs_single_rhs"] = (res["single_rhs"]["s_per_gradient"] /
+                                            res["batched_rhs"]["s_per_gradient"])
+    return res
 
 
 def cpu_baseline(f, iters_expected, sample_iters=3):
@@ -144,6 +283,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and differentiated forms")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only run the calibration copy and the apply kernel (counter runs)")
     args = ap.parse_args()
@@ -171,6 +312,8 @@ def main():
             S, b, u, res = run_leg(torch, Solver, f, alpha, prec, args.steps, args.warmup)
             res["dof_per_s"] = ndof / res["s_per_solve_total"]
             legs[f"{prec}@alpha={alpha:g}"] = res
+            log(f"128^3 {prec} alpha={alpha:g}: {res['s_per_solve_total'] * 1e3:.1f} ms/solve, "
+                f"{res['iters']} iterations")
             sols[(alpha, prec)] = u.clone()
             if alpha == 1.0 and prec == "fp64":
                 t_apply = time_apply(torch, S)
@@ -207,6 +350,9 @@ def main():
         "speedup_mixed_vs_fp64": fp64["s_per_solve_total"] / head["s_per_solve_total"],
         "legs": legs, "roofline": roofline,
     }
+    if not args.no_forms:
+        out["forms"] = {"batched": batched_leg(torch, max(1, args.steps // 2), 1),
+                        "differentiation": diff_leg(torch, 1, 1)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"])
     print(json.dumps(out), flush=True)

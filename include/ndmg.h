@@ -6,12 +6,15 @@
  *        (arXiv 2205.05840), used as a preconditioner inside conjugate gradients.
  *
  * C ABI.  Every pointer argument named d_* is a device (HIP, gfx950) pointer owned by
- * the caller; every other pointer is a host pointer owned by the caller.  Nothing
- * here allocates device memory except ndmg_setup's per-context host metadata: the
- * caller passes a device workspace of the size ndmg_plan reports.  All device work
- * is enqueued on the stream given to ndmg_setup.  A context must not be used from two
- * threads at once.  Functions return NDMG_OK or one of the error codes below and
- * never abort or throw; ndmg_last_error() then describes the failure (per thread).
+ * the caller; every other pointer is a host pointer owned by the caller.  The library
+ * allocates no device memory: the caller passes a device workspace of the size
+ * ndmg_plan (or ndmg_plan_batched) reports.  A context owns host metadata, a few pinned
+ * host words for the convergence test and, when it holds several problem sizes, one
+ * side stream and event per extra size.  All device work is enqueued on the stream
+ * given at setup (work of extra sizes forks from it and joins back before a call
+ * returns its last enqueued operation).  A context must not be used from two threads
+ * at once.  Functions return NDMG_OK or one of the error codes below and never abort
+ * or throw; ndmg_last_error() then describes the failure (per thread).
  *
  * Vector layout ("padded edge layout").  The mesh has n^3 cubes of side h = length/n.
  * An edge of direction d (0 = x, 1 = y, 2 = z) is addressed by (i, j, k): along axis
@@ -24,6 +27,13 @@
  * entry (boundary edges, the unused i = n of x-edges etc., the row padding) must be 0
  * on input and is written as 0 (or left untouched, where stated) on output.
  * Floating-point vectors at the boundary are always double (FP64).
+ *
+ * Batches.  A batched context (ndmg_setup_batched) holds nprob independent problems,
+ * each with its own n and alpha, with nrhs right-hand sides each.  A "batch vector"
+ * concatenates one padded vector per (problem, right-hand side) pair; ndmg_batch_layout
+ * gives the offset of each problem's first vector (its nrhs vectors follow each other).
+ * ndmg_apply and ndmg_vcycle act on batch vectors; a single-problem context is the
+ * batch of one pair, whose batch vector is the plain padded vector.
  */
 #ifndef NDMG_H
 #define NDMG_H
@@ -92,11 +102,46 @@ int ndmg_setup(ndmg_ctx** out, int n, double length, double alpha, const ndmg_op
                void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* ndmg_layout: describe the padded edge layout of a level (level 0 = coarsest,
- * level -1 = finest).  info[0] = n, info[1] = P (row pitch), info[2] = B (block
- * length), info[3] = vector length 3 B, info[4] = number of levels,
- * info[5] = number of unknowns 3 n (n-1)^2.  Errors: NDMG_EINVAL.
+ * level -1 = finest) of a context with a single problem size.  info[0] = n,
+ * info[1] = P (row pitch), info[2] = B (block length), info[3] = vector length 3 B,
+ * info[4] = number of levels, info[5] = number of unknowns 3 n (n-1)^2.
+ * Errors: NDMG_EINVAL.
  */
 int ndmg_layout(const ndmg_ctx* ctx, int level, int64_t info[6]);
+
+/* ---- batches (Sec. 2 problem statement per problem; Sec. 3.3 V-cycle; CG per pair) ---
+ * ndmg_plan_batched: validate nprob problems on cubes of side `length` with n[p]
+ * elements per axis (host array) and nrhs right-hand sides each, and report the
+ * workspace size in bytes and the batch vector length in elements.  Problems with the
+ * same n form one size class; every kernel launch covers all pairs of a class.
+ * Limits: nprob * nrhs <= 65535.  Either output pointer may be NULL.
+ * Errors: NDMG_EINVAL. */
+int ndmg_plan_batched(int nprob, const int* n, double length, int nrhs, const ndmg_opts* opts,
+                      size_t* workspace_bytes, size_t* total_len);
+
+/* ndmg_setup_batched: as ndmg_setup for every problem p with alpha[p] (host array, all
+ * > 0); the local factors of each (problem, level) are built in FP64 on host threads.
+ * Errors: NDMG_EINVAL, NDMG_EWORKSPACE, NDMG_EHIP. */
+int ndmg_setup_batched(ndmg_ctx** out, int nprob, const int* n, double length,
+                       const double* alpha, int nrhs, const ndmg_opts* opts, void* d_workspace,
+                       size_t workspace_bytes, void* stream);
+
+/* ndmg_batch_layout: info[0] = offset (elements) of problem `prob`'s first vector in a
+ * batch vector, info[1] = its padded vector length 3 B, info[2] = n, info[3] = P,
+ * info[4] = B, info[5] = number of levels.  Errors: NDMG_EINVAL. */
+int ndmg_batch_layout(const ndmg_ctx* ctx, int prob, int64_t info[6]);
+
+/* Solve A_p u = b for every (problem p, right-hand side) pair of the context as in
+ * ndmg_pcg_solve, each pair with its own CG scalars and stopping test: a pair that has
+ * converged (or broken down) is left out of every later kernel.  d_b and d_u are batch
+ * vectors.  iters and relres (host, may be NULL) receive nprob * nrhs entries, entry
+ * p * nrhs + r for right-hand side r of problem p.  The stream is synchronised once per
+ * iteration of the slowest pair; with use_graphs one iteration of the whole batch (all
+ * sizes) is replayed from one captured graph.
+ * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (some pair reached maxit; every output
+ * still written), NDMG_EBREAKDOWN (some pair broke down). */
+int ndmg_pcg_solve_batched(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
+                           int* iters, double* relres);
 
 /* ---- operations (all FP64 vectors in the padded layout of the finest level) -------- */
 
@@ -112,8 +157,10 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
 /* Solve A u = b (eq. fem) by conjugate gradients preconditioned with the V-cycle,
  * from u = 0, until ||b - A u||_2 <= rtol ||b||_2 (recursive residual) or maxit
  * iterations.  iters and relres (host pointers, may be NULL) receive the iteration
- * count and the final relative residual.  The stream is synchronised once per
- * iteration for the convergence test.  With use_graphs, the iterations after the first
+ * count and the final relative residual ||r|| / ||b|| (computed on the device, the
+ * value the stopping test used).  The context must hold one pair (one problem, one
+ * right-hand side).  The stream is synchronised once per iteration for the convergence
+ * test.  With use_graphs, the iterations after the first
  * are replayed from two HIP graphs captured on first use (and again whenever d_u
  * changes); the stream must then not be the null stream and must not be captured by
  * the caller.
@@ -125,17 +172,20 @@ int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, i
  * 2x2x2 Gauss-Legendre points of every element: d_f is [n^3][8][3] doubles, element
  * (c0, c1, c2) at row (c2 n + c1) n + c0, point q = q0 + 2 q1 + 4 q2 at local
  * coordinates (x_{q0}, x_{q1}, x_{q2}), x = (1 -+ 1/sqrt 3) / 2, components x, y, z.
- * d_b receives the padded layout.  Errors: NDMG_EINVAL, NDMG_EHIP. */
+ * d_b receives the padded layout.  For a batched context d_f holds one such array per
+ * pair, in the pair order of the batch vectors, and d_b is a batch vector.
+ * Errors: NDMG_EINVAL, NDMG_EHIP. */
 int ndmg_assemble_rhs(ndmg_ctx* ctx, const double* d_f, double* d_b);
 
 /* out = sum_r lam_r^T K u_r for nrhs vector pairs stored back to back (each of the
- * padded vector length), K = dA/dalpha the curl-curl matrix of eq. (def bilinear
- * form).  out is a host pointer.  Used for dL/dalpha = -sum_r lam_r^T K u_r.
+ * padded vector length of the context's single problem size), K = dA/dalpha the
+ * curl-curl matrix of eq. (def bilinear form).  out is a host pointer.  Used for dL/dalpha = -sum_r lam_r^T K u_r.
  * Errors: NDMG_EINVAL, NDMG_EHIP. */
 int ndmg_curlcurl_form(ndmg_ctx* ctx, const double* d_lam, const double* d_u, int nrhs,
                        double* out);
 
-/* Debug export of the FP64 local factors of a level (level as in ndmg_layout, >= 1):
+/* Debug export of the FP64 local factors of a level (level as in ndmg_layout, >= 1) of
+ * the first problem of a context with a single problem size (rebuilt on the host):
  * which = 0: A_T^{-1} (nI x nI, row-major), which = 1: the padded inverse Schur
  * complement of the vertex type `type` (0..26, per axis 0 low face, 1 inside, 2 high
  * face; 13 = interior), npad x npad row-major with zero rows/columns for slots that do
@@ -145,8 +195,8 @@ int ndmg_export_factor(const ndmg_ctx* ctx, int level, int which, int type, doub
                        int* dims);
 
 /* ---- single steps of one level (FP64 contexts; for tests and diagnostics) ----------
- * Vectors use the padded layout of the level(s) named (ndmg_layout).  level as in
- * ndmg_layout.
+ * Vectors use the padded layout of the level(s) named (ndmg_layout), one per pair of
+ * the context (a single problem size) back to back.  level as in ndmg_layout.
  *   NDMG_OP_APPLY     out = A_k in                                  (any level)
  *   NDMG_OP_SMOOTH    out = M_k^{-1} in, the vertex-based smoother of
  *                     eq. (Preconditioner P) including its damping eta   (level >= 1)

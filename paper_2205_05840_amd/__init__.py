@@ -6,13 +6,16 @@ solver does, and fails loudly if it has not been built.
 """
 from . import synth  # noqa: F401
 
-__all__ = ["Solver", "solve", "synth"]
+__all__ = ["Solver", "BatchedSolver", "solve", "synth"]
 
 
 def __getattr__(name):
     if name == "Solver":
         from .solver import Solver
         return Solver
+    if name == "BatchedSolver":
+        from .solver import BatchedSolver
+        return BatchedSolver
     if name == "solve":
         from .autograd import solve
         return solve

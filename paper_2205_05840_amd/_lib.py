@@ -21,6 +21,7 @@ EXPORTED = [
     "ndmg_default_opts", "ndmg_plan", "ndmg_setup", "ndmg_layout", "ndmg_apply",
     "ndmg_vcycle", "ndmg_pcg_solve", "ndmg_assemble_rhs", "ndmg_curlcurl_form",
     "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
+    "ndmg_plan_batched", "ndmg_setup_batched", "ndmg_batch_layout", "ndmg_pcg_solve_batched",
 ]
 
 NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE = range(5)
@@ -71,6 +72,10 @@ def lib():
     L.ndmg_curlcurl_form.argtypes = [vp, vp, vp, i, P(d)]
     L.ndmg_export_factor.argtypes = [vp, i, i, i, P(d), P(i)]
     L.ndmg_level_op.argtypes = [vp, i, i, vp, vp]
+    L.ndmg_plan_batched.argtypes = [i, P(i), d, i, P(ndmg_opts), P(sz), P(sz)]
+    L.ndmg_setup_batched.argtypes = [P(vp), i, P(i), d, P(d), i, P(ndmg_opts), vp, sz, vp]
+    L.ndmg_batch_layout.argtypes = [vp, i, P(ctypes.c_int64)]
+    L.ndmg_pcg_solve_batched.argtypes = [vp, vp, vp, d, i, P(i), P(d)]
     L.ndmg_destroy.argtypes = [vp]
     L.ndmg_last_error.argtypes = []
     L.ndmg_last_error.restype = ctypes.c_char_p
@@ -126,6 +131,45 @@ def ndmg_pcg_solve(ctx, d_b, d_u, rtol, maxit, raise_on_noconv=True):
     if code != NDMG_OK and (raise_on_noconv or code != NDMG_ENOCONV):
         check(code)
     return code, it.value, rel.value
+
+
+def ndmg_plan_batched(ns, length, nrhs, opts):
+    arr = (ctypes.c_int * len(ns))(*[int(v) for v in ns])
+    ws, tl = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().ndmg_plan_batched(len(ns), arr, length, nrhs, ctypes.byref(opts), ctypes.byref(ws),
+                                  ctypes.byref(tl)))
+    return ws.value, tl.value
+
+
+def ndmg_setup_batched(ns, length, alphas, nrhs, opts, d_workspace, workspace_bytes, stream):
+    if len(alphas) != len(ns):
+        raise ValueError("one alpha per problem")
+    narr = (ctypes.c_int * len(ns))(*[int(v) for v in ns])
+    aarr = (ctypes.c_double * len(ns))(*[float(v) for v in alphas])
+    ctx = ctypes.c_void_p()
+    check(lib().ndmg_setup_batched(ctypes.byref(ctx), len(ns), narr, length, aarr, nrhs,
+                                   ctypes.byref(opts), d_workspace, workspace_bytes, stream))
+    return ctx
+
+
+def ndmg_batch_layout(ctx, prob):
+    info = (ctypes.c_int64 * 6)()
+    check(lib().ndmg_batch_layout(ctx, prob, info))
+    return list(info)
+
+
+def ndmg_pcg_solve_batched(ctx, d_b, d_u, rtol, maxit, npairs, raise_on_noconv=True,
+                           raise_on_breakdown=True):
+    """Returns (status, iterations, relative residuals) per pair; ENOCONV and EBREAKDOWN
+    are returned instead of raised when the matching flag is False."""
+    it = (ctypes.c_int * npairs)()
+    rel = (ctypes.c_double * npairs)()
+    code = lib().ndmg_pcg_solve_batched(ctx, d_b, d_u, rtol, maxit, it, rel)
+    quiet = ((code == NDMG_ENOCONV and not raise_on_noconv)
+             or (code == NDMG_EBREAKDOWN and not raise_on_breakdown))
+    if code != NDMG_OK and not quiet:
+        check(code)
+    return code, list(it), list(rel)
 
 
 def ndmg_assemble_rhs(ctx, d_f, d_b):

@@ -11,17 +11,30 @@ import torch
 from .solver import Solver
 
 
+def _solve_rows(solver, B2, rtol, maxit):
+    """Solve every row of B2 [k, vec_len]: all at once when the solver holds k
+    right-hand sides, else one row at a time (single right-hand-side solver)."""
+    k = B2.shape[0]
+    if solver.nrhs == k:
+        U, it, _ = solver.solve(B2, rtol, maxit)
+        return U, (list(it) if isinstance(it, list) else [it])
+    if solver.nrhs != 1:
+        raise ValueError(f"the solver holds {solver.nrhs} right-hand sides, got {k}")
+    U = torch.zeros_like(B2)
+    iters = []
+    for r in range(k):
+        _, it, _ = solver.solve(B2[r].contiguous(), rtol, maxit, u=U[r])
+        iters.append(it)
+    return U, iters
+
+
 class _SolveFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, B, alpha, solver, rtol, maxit):
         if abs(float(alpha) - solver.alpha) > 1e-14 * max(1.0, abs(solver.alpha)):
             raise ValueError("alpha must equal the solver's alpha (build one solver per alpha)")
         B2 = B.reshape(-1, solver.vec_len)
-        U = torch.zeros_like(B2)
-        iters = []
-        for r in range(B2.shape[0]):
-            _, it, _ = solver.solve(B2[r].contiguous(), rtol, maxit, u=U[r])
-            iters.append(it)
+        U, iters = _solve_rows(solver, B2.contiguous(), rtol, maxit)
         ctx.solver, ctx.rtol, ctx.maxit = solver, rtol, maxit
         ctx.iters = iters
         ctx.save_for_backward(U)
@@ -32,9 +45,7 @@ class _SolveFn(torch.autograd.Function):
         (U,) = ctx.saved_tensors
         S = ctx.solver
         G = (gU.reshape(-1, S.vec_len) * S.unknown_mask()).contiguous()
-        Lam = torch.zeros_like(G)
-        for r in range(G.shape[0]):
-            S.solve(G[r], ctx.rtol, ctx.maxit, u=Lam[r])
+        Lam, _ = _solve_rows(S, G, ctx.rtol, ctx.maxit)
         galpha = -S.curlcurl_form(Lam, U)
         return (Lam.reshape(gU.shape),
                 torch.tensor(galpha, dtype=torch.float64, device=gU.device), None, None, None)

@@ -1,5 +1,12 @@
 // C ABI of the ndmg library: planning, setup, the symmetric V-cycle MG(k, g, z0, m)
-// (Sec. 3.3, Fig. 1) and preconditioned conjugate gradients around it.
+// (Sec. 3.3, Fig. 1) and preconditioned conjugate gradients around it, for one problem
+// or for a batch of problems of uneven sizes with several right-hand sides each.
+//
+// A context holds one or more size classes (all problems with the same n).  Every
+// kernel of a class works on all its (problem, right-hand side) pairs at once; the
+// classes run on forked streams, and a CG iteration of the whole batch is captured as
+// one HIP graph.  Each pair carries its own CG scalars and an active flag on the device:
+// a converged pair drops out of every kernel of the following iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ndmg.h"
@@ -29,12 +37,24 @@ int fail(int code, const std::string& msg) {
       return fail(NDMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
   } while (0)
 
+#define NDMG_TRY(expr)          \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != NDMG_OK) return rc_; \
+  } while (0)
+
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Scalar slots of the CG driver (device array of doubles).
-enum { S_BB = 0, S_PQ = 1, S_RR = 2, S_RZA = 3, S_ZQA = 4, S_RZB = 5, S_ZQB = 6, S_CC = 8, S_N = 16 };
+using ndmg::kS_BB;
+using ndmg::kS_CC;
+using ndmg::kS_PQ;
+using ndmg::kS_REL;
+using ndmg::kS_RR;
+using ndmg::kS_RZA;
+using ndmg::kS_RZB;
+using ndmg::kScalStride;
 
 struct LevelHost {
   ndmg::Geom g;
@@ -42,26 +62,38 @@ struct LevelHost {
   ndmg::SubInfo sub{};
   std::vector<ndmg::Segment> segs;
   std::vector<int> chunks;             // (segment, first) pairs
-  ndmg::LevelFactors fac;              // FP64 host copies (smoothed levels)
-  std::vector<double> A0inv;           // coarsest level
-  std::vector<int64_t> map;
-  // offsets into the workspace
-  size_t o_z = 0, o_r = 0, o_zi = 0, o_gg = 0, o_w = 0, o_g = 0, o_Y = 0;
-  size_t o_ATinv = 0, o_Sinv = 0, o_lut = 0, o_slots = 0, o_segs = 0, o_chunks = 0;
-  size_t o_XT = 0, o_bofs = 0;
+  std::vector<int64_t> map;            // coarsest level: padded offset of each unknown
   int nB = 0;
-  size_t o_A0 = 0, o_map = 0;
+  // workspace offsets; per-pair arrays hold `count` copies, factors `nprob` copies
+  size_t o_z = 0, o_g = 0, o_r = 0, o_zi = 0, o_gg = 0, o_w = 0, o_Y = 0;
+  size_t o_ATinv = 0, o_XT = 0, o_Sinv = 0, o_A0 = 0;
+  size_t o_lut = 0, o_slots = 0, o_segs = 0, o_chunks = 0, o_bofs = 0, o_map = 0;
   size_t nY = 0;
+  size_t blk_ATinv = 0, blk_XT = 0, blk_Sinv = 0, blk_A0 = 0;   // elements per problem
+};
+
+struct Cls {
+  int n = 0, nprob = 0, nrhs = 1, count = 0;
+  std::vector<int> probs;          // problem indices, input order
+  std::vector<double> alpha;       // per problem
+  std::vector<LevelHost> lv;       // coarsest first
+  int64_t vlen = 0;                // vector length of the finest level (per pair)
+  int64_t vec_off = 0;             // first element of the class in a batch vector
+  int64_t pstride = 0;             // partial sums per pair
+  size_t o_pr = 0, o_pz = 0, o_pp = 0, o_pq = 0, o_part = 0, o_scal = 0;
+  size_t o_alpha = 0, o_act = 0, o_iters = 0, o_status = 0;
 };
 
 struct Plan {
-  int n = 0;
-  double length = 1.0, alpha = 1.0;
+  double length = 1.0;
   ndmg_opts opts{};
-  std::vector<LevelHost> lv;   // coarsest first
-  size_t elem = 8;             // bytes of the V-cycle scalar type
-  size_t o_pr = 0, o_pz = 0, o_pp = 0, o_pq = 0, o_part = 0, o_scal = 0;
-  size_t npart = 0;
+  size_t elem = 8;                 // bytes of the V-cycle scalar type
+  int nprob = 0, nrhs = 1;
+  std::vector<Cls> cls;            // ascending n
+  std::vector<int> prob_cls, prob_pos;
+  int64_t total_len = 0;           // batch vector length
+  int npairs = 0;
+  size_t o_nact = 0;               // one int per class
   size_t bytes = 0;
 };
 
@@ -71,62 +103,61 @@ struct ndmg_ctx {
   Plan plan;
   char* ws = nullptr;
   hipStream_t st = nullptr;
-  double* host_scal = nullptr;   // pinned
+  std::vector<hipStream_t> side;           // class i >= 1 runs on side[i - 1]
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  int* host_nact = nullptr;                // pinned, one per class
+  double* host_scal = nullptr;             // pinned, kScalStride per pair
+  int* host_int = nullptr;                 // pinned, iters and status per pair
   hipGraphExec_t gexec[2] = {nullptr, nullptr};   // CG iteration body, by scalar-slot parity
   double* graph_u = nullptr;                       // solution pointer the graphs were captured with
 };
 
 namespace {
 
-int make_plan(int n, double length, double alpha, const ndmg_opts* o_in, Plan* pl) {
-  ndmg_opts o;
-  ndmg_default_opts(&o);
-  if (o_in) o = *o_in;
-  if (n < 2) return fail(NDMG_EINVAL, "n must be >= 2");
-  if (!(length > 0.0) || !std::isfinite(length)) return fail(NDMG_EINVAL, "length must be > 0");
-  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NDMG_EINVAL, "alpha must be > 0");
-  if (o.smoother != NDMG_SMOOTHER_VERTEX) return fail(NDMG_EINVAL, "unsupported smoother");
-  if (o.m < 1 || o.m > 64) return fail(NDMG_EINVAL, "m must be in [1, 64]");
-  if (o.precision != NDMG_PREC_FP64 && o.precision != NDMG_PREC_FP32)
+int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
+  ndmg_default_opts(o);
+  if (o_in) *o = *o_in;
+  if (o->smoother != NDMG_SMOOTHER_VERTEX) return fail(NDMG_EINVAL, "unsupported smoother");
+  if (o->m < 1 || o->m > 64) return fail(NDMG_EINVAL, "m must be in [1, 64]");
+  if (o->precision != NDMG_PREC_FP64 && o->precision != NDMG_PREC_FP32)
     return fail(NDMG_EINVAL, "unsupported precision");
-  if (o.subdomain != 2) return fail(NDMG_EINVAL, "subdomain size must be 2");
-  if (o.eta <= 0.0) o.eta = 1.0 / 9.0;
-  if (n > 2048) return fail(NDMG_EINVAL, "n too large");
-  pl->n = n;
-  pl->length = length;
-  pl->alpha = alpha;
-  pl->opts = o;
-  pl->elem = (o.precision == NDMG_PREC_FP32) ? 4 : 8;
+  if (o->subdomain != 2) return fail(NDMG_EINVAL, "subdomain size must be 2");
+  if (o->eta <= 0.0) o->eta = 1.0 / 9.0;
+  return NDMG_OK;
+}
+
+// Workspace layout of one size class; `take` hands out aligned offsets.
+template <typename Take>
+int plan_class(Cls& C, const Plan& pl, Take&& take) {
+  const int n = C.n;
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 2) sizes.push_back(sizes.back() / 2);
   std::reverse(sizes.begin(), sizes.end());
-  pl->lv.clear();
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o2 = off;
-    off = align_up(off + bytes);
-    return o2;
-  };
+  const size_t cnt = (size_t)C.count, np = (size_t)C.nprob, el = pl.elem;
+  C.lv.clear();
   for (size_t k = 0; k < sizes.size(); ++k) {
     LevelHost L;
-    L.g = ndmg::make_geom(sizes[k], length);
-    const size_t vb = (size_t)L.g.len * pl->elem;
+    L.g = ndmg::make_geom(sizes[k], pl.length);
+    const size_t vb = (size_t)L.g.len * el * cnt;
     L.o_z = take(vb);
     L.o_g = take(vb);
     if (k == 0) {
       const int nc = sizes[k];
       const int64_t N0 = 3LL * nc * (nc - 1) * (nc - 1);
       if (N0 > 1024)
-        return fail(NDMG_EINVAL, "coarsest level has more than 1024 unknowns; choose n = c 2^j "
-                                 "with c <= 7");
-      L.o_A0 = take((size_t)N0 * N0 * pl->elem);
+        return fail(NDMG_EINVAL, "n = " + std::to_string(n) +
+                                     ": coarsest level has more than 1024 unknowns; choose n = c 2^j "
+                                     "with c <= 7");
+      L.blk_A0 = (size_t)N0 * N0;
+      L.o_A0 = take(L.blk_A0 * el * np);
       L.o_map = take((size_t)N0 * sizeof(int64_t));
     } else {
-      const int s = std::min(o.subdomain, sizes[k] / 2);
+      const int s = std::min(pl.opts.subdomain, sizes[k] / 2);
       if (sizes[k] % s) return fail(NDMG_EINVAL, "level not divisible by the subdomain size");
       L.smoothed = true;
       L.sub = ndmg::make_sub(s, sizes[k]);
-      L.segs = ndmg::vertex_segments(L.sub.nH, o.boundary_patches != 0);
+      L.segs = ndmg::vertex_segments(L.sub.nH, pl.opts.boundary_patches != 0);
       L.chunks.clear();
       for (size_t si = 0; si < L.segs.size(); ++si)
         for (int f = 0; f < L.segs[si].count; f += 64 * ndmg::patch_groups(L.sub.nH)) {
@@ -139,30 +170,88 @@ int make_plan(int n, double length, double alpha, const ndmg_opts* o_in, Plan* p
       L.o_w = take(vb);
       const size_t nv = (size_t)(L.sub.nH + 1);
       L.nY = nv * nv * nv * (size_t)L.sub.npad;
-      L.o_Y = take(L.nY * pl->elem);
-      L.o_ATinv = take((size_t)L.sub.nI * L.sub.nI * pl->elem);
+      L.o_Y = take(L.nY * el * cnt);
       L.nB = (int)ndmg::boundary_dofs(L.sub.s).size();
-      L.o_XT = take((size_t)L.sub.nI * L.nB * pl->elem);
+      L.blk_ATinv = (size_t)L.sub.nI * L.sub.nI;
+      L.blk_XT = (size_t)L.sub.nI * L.nB;
+      L.blk_Sinv = (size_t)27 * L.sub.npad * L.sub.npad;
+      L.o_ATinv = take(L.blk_ATinv * el * np);
+      L.o_XT = take(L.blk_XT * el * np);
+      L.o_Sinv = take(L.blk_Sinv * el * np);
       L.o_bofs = take((size_t)L.nB * sizeof(int64_t));
-      L.o_Sinv = take((size_t)27 * L.sub.npad * L.sub.npad * pl->elem);
       L.o_lut = take((size_t)3 * L.sub.lut_w * L.sub.lut_w * L.sub.lut_w * sizeof(int));
       L.o_slots = take((size_t)L.sub.nG * 4 * sizeof(int));
       L.o_segs = take(std::max<size_t>(1, L.segs.size()) * 8 * sizeof(int));
       L.o_chunks = take(std::max<size_t>(1, L.chunks.size()) * sizeof(int));
     }
-    pl->lv.push_back(std::move(L));
+    C.lv.push_back(std::move(L));
   }
-  const ndmg::Geom& gf = pl->lv.back().g;
-  const size_t v8 = (size_t)gf.len * sizeof(double);
-  pl->o_pr = take(v8);
-  pl->o_pz = take(v8);
-  pl->o_pp = take(v8);
-  pl->o_pq = take(v8);
-  const size_t cc_parts = (size_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
-  pl->npart = std::max<size_t>(std::max<size_t>(2 * ndmg::kRedBlocks, cc_parts),
-                               (size_t)ndmg::stencil_blocks(gf));
-  pl->o_part = take(pl->npart * sizeof(double));
-  pl->o_scal = take(S_N * sizeof(double));
+  const ndmg::Geom& gf = C.lv.back().g;
+  C.vlen = gf.len;
+  const size_t v8 = (size_t)gf.len * sizeof(double) * cnt;
+  C.o_pr = take(v8);
+  C.o_pz = take(v8);
+  C.o_pp = take(v8);
+  C.o_pq = take(v8);
+  const int64_t cc_parts = (int64_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
+  C.pstride = std::max<int64_t>(std::max<int64_t>(2 * ndmg::kRedBlocks, cc_parts),
+                                (int64_t)ndmg::stencil_blocks(gf));
+  C.o_part = take((size_t)C.pstride * sizeof(double) * cnt);
+  C.o_scal = take((size_t)kScalStride * sizeof(double) * cnt);
+  C.o_alpha = take(np * sizeof(double));
+  C.o_act = take(cnt * sizeof(int));
+  C.o_iters = take(cnt * sizeof(int));
+  C.o_status = take(cnt * sizeof(int));
+  return NDMG_OK;
+}
+
+int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts* o_in, Plan* pl) {
+  if (nprob < 1) return fail(NDMG_EINVAL, "nprob must be >= 1");
+  if (!ns) return fail(NDMG_EINVAL, "null size array");
+  if (nrhs < 1 || nrhs > 4096) return fail(NDMG_EINVAL, "nrhs must be in [1, 4096]");
+  if ((int64_t)nprob * nrhs > 65535) return fail(NDMG_EINVAL, "more than 65535 (problem, rhs) pairs");
+  if (!(length > 0.0) || !std::isfinite(length)) return fail(NDMG_EINVAL, "length must be > 0");
+  NDMG_TRY(check_opts(o_in, &pl->opts));
+  for (int p = 0; p < nprob; ++p) {
+    if (ns[p] < 2) return fail(NDMG_EINVAL, "n must be >= 2");
+    if (ns[p] > 2048) return fail(NDMG_EINVAL, "n too large");
+  }
+  pl->length = length;
+  pl->nprob = nprob;
+  pl->nrhs = nrhs;
+  pl->elem = (pl->opts.precision == NDMG_PREC_FP32) ? 4 : 8;
+  std::vector<int> distinct(ns, ns + nprob);
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  pl->cls.assign(distinct.size(), Cls{});
+  pl->prob_cls.assign(nprob, 0);
+  pl->prob_pos.assign(nprob, 0);
+  for (size_t ci = 0; ci < distinct.size(); ++ci) pl->cls[ci].n = distinct[ci];
+  for (int p = 0; p < nprob; ++p) {
+    const int ci = (int)(std::lower_bound(distinct.begin(), distinct.end(), ns[p]) - distinct.begin());
+    Cls& C = pl->cls[ci];
+    pl->prob_cls[p] = ci;
+    pl->prob_pos[p] = C.nprob++;
+    C.probs.push_back(p);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o2 = off;
+    off = align_up(off + bytes);
+    return o2;
+  };
+  int64_t voff = 0;
+  pl->npairs = 0;
+  for (auto& C : pl->cls) {
+    C.nrhs = nrhs;
+    C.count = C.nprob * nrhs;
+    NDMG_TRY(plan_class(C, *pl, take));
+    C.vec_off = voff;
+    voff += (int64_t)C.count * C.vlen;
+    pl->npairs += C.count;
+  }
+  pl->total_len = voff;
+  pl->o_nact = take(pl->cls.size() * sizeof(int));
   pl->bytes = off;
   return NDMG_OK;
 }
@@ -184,7 +273,6 @@ ndmg::LevelPtrs<T> level_ptrs(ndmg_ctx* c, const LevelHost& L) {
   p.ATinv = at<T>(c, L.o_ATinv);
   p.Sinv = at<T>(c, L.o_Sinv);
   p.XT = at<T>(c, L.o_XT);
-  p.bofs = at<int64_t>(c, L.o_bofs);
   return p;
 }
 
@@ -196,62 +284,123 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.nG = L.sub.nG;
   d.npad = L.sub.npad;
   d.lut_w = L.sub.lut_w;
+  d.nB = L.nB;
   d.lut = at<int>(c, L.o_lut);
   d.slots = at<int>(c, L.o_slots);
   d.segs = at<int>(c, L.o_segs);
   d.chunks = at<int>(c, L.o_chunks);
   d.nchunks = (int)(L.chunks.size() / 2);
   d.gpw = ndmg::patch_groups(L.sub.nH);
+  d.bofs = at<int64_t>(c, L.o_bofs);
   return d;
 }
 
-template <typename T>
-std::vector<T> cast_vec(const std::vector<double>& v) {
-  return std::vector<T>(v.begin(), v.end());
+// All pairs of a class, or only its active ones.
+ndmg::Bat class_batch(ndmg_ctx* c, const Cls& C, bool masked) {
+  return ndmg::Bat{C.count, C.nrhs, at<double>(c, C.o_alpha), masked ? at<int>(c, C.o_act) : nullptr};
 }
 
-template <typename T>
-int upload_factors(ndmg_ctx* c) {
-  Plan& pl = c->plan;
+// Host staging of everything uploaded at setup; freed after the stream has synchronised.
+struct Staging {
   std::vector<std::vector<char>> keep;
-  auto put = [&](size_t off, const void* src, size_t bytes) -> int {
+  int put(ndmg_ctx* c, size_t off, const void* src, size_t bytes) {
     if (bytes == 0) return NDMG_OK;
     keep.emplace_back((const char*)src, (const char*)src + bytes);
     NDMG_HIP(hipMemcpyAsync(c->ws + off, keep.back().data(), bytes, hipMemcpyHostToDevice, c->st));
     return NDMG_OK;
+  }
+  template <typename V>
+  int put_vec(ndmg_ctx* c, size_t off, const V& v) {
+    return put(c, off, v.data(), v.size() * sizeof(typename V::value_type));
+  }
+};
+
+// Local factors of every (problem, level) of a class, built on host threads in FP64 and
+// cast to the working precision (Sec. 3.2: A_T of eq. ATDef, A_V of eq. AVDef; coarsest
+// level exact).
+template <typename T>
+int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
+  Plan& pl = c->plan;
+  const int nl = (int)C.lv.size();
+  std::vector<std::vector<T>> ATinv(nl), XT(nl), Sinv(nl), A0(nl);
+  for (int k = 0; k < nl; ++k) {
+    LevelHost& L = C.lv[k];
+    if (L.smoothed) {
+      ATinv[k].assign(L.blk_ATinv * C.nprob, T(0));
+      XT[k].assign(L.blk_XT * C.nprob, T(0));
+      Sinv[k].assign(L.blk_Sinv * C.nprob, T(0));
+    } else {
+      A0[k].assign(L.blk_A0 * C.nprob, T(0));
+    }
+  }
+  const bool bp = pl.opts.boundary_patches != 0;
+  unsigned hw = std::thread::hardware_concurrency();
+  const int nth = std::max(1, std::min<int>(C.nprob, std::min<int>(16, hw ? (int)hw : 4)));
+  std::vector<std::string> errs(nth);
+  std::vector<std::vector<int64_t>> maps(nth);
+  auto work = [&](int t) {
+    for (int p = t; p < C.nprob; p += nth) {
+      const double a = C.alpha[p];
+      for (int k = 0; k < nl; ++k) {
+        LevelHost& L = C.lv[k];
+        std::string err;
+        if (!L.smoothed) {
+          std::vector<double> inv;
+          std::vector<int64_t> map;
+          if (!ndmg::build_coarse(L.g, a, &inv, &map, &err)) {
+            errs[t] = err;
+            return;
+          }
+          std::copy(inv.begin(), inv.end(), A0[k].begin() + (size_t)p * L.blk_A0);
+          if (maps[t].empty()) maps[t] = map;
+          continue;
+        }
+        ndmg::LevelFactors fac;
+        if (!ndmg::build_level_factors(L.g.h, a, L.sub, bp, &fac, &err)) {
+          errs[t] = err;
+          return;
+        }
+        std::copy(fac.ATinv.begin(), fac.ATinv.end(), ATinv[k].begin() + (size_t)p * L.blk_ATinv);
+        std::copy(fac.XT.begin(), fac.XT.end(), XT[k].begin() + (size_t)p * L.blk_XT);
+        std::copy(fac.Sinv.begin(), fac.Sinv.end(), Sinv[k].begin() + (size_t)p * L.blk_Sinv);
+      }
+    }
   };
-  for (auto& L : pl.lv) {
-    int rc;
+  if (nth == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  for (auto& e : errs)
+    if (!e.empty()) return fail(NDMG_EINVAL, e);
+  for (int k = 0; k < nl; ++k) {
+    LevelHost& L = C.lv[k];
     if (!L.smoothed) {
-      auto a = cast_vec<T>(L.A0inv);
-      if ((rc = put(L.o_A0, a.data(), a.size() * sizeof(T)))) return rc;
-      if ((rc = put(L.o_map, L.map.data(), L.map.size() * sizeof(int64_t)))) return rc;
+      L.map = maps[0];
+      NDMG_TRY(stg.put_vec(c, L.o_A0, A0[k]));
+      NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
       continue;
     }
-    auto at_ = cast_vec<T>(L.fac.ATinv);
-    auto si = cast_vec<T>(L.fac.Sinv);
-    auto xt = cast_vec<T>(L.fac.XT);
-    if ((rc = put(L.o_ATinv, at_.data(), at_.size() * sizeof(T)))) return rc;
-    if ((rc = put(L.o_XT, xt.data(), xt.size() * sizeof(T)))) return rc;
+    NDMG_TRY(stg.put_vec(c, L.o_ATinv, ATinv[k]));
+    NDMG_TRY(stg.put_vec(c, L.o_XT, XT[k]));
+    NDMG_TRY(stg.put_vec(c, L.o_Sinv, Sinv[k]));
     {
-      auto bd = ndmg::boundary_dofs(L.sub.s);
       std::vector<int64_t> bo;
-      for (auto& q : bd)
+      for (auto& q : ndmg::boundary_dofs(L.sub.s))
         bo.push_back(q.d * L.g.B + (int64_t)q.dz * L.g.plane + (int64_t)q.dy * L.g.P + q.dx);
-      if ((rc = put(L.o_bofs, bo.data(), bo.size() * sizeof(int64_t)))) return rc;
+      NDMG_TRY(stg.put_vec(c, L.o_bofs, bo));
     }
-    if ((rc = put(L.o_Sinv, si.data(), si.size() * sizeof(T)))) return rc;
-    auto lut = ndmg::slot_lookup(L.sub.s);
-    if ((rc = put(L.o_lut, lut.data(), lut.size() * sizeof(int)))) return rc;
-    auto slots = ndmg::vertex_slots(L.sub.s);
+    NDMG_TRY(stg.put_vec(c, L.o_lut, ndmg::slot_lookup(L.sub.s)));
     std::vector<int> sl;
-    for (auto& q : slots) {
+    for (auto& q : ndmg::vertex_slots(L.sub.s)) {
       sl.push_back(q.d);
       sl.push_back(q.dx);
       sl.push_back(q.dy);
       sl.push_back(q.dz);
     }
-    if ((rc = put(L.o_slots, sl.data(), sl.size() * sizeof(int)))) return rc;
+    NDMG_TRY(stg.put_vec(c, L.o_slots, sl));
     std::vector<int> sg;
     for (auto& q : L.segs) {
       sg.push_back(q.type);
@@ -259,113 +408,162 @@ int upload_factors(ndmg_ctx* c) {
       for (int a = 0; a < 3; ++a) sg.push_back(q.dims[a]);
       sg.push_back(q.count);
     }
-    if ((rc = put(L.o_segs, sg.data(), sg.size() * sizeof(int)))) return rc;
-    if ((rc = put(L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(int)))) return rc;
+    NDMG_TRY(stg.put_vec(c, L.o_segs, sg));
+    NDMG_TRY(stg.put_vec(c, L.o_chunks, L.chunks));
   }
-  NDMG_HIP(hipStreamSynchronize(c->st));   // host staging buffers die with `keep`
+  NDMG_TRY(stg.put_vec(c, C.o_alpha, C.alpha));
   return NDMG_OK;
 }
 
-// z = MG(k, g, 0, m) (Fig. 1).
+// z = MG(k, g, 0, m) (Fig. 1) for the pairs of a class.
 template <typename T>
-int vcycle_rec(ndmg_ctx* c, int k, const T* g, T* z) {
+int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt, hipStream_t st) {
   Plan& pl = c->plan;
-  LevelHost& L = pl.lv[k];
+  LevelHost& L = C.lv[k];
   if (k == 0) {
-    NDMG_HIP(ndmg::launch_coarse<T>(g, z, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map),
-                                    (int)L.map.size(), c->st));
+    NDMG_HIP(ndmg::launch_coarse<T>(g, z, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map), (int)L.map.size(),
+                                    L.g.len, bt, st));
     return NDMG_OK;
   }
   const int m = pl.opts.m;
-  const double eta = pl.opts.eta, alpha = pl.alpha;
+  const double eta = pl.opts.eta;
   auto P = level_ptrs<T>(c, L);
   auto D = level_dsub(c, L);
-  LevelHost& Lc = pl.lv[k - 1];
+  LevelHost& Lc = C.lv[k - 1];
   // z_1 .. z_m: pre-smoothing from z_0 = 0
-  NDMG_HIP(ndmg::launch_smooth<T>(g, z, P, D, L.g, alpha, eta, 1, c->st));
+  NDMG_HIP(ndmg::launch_smooth<T>(g, z, P, D, L.g, bt, eta, 1, st));
   for (int l = 1; l < m; ++l) {
-    NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, alpha, 1, c->st));
-    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, alpha, eta, 0, c->st));
+    NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
+    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, bt, eta, 0, st));
   }
   // gbar = I_k^{k-1} (g - A z_m)
-  NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, alpha, 1, c->st));
-  NDMG_HIP(ndmg::launch_restrict<T>(P.r, at<T>(c, Lc.o_g), L.g, Lc.g, c->st));
-  int rc = vcycle_rec<T>(c, k - 1, at<T>(c, Lc.o_g), at<T>(c, Lc.o_z));
-  if (rc) return rc;
+  NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
+  NDMG_HIP(ndmg::launch_restrict<T>(P.r, at<T>(c, Lc.o_g), L.g, Lc.g, bt, st));
+  NDMG_TRY(vcycle_rec<T>(c, C, k - 1, at<T>(c, Lc.o_g), at<T>(c, Lc.o_z), bt, st));
   // z_{m+1} = z_m + I_{k-1}^k MG(k-1, gbar, 0, m)
-  NDMG_HIP(ndmg::launch_prolong_add<T>(at<T>(c, Lc.o_z), z, L.g, Lc.g, c->st));
+  NDMG_HIP(ndmg::launch_prolong_add<T>(at<T>(c, Lc.o_z), z, L.g, Lc.g, bt, st));
   // post-smoothing
   for (int l = 0; l < m; ++l) {
-    NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, alpha, 1, c->st));
-    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, alpha, eta, 0, c->st));
+    NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
+    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, bt, eta, 0, st));
   }
   return NDMG_OK;
 }
 
-// B g for FP64 vectors of the finest level, in the context's precision.
-int precondition(ndmg_ctx* c, const double* g, double* z) {
+// z = B g for FP64 vectors of the finest level of a class, in the context's precision.
+int precondition(ndmg_ctx* c, Cls& C, const double* g, double* z, const ndmg::Bat& bt, hipStream_t st) {
   Plan& pl = c->plan;
-  const int J = (int)pl.lv.size() - 1;
-  LevelHost& L = pl.lv[J];
-  if (pl.opts.precision == NDMG_PREC_FP64) {
-    if (J == 0) {
-      NDMG_HIP(ndmg::launch_coarse<double>(g, z, at<double>(c, L.o_A0), at<int64_t>(c, L.o_map),
-                                           (int)L.map.size(), c->st));
-      return NDMG_OK;
-    }
-    return vcycle_rec<double>(c, J, g, z);
-  }
+  const int J = (int)C.lv.size() - 1;
+  LevelHost& L = C.lv[J];
+  if (pl.opts.precision == NDMG_PREC_FP64) return vcycle_rec<double>(c, C, J, g, z, bt, st);
   float* gf = at<float>(c, L.o_g);
   float* zf = at<float>(c, L.o_z);
-  NDMG_HIP((ndmg::launch_convert<double, float>(g, gf, L.g.len, c->st)));
-  int rc = vcycle_rec<float>(c, J, gf, zf);
-  if (rc) return rc;
-  NDMG_HIP((ndmg::launch_convert<float, double>(zf, z, L.g.len, c->st)));
+  NDMG_HIP((ndmg::launch_convert<double, float>(g, gf, L.g.len, bt, st)));
+  NDMG_TRY(vcycle_rec<float>(c, C, J, gf, zf, bt, st));
+  NDMG_HIP((ndmg::launch_convert<float, double>(zf, z, L.g.len, bt, st)));
   return NDMG_OK;
 }
 
-// q = A p with p^T q (slot S_PQ), then u += alpha p, r -= alpha q (alpha = s[num] / s[PQ])
-// and r . r (slot S_RR).
-int cg_apply_update(ndmg_ctx* c, double* u, int num) {
-  Plan& pl = c->plan;
-  const ndmg::Geom& g = pl.lv.back().g;
+// q = A p with p^T q (slot PQ), then u += a p, r -= a q (a = s[num] / s[PQ]) and r . r.
+int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt, hipStream_t st) {
+  const ndmg::Geom& g = C.lv.back().g;
   const int64_t len = g.len;
-  double* r = at<double>(c, pl.o_pr);
-  double* p = at<double>(c, pl.o_pp);
-  double* q = at<double>(c, pl.o_pq);
-  double* part = at<double>(c, pl.o_part);
-  double* sc = at<double>(c, pl.o_scal);
+  double* r = at<double>(c, C.o_pr);
+  double* p = at<double>(c, C.o_pp);
+  double* q = at<double>(c, C.o_pq);
+  double* part = at<double>(c, C.o_part);
+  double* sc = at<double>(c, C.o_scal);
   if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
-    int np = 0;
-    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, pl.alpha, 2, part, &np, c->st));
-    NDMG_HIP(ndmg::launch_final(part, np, 1, sc + S_PQ, c->st));
+    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, st));
+    NDMG_HIP(ndmg::launch_final(part, ndmg::stencil_blocks(g), C.pstride, 1, sc + kS_PQ, bt, st));
   } else {
-    NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, pl.alpha, 0, c->st));
-    NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, sc + S_PQ, len, c->st));
+    NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));
+    NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, C.pstride, sc + kS_PQ, len, bt, st));
   }
-  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, S_PQ, part, sc + S_RR, len, c->st));
+  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, kS_PQ, kS_RR, part, C.pstride, len, bt, st));
   return NDMG_OK;
 }
 
-// One CG iteration after the first: z = B r; s[nxt] = r . z (and s[nxt+1] = z . q for the
-// flexible beta); p = z + beta p; then cg_apply_update with alpha = s[nxt] / p^T A p.
-int cg_body_eager(ndmg_ctx* c, double* u, int cur, int nxt) {
-  Plan& pl = c->plan;
-  const int64_t len = pl.lv.back().g.len;
-  double* r = at<double>(c, pl.o_pr);
-  double* z = at<double>(c, pl.o_pz);
-  double* p = at<double>(c, pl.o_pp);
-  double* q = at<double>(c, pl.o_pq);
-  double* part = at<double>(c, pl.o_part);
-  double* sc = at<double>(c, pl.o_scal);
-  const bool flexible =
-      pl.opts.flexible > 0 || (pl.opts.flexible < 0 && pl.opts.precision == NDMG_PREC_FP32);
-  int rc = precondition(c, r, z);
-  if (rc) return rc;
-  NDMG_HIP(ndmg::launch_dot(z, r, flexible ? q : nullptr, part, sc + nxt, len, c->st));
-  NDMG_HIP(ndmg::launch_cg_direction(p, z, sc, nxt, cur, flexible ? 1 : 0, nxt + 1, cur, S_PQ, len,
-                                     c->st));
-  return cg_apply_update(c, u, nxt);
+bool flexible_beta(const Plan& pl) {
+  return pl.opts.flexible > 0 || (pl.opts.flexible < 0 && pl.opts.precision == NDMG_PREC_FP32);
+}
+
+int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, hipStream_t st) {
+  Cls& C = c->plan.cls[ci];
+  NDMG_HIP(ndmg::launch_pcg_check(at<double>(c, C.o_scal), at<int>(c, C.o_act), at<int>(c, C.o_iters),
+                                  at<int>(c, C.o_status), C.count, i_rz,
+                                  at<int>(c, c->plan.o_nact) + ci, st));
+  return NDMG_OK;
+}
+
+// Start of a solve for one class: r = b, u = 0, b . b, per-pair state, z = B r,
+// s[cur] = r . z, p = z and the first update.
+int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol, hipStream_t st) {
+  Cls& C = c->plan.cls[ci];
+  const int64_t len = C.vlen;
+  double* r = at<double>(c, C.o_pr);
+  double* z = at<double>(c, C.o_pz);
+  double* p = at<double>(c, C.o_pp);
+  double* part = at<double>(c, C.o_part);
+  double* sc = at<double>(c, C.o_scal);
+  const ndmg::Bat all = class_batch(c, C, false), act = class_batch(c, C, true);
+  NDMG_HIP(ndmg::launch_copy(b, r, len, all, st));
+  NDMG_HIP(ndmg::launch_zero(u, len, all, st));
+  NDMG_HIP(ndmg::launch_dot(b, b, nullptr, part, C.pstride, sc + kS_BB, len, all, st));
+  NDMG_HIP(ndmg::launch_pcg_init(sc, at<int>(c, C.o_act), at<int>(c, C.o_iters), at<int>(c, C.o_status),
+                                 C.count, rtol, st));
+  NDMG_TRY(precondition(c, C, r, z, act, st));
+  NDMG_HIP(ndmg::launch_dot(r, z, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
+  NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
+  NDMG_TRY(cg_apply_update(c, C, u, kS_RZA, act, st));
+  return pcg_check(c, ci, kS_RZA, st);
+}
+
+// One CG iteration after the first for one class: z = B r; s[nxt] = r . z (and
+// s[nxt + 1] = z . q for the flexible beta); p = z + beta p; the update with
+// a = s[nxt] / p^T A p; the convergence test.
+int pcg_body(ndmg_ctx* c, size_t ci, double* u, int cur, int nxt, hipStream_t st) {
+  Cls& C = c->plan.cls[ci];
+  const int64_t len = C.vlen;
+  double* r = at<double>(c, C.o_pr);
+  double* z = at<double>(c, C.o_pz);
+  double* p = at<double>(c, C.o_pp);
+  double* q = at<double>(c, C.o_pq);
+  double* part = at<double>(c, C.o_part);
+  double* sc = at<double>(c, C.o_scal);
+  const bool flex = flexible_beta(c->plan);
+  const ndmg::Bat act = class_batch(c, C, true);
+  NDMG_TRY(precondition(c, C, r, z, act, st));
+  NDMG_HIP(ndmg::launch_dot(z, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
+  NDMG_HIP(ndmg::launch_cg_direction(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act, st));
+  NDMG_TRY(cg_apply_update(c, C, u, nxt, act, st));
+  return pcg_check(c, ci, nxt, st);
+}
+
+// Run fn(ci, stream) for every class: class 0 on the context's stream, class i >= 1 on
+// a side stream forked from it and joined back.
+template <typename F>
+int for_classes(ndmg_ctx* c, F&& fn) {
+  const size_t nc = c->plan.cls.size();
+  if (nc == 1) return fn((size_t)0, c->st);
+  NDMG_HIP(hipEventRecord(c->ev_fork, c->st));
+  for (size_t i = 1; i < nc; ++i) NDMG_HIP(hipStreamWaitEvent(c->side[i - 1], c->ev_fork, 0));
+  int rc = NDMG_OK;
+  for (size_t i = 0; i < nc && rc == NDMG_OK; ++i) rc = fn(i, i == 0 ? c->st : c->side[i - 1]);
+  // join every side stream, also after a failure, so that none is left forked
+  for (size_t i = 1; i < nc; ++i) {
+    hipError_t e = hipEventRecord(c->ev_join[i - 1], c->side[i - 1]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_join[i - 1], 0);
+    if (e != hipSuccess && rc == NDMG_OK)
+      rc = fail(NDMG_EHIP, std::string("stream join: ") + hipGetErrorString(e));
+  }
+  return rc;
+}
+
+int body_all_eager(ndmg_ctx* c, double* u, int cur, int nxt) {
+  return for_classes(c, [&](size_t ci, hipStream_t st) {
+    return pcg_body(c, ci, u + c->plan.cls[ci].vec_off, cur, nxt, st);
+  });
 }
 
 void drop_graphs(ndmg_ctx* c) {
@@ -377,14 +575,14 @@ void drop_graphs(ndmg_ctx* c) {
   c->graph_u = nullptr;
 }
 
-int cg_body(ndmg_ctx* c, double* u, int cur, int nxt) {
-  if (!c->plan.opts.use_graphs || c->st == nullptr) return cg_body_eager(c, u, cur, nxt);
+int body_all(ndmg_ctx* c, double* u, int cur, int nxt) {
+  if (!c->plan.opts.use_graphs || c->st == nullptr) return body_all_eager(c, u, cur, nxt);
   if (c->graph_u != u) drop_graphs(c);
-  const int par = (cur == S_RZA) ? 0 : 1;
+  const int par = (cur == kS_RZA) ? 0 : 1;
   if (!c->gexec[par]) {
     hipGraph_t graph = nullptr;
     NDMG_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-    int rc = cg_body_eager(c, u, cur, nxt);
+    int rc = body_all_eager(c, u, cur, nxt);
     hipError_t e = hipStreamEndCapture(c->st, &graph);
     if (rc) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -403,8 +601,150 @@ int cg_body(ndmg_ctx* c, double* u, int cur, int nxt) {
   return NDMG_OK;
 }
 
+// Pairs still active, summed over the classes (synchronises the stream).
+int active_pairs(ndmg_ctx* c, int* out) {
+  const size_t nc = c->plan.cls.size();
+  NDMG_HIP(hipMemcpyAsync(c->host_nact, at<int>(c, c->plan.o_nact), nc * sizeof(int),
+                          hipMemcpyDeviceToHost, c->st));
+  NDMG_HIP(hipStreamSynchronize(c->st));
+  int t = 0;
+  for (size_t i = 0; i < nc; ++i) t += c->host_nact[i];
+  *out = t;
+  return NDMG_OK;
+}
+
+// Whole PCG over all pairs; per-pair results in problem order (p * nrhs + rhs).
+int pcg_all(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int* iters,
+            double* relres) {
+  Plan& pl = c->plan;
+  NDMG_TRY(for_classes(c, [&](size_t ci, hipStream_t st) {
+    const Cls& C = pl.cls[ci];
+    return pcg_prologue(c, ci, b + C.vec_off, u + C.vec_off, rtol, st);
+  }));
+  int nact = 0;
+  NDMG_TRY(active_pairs(c, &nact));
+  int cur = kS_RZA, nxt = kS_RZB;
+  for (int it = 2; it <= maxit && nact > 0; ++it) {
+    NDMG_TRY(body_all(c, u, cur, nxt));
+    std::swap(cur, nxt);
+    NDMG_TRY(active_pairs(c, &nact));
+  }
+  // per-pair results
+  int nbroken = 0, nrun = 0, first_bad = -1;
+  for (const Cls& C : pl.cls) {
+    NDMG_HIP(hipMemcpyAsync(c->host_scal, at<double>(c, C.o_scal), (size_t)C.count * kScalStride * 8,
+                            hipMemcpyDeviceToHost, c->st));
+    NDMG_HIP(hipMemcpyAsync(c->host_int, at<int>(c, C.o_iters), (size_t)C.count * sizeof(int),
+                            hipMemcpyDeviceToHost, c->st));
+    NDMG_HIP(hipMemcpyAsync(c->host_int + C.count, at<int>(c, C.o_status), (size_t)C.count * sizeof(int),
+                            hipMemcpyDeviceToHost, c->st));
+    NDMG_HIP(hipStreamSynchronize(c->st));
+    for (int j = 0; j < C.nprob; ++j)
+      for (int r = 0; r < C.nrhs; ++r) {
+        const int pair = j * C.nrhs + r;
+        const int out = C.probs[j] * pl.nrhs + r;
+        if (iters) iters[out] = c->host_int[pair];
+        if (relres) relres[out] = c->host_scal[(size_t)pair * kScalStride + kS_REL];
+        const int stt = c->host_int[C.count + pair];
+        if (stt == ndmg::kPairBroken) {
+          ++nbroken;
+          if (first_bad < 0) first_bad = out;
+        } else if (stt == ndmg::kPairRun) {
+          ++nrun;
+        }
+      }
+  }
+  if (nbroken)
+    return fail(NDMG_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite scalar) in " +
+                                     std::to_string(nbroken) + " pair(s), first (problem*nrhs+rhs) " +
+                                     std::to_string(first_bad));
+  if (nrun) return fail(NDMG_ENOCONV, "PCG reached maxit in " + std::to_string(nrun) + " pair(s)");
+  return NDMG_OK;
+}
+
 int check_ctx(const ndmg_ctx* c) {
   if (!c) return fail(NDMG_EINVAL, "null context");
+  return NDMG_OK;
+}
+
+int one_class(const ndmg_ctx* c) {
+  if (c->plan.cls.size() != 1)
+    return fail(NDMG_EINVAL, "this call needs a context with a single problem size");
+  return NDMG_OK;
+}
+
+void release(ndmg_ctx* c) {
+  drop_graphs(c);
+  for (auto s : c->side)
+    if (s) (void)hipStreamDestroy(s);
+  c->side.clear();
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  c->ev_fork = nullptr;
+  for (auto e : c->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  c->ev_join.clear();
+  if (c->host_nact) (void)hipHostFree(c->host_nact);
+  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  if (c->host_int) (void)hipHostFree(c->host_int);
+  c->host_nact = nullptr;
+  c->host_scal = nullptr;
+  c->host_int = nullptr;
+}
+
+struct CtxDeleter {
+  void operator()(ndmg_ctx* c) const {
+    release(c);
+    delete c;
+  }
+};
+
+int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const double* alpha,
+                 int nrhs, const ndmg_opts* opts, void* d_workspace, size_t workspace_bytes,
+                 void* stream) {
+  if (!out) return fail(NDMG_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!alpha) return fail(NDMG_EINVAL, "null alpha array");
+  std::unique_ptr<ndmg_ctx, CtxDeleter> c(new ndmg_ctx());
+  NDMG_TRY(make_plan(nprob, ns, length, nrhs, opts, &c->plan));
+  for (int p = 0; p < nprob; ++p)
+    if (!(alpha[p] > 0.0) || !std::isfinite(alpha[p])) return fail(NDMG_EINVAL, "alpha must be > 0");
+  if (!d_workspace) return fail(NDMG_EINVAL, "null workspace");
+  if (workspace_bytes < c->plan.bytes)
+    return fail(NDMG_EWORKSPACE, "workspace smaller than the planned size");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+    return fail(NDMG_EWORKSPACE, "workspace must be 256-byte aligned");
+  c->ws = static_cast<char*>(d_workspace);
+  c->st = static_cast<hipStream_t>(stream);
+  Plan& pl = c->plan;
+  for (auto& C : pl.cls) {
+    C.alpha.clear();
+    for (int p : C.probs) C.alpha.push_back(alpha[p]);
+  }
+  NDMG_HIP(hipMemsetAsync(c->ws, 0, pl.bytes, c->st));
+  {
+    Staging stg;
+    for (auto& C : pl.cls)
+      NDMG_TRY(pl.elem == 8 ? build_class_factors<double>(c.get(), C, stg)
+                            : build_class_factors<float>(c.get(), C, stg));
+    NDMG_HIP(hipStreamSynchronize(c->st));   // staging buffers die with stg
+  }
+  const size_t nc = pl.cls.size();
+  for (size_t i = 1; i < nc; ++i) {
+    hipStream_t s = nullptr;
+    NDMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    c->side.push_back(s);
+    hipEvent_t e = nullptr;
+    NDMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->ev_join.push_back(e);
+  }
+  if (nc > 1) NDMG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  int maxcount = 0;
+  for (auto& C : pl.cls) maxcount = std::max(maxcount, C.count);
+  NDMG_HIP(hipHostMalloc((void**)&c->host_nact, nc * sizeof(int), hipHostMallocDefault));
+  NDMG_HIP(hipHostMalloc((void**)&c->host_scal, (size_t)maxcount * kScalStride * sizeof(double),
+                         hipHostMallocDefault));
+  NDMG_HIP(hipHostMalloc((void**)&c->host_int, (size_t)maxcount * 2 * sizeof(int), hipHostMallocDefault));
+  *out = c.release();
   return NDMG_OK;
 }
 
@@ -428,53 +768,59 @@ const char* ndmg_last_error(void) { return g_err.c_str(); }
 
 int ndmg_plan(int n, double length, double alpha, const ndmg_opts* opts, size_t* workspace_bytes,
               size_t* vec_len) {
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NDMG_EINVAL, "alpha must be > 0");
   Plan pl;
-  int rc = make_plan(n, length, alpha, opts, &pl);
-  if (rc) return rc;
+  NDMG_TRY(make_plan(1, &n, length, 1, opts, &pl));
   if (workspace_bytes) *workspace_bytes = pl.bytes;
-  if (vec_len) *vec_len = (size_t)pl.lv.back().g.len;
+  if (vec_len) *vec_len = (size_t)pl.total_len;
   return NDMG_OK;
 }
 
 int ndmg_setup(ndmg_ctx** out, int n, double length, double alpha, const ndmg_opts* opts,
                void* d_workspace, size_t workspace_bytes, void* stream) {
-  if (!out) return fail(NDMG_EINVAL, "null output pointer");
-  *out = nullptr;
-  std::unique_ptr<ndmg_ctx> c(new ndmg_ctx());
-  int rc = make_plan(n, length, alpha, opts, &c->plan);
-  if (rc) return rc;
-  if (!d_workspace) return fail(NDMG_EINVAL, "null workspace");
-  if (workspace_bytes < c->plan.bytes)
-    return fail(NDMG_EWORKSPACE, "workspace smaller than ndmg_plan reports");
-  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
-    return fail(NDMG_EWORKSPACE, "workspace must be 256-byte aligned");
-  c->ws = static_cast<char*>(d_workspace);
-  c->st = static_cast<hipStream_t>(stream);
-  Plan& pl = c->plan;
-  std::string err;
-  for (auto& L : pl.lv) {
-    if (!L.smoothed) {
-      if (!ndmg::build_coarse(L.g, alpha, &L.A0inv, &L.map, &err)) return fail(NDMG_EINVAL, err);
-      continue;
-    }
-    if (!ndmg::build_level_factors(L.g.h, alpha, L.sub, pl.opts.boundary_patches != 0, &L.fac, &err))
-      return fail(NDMG_EINVAL, err);
-  }
-  NDMG_HIP(hipMemsetAsync(c->ws, 0, pl.bytes, c->st));
-  rc = (pl.elem == 8) ? upload_factors<double>(c.get()) : upload_factors<float>(c.get());
-  if (rc) return rc;
-  NDMG_HIP(hipHostMalloc((void**)&c->host_scal, S_N * sizeof(double), hipHostMallocDefault));
-  *out = c.release();
+  return setup_common(out, 1, &n, length, &alpha, 1, opts, d_workspace, workspace_bytes, stream);
+}
+
+int ndmg_plan_batched(int nprob, const int* n, double length, int nrhs, const ndmg_opts* opts,
+                      size_t* workspace_bytes, size_t* total_len) {
+  Plan pl;
+  NDMG_TRY(make_plan(nprob, n, length, nrhs, opts, &pl));
+  if (workspace_bytes) *workspace_bytes = pl.bytes;
+  if (total_len) *total_len = (size_t)pl.total_len;
+  return NDMG_OK;
+}
+
+int ndmg_setup_batched(ndmg_ctx** out, int nprob, const int* n, double length, const double* alpha,
+                       int nrhs, const ndmg_opts* opts, void* d_workspace, size_t workspace_bytes,
+                       void* stream) {
+  return setup_common(out, nprob, n, length, alpha, nrhs, opts, d_workspace, workspace_bytes, stream);
+}
+
+int ndmg_batch_layout(const ndmg_ctx* c, int prob, int64_t info[6]) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!info) return fail(NDMG_EINVAL, "null info");
+  const Plan& pl = c->plan;
+  if (prob < 0 || prob >= pl.nprob) return fail(NDMG_EINVAL, "problem index out of range");
+  const Cls& C = pl.cls[pl.prob_cls[prob]];
+  const ndmg::Geom& g = C.lv.back().g;
+  info[0] = C.vec_off + (int64_t)pl.prob_pos[prob] * C.nrhs * C.vlen;
+  info[1] = C.vlen;
+  info[2] = g.n;
+  info[3] = g.P;
+  info[4] = g.B;
+  info[5] = (int64_t)C.lv.size();
   return NDMG_OK;
 }
 
 int ndmg_layout(const ndmg_ctx* c, int level, int64_t info[6]) {
   if (int rc = check_ctx(c)) return rc;
+  if (int rc = one_class(c)) return rc;
   if (!info) return fail(NDMG_EINVAL, "null info");
-  const int nl = (int)c->plan.lv.size();
+  const Cls& C = c->plan.cls[0];
+  const int nl = (int)C.lv.size();
   if (level < 0) level += nl;
   if (level < 0 || level >= nl) return fail(NDMG_EINVAL, "level out of range");
-  const ndmg::Geom& g = c->plan.lv[level].g;
+  const ndmg::Geom& g = C.lv[level].g;
   info[0] = g.n;
   info[1] = g.P;
   info[2] = g.B;
@@ -487,90 +833,79 @@ int ndmg_layout(const ndmg_ctx* c, int level, int64_t info[6]) {
 int ndmg_apply(ndmg_ctx* c, const double* x, double* y) {
   if (int rc = check_ctx(c)) return rc;
   if (!x || !y) return fail(NDMG_EINVAL, "null vector");
-  NDMG_HIP(ndmg::launch_apply<double>(x, nullptr, y, c->plan.lv.back().g, c->plan.alpha, 0, c->st));
-  return NDMG_OK;
+  return for_classes(c, [&](size_t ci, hipStream_t st) {
+    Cls& C = c->plan.cls[ci];
+    NDMG_HIP(ndmg::launch_apply<double>(x + C.vec_off, nullptr, y + C.vec_off, C.lv.back().g,
+                                        class_batch(c, C, false), 0, st));
+    return NDMG_OK;
+  });
 }
 
 int ndmg_vcycle(ndmg_ctx* c, const double* g, double* z) {
   if (int rc = check_ctx(c)) return rc;
   if (!g || !z) return fail(NDMG_EINVAL, "null vector");
-  return precondition(c, g, z);
+  return for_classes(c, [&](size_t ci, hipStream_t st) {
+    Cls& C = c->plan.cls[ci];
+    return precondition(c, C, g + C.vec_off, z + C.vec_off, class_batch(c, C, false), st);
+  });
 }
 
 int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int* iters,
                    double* relres) {
   if (int rc = check_ctx(c)) return rc;
+  if (c->plan.npairs != 1)
+    return fail(NDMG_EINVAL, "the context holds several right-hand sides; use ndmg_pcg_solve_batched");
+  return ndmg_pcg_solve_batched(c, b, u, rtol, maxit, iters, relres);
+}
+
+int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit,
+                           int* iters, double* relres) {
+  if (int rc = check_ctx(c)) return rc;
   if (!b || !u) return fail(NDMG_EINVAL, "null vector");
   if (!(rtol >= 0.0) || maxit < 1) return fail(NDMG_EINVAL, "bad rtol or maxit");
-  Plan& pl = c->plan;
-  const ndmg::Geom& g = pl.lv.back().g;
-  const int64_t len = g.len;
-  double* r = at<double>(c, pl.o_pr);
-  double* z = at<double>(c, pl.o_pz);
-  double* p = at<double>(c, pl.o_pp);
-  double* part = at<double>(c, pl.o_part);
-  double* sc = at<double>(c, pl.o_scal);
-  if (iters) *iters = 0;
-  if (relres) *relres = 0.0;
-  NDMG_HIP(ndmg::launch_copy(b, r, len, c->st));
-  NDMG_HIP(ndmg::launch_zero(u, len, c->st));
-  NDMG_HIP(ndmg::launch_dot(b, b, nullptr, part, sc + S_BB, len, c->st));
-  NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, S_N * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  NDMG_HIP(hipStreamSynchronize(c->st));
-  const double bb = c->host_scal[S_BB];
-  if (!std::isfinite(bb)) return fail(NDMG_EBREAKDOWN, "non-finite right-hand side");
-  if (bb == 0.0) return NDMG_OK;
-  const double bnorm = std::sqrt(bb);
-  int rc = precondition(c, r, z);
-  if (rc) return rc;
-  int cur = S_RZA, nxt = S_RZB;
-  NDMG_HIP(ndmg::launch_dot(r, z, nullptr, part, sc + cur, len, c->st));
-  NDMG_HIP(ndmg::launch_copy(z, p, len, c->st));
-  if ((rc = cg_apply_update(c, u, cur))) return rc;
-  for (int it = 1; it <= maxit; ++it) {
-    if (it > 1) {
-      // z = B r, rz_new, p = z + beta p, q = A p, u += alpha p, r -= alpha q, r . r:
-      // replayed from a captured graph when the stream allows it
-      if ((rc = cg_body(c, u, cur, nxt))) return rc;
-      std::swap(cur, nxt);
-    }
-    NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, S_N * sizeof(double), hipMemcpyDeviceToHost, c->st));
-    NDMG_HIP(hipStreamSynchronize(c->st));
-    const double pq = c->host_scal[S_PQ], rr = c->host_scal[S_RR], rz = c->host_scal[cur];
-    if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rr) || !std::isfinite(rz)) {
-      if (iters) *iters = it;
-      if (relres) *relres = std::sqrt(rr) / bnorm;
-      return fail(NDMG_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite scalar)");
-    }
-    const double rel = std::sqrt(rr) / bnorm;
-    if (iters) *iters = it;
-    if (relres) *relres = rel;
-    if (rel <= rtol) return NDMG_OK;
-  }
-  return fail(NDMG_ENOCONV, "PCG reached maxit");
+  const int np = c->plan.npairs;
+  if (iters) std::fill(iters, iters + np, 0);
+  if (relres) std::fill(relres, relres + np, 0.0);
+  return pcg_all(c, b, u, rtol, maxit, iters, relres);
 }
 
 int ndmg_assemble_rhs(ndmg_ctx* c, const double* f, double* b) {
   if (int rc = check_ctx(c)) return rc;
   if (!f || !b) return fail(NDMG_EINVAL, "null pointer");
-  NDMG_HIP(ndmg::launch_assemble_rhs(f, b, c->plan.lv.back().g, c->st));
+  const Plan& pl = c->plan;
+  for (const Cls& C : pl.cls) {
+    const ndmg::Geom& g = C.lv.back().g;
+    const int64_t flen = 24LL * g.n * g.n * g.n;
+    // f follows the pair order of the batch vectors
+    const int64_t f0 = [&] {
+      int64_t s = 0;
+      for (const Cls& D : pl.cls) {
+        if (&D == &C) break;
+        s += 24LL * D.n * D.n * D.n * D.count;
+      }
+      return s;
+    }();
+    for (int pr = 0; pr < C.count; ++pr)
+      NDMG_HIP(ndmg::launch_assemble_rhs(f + f0 + pr * flen, b + C.vec_off + pr * C.vlen, g, c->st));
+  }
   return NDMG_OK;
 }
 
 int ndmg_curlcurl_form(ndmg_ctx* c, const double* lam, const double* u, int nrhs, double* out) {
   if (int rc = check_ctx(c)) return rc;
+  if (int rc = one_class(c)) return rc;
   if (!lam || !u || !out || nrhs < 0) return fail(NDMG_EINVAL, "bad arguments");
-  Plan& pl = c->plan;
-  const ndmg::Geom& g = pl.lv.back().g;
-  double* part = at<double>(c, pl.o_part);
-  double* sc = at<double>(c, pl.o_scal);
+  Cls& C = c->plan.cls[0];
+  const ndmg::Geom& g = C.lv.back().g;
+  double* part = at<double>(c, C.o_part);
+  double* sc = at<double>(c, C.o_scal);
   double total = 0.0;
   for (int r = 0; r < nrhs; ++r) {
     NDMG_HIP(ndmg::launch_curlcurl_form(lam + (int64_t)r * g.len, u + (int64_t)r * g.len, g, part,
-                                        sc + S_CC, c->st));
-    NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, S_N * sizeof(double), hipMemcpyDeviceToHost, c->st));
+                                        sc + kS_CC, c->st));
+    NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, kScalStride * sizeof(double), hipMemcpyDeviceToHost, c->st));
     NDMG_HIP(hipStreamSynchronize(c->st));
-    total += c->host_scal[S_CC];
+    total += c->host_scal[kS_CC];
   }
   *out = total;
   return NDMG_OK;
@@ -578,59 +913,66 @@ int ndmg_curlcurl_form(ndmg_ctx* c, const double* lam, const double* u, int nrhs
 
 int ndmg_export_factor(const ndmg_ctx* c, int level, int which, int type, double* buf, int* dims) {
   if (int rc = check_ctx(c)) return rc;
+  if (int rc = one_class(c)) return rc;
   if (!dims) return fail(NDMG_EINVAL, "null dims");
-  const int nl = (int)c->plan.lv.size();
+  const Cls& C = c->plan.cls[0];
+  const int nl = (int)C.lv.size();
   if (level < 0) level += nl;
   if (level < 1 || level >= nl) return fail(NDMG_EINVAL, "level must be a smoothed level");
-  const LevelHost& L = c->plan.lv[level];
+  if (which != 0 && which != 1) return fail(NDMG_EINVAL, "which must be 0 or 1");
+  if (which == 1 && (type < 0 || type > 26)) return fail(NDMG_EINVAL, "type out of range");
+  const LevelHost& L = C.lv[level];
+  dims[0] = which == 0 ? L.sub.nI : L.sub.npad;
+  if (!buf) return NDMG_OK;
+  // rebuilt in FP64 for the first problem (the device copy is in the working precision)
+  ndmg::LevelFactors fac;
+  std::string err;
+  if (!ndmg::build_level_factors(L.g.h, C.alpha[0], L.sub, c->plan.opts.boundary_patches != 0, &fac, &err))
+    return fail(NDMG_EINVAL, err);
   if (which == 0) {
-    dims[0] = L.sub.nI;
-    if (buf) std::memcpy(buf, L.fac.ATinv.data(), L.fac.ATinv.size() * sizeof(double));
-    return NDMG_OK;
-  }
-  if (which == 1) {
-    if (type < 0 || type > 26) return fail(NDMG_EINVAL, "type out of range");
+    std::memcpy(buf, fac.ATinv.data(), fac.ATinv.size() * sizeof(double));
+  } else {
     const int np = L.sub.npad;
-    dims[0] = np;
-    if (buf)
-      std::memcpy(buf, L.fac.Sinv.data() + (size_t)type * np * np, (size_t)np * np * sizeof(double));
-    return NDMG_OK;
+    std::memcpy(buf, fac.Sinv.data() + (size_t)type * np * np, (size_t)np * np * sizeof(double));
   }
-  return fail(NDMG_EINVAL, "which must be 0 or 1");
+  return NDMG_OK;
 }
 
 int ndmg_level_op(ndmg_ctx* c, int level, int op, const double* in, double* out) {
   if (int rc = check_ctx(c)) return rc;
+  if (int rc = one_class(c)) return rc;
   if (!in || !out) return fail(NDMG_EINVAL, "null vector");
   Plan& pl = c->plan;
   if (pl.elem != 8) return fail(NDMG_EINVAL, "level operations need an FP64 context");
-  const int nl = (int)pl.lv.size();
+  Cls& C = pl.cls[0];
+  const int nl = (int)C.lv.size();
   if (level < 0) level += nl;
   if (level < 0 || level >= nl) return fail(NDMG_EINVAL, "level out of range");
-  LevelHost& L = pl.lv[level];
+  LevelHost& L = C.lv[level];
+  const ndmg::Bat bt = class_batch(c, C, false);
   switch (op) {
     case NDMG_OP_APPLY:
-      NDMG_HIP(ndmg::launch_apply<double>(in, nullptr, out, L.g, pl.alpha, 0, c->st));
+      NDMG_HIP(ndmg::launch_apply<double>(in, nullptr, out, L.g, bt, 0, c->st));
       return NDMG_OK;
     case NDMG_OP_SMOOTH: {
       if (!L.smoothed) return fail(NDMG_EINVAL, "the coarsest level has no smoother");
       auto P = level_ptrs<double>(c, L);
       auto D = level_dsub(c, L);
-      NDMG_HIP(ndmg::launch_smooth<double>(in, out, P, D, L.g, pl.alpha, pl.opts.eta, 1, c->st));
+      NDMG_HIP(ndmg::launch_smooth<double>(in, out, P, D, L.g, bt, pl.opts.eta, 1, c->st));
       return NDMG_OK;
     }
     case NDMG_OP_RESTRICT:
       if (level < 1) return fail(NDMG_EINVAL, "restriction needs level >= 1");
-      NDMG_HIP(ndmg::launch_restrict<double>(in, out, L.g, pl.lv[level - 1].g, c->st));
+      NDMG_HIP(ndmg::launch_restrict<double>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
       return NDMG_OK;
     case NDMG_OP_PROLONG:
       if (level < 1) return fail(NDMG_EINVAL, "prolongation needs level >= 1");
-      NDMG_HIP(ndmg::launch_prolong_add<double>(in, out, L.g, pl.lv[level - 1].g, c->st));
+      NDMG_HIP(ndmg::launch_prolong_add<double>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
       return NDMG_OK;
     case NDMG_OP_COARSE:
       if (level != 0) return fail(NDMG_EINVAL, "coarse solve needs level 0");
       NDMG_HIP(ndmg::launch_coarse<double>(in, out, at<double>(c, L.o_A0), at<int64_t>(c, L.o_map),
-                                           (int)L.map.size(), c->st));
+                                           (int)L.map.size(), L.g.len, bt, c->st));
       return NDMG_OK;
     default:
       return fail(NDMG_EINVAL, "unknown operation");
@@ -639,8 +981,7 @@ int ndmg_level_op(ndmg_ctx* c, int level, int op, const double* in, double* out)
 
 int ndmg_destroy(ndmg_ctx* c) {
   if (!c) return NDMG_OK;
-  drop_graphs(c);
-  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  release(c);
   delete c;
   return NDMG_OK;
 }

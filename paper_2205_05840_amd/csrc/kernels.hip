@@ -12,7 +12,12 @@
 //   (C^T G)_a(p) = G_b(p - e_c) - G_b(p) - G_c(p - e_b) + G_c(p).
 // All reads of an interior edge's stencil stay inside [0, n]^3 of the padded layout and
 // boundary entries are zero, so no bounds checks are needed inside the stencil.
+//
+// Batching: see kernels.hpp.  Grids carry the pair index in blockIdx.x (node and
+// subdomain grids, as pair * blocks_per_pair + block) or in blockIdx.y (1-D grids).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -23,6 +28,8 @@ namespace {
 __device__ __forceinline__ int64_t lin(const DGeom& g, int i, int j, int k) {
   return (int64_t)k * g.plane + (int64_t)j * g.P + i;
 }
+
+__device__ __forceinline__ int64_t vlen(const DGeom& g) { return 3 * g.B; }
 
 // Edge of direction d at (i, j, k) is an unknown: cell index along d in [0, n),
 // node indices across in [1, n-1].
@@ -35,6 +42,10 @@ __device__ __forceinline__ bool is_unknown(const DGeom& g, int d, int i, int j, 
     else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
   }
   return ok;
+}
+
+__device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
+  return bt.act != nullptr && bt.act[pair] == 0;
 }
 
 template <typename T>
@@ -58,14 +69,20 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, i
 }
 
 // ---------------------------------------------------------------------------------
-// operator apply / residual
+// operator apply / residual (one thread per node position, small levels)
 // ---------------------------------------------------------------------------------
 template <typename T, int MODE>
 __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y, DGeom g, T ah, T h3) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                              T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
-  if (i > g.n) return;
+  if (i > g.n || inactive(bt, pair)) return;
+  const int64_t off = (int64_t)pair * vlen(g);
+  x += off;
+  y += off;
+  if (MODE == 1) b += off;
+  const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
   const int64_t p = lin(g, i, j, k);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -83,10 +100,13 @@ __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* 
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
-                                                 DGeom f, DGeom c) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 DGeom f, DGeom c, Bat bt, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int I = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int J = blockIdx.y, K = blockIdx.z;
-  if (I > c.n) return;
+  if (I > c.n || inactive(bt, pair)) return;
+  rf += (int64_t)pair * vlen(f);
+  gc += (int64_t)pair * vlen(c);
   const int64_t stf[3] = {1, (int64_t)f.P, f.plane};
   const int64_t pc = lin(c, I, J, K);
   const int64_t pf = lin(f, 2 * I, 2 * J, 2 * K);
@@ -113,10 +133,13 @@ __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
-                                                    DGeom f, DGeom c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                    DGeom f, DGeom c, Bat bt, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
-  if (i > f.n) return;
+  if (i > f.n || inactive(bt, pair)) return;
+  ec += (int64_t)pair * vlen(c);
+  zf += (int64_t)pair * vlen(f);
   const int o[3] = {i, j, k};
   const int64_t stc[3] = {1, (int64_t)c.P, c.plane};
   const int64_t pf = lin(f, i, j, k);
@@ -145,27 +168,29 @@ __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T*
 // Interior unknowns of the subdomain with lower fine node (2a, 2b, 2c), in the order of
 // interior_dofs(2): x-edges (0,1,1), (1,1,1); y-edges (1,0,1), (1,1,1);
 // z-edges (1,1,0), (1,1,1).
-__device__ __forceinline__ void interior_offsets_s2(const DGeom& g, int64_t base, int64_t off[6],
-                                                    int dir[6]) {
+__device__ __forceinline__ void interior_offsets_s2(const DGeom& g, int64_t base, int64_t off[6]) {
   const int64_t sx = 1, sy = g.P, sz = g.plane;
-  off[0] = 0 * g.B + base + sy + sz;           dir[0] = 0;
-  off[1] = 0 * g.B + base + sx + sy + sz;      dir[1] = 0;
-  off[2] = 1 * g.B + base + sx + sz;           dir[2] = 1;
-  off[3] = 1 * g.B + base + sx + sy + sz;      dir[3] = 1;
-  off[4] = 2 * g.B + base + sx + sy;           dir[4] = 2;
-  off[5] = 2 * g.B + base + sx + sy + sz;      dir[5] = 2;
+  off[0] = 0 * g.B + base + sy + sz;
+  off[1] = 0 * g.B + base + sx + sy + sz;
+  off[2] = 1 * g.B + base + sx + sz;
+  off[3] = 1 * g.B + base + sx + sy + sz;
+  off[4] = 2 * g.B + base + sx + sy;
+  off[5] = 2 * g.B + base + sx + sy + sz;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, T* __restrict__ zi,
                                                        const T* __restrict__ ATinv, DGeom g,
-                                                       int nH) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+                                                       int nH, Bat bt, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH) return;
+  if (a >= nH || inactive(bt, pair)) return;
+  r += (int64_t)pair * vlen(g);
+  zi += (int64_t)pair * vlen(g);
+  ATinv += (int64_t)(pair / bt.nrhs) * 36;
   int64_t off[6];
-  int dir[6];
-  interior_offsets_s2(g, lin(g, 2 * a, 2 * b, 2 * c), off, dir);
+  interior_offsets_s2(g, lin(g, 2 * a, 2 * b, 2 * c), off);
   T rv[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) rv[q] = r[off[q]];
@@ -178,34 +203,12 @@ __global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, 
   }
 }
 
-// gg = r - A zi on interface unknowns (zi vanishes off subdomain interiors).
-template <typename T, int S>
-__global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, const T* __restrict__ zi,
-                                                    T* __restrict__ gg, DGeom g, T ah, T h3) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i > g.n) return;
-  const int o[3] = {i, j, k};
-  const int64_t p = lin(g, i, j, k);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (!is_unknown(g, d, i, j, k)) continue;
-    const int b = (d + 1) % 3, c = (d + 2) % 3;
-    if ((o[b] % S) != 0 && (o[c] % S) != 0) continue;   // subdomain interior
-    gg[d * g.B + p] = r[d * g.B + p] - apply_at(zi, g, d, p, ah, h3);
-  }
-}
-
-// Vertex patch solves y_V = S_type^{-1} g|Gamma_V on MFMA.  A workgroup (4 waves) takes
-// NCOL = 64 vertices of one segment (one patch type); wave w owns columns
-// [16 w, 16 w + 16) and all npad rows.  Gathered g values are staged in LDS as
-// Gs[slot][col]; S^{-1} (row-major npad x npad) is read from global memory (L2).
-template <typename T>
-struct Mfma;
-
 // Operands of the 16x16x4 MFMAs: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result register q of lane l holds D[row(l / 16, q)][l % 16], where (measured on
 // gfx950) row = 4 q + l / 16 for the f64 instruction and 4 (l / 16) + q for f32.
+template <typename T>
+struct Mfma;
+
 template <>
 struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
@@ -224,94 +227,16 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
 };
 
+// Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
+// segment (one patch type) of one pair (blockIdx.y).  S_type^{-1} is staged in LDS; wave w
+// then walks its gpw groups of 16 vertices: lane l gathers the B-operand column values
+// g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (prefetching the next
+// group), reads the A-operand fragment S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and
+// accumulates the 16 x 16 output tile per mb; results go to the slot-major Y.
 template <typename T, int S>
 __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* __restrict__ Y,
-                                                  const T* __restrict__ Sinv, DGeom g, DSub sub) {
-  constexpr int NG = 6 * S * (4 * S - 3);
-  constexpr int NPAD = (NG + 15) / 16 * 16;
-  constexpr int NCOL = 64;
-  __shared__ T Gs[NPAD * NCOL];
-  __shared__ int64_t cbase[NCOL];   // linear position of the vertex's fine node
-  __shared__ int cvx[NCOL], cvy[NCOL], cvz[NCOL];
-  __shared__ int64_t crow[NCOL];    // Y row, -1 for an unused column
-
-  const int tid = threadIdx.x;
-  const int chunk = blockIdx.x;
-  const int seg = sub.chunks[2 * chunk];
-  const int first = sub.chunks[2 * chunk + 1];
-  const int* sg = sub.segs + 8 * seg;
-  const int type = sg[0];
-  const int nv = sub.nH + 1;
-  if (tid < NCOL) {
-    const int v = first + tid;
-    if (v < sg[7]) {
-      const int vx = sg[1] + v % sg[4];
-      const int vy = sg[2] + (v / sg[4]) % sg[5];
-      const int vz = sg[3] + v / (sg[4] * sg[5]);
-      cvx[tid] = vx; cvy[tid] = vy; cvz[tid] = vz;
-      cbase[tid] = lin(g, S * vx, S * vy, S * vz);
-      crow[tid] = ((int64_t)vz * nv + vy) * nv + vx;
-    } else {
-      cvx[tid] = cvy[tid] = cvz[tid] = 0;
-      cbase[tid] = 0;
-      crow[tid] = -1;
-    }
-  }
-  __syncthreads();
-  // gather
-  for (int e = tid; e < NPAD * NCOL; e += 256) {
-    const int slot = e / NCOL, col = e % NCOL;
-    T v = T(0);
-    if (slot < NG && crow[col] >= 0) {
-      const int* sl = sub.slots + 4 * slot;
-      const int d = sl[0];
-      const int px = S * cvx[col] + sl[1], py = S * cvy[col] + sl[2], pz = S * cvz[col] + sl[3];
-      // an edge exists if its cell index along d is in [0, n) and node indices across
-      // are in [1, n-1]; absent slots of boundary patches read as zero
-      const int o[3] = {px, py, pz};
-      bool ok = true;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        if (ax == d) ok = ok && (o[ax] >= 0 && o[ax] < g.n);
-        else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
-      }
-      if (ok) v = gg[d * g.B + lin(g, px, py, pz)];
-    }
-    Gs[slot * NCOL + col] = v;
-  }
-  __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int col = wave * 16 + lr;
-  const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
-  const int64_t row = crow[col];
-  const int64_t NV = (int64_t)nv * nv * nv;
-  for (int mb = 0; mb < NPAD / 16; ++mb) {
-    typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-    const T* __restrict__ Arow = Sm + (int64_t)(16 * mb + lr) * NPAD;
-    for (int ks = 0; ks < NPAD / 4; ++ks) {
-      const T av = Arow[4 * ks + lk];
-      const T bv = Gs[(4 * ks + lk) * NCOL + col];
-      acc = Mfma<T>::mma(av, bv, acc);
-    }
-    // Y is slot-major: Y[slot * NV + vertex]
-    if (row >= 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Y[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV + row] = acc[q];
-    }
-  }
-}
-
-// Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
-// segment (one patch type).  S_type^{-1} is staged in LDS; wave w then walks its gpw
-// groups of 16 vertices: lane l gathers the B-operand column values g[slot = 4 ks + l / 16]
-// of vertex l % 16 straight from memory (prefetching the next group), reads the A-operand
-// fragment S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and accumulates the 16 x 16
-// output tile per mb; results go to the slot-major Y.
-template <typename T, int S>
-__global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, T* __restrict__ Y,
-                                                      const T* __restrict__ Sinv, DGeom g, DSub sub,
-                                                      int gpw) {
+                                                  const T* __restrict__ Sinv, DGeom g, DSub sub,
+                                                  Bat bt) {
   constexpr int NG = 6 * S * (4 * S - 3);
   constexpr int NPAD = (NG + 15) / 16 * 16;
   constexpr int NKS = NPAD / 4, NMB = NPAD / 16;
@@ -319,14 +244,20 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
   __shared__ T sA[NPAD * LDA];
   __shared__ int sslot[NPAD][4];
   __shared__ int64_t soff[NPAD];
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
   const int tid = threadIdx.x;
+  const int nv = sub.nH + 1;
+  const int64_t NV = (int64_t)nv * nv * nv;
+  gg += (int64_t)pair * vlen(g);
+  Y += (int64_t)pair * NV * NPAD;
   const int chunk = blockIdx.x;
   const int seg = sub.chunks[2 * chunk];
   const int first = sub.chunks[2 * chunk + 1];
   const int* sg = sub.segs + 8 * seg;
   const int type = sg[0], count = sg[7];
   const bool inner = (type == 13);
-  const T* __restrict__ Sm = Sinv + (int64_t)type * NPAD * NPAD;
+  const T* __restrict__ Sm = Sinv + ((int64_t)(pair / bt.nrhs) * 27 + type) * NPAD * NPAD;
   for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[(e / NPAD) * LDA + e % NPAD] = Sm[e];
   for (int e = tid; e < NPAD; e += blockDim.x) {
     if (e < NG) {
@@ -339,8 +270,7 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
     }
   }
   __syncthreads();
-  const int nv = sub.nH + 1;
-  const int64_t NV = (int64_t)nv * nv * nv;
+  const int gpw = sub.gpw;
   const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int wfirst = first + wave * gpw * 16;
@@ -412,18 +342,25 @@ __global__ void __launch_bounds__(256) k_sm_patch_reg(const T* __restrict__ gg, 
 template <typename T, int S>
 __global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
                                                  T* __restrict__ z, DGeom g, DSub sub, T eta,
-                                                 int assign) {
+                                                 int assign, Bat bt, int nbx) {
   constexpr int W = 2 * S + 1;
+  constexpr int NG = 6 * S * (4 * S - 3);
+  constexpr int NPAD = (NG + 15) / 16 * 16;
   __shared__ int slut[3 * W * W * W];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
   for (int e = threadIdx.x; e < 3 * W * W * W; e += blockDim.x) slut[e] = sub.lut[e];
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
   if (i >= g.n) return;   // i = n is never an unknown
-  const int o[3] = {i, j, k};
-  const int64_t p = lin(g, i, j, k);
   const int nv = sub.nH + 1;
   const int64_t NV = (int64_t)nv * nv * nv;
+  Y += (int64_t)pair * NV * NPAD;
+  w += (int64_t)pair * vlen(g);
+  z += (int64_t)pair * vlen(g);
+  const int o[3] = {i, j, k};
+  const int64_t p = lin(g, i, j, k);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (!is_unknown(g, d, i, j, k)) continue;
@@ -463,15 +400,21 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
                                                      T* __restrict__ z, const T* __restrict__ XT,
                                                      const int64_t* __restrict__ bofs, DGeom g,
-                                                     int nH, T eta, int assign) {
+                                                     int nH, T eta, int assign, Bat bt, int nbx) {
   __shared__ T sX[6 * 48];
   __shared__ int64_t sofs[48];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
+  XT += (int64_t)(pair / bt.nrhs) * 6 * 48;
   for (int e = threadIdx.x; e < 6 * 48; e += blockDim.x) sX[e] = XT[e];
   for (int e = threadIdx.x; e < 48; e += blockDim.x) sofs[e] = bofs[e];
   __syncthreads();
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, c = blockIdx.z;
   if (a >= nH) return;
+  w += (int64_t)pair * vlen(g);
+  zi += (int64_t)pair * vlen(g);
+  z += (int64_t)pair * vlen(g);
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
   T wv[48];
 #pragma unroll
@@ -493,13 +436,19 @@ __global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, co
 }
 
 // ---------------------------------------------------------------------------------
-// coarsest level: dense inverse
+// coarsest level: dense inverse (one workgroup per pair)
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __restrict__ z,
                                                 const T* __restrict__ A0inv,
-                                                const int64_t* __restrict__ map, int N0) {
+                                                const int64_t* __restrict__ map, int N0, int64_t len,
+                                                Bat bt) {
   __shared__ T gl[1024];
+  const int pair = blockIdx.x;
+  if (inactive(bt, pair)) return;
+  g += (int64_t)pair * len;
+  z += (int64_t)pair * len;
+  A0inv += (int64_t)(pair / bt.nrhs) * N0 * N0;
   for (int i = threadIdx.x; i < N0; i += blockDim.x) gl[i] = g[map[i]];
   __syncthreads();
   for (int i = threadIdx.x; i < N0; i += blockDim.x) {
@@ -510,7 +459,11 @@ __global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __re
 }
 
 template <typename Tin, typename Tout>
-__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t len) {
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  in += (int64_t)pair * len;
+  out += (int64_t)pair * len;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x)
     out[e] = (Tout)in[e];
@@ -520,7 +473,7 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, in
 // reductions (FP64)
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  // wavefront reduction by shuffles, then across the 4 waves of a 256-thread block
+  // wavefront reduction by shuffles, then across the waves of the block
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -536,8 +489,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const double* __restrict__ b,
                                              const double* __restrict__ c, double* __restrict__ part,
-                                             int64_t len) {
+                                             int64_t pstride, int64_t len, Bat bt) {
   __shared__ double sh[8];
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  a += (int64_t)pair * len;
+  b += (int64_t)pair * len;
+  if (c) c += (int64_t)pair * len;
+  part += (int64_t)pair * pstride;
   double s1 = 0.0, s2 = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -554,8 +513,13 @@ __global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const
 }
 
 __global__ void __launch_bounds__(256) k_final(const double* __restrict__ part, int nparts,
-                                               int nout, double* __restrict__ out) {
+                                               int64_t pstride, int nout, double* __restrict__ out,
+                                               Bat bt) {
   __shared__ double sh[8];
+  const int pair = blockIdx.x;
+  if (inactive(bt, pair)) return;
+  part += (int64_t)pair * pstride;
+  out += (int64_t)pair * kScalStride;
   for (int o = 0; o < nout; ++o) {
     double s = 0.0;
     for (int e = threadIdx.x; e < nparts; e += blockDim.x) s += part[o * nparts + e];
@@ -569,8 +533,17 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
                                                    const double* __restrict__ q,
                                                    const double* __restrict__ scal, int i_num,
                                                    int i_den, double* __restrict__ part,
-                                                   int64_t len) {
+                                                   int64_t pstride, int64_t len, Bat bt) {
   __shared__ double sh[8];
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  const int64_t off = (int64_t)pair * len;
+  u += off;
+  r += off;
+  p += off;
+  q += off;
+  scal += (int64_t)pair * kScalStride;
+  part += (int64_t)pair * pstride;
   const double alpha = scal[i_num] / scal[i_den];
   double s = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
@@ -587,7 +560,12 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
 __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const double* __restrict__ z,
                                                       const double* __restrict__ scal, int i_num,
                                                       int i_den, int flexible, int i_zq, int i_an,
-                                                      int i_ad, int64_t len) {
+                                                      int i_ad, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  p += (int64_t)pair * len;
+  z += (int64_t)pair * len;
+  scal += (int64_t)pair * kScalStride;
   double beta;
   if (flexible) beta = -(scal[i_an] / scal[i_ad]) * scal[i_zq] / scal[i_den];
   else beta = scal[i_num] / scal[i_den];
@@ -596,13 +574,76 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
     p[e] = z[e] + beta * p[e];
 }
 
-__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t len) {
+__global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, int* __restrict__ act,
+                                                   int* __restrict__ iters, int* __restrict__ status,
+                                                   int count, double rtol) {
+  for (int p = threadIdx.x; p < count; p += blockDim.x) {
+    double* s = scal + (int64_t)p * kScalStride;
+    const double bb = s[kS_BB];
+    s[kS_TOL] = rtol;
+    s[kS_REL] = 0.0;
+    iters[p] = 0;
+    if (!isfinite(bb)) {
+      act[p] = 0;
+      status[p] = kPairBroken;
+    } else if (bb == 0.0) {
+      act[p] = 0;
+      status[p] = kPairDone;
+    } else {
+      act[p] = 1;
+      status[p] = kPairRun;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_pcg_check(double* __restrict__ scal, int* __restrict__ act,
+                                                    int* __restrict__ iters, int* __restrict__ status,
+                                                    int count, int i_rz, int* __restrict__ nact) {
+  __shared__ int sh[16];
+  int c = 0;
+  for (int p = threadIdx.x; p < count; p += blockDim.x) {
+    if (act[p] == 0) continue;
+    double* s = scal + (int64_t)p * kScalStride;
+    iters[p] += 1;
+    const double pq = s[kS_PQ], rr = s[kS_RR], rz = s[i_rz];
+    const double rel = sqrt(rr) / sqrt(s[kS_BB]);
+    s[kS_REL] = rel;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz)) {
+      act[p] = 0;
+      status[p] = kPairBroken;
+    } else if (rel <= s[kS_TOL]) {
+      act[p] = 0;
+      status[p] = kPairDone;
+    } else {
+      ++c;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    nact[0] = t;
+  }
+}
+
+__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  x += (int64_t)pair * len;
+  y += (int64_t)pair * len;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x)
     y[e] = x[e];
 }
 
-__global__ void k_zero(double* __restrict__ y, int64_t len) {
+__global__ void k_zero(double* __restrict__ y, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  y += (int64_t)pair * len;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x)
     y[e] = 0.0;
@@ -669,8 +710,19 @@ __global__ void __launch_bounds__(64) k_curlcurl_form(const double* __restrict__
     part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
-inline dim3 node_grid(const Geom& g) {
-  return dim3((unsigned)((g.n + 1 + 63) / 64), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
+// node grid: x = blocks per pair * pairs, y = j, z = k
+inline dim3 node_grid(const Geom& g, int nbx, int count) {
+  return dim3((unsigned)(nbx * count), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
+}
+
+inline int nbx64(int n) { return (n + 1 + 63) / 64; }
+
+// blocks per pair of the grid-stride vector kernels: enough for a level, fewer for many pairs
+inline unsigned vec_blocks(int64_t len, int count, unsigned cap) {
+  const int64_t want = (len + 255) / 256;
+  unsigned b = (unsigned)std::min<int64_t>(want, (int64_t)cap);
+  if (count > 1) b = std::min<unsigned>(b, std::max<unsigned>(4u, 4096u / (unsigned)count));
+  return std::max<unsigned>(b, 1u);
 }
 
 }  // namespace
@@ -679,143 +731,176 @@ inline dim3 node_grid(const Geom& g) {
 // launchers
 // ---------------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
+hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st) {
   if (g.n > stencil_min_n() && g.n <= stencil_max_n())
-    return launch_stencil<T>(x, b, y, g, alpha, mode, nullptr, nullptr, st);
-  const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
+    return launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, st);
+  const int nbx = nbx64(g.n);
   if (mode == 0)
-    hipLaunchKernelGGL((k_apply<T, 0>), node_grid(g), dim3(64), 0, st, x, b, y, dgeom(g), ah, h3);
+    hipLaunchKernelGGL((k_apply<T, 0>), node_grid(g, nbx, bt.count), dim3(64), 0, st, x, b, y, dgeom(g),
+                       bt, g.h, nbx);
   else
-    hipLaunchKernelGGL((k_apply<T, 1>), node_grid(g), dim3(64), 0, st, x, b, y, dgeom(g), ah, h3);
+    hipLaunchKernelGGL((k_apply<T, 1>), node_grid(g, nbx, bt.count), dim3(64), 0, st, x, b, y, dgeom(g),
+                       bt, g.h, nbx);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, hipStream_t st) {
-  hipLaunchKernelGGL((k_restrict<T>), node_grid(c), dim3(64), 0, st, rf, gc, dgeom(f), dgeom(c));
+hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, const Bat& bt,
+                           hipStream_t st) {
+  const int nbx = nbx64(c.n);
+  hipLaunchKernelGGL((k_restrict<T>), node_grid(c, nbx, bt.count), dim3(64), 0, st, rf, gc, dgeom(f),
+                     dgeom(c), bt, nbx);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, hipStream_t st) {
-  hipLaunchKernelGGL((k_prolong_add<T>), node_grid(f), dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c));
+hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
+                              hipStream_t st) {
+  const int nbx = nbx64(f.n);
+  hipLaunchKernelGGL((k_prolong_add<T>), node_grid(f, nbx, bt.count), dim3(64), 0, st, ec, zf, dgeom(f),
+                     dgeom(c), bt, nbx);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
-                         const Geom& g, double alpha, double eta, int assign, hipStream_t st) {
+                         const Geom& g, const Bat& bt, double eta, int assign, hipStream_t st) {
   if (sub.s != 2) return hipErrorInvalidValue;
   const DGeom dg = dgeom(g);
-  const dim3 eg((unsigned)((sub.nH + 63) / 64), (unsigned)sub.nH, (unsigned)sub.nH);
-  hipLaunchKernelGGL((k_sm_interior_s2<T>), eg, dim3(64), 0, st, r, L.zi, L.ATinv, dg, sub.nH);
+  const int nbs = (sub.nH + 63) / 64;
+  const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, (unsigned)sub.nH);
+  hipLaunchKernelGGL((k_sm_interior_s2<T>), eg, dim3(64), 0, st, r, L.zi, L.ATinv, dg, sub.nH, bt, nbs);
   // condensed interface residual gg = r - A zi (zi vanishes off subdomain interiors;
   // the interior entries of gg come out as rounding-level values and are never read)
-  hipError_t e = launch_apply<T>(L.zi, r, L.gg, g, alpha, 1, st);
+  hipError_t e = launch_apply<T>(L.zi, r, L.gg, g, bt, 1, st);
   if (e != hipSuccess) return e;
   if (sub.nchunks > 0)
-    hipLaunchKernelGGL((k_sm_patch_reg<T, 2>), dim3((unsigned)sub.nchunks), dim3(256), 0, st, L.gg, L.Y,
-                       L.Sinv, dg, sub, sub.gpw);
+    hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks, (unsigned)bt.count), dim3(256), 0,
+                       st, L.gg, L.Y, L.Sinv, dg, sub, bt);
   {
     const int bx = (g.n <= 64) ? 64 : 128;
-    const dim3 pg((unsigned)((g.n + bx - 1) / bx), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
-    hipLaunchKernelGGL((k_sm_pull<T, 2>), pg, dim3(bx), 0, st, L.Y, L.w, z, dg, sub, (T)eta, assign);
+    const int nbp = (g.n + bx - 1) / bx;
+    const dim3 pg((unsigned)(nbp * bt.count), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
+    hipLaunchKernelGGL((k_sm_pull<T, 2>), pg, dim3(bx), 0, st, L.Y, L.w, z, dg, sub, (T)eta, assign, bt,
+                       nbp);
   }
-  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.XT, L.bofs, dg, sub.nH,
-                     (T)eta, assign);
+  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.XT, sub.bofs, dg, sub.nH,
+                     (T)eta, assign, bt, nbs);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,
-                         hipStream_t st) {
+                         int64_t len, const Bat& bt, hipStream_t st) {
   if (N0 > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, st, g, z, A0inv, map, N0);
+  hipLaunchKernelGGL((k_coarse<T>), dim3((unsigned)bt.count), dim3(256), 0, st, g, z, A0inv, map, N0,
+                     len, bt);
   return hipGetLastError();
 }
 
 template <typename Tin, typename Tout>
-hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(2048), dim3(256), 0, st, in, out, len);
+hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count),
+                     dim3(256), 0, st, in, out, len, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_dot(const double* a, const double* b, const double* c, double* partial,
-                      double* out, int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot, dim3(kRedBlocks), dim3(256), 0, st, a, b, c, partial, len);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, kRedBlocks, c ? 2 : 1, out);
+hipError_t launch_dot(const double* a, const double* b, const double* c, double* part,
+                      int64_t pstride, double* out, int64_t len, const Bat& bt, hipStream_t st) {
+  const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
+  hipLaunchKernelGGL(k_dot, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, a, b, c, part, pstride, len,
+                     bt);
+  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride,
+                     c ? 2 : 1, out, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_final(const double* part, int nparts, int nout, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, part, nparts, nout, out);
+hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nout, double* out,
+                        const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, nparts, pstride, nout, out,
+                     bt);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q,
-                            const double* scal, int i_num, int i_den, double* partial,
-                            double* out, int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(256), 0, st, u, r, p, q, scal, i_num, i_den,
-                     partial, len);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, kRedBlocks, 1, out);
+hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
+                            int i_num, int i_den, int i_out, double* part, int64_t pstride,
+                            int64_t len, const Bat& bt, hipStream_t st) {
+  const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal, i_num,
+                     i_den, part, pstride, len, bt);
+  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, 1,
+                     scal + i_out, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_direction(double* p, const double* z, const double* scal, int i_num,
                                int i_den, int flexible, int i_zq, int i_an, int i_ad,
-                               int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(2048), dim3(256), 0, st, p, z, scal, i_num, i_den, flexible,
-                     i_zq, i_an, i_ad, len);
+                               int64_t len, const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256),
+                     0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, len, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const double* x, double* y, int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, st, x, y, len);
+hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1024), 0, st, scal, act, iters, status, count, rtol);
   return hipGetLastError();
 }
 
-hipError_t launch_zero(double* y, int64_t len, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, y, len);
+hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
+                            int* nact, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1024), 0, st, scal, act, iters, status, count, i_rz,
+                     nact);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0, st, x,
+                     y, len, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0, st, y,
+                     len, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st) {
   const double w8 = g.h * g.h * g.h / 8.0;
-  hipLaunchKernelGGL(k_assemble_rhs, node_grid(g), dim3(64), 0, st, f, b, dgeom(g), w8);
+  hipLaunchKernelGGL(k_assemble_rhs, node_grid(g, nbx64(g.n), 1), dim3(64), 0, st, f, b, dgeom(g), w8);
   return hipGetLastError();
 }
 
 hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,
                                 double* partial, double* out, hipStream_t st) {
-  const dim3 grid = node_grid(g);
+  const dim3 grid = node_grid(g, nbx64(g.n), 1);
   const int nparts = (int)(grid.x * grid.y * grid.z);
   hipLaunchKernelGGL(k_curlcurl_form, grid, dim3(64), 0, st, lam, u, partial, dgeom(g), g.h);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, nparts, 1, out);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, nparts, (int64_t)0, 1, out,
+                     Bat{1, 1, nullptr, nullptr});
   return hipGetLastError();
 }
 
 // explicit instantiations
-template hipError_t launch_apply<double>(const double*, const double*, double*, const Geom&, double,
-                                         int, hipStream_t);
-template hipError_t launch_apply<float>(const float*, const float*, float*, const Geom&, double, int,
-                                        hipStream_t);
-template hipError_t launch_restrict<double>(const double*, double*, const Geom&, const Geom&,
-                                            hipStream_t);
-template hipError_t launch_restrict<float>(const float*, float*, const Geom&, const Geom&, hipStream_t);
-template hipError_t launch_prolong_add<double>(const double*, double*, const Geom&, const Geom&,
-                                               hipStream_t);
-template hipError_t launch_prolong_add<float>(const float*, float*, const Geom&, const Geom&,
-                                              hipStream_t);
-template hipError_t launch_smooth<double>(const double*, double*, const LevelPtrs<double>&,
-                                          const DSub&, const Geom&, double, double, int, hipStream_t);
-template hipError_t launch_smooth<float>(const float*, float*, const LevelPtrs<float>&, const DSub&,
-                                         const Geom&, double, double, int, hipStream_t);
-template hipError_t launch_coarse<double>(const double*, double*, const double*, const int64_t*, int,
-                                          hipStream_t);
-template hipError_t launch_coarse<float>(const float*, float*, const float*, const int64_t*, int,
-                                         hipStream_t);
-template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
-template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+#define NDMG_INST(T)                                                                              \
+  template hipError_t launch_apply<T>(const T*, const T*, T*, const Geom&, const Bat&, int,       \
+                                      hipStream_t);                                               \
+  template hipError_t launch_restrict<T>(const T*, T*, const Geom&, const Geom&, const Bat&,      \
+                                         hipStream_t);                                            \
+  template hipError_t launch_prolong_add<T>(const T*, T*, const Geom&, const Geom&, const Bat&,   \
+                                            hipStream_t);                                         \
+  template hipError_t launch_smooth<T>(const T*, T*, const LevelPtrs<T>&, const DSub&,            \
+                                       const Geom&, const Bat&, double, int, hipStream_t);       \
+  template hipError_t launch_coarse<T>(const T*, T*, const T*, const int64_t*, int, int64_t,      \
+                                       const Bat&, hipStream_t);
+NDMG_INST(double)
+NDMG_INST(float)
+#undef NDMG_INST
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, const Bat&,
+                                                  hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, int64_t, const Bat&,
+                                                  hipStream_t);
 
 }  // namespace ndmg

@@ -1,4 +1,10 @@
 // Device kernels of the ndmg library and their launchers (host side).
+//
+// Every launcher works on a batch of "pairs" (problem, right-hand side) of one size
+// class: all pairs share the level geometry, their vectors follow each other with a
+// stride of the level's vector length, pairs p*nrhs .. p*nrhs + nrhs - 1 belong to
+// problem p and share its alpha and its local factors (which follow each other with a
+// stride of one factor block).  A single solve is the batch of one pair.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,15 +25,26 @@ struct DGeom {
 
 inline DGeom dgeom(const Geom& g) { return DGeom{g.n, g.P, g.plane, g.B}; }
 
-// Smoother tables of one level on the device.
+// Batch description passed by value to kernels.
+struct Bat {
+  int count;               // pairs in the launch
+  int nrhs;                // consecutive pairs per problem
+  const double* alpha;     // per problem (device)
+  const int* act;          // per pair, 0 = skip (converged); nullptr = all active
+};
+
+inline Bat single_batch(const double* d_alpha) { return Bat{1, 1, d_alpha, nullptr}; }
+
+// Smoother tables of one level on the device (shared by all pairs of a class).
 struct DSub {
-  int s, nH, nI, nG, npad, lut_w;
+  int s, nH, nI, nG, npad, lut_w, nB;
   const int* lut;       // [3][w][w][w] slot lookup
   const int* slots;     // [nG][4]: d, dx, dy, dz
   const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, d2, count
   const int* chunks;    // [nchunks][2]: segment, first vertex
   int nchunks;
   int gpw;              // 16-vertex groups per wave in the patch kernel
+  const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };
 
 template <typename T>
@@ -37,76 +54,105 @@ struct LevelPtrs {
   T* zi;      // interior solves (only interior-of-subdomain entries ever written)
   T* gg;      // condensed interface residual
   T* w;       // interface correction (only interface entries ever written)
-  T* Y;       // vertex patch results, slot-major [npad][(nH+1)^3]
-  const T* ATinv;   // nI x nI
-  const T* Sinv;    // 27 x npad x npad
-  const T* XT;      // nI x nB
-  const int64_t* bofs;   // nB offsets of the subdomain boundary edges from its lower node
+  T* Y;       // vertex patch results, slot-major [npad][(nH+1)^3] per pair
+  const T* ATinv;   // nI x nI per problem
+  const T* Sinv;    // 27 x npad x npad per problem
+  const T* XT;      // nI x nB per problem
 };
 
-// Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
-// part[block] = partial sums of x . y (then k_final over stencil_blocks(g) partials).
-template <typename T>
-hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
-                          double* part, int* nparts, hipStream_t st);
 int stencil_max_n();
 int stencil_min_n();   // the plane-marching kernel serves stencil_min_n() < n <= stencil_max_n()
+int stencil_blocks(const Geom& g);   // partial sums per pair of the stencil's dot mode
 // groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
 // S^{-1} stagings), one on small levels (more workgroups)
 inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
-int stencil_blocks(const Geom& g);
-hipError_t launch_final(const double* part, int nparts, int nout, double* out, hipStream_t st);
 
-// y = A x (mode 0) or y = b - A x (mode 1); all entries of y written.
+// Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
+// part[pair * pstride + block] = partial sums of x . y.
 template <typename T>
-hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
+hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
+                          double* part, int64_t pstride, hipStream_t st);
+
+// y = A x (mode 0) or y = b - A x (mode 1); all entries of y in [0, n]^3 written.
+template <typename T>
+hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st);
 
 // gc = I_k^{k-1} rf (restriction, eq. F2C); all entries of gc written.
 template <typename T>
-hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, hipStream_t st);
+hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, const Bat& bt,
+                           hipStream_t st);
 
 // zf += I_{k-1}^k ec (prolongation by natural injection) on interior edges.
 template <typename T>
-hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, hipStream_t st);
+hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
+                              hipStream_t st);
 
-// z (assign != 0: z =, else z +=) eta * M_V^{-1} r  (vertex-based smoother).
+// z (assign != 0: z =, else z +=) M_V^{-1} r  (vertex-based smoother, damping eta included).
 template <typename T>
 hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
-                         const Geom& g, double alpha, double eta, int assign, hipStream_t st);
+                         const Geom& g, const Bat& bt, double eta, int assign, hipStream_t st);
 
-// z = A_0^{-1} g on the coarsest level.
+// z = A_0^{-1} g on the coarsest level (A0inv: N0 x N0 per problem).
 template <typename T>
 hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,
-                         hipStream_t st);
+                         int64_t len, const Bat& bt, hipStream_t st);
 
 template <typename Tin, typename Tout>
-hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, hipStream_t st);
+hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, hipStream_t st);
 
 // ---- FP64 CG vector kernels with device-resident scalars ----------------------------
-constexpr int kRedBlocks = 512;   // partial sums per reduction
+// Per pair: scalars at scal + pair * kScalStride, partial sums at part + pair * pstride.
+constexpr int kRedBlocks = 512;    // partial sums per reduction per pair (single solve)
+constexpr int kScalStride = 16;
+// scalar slots of a pair
+enum : int {
+  kS_BB = 0,    // b . b
+  kS_PQ = 1,    // p . A p
+  kS_RR = 2,    // r . r
+  kS_RZA = 3,   // r . z (even iterations)
+  kS_ZQA = 4,   // z . q (flexible beta)
+  kS_RZB = 5,   // r . z (odd iterations)
+  kS_ZQB = 6,
+  kS_TOL = 7,   // relative tolerance
+  kS_REL = 8,   // ||r|| / ||b|| after the last iteration
+  kS_CC = 9,    // curl-curl form
+};
+// per-pair PCG state
+enum : int { kPairRun = 0, kPairDone = 1, kPairBroken = 2 };
 
-// out[0] = a . b (and out[1] = a . c when c != nullptr); deterministic two-stage sum.
-hipError_t launch_dot(const double* a, const double* b, const double* c, double* partial,
-                      double* out, int64_t len, hipStream_t st);
-// alpha = s[i_num] / s[i_den]; u += alpha p; r -= alpha q; out = r . r
-hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q,
-                            const double* scal, int i_num, int i_den, double* partial,
-                            double* out, int64_t len, hipStream_t st);
-// beta = s[i_num] / s[i_den] (flexible: beta = -alpha s[i_zq] / s[i_den] with alpha =
-// s[i_an]/s[i_ad]); p = z + beta p
+// out[pair*kScalStride + 0] = a . b (and [+1] = a . c when c != nullptr).
+hipError_t launch_dot(const double* a, const double* b, const double* c, double* part,
+                      int64_t pstride, double* out, int64_t len, const Bat& bt, hipStream_t st);
+// per pair: out[pair*kScalStride + o] = sum of nparts partials (o < nout)
+hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nout, double* out,
+                        const Bat& bt, hipStream_t st);
+// alpha = s[i_num] / s[i_den]; u += alpha p; r -= alpha q; s[i_out] = r . r
+hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
+                            int i_num, int i_den, int i_out, double* part, int64_t pstride,
+                            int64_t len, const Bat& bt, hipStream_t st);
+// beta = s[i_num] / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) s[i_zq] / s[i_den]);
+// p = z + beta p
 hipError_t launch_cg_direction(double* p, const double* z, const double* scal, int i_num,
                                int i_den, int flexible, int i_zq, int i_an, int i_ad,
-                               int64_t len, hipStream_t st);
-// y = x (copy) and y = 0
-hipError_t launch_copy(const double* x, double* y, int64_t len, hipStream_t st);
-hipError_t launch_zero(double* y, int64_t len, hipStream_t st);
+                               int64_t len, const Bat& bt, hipStream_t st);
+// Start of a solve: s[kS_TOL] = rtol, iters = 0; pairs with b = 0 are done, pairs with a
+// non-finite b . b broken, all others active.
+hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
+                           hipStream_t st);
+// End of an iteration, per active pair: iters += 1; broken if s[kS_PQ] <= 0 or a scalar is
+// not finite; done if ||r|| / ||b|| <= rtol (s[kS_REL] = that ratio).  *nact = pairs still
+// active.
+hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
+                            int* nact, hipStream_t st);
+hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, hipStream_t st);
+hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st);
 
-// b = load vector of f sampled at the 2x2x2 Gauss points.
+// b = load vector of f sampled at the 2x2x2 Gauss points (single problem).
 hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st);
 
-// partial sums of lam . (K u) for one pair; accumulates into out[0] via final stage.
+// out[0] = lam . (K u) for one pair of vectors (single problem), K = dA/dalpha.
 hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,
-                                double* partial, double* out, hipStream_t st);
+                                double* part, double* out, hipStream_t st);
 
 }  // namespace ndmg

@@ -85,8 +85,9 @@ __device__ __forceinline__ void load_row(const T* __restrict__ base, const DGeom
 
 template <typename T, int R, int NW, int MODE>
 __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, const T* __restrict__ bv,
-                                                     T* __restrict__ y, DGeom g, T ah, T h3, int KZ,
-                                                     int ntj, int ntiles, double* __restrict__ part) {
+                                                     T* __restrict__ y, DGeom g, Bat bt, double h,
+                                                     int KZ, int ntj, int ntiles,
+                                                     double* __restrict__ part, int64_t pstride) {
   constexpr int TJ = NW - 2;
   constexpr int W = 64 * R;
   // LDS: phase A (x, z of the current plane), phase B (F_y, G_z, G_x, Tz x, Tx z)
@@ -94,6 +95,15 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   __shared__ T sB[5][NW][W];
   __shared__ double sred[NW];
 
+  const int pair = blockIdx.y;
+  if (bt.act != nullptr && bt.act[pair] == 0) return;
+  {
+    const int64_t off = (int64_t)pair * 3 * g.B;
+    x += off;
+    y += off;
+    if (MODE == 1) bv += off;
+  }
+  const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
   // XCD-aware tile order: blocks b, b + 8, b + 16, ... run on one XCD, so give them
   // consecutive tiles (neighbouring j-tiles share halo rows in that XCD's L2).
   const int nb = gridDim.x;
@@ -290,7 +300,7 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int w = 0; w < NW; ++w) t += sred[w];
-      part[blockIdx.x] = t;
+      part[(int64_t)pair * pstride + blockIdx.x] = t;
     }
   }
 }
@@ -313,21 +323,21 @@ Tiling tiling(int n, int NW) {
 int waves_for(int n) { return (n <= 128) ? 8 : 4; }
 
 template <typename T, int R, int NW>
-hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, T ah, T h3, int mode,
-                    double* part, int* nparts, hipStream_t st) {
+hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
+                    double* part, int64_t pstride, hipStream_t st) {
   const Tiling tl = tiling(g.n, NW);
   const int ntj = tl.ntj, KZ = tl.KZ, ntiles = tl.ntiles, nbr = tl.nblocks;
-  if (nparts) *nparts = nbr;
   const DGeom dg = dgeom(g);
+  const dim3 grid((unsigned)nbr, (unsigned)bt.count);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stencil<T, R, NW, 0>), dim3(nbr), dim3(64 * NW), 0, st, x, b, y, dg, ah, h3,
-                       KZ, ntj, ntiles, part);
+    hipLaunchKernelGGL((k_stencil<T, R, NW, 0>), grid, dim3(64 * NW), 0, st, x, b, y, dg, bt, g.h, KZ, ntj,
+                       ntiles, part, pstride);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_stencil<T, R, NW, 1>), dim3(nbr), dim3(64 * NW), 0, st, x, b, y, dg, ah, h3,
-                       KZ, ntj, ntiles, part);
+    hipLaunchKernelGGL((k_stencil<T, R, NW, 1>), grid, dim3(64 * NW), 0, st, x, b, y, dg, bt, g.h, KZ, ntj,
+                       ntiles, part, pstride);
   else
-    hipLaunchKernelGGL((k_stencil<T, R, NW, 2>), dim3(nbr), dim3(64 * NW), 0, st, x, b, y, dg, ah, h3,
-                       KZ, ntj, ntiles, part);
+    hipLaunchKernelGGL((k_stencil<T, R, NW, 2>), grid, dim3(64 * NW), 0, st, x, b, y, dg, bt, g.h, KZ, ntj,
+                       ntiles, part, pstride);
   return hipGetLastError();
 }
 
@@ -339,18 +349,17 @@ int stencil_min_n() { return 64; }
 int stencil_blocks(const Geom& g) { return tiling(g.n, waves_for(g.n)).nblocks; }
 
 template <typename T>
-hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, double alpha, int mode,
-                          double* part, int* nparts, hipStream_t st) {
-  const T ah = (T)(alpha * g.h), h3 = (T)(g.h * g.h * g.h);
-  if (g.n <= 64) return launch_r<T, 1, 8>(x, b, y, g, ah, h3, mode, part, nparts, st);
-  if (g.n <= 128) return launch_r<T, 2, 8>(x, b, y, g, ah, h3, mode, part, nparts, st);
-  if (g.n <= 256) return launch_r<T, 4, 4>(x, b, y, g, ah, h3, mode, part, nparts, st);
+hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
+                          double* part, int64_t pstride, hipStream_t st) {
+  if (g.n <= 64) return launch_r<T, 1, 8>(x, b, y, g, bt, mode, part, pstride, st);
+  if (g.n <= 128) return launch_r<T, 2, 8>(x, b, y, g, bt, mode, part, pstride, st);
+  if (g.n <= 256) return launch_r<T, 4, 4>(x, b, y, g, bt, mode, part, pstride, st);
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_stencil<double>(const double*, const double*, double*, const Geom&, double,
-                                           int, double*, int*, hipStream_t);
-template hipError_t launch_stencil<float>(const float*, const float*, float*, const Geom&, double, int,
-                                          double*, int*, hipStream_t);
+template hipError_t launch_stencil<double>(const double*, const double*, double*, const Geom&,
+                                           const Bat&, int, double*, int64_t, hipStream_t);
+template hipError_t launch_stencil<float>(const float*, const float*, float*, const Geom&, const Bat&,
+                                          int, double*, int64_t, hipStream_t);
 
 }  // namespace ndmg

@@ -11,41 +11,85 @@ from . import _lib
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
-class Solver:
-    """V-cycle-preconditioned CG for curl(alpha curl u) + u = f on (0, length)^3 with
-    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace."""
+def _opts(m, eta, precision, boundary_patches, flexible, use_graphs):
+    o = _lib.ndmg_default_opts()
+    o.m = int(m)
+    if eta is not None:
+        o.eta = float(eta)
+    o.precision = PRECISIONS[precision]
+    o.boundary_patches = 1 if boundary_patches else 0
+    o.flexible = -1 if flexible is None else int(bool(flexible))
+    o.use_graphs = 1 if use_graphs else 0
+    return o
 
-    def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
-                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0"):
-        self.n, self.alpha, self.length = int(n), float(alpha), float(length)
+
+class _Context:
+    """Workspace, private stream and context handle shared by both solver kinds."""
+
+    def _alloc(self, ws_bytes, device):
         self.device = torch.device(device)
-        o = _lib.ndmg_default_opts()
-        o.m = int(m)
-        if eta is not None:
-            o.eta = float(eta)
-        o.precision = PRECISIONS[precision]
-        o.boundary_patches = 1 if boundary_patches else 0
-        o.flexible = -1 if flexible is None else int(bool(flexible))
-        o.use_graphs = 1 if use_graphs else 0
-        self.opts = o
-        self.precision = precision
-        self.ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o)
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = ws_bytes
+        self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
         # the library works on a stream of its own (default priority; graph capture needs a
         # non-null stream); calls are ordered after the caller's current stream and the
         # caller's stream waits for them
         self.stream = torch.cuda.Stream(device=self.device)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        self.ctx = _lib.ndmg_setup(self.n, self.length, self.alpha, o, self._ws_ptr,
-                                   self.ws_bytes, self.stream.cuda_stream)
+
+    def _run(self, fn, *args):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        try:
+            return fn(self.ctx, *args)
+        finally:
+            cur.wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            self.stream.synchronize()
+            _lib.ndmg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver(_Context):
+    """V-cycle-preconditioned CG for curl(alpha curl u) + u = f on (0, length)^3 with
+    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace.  With
+    nrhs > 1 every call works on nrhs vectors at once ([nrhs, vec_len] tensors), each
+    right-hand side with its own CG scalars."""
+
+    def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
+                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1):
+        self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs)
+        self.opts = o
+        self.precision = precision
+        if self.nrhs == 1:
+            ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o)
+        else:
+            ws_bytes, tl = _lib.ndmg_plan_batched([self.n], self.length, self.nrhs, o)
+            self.vec_len = tl // self.nrhs
+        self._alloc(ws_bytes, device)
+        if self.nrhs == 1:
+            self.ctx = _lib.ndmg_setup(self.n, self.length, self.alpha, o, self._ws_ptr, ws_bytes,
+                                       self.stream.cuda_stream)
+        else:
+            self.ctx = _lib.ndmg_setup_batched([self.n], self.length, [self.alpha], self.nrhs, o,
+                                               self._ws_ptr, ws_bytes, self.stream.cuda_stream)
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         info = _lib.ndmg_layout(self.ctx, -1)
         self.P, self.B, self.levels, self.ndof = info[1], info[2], info[4], info[5]
 
     # ---- helpers -------------------------------------------------------------------
     def zeros(self, *lead):
+        if not lead and self.nrhs > 1:
+            lead = (self.nrhs,)
         return torch.zeros(*lead, self.vec_len, dtype=torch.float64, device=self.device)
 
     def _check(self, t):
@@ -53,6 +97,8 @@ class Solver:
             raise ValueError("vectors must be contiguous float64 tensors on the solver's device")
         if t.shape[-1] != self.vec_len:
             raise ValueError(f"vector length {t.shape[-1]} != {self.vec_len}")
+        if t.numel() != self.nrhs * self.vec_len:
+            raise ValueError(f"expected {self.nrhs} vector(s) of length {self.vec_len}")
         return t.data_ptr()
 
     def layout(self, level=-1):
@@ -74,13 +120,6 @@ class Solver:
         return self._mask
 
     # ---- operations -----------------------------------------------------------------
-    def _run(self, fn, *args):
-        cur = torch.cuda.current_stream(self.device)
-        self.stream.wait_stream(cur)
-        try:
-            return fn(self.ctx, *args)
-        finally:
-            cur.wait_stream(self.stream)
 
     def apply(self, x, y=None):
         y = self.zeros() if y is None else y
@@ -93,25 +132,33 @@ class Solver:
         return z
 
     def solve(self, b, rtol=1e-10, maxit=500, u=None, raise_on_noconv=True):
+        """u = A^{-1} b by V-cycle PCG; returns (u, iterations, relative residual), the
+        last two as lists over the right-hand sides when nrhs > 1."""
         u = self.zeros() if u is None else u
-        code, it, rel = self._run(_lib.ndmg_pcg_solve, self._check(b), self._check(u), rtol, maxit,
-                                  raise_on_noconv)
+        if self.nrhs == 1:
+            code, it, rel = self._run(_lib.ndmg_pcg_solve, self._check(b), self._check(u), rtol,
+                                      maxit, raise_on_noconv)
+            return u, it, rel
+        code, it, rel = self._run(_lib.ndmg_pcg_solve_batched, self._check(b), self._check(u), rtol,
+                                  maxit, self.nrhs, raise_on_noconv)
         return u, it, rel
 
     def assemble_rhs(self, f):
         """b from f sampled at the 2x2x2 Gauss points ([n^3, 8, 3] float64)."""
         f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
-        if f.numel() != self.n ** 3 * 24:
-            raise ValueError("f must hold n^3 x 8 x 3 values")
+        if f.numel() != self.nrhs * self.n ** 3 * 24:
+            raise ValueError("f must hold nrhs x n^3 x 8 x 3 values")
         b = self.zeros()
         self._run(_lib.ndmg_assemble_rhs, f.data_ptr(), self._check(b))
         return b
 
     def curlcurl_form(self, lam, u):
-        """sum_r lam_r^T K u_r for stacked vectors [nrhs, vec_len]."""
+        """sum_r lam_r^T K u_r for stacked vectors [k, vec_len] (any k)."""
         lam = lam.reshape(-1, self.vec_len).contiguous()
         u = u.reshape(-1, self.vec_len).contiguous()
-        return self._run(_lib.ndmg_curlcurl_form, self._check(lam), self._check(u), lam.shape[0])
+        if lam.shape != u.shape or lam.dtype != torch.float64 or u.dtype != torch.float64:
+            raise ValueError("lam and u must be float64 of the same shape")
+        return self._run(_lib.ndmg_curlcurl_form, lam.data_ptr(), u.data_ptr(), lam.shape[0])
 
     def level_op(self, level, op, x, out=None):
         """One step on one level (FP64 solvers): op in 'apply', 'smooth', 'restrict',
@@ -120,8 +167,8 @@ class Solver:
         lvl = level if level >= 0 else self.levels + level
         in_level = lvl - 1 if op == "prolong" else lvl
         out_level = lvl - 1 if op == "restrict" else lvl
-        ln_in = _lib.ndmg_layout(self.ctx, in_level)[3]
-        ln_out = _lib.ndmg_layout(self.ctx, out_level)[3]
+        ln_in = _lib.ndmg_layout(self.ctx, in_level)[3] * self.nrhs
+        ln_out = _lib.ndmg_layout(self.ctx, out_level)[3] * self.nrhs
         x = x.contiguous()
         if x.numel() != ln_in or x.dtype != torch.float64:
             raise ValueError("input has the wrong length or dtype")
@@ -136,14 +183,87 @@ class Solver:
         buf, d = _lib.ndmg_export_factor(self.ctx, level, which, typ)
         return np.array(buf).reshape(d, d)
 
-    def close(self):
-        if getattr(self, "ctx", None) is not None:
-            self.stream.synchronize()
-            _lib.ndmg_destroy(self.ctx)
-            self.ctx = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+class BatchedSolver(_Context):
+    """Many independent problems of uneven sizes (n[p] cubes per axis, alpha[p]) with
+    nrhs right-hand sides each, solved together: every kernel covers all pairs of one
+    size, sizes run concurrently, and each (problem, right-hand side) pair has its own
+    CG scalars and stops on its own.  Vectors are batch vectors (see `offset`)."""
+
+    def __init__(self, ns, alphas, nrhs=1, length=1.0, m=1, eta=None, precision="fp32",
+                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0"):
+        self.ns = [int(v) for v in ns]
+        self.alphas = [float(v) for v in alphas]
+        self.nrhs, self.length, self.precision = int(nrhs), float(length), precision
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs)
+        self.opts = o
+        ws_bytes, self.total_len = _lib.ndmg_plan_batched(self.ns, self.length, self.nrhs, o)
+        self._alloc(ws_bytes, device)
+        self.ctx = _lib.ndmg_setup_batched(self.ns, self.length, self.alphas, self.nrhs, o,
+                                           self._ws_ptr, ws_bytes, self.stream.cuda_stream)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        self.layouts = [_lib.ndmg_batch_layout(self.ctx, p) for p in range(len(self.ns))]
+        self.npairs = len(self.ns) * self.nrhs
+
+    @property
+    def nprob(self):
+        return len(self.ns)
+
+    def offset(self, p):
+        """(first element, vector length, n, P, B, levels) of problem p in a batch vector."""
+        return tuple(self.layouts[p])
+
+    def zeros(self):
+        return torch.zeros(self.total_len, dtype=torch.float64, device=self.device)
+
+    def view(self, X, p):
+        """The [nrhs, vec_len] block of problem p in batch vector X (a view)."""
+        off, vl = self.layouts[p][0], self.layouts[p][1]
+        return X[off:off + self.nrhs * vl].view(self.nrhs, vl)
+
+    def pack(self, blocks):
+        """Batch vector from a list of per-problem [nrhs, vec_len] tensors."""
+        X = self.zeros()
+        for p, blk in enumerate(blocks):
+            self.view(X, p).copy_(blk.reshape(self.nrhs, -1))
+        return X
+
+    def _check(self, t):
+        if (t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous()
+                or t.numel() != self.total_len):
+            raise ValueError(f"batch vectors must be contiguous float64 [{self.total_len}] tensors")
+        return t.data_ptr()
+
+    def apply(self, x, y=None):
+        y = self.zeros() if y is None else y
+        self._run(_lib.ndmg_apply, self._check(x), self._check(y))
+        return y
+
+    def vcycle(self, g, z=None):
+        z = self.zeros() if z is None else z
+        self._run(_lib.ndmg_vcycle, self._check(g), self._check(z))
+        return z
+
+    def sample_len(self):
+        """Length of the Gauss-point sample array of assemble_rhs: n^3 x 8 x 3 values per
+        pair, pairs in batch-vector order."""
+        return sum(24 * n ** 3 * self.nrhs for n in self.ns)
+
+    def assemble_rhs(self, f):
+        """Batch vector of load vectors from f sampled at the 2x2x2 Gauss points of every
+        element of every pair (see sample_len; pairs ordered as in batch vectors)."""
+        if (f.dtype != torch.float64 or f.device != self.device or not f.is_contiguous()
+                or f.numel() != self.sample_len()):
+            raise ValueError(f"f must be a contiguous float64 tensor of {self.sample_len()} values")
+        b = self.zeros()
+        self._run(_lib.ndmg_assemble_rhs, f.data_ptr(), self._check(b))
+        return b
+
+    def solve(self, B, rtol=1e-10, maxit=500, U=None, raise_on_noconv=True):
+        """U = A_p^{-1} B for every pair; returns (U, iterations [nprob, nrhs],
+        relative residuals [nprob, nrhs])."""
+        U = self.zeros() if U is None else U
+        code, it, rel = self._run(_lib.ndmg_pcg_solve_batched, self._check(B), self._check(U), rtol,
+                                  maxit, self.npairs, raise_on_noconv)
+        return (U, np.array(it, dtype=np.int64).reshape(self.nprob, self.nrhs),
+                np.array(rel).reshape(self.nprob, self.nrhs))

@@ -87,3 +87,37 @@ def test_product_path_does_not_import_oracle():
             if f.endswith(".py"):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
+
+
+def test_plan_batched_matches_single(lib):
+    o = lib.ndmg_default_opts()
+    # one problem, one right-hand side: same vector length as the single plan
+    ws1, vl1 = lib.ndmg_plan(16, 1.0, 1.0, o)
+    wsb, tl = lib.ndmg_plan_batched([16], 1.0, 1, o)
+    assert tl == vl1 and wsb >= ws1 // 2
+    # uneven sizes: the batch vector concatenates nrhs padded vectors per problem
+    ns, nrhs = [8, 12, 16, 8, 24, 32, 12], 4
+    ws, tl = lib.ndmg_plan_batched(ns, 1.0, nrhs, o)
+    per = [3 * (n + 1) ** 2 * (((n + 1) + 7) // 8 * 8) for n in ns]
+    assert tl == nrhs * sum(per)
+    assert ws % 256 == 0 and ws > 4 * tl * 8
+
+
+@pytest.mark.parametrize("ns,nrhs", [([8, 1], 1), ([8, 22], 1), ([8], 0), ([], 1),
+                                     ([8] * 20000, 4)])
+def test_plan_batched_rejects(lib, ns, nrhs):
+    o = lib.ndmg_default_opts()
+    with pytest.raises(lib.NdmgError) as e:
+        lib.ndmg_plan_batched(ns, 1.0, nrhs, o)
+    assert e.value.code == lib.NDMG_EINVAL
+
+
+def test_batched_null_arguments(lib):
+    L = lib.lib()
+    ctx = ctypes.c_void_p()
+    o = lib.ndmg_default_opts()
+    n = (ctypes.c_int * 2)(8, 12)
+    assert L.ndmg_setup_batched(ctypes.byref(ctx), 2, n, 1.0, None, 1, ctypes.byref(o), None, 0,
+                                None) == lib.NDMG_EINVAL
+    assert L.ndmg_batch_layout(None, 0, None) == lib.NDMG_EINVAL
+    assert L.ndmg_pcg_solve_batched(None, None, None, 1e-10, 10, None, None) == lib.NDMG_EINVAL
