@@ -195,7 +195,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   C.o_pq = take(v8);
   const int64_t cc_parts = (int64_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
   C.pstride = std::max<int64_t>(std::max<int64_t>(2 * ndmg::kRedBlocks, cc_parts),
-                                (int64_t)ndmg::stencil_blocks(gf));
+                                (int64_t)ndmg::stencil_blocks(gf, C.count));
   C.o_part = take((size_t)C.pstride * sizeof(double) * cnt);
   C.o_scal = take((size_t)kScalStride * sizeof(double) * cnt);
   C.o_alpha = take(np * sizeof(double));
@@ -475,7 +475,7 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt
   double* sc = at<double>(c, C.o_scal);
   if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
     NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, st));
-    NDMG_HIP(ndmg::launch_final(part, ndmg::stencil_blocks(g), C.pstride, 1, sc + kS_PQ, bt, st));
+    NDMG_HIP(ndmg::launch_final(part, ndmg::stencil_blocks(g, C.count), C.pstride, 1, sc + kS_PQ, bt, st));
   } else {
     NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));
     NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, C.pstride, sc + kS_PQ, len, bt, st));

@@ -733,8 +733,10 @@ inline unsigned vec_blocks(int64_t len, int count, unsigned cap) {
 template <typename T>
 hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st) {
-  if (g.n > stencil_min_n() && g.n <= stencil_max_n())
-    return launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, st);
+  if (g.n > stencil_min_n() && g.n <= stencil_max_n()) {
+    const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, st);
+    if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
+  }
   const int nbx = nbx64(g.n);
   if (mode == 0)
     hipLaunchKernelGGL((k_apply<T, 0>), node_grid(g, nbx, bt.count), dim3(64), 0, st, x, b, y, dgeom(g),

@@ -62,13 +62,14 @@ struct LevelPtrs {
 
 int stencil_max_n();
 int stencil_min_n();   // the plane-marching kernel serves stencil_min_n() < n <= stencil_max_n()
-int stencil_blocks(const Geom& g);   // partial sums per pair of the stencil's dot mode
+int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the dot mode
 // groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
 // S^{-1} stagings), one on small levels (more workgroups)
 inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
 
 // Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
-// part[pair * pstride + block] = partial sums of x . y.
+// part[pair * pstride + block] = partial sums of x . y.  Returns hipErrorNotSupported
+// (launching nothing) for a mode and size it does not serve.
 template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                           double* part, int64_t pstride, hipStream_t st);
