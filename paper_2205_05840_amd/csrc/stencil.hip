@@ -209,6 +209,8 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   const int tk = tile / ntj;
   const int j0 = tj * TJ;
   const int k0 = tk * KZ;
+  // output planes [k0, kend); the last tile also writes the boundary plane k = n (zero)
+  const int kend = (k0 + KZ >= g.n) ? g.n + 1 : k0 + KZ;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = j0 - 1 + wave;
   const int i0 = R * lane;
@@ -243,9 +245,11 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
     else if constexpr (sl == 2) return ring2;
     else return ring3;
   };
-  // ring loads of plane p into slot SL
+  // ring loads of plane p into slot SL.  Only planes k0 - 1 .. kend feed written outputs;
+  // loads of other planes (and of rows outside [0, n)) read row (0, 0) of plane 0, which
+  // is zero and stays cached, so they cost no memory traffic
   auto issue_plane = [&](auto SL, int p) {
-    const bool ok = row_ok && p >= 0 && p < g.n;
+    const bool ok = row_ok && p >= 0 && p < g.n && p >= k0 - 1 && p <= kend;
     const int64_t roff = ok ? (int64_t)p * g.plane + (int64_t)j * g.P : 0;
     unsigned char* dst = slot_base(SL) + wave * CH;
 #pragma unroll
@@ -267,8 +271,6 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   }
   double dot = 0.0;
   const int kstart = k0 - 1;
-  // output planes [k0, kend); the last tile also writes the boundary plane k = n (zero)
-  const int kend = (k0 + KZ >= g.n) ? g.n + 1 : k0 + KZ;
   const int s0 = kstart - D;                // first step: ring loads only
 
   // one step; PH = (s - s0) mod U.  Plane s0 + m lives in slot m mod D, so plane s + a is
