@@ -116,3 +116,43 @@ def gradient(n, h):
     Gy = _kron3(In, D, In)
     Gz = _kron3(D, In, In)
     return (sp.vstack([Gx, Gy, Gz], format="csr") / h).tocsr()
+
+
+def apply_rows(n, h, alpha, x, rows):
+    """Selected entries of A x by the element definition: (A x)_e is the sum, over the
+    (at most four) cubes T that contain edge e, of the row of the element matrix for e's
+    local edge times T's edge values (boundary edges contribute zero).  For sizes where
+    assembling A is too costly; ``rows`` are compact indices."""
+    Ae = element.element_matrix(h, alpha)
+    rows = np.asarray(rows, dtype=np.int64)
+    d_all, p_all = mesh.edge_coords(n)
+    d = d_all[rows]
+    p = p_all[rows]
+    x = np.asarray(x)
+    out = np.zeros(rows.size)
+    for b in range(2):
+        for a in range(2):
+            # the cube in which e is the local edge (d, a, b): its lower node is e's node
+            # minus a along the first and b along the second transverse axis
+            c = p.copy()
+            for dd in range(3):
+                ea, eb = [ax for ax in range(3) if ax != dd]
+                m = d == dd
+                c[m, ea] -= a
+                c[m, eb] -= b
+            inside = np.all((c >= 0) & (c < n), axis=1)
+            vals = np.zeros((rows.size, 12))
+            for dd in range(3):
+                ea, eb = [ax for ax in range(3) if ax != dd]
+                for bb in range(2):
+                    for aa in range(2):
+                        q = c.copy()
+                        q[:, ea] += aa
+                        q[:, eb] += bb
+                        q = np.where(inside[:, None], q, 0)
+                        idx = np.asarray(mesh.compact_index(n, dd, q[:, 0], q[:, 1], q[:, 2]))
+                        ok = inside & (idx >= 0)
+                        vals[ok, element.local_edge(dd, aa, bb)] = x[idx[ok]]
+            loc = 4 * d + a + 2 * b
+            out += np.where(inside, np.einsum("ij,ij->i", Ae[loc], vals), 0.0)
+    return out

@@ -464,7 +464,22 @@ int precondition(ndmg_ctx* c, Cls& C, const double* g, double* z, const ndmg::Ba
   return NDMG_OK;
 }
 
-// q = A p with p^T q (slot PQ), then u += a p, r -= a q (a = s[num] / s[PQ]) and r . r.
+// In the CG driver the V-cycle reads the FP64 residual r (FP64 contexts) or its FP32 copy
+// in the finest level's g (mixed precision: written by the update that produced r), and
+// its result z stays in the V-cycle's precision (the finest level's z when FP32).
+bool mixed(const Plan& pl) { return pl.opts.precision == NDMG_PREC_FP32; }
+
+float* r32_of(ndmg_ctx* c, Cls& C) { return mixed(c->plan) ? at<float>(c, C.lv.back().o_g) : nullptr; }
+
+int precondition_cg(ndmg_ctx* c, Cls& C, const ndmg::Bat& bt, hipStream_t st) {
+  const int J = (int)C.lv.size() - 1;
+  LevelHost& L = C.lv[J];
+  if (!mixed(c->plan)) return vcycle_rec<double>(c, C, J, at<double>(c, C.o_pr), at<double>(c, C.o_pz), bt, st);
+  return vcycle_rec<float>(c, C, J, at<float>(c, L.o_g), at<float>(c, L.o_z), bt, st);
+}
+
+// q = A p with p^T q (slot PQ), then u += a p, r -= a q (a = s[num] / s[PQ]) and r . r
+// (and the FP32 copy of r when mixed).
 int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt, hipStream_t st) {
   const ndmg::Geom& g = C.lv.back().g;
   const int64_t len = g.len;
@@ -474,13 +489,13 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt
   double* part = at<double>(c, C.o_part);
   double* sc = at<double>(c, C.o_scal);
   if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
-    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, st));
-    NDMG_HIP(ndmg::launch_final(part, ndmg::stencil_blocks(g, C.count), C.pstride, 1, sc + kS_PQ, bt, st));
+    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, sc + kS_PQ, st));
   } else {
     NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));
-    NDMG_HIP(ndmg::launch_dot(p, q, nullptr, part, C.pstride, sc + kS_PQ, len, bt, st));
+    NDMG_HIP(ndmg::launch_dot<double>(p, q, nullptr, part, C.pstride, sc + kS_PQ, len, bt, st));
   }
-  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, kS_PQ, kS_RR, part, C.pstride, len, bt, st));
+  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, kS_PQ, kS_RR, r32_of(c, C), part, C.pstride, len,
+                                  bt, st));
   return NDMG_OK;
 }
 
@@ -509,12 +524,19 @@ int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol
   const ndmg::Bat all = class_batch(c, C, false), act = class_batch(c, C, true);
   NDMG_HIP(ndmg::launch_copy(b, r, len, all, st));
   NDMG_HIP(ndmg::launch_zero(u, len, all, st));
-  NDMG_HIP(ndmg::launch_dot(b, b, nullptr, part, C.pstride, sc + kS_BB, len, all, st));
+  NDMG_HIP(ndmg::launch_dot<double>(b, b, nullptr, part, C.pstride, sc + kS_BB, len, all, st));
   NDMG_HIP(ndmg::launch_pcg_init(sc, at<int>(c, C.o_act), at<int>(c, C.o_iters), at<int>(c, C.o_status),
                                  C.count, rtol, st));
-  NDMG_TRY(precondition(c, C, r, z, act, st));
-  NDMG_HIP(ndmg::launch_dot(r, z, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
-  NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
+  if (mixed(c->plan)) NDMG_HIP((ndmg::launch_convert<double, float>(r, r32_of(c, C), len, act, st)));
+  NDMG_TRY(precondition_cg(c, C, act, st));
+  if (mixed(c->plan)) {
+    const float* zf = at<float>(c, C.lv.back().o_z);
+    NDMG_HIP(ndmg::launch_dot<float>(zf, r, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
+    NDMG_HIP((ndmg::launch_convert<float, double>(zf, p, len, act, st)));
+  } else {
+    NDMG_HIP(ndmg::launch_dot<double>(z, r, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
+    NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
+  }
   NDMG_TRY(cg_apply_update(c, C, u, kS_RZA, act, st));
   return pcg_check(c, ci, kS_RZA, st);
 }
@@ -533,9 +555,17 @@ int pcg_body(ndmg_ctx* c, size_t ci, double* u, int cur, int nxt, hipStream_t st
   double* sc = at<double>(c, C.o_scal);
   const bool flex = flexible_beta(c->plan);
   const ndmg::Bat act = class_batch(c, C, true);
-  NDMG_TRY(precondition(c, C, r, z, act, st));
-  NDMG_HIP(ndmg::launch_dot(z, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
-  NDMG_HIP(ndmg::launch_cg_direction(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act, st));
+  NDMG_TRY(precondition_cg(c, C, act, st));
+  if (mixed(c->plan)) {
+    const float* zf = at<float>(c, C.lv.back().o_z);
+    NDMG_HIP(ndmg::launch_dot<float>(zf, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<float>(p, zf, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act,
+                                              st));
+  } else {
+    NDMG_HIP(ndmg::launch_dot<double>(z, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<double>(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act,
+                                               st));
+  }
   NDMG_TRY(cg_apply_update(c, C, u, nxt, act, st));
   return pcg_check(c, ci, nxt, st);
 }

@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace ndmg {
 
@@ -472,22 +473,8 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, in
 // ---------------------------------------------------------------------------------
 // reductions (FP64)
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  // wavefront reduction by shuffles, then across the waves of the block
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) sh[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-  }
-  __syncthreads();
-  return t;
-}
-
-__global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const double* __restrict__ b,
+template <typename TA>
+__global__ void __launch_bounds__(256) k_dot(const TA* __restrict__ a, const double* __restrict__ b,
                                              const double* __restrict__ c, double* __restrict__ part,
                                              int64_t pstride, int64_t len, Bat bt) {
   __shared__ double sh[8];
@@ -500,7 +487,7 @@ __global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const
   double s1 = 0.0, s2 = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double av = a[e];
+    const double av = (double)a[e];
     s1 += av * b[e];
     if (c) s2 += av * c[e];
   }
@@ -528,11 +515,13 @@ __global__ void __launch_bounds__(256) k_final(const double* __restrict__ part, 
   }
 }
 
+// u += a p, r -= a q (a = s[i_num] / s[i_den]), partial sums of r . r; with r32 the new
+// residual is also written in FP32 (input of the next mixed-precision V-cycle)
 __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, double* __restrict__ r,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ q,
-                                                   const double* __restrict__ scal, int i_num,
-                                                   int i_den, double* __restrict__ part,
+                                                   double* __restrict__ scal, int i_num, int i_den,
+                                                   float* __restrict__ r32, double* __restrict__ part,
                                                    int64_t pstride, int64_t len, Bat bt) {
   __shared__ double sh[8];
   const int pair = blockIdx.y;
@@ -542,6 +531,7 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   r += off;
   p += off;
   q += off;
+  if (r32) r32 += off;
   scal += (int64_t)pair * kScalStride;
   part += (int64_t)pair * pstride;
   const double alpha = scal[i_num] / scal[i_den];
@@ -551,13 +541,15 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
     u[e] += alpha * p[e];
     const double rv = r[e] - alpha * q[e];
     r[e] = rv;
+    if (r32) r32[e] = (float)rv;
     s += rv * rv;
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const double* __restrict__ z,
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const TZ* __restrict__ z,
                                                       const double* __restrict__ scal, int i_num,
                                                       int i_den, int flexible, int i_zq, int i_an,
                                                       int i_ad, int64_t len, Bat bt) {
@@ -571,7 +563,7 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
   else beta = scal[i_num] / scal[i_den];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = z[e] + beta * p[e];
+    p[e] = (double)z[e] + beta * p[e];
 }
 
 __global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, int* __restrict__ act,
@@ -734,7 +726,7 @@ template <typename T>
 hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st) {
   if (g.n > stencil_min_n() && g.n <= stencil_max_n()) {
-    const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, st);
+    const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, nullptr, st);
     if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
   }
   const int nbx = nbx64(g.n);
@@ -808,13 +800,14 @@ hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, 
   return hipGetLastError();
 }
 
-hipError_t launch_dot(const double* a, const double* b, const double* c, double* part,
-                      int64_t pstride, double* out, int64_t len, const Bat& bt, hipStream_t st) {
+template <typename TA>
+hipError_t launch_dot(const TA* a, const double* b, const double* c, double* part, int64_t pstride,
+                      double* out, int64_t len, const Bat& bt, hipStream_t st) {
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
-  hipLaunchKernelGGL(k_dot, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, a, b, c, part, pstride, len,
-                     bt);
-  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride,
-                     c ? 2 : 1, out, bt);
+  hipLaunchKernelGGL((k_dot<TA>), dim3(nb, (unsigned)bt.count), dim3(256), 0, st, a, b, c, part, pstride,
+                     len, bt);
+  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, c ? 2 : 1,
+                     out, bt);
   return hipGetLastError();
 }
 
@@ -826,23 +819,33 @@ hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nou
 }
 
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
-                            int i_num, int i_den, int i_out, double* part, int64_t pstride,
-                            int64_t len, const Bat& bt, hipStream_t st) {
+                            int i_num, int i_den, int i_out, float* r32, double* part,
+                            int64_t pstride, int64_t len, const Bat& bt, hipStream_t st) {
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
   hipLaunchKernelGGL(k_cg_update, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal, i_num,
-                     i_den, part, pstride, len, bt);
+                     i_den, r32, part, pstride, len, bt);
   hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, 1,
                      scal + i_out, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_direction(double* p, const double* z, const double* scal, int i_num,
-                               int i_den, int flexible, int i_zq, int i_an, int i_ad,
-                               int64_t len, const Bat& bt, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256),
-                     0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, len, bt);
+template <typename TZ>
+hipError_t launch_cg_direction(double* p, const TZ* z, const double* scal, int i_num, int i_den,
+                               int flexible, int i_zq, int i_an, int i_ad, int64_t len, const Bat& bt,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_direction<TZ>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count),
+                     dim3(256), 0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, len, bt);
   return hipGetLastError();
 }
+
+template hipError_t launch_dot<double>(const double*, const double*, const double*, double*, int64_t,
+                                       double*, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_dot<float>(const float*, const double*, const double*, double*, int64_t,
+                                      double*, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<double>(double*, const double*, const double*, int, int, int,
+                                                int, int, int, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<float>(double*, const float*, const double*, int, int, int, int,
+                                               int, int, int64_t, const Bat&, hipStream_t);
 
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
                            hipStream_t st) {

@@ -68,11 +68,12 @@ int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the 
 inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
 
 // Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
-// part[pair * pstride + block] = partial sums of x . y.  Returns hipErrorNotSupported
-// (launching nothing) for a mode and size it does not serve.
+// dot[pair * kScalStride] = x . y (partial sums per tile in part[pair * pstride + tile],
+// then reduced by a second small kernel).  Returns hipErrorNotSupported (launching
+// nothing) for a mode and size it does not serve.
 template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
-                          double* part, int64_t pstride, hipStream_t st);
+                          double* part, int64_t pstride, double* dot, hipStream_t st);
 
 // y = A x (mode 0) or y = b - A x (mode 1); all entries of y in [0, n]^3 written.
 template <typename T>
@@ -122,21 +123,26 @@ enum : int {
 // per-pair PCG state
 enum : int { kPairRun = 0, kPairDone = 1, kPairBroken = 2 };
 
-// out[pair*kScalStride + 0] = a . b (and [+1] = a . c when c != nullptr).
-hipError_t launch_dot(const double* a, const double* b, const double* c, double* part,
-                      int64_t pstride, double* out, int64_t len, const Bat& bt, hipStream_t st);
+// out[pair*kScalStride + 0] = a . b (and [+1] = a . c when c != nullptr): partial sums
+// per block, then one block per pair reduces them (a second small kernel: a reduction
+// inside the first kernel would need a device-wide fence per block, which costs more).
+template <typename TA>
+hipError_t launch_dot(const TA* a, const double* b, const double* c, double* part, int64_t pstride,
+                      double* out, int64_t len, const Bat& bt, hipStream_t st);
 // per pair: out[pair*kScalStride + o] = sum of nparts partials (o < nout)
 hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nout, double* out,
                         const Bat& bt, hipStream_t st);
-// alpha = s[i_num] / s[i_den]; u += alpha p; r -= alpha q; s[i_out] = r . r
+// alpha = s[i_num] / s[i_den]; u += alpha p; r -= alpha q; s[i_out] = r . r; r32 (may be
+// null) receives r in FP32
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
-                            int i_num, int i_den, int i_out, double* part, int64_t pstride,
-                            int64_t len, const Bat& bt, hipStream_t st);
+                            int i_num, int i_den, int i_out, float* r32, double* part,
+                            int64_t pstride, int64_t len, const Bat& bt, hipStream_t st);
 // beta = s[i_num] / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) s[i_zq] / s[i_den]);
 // p = z + beta p
-hipError_t launch_cg_direction(double* p, const double* z, const double* scal, int i_num,
-                               int i_den, int flexible, int i_zq, int i_an, int i_ad,
-                               int64_t len, const Bat& bt, hipStream_t st);
+template <typename TZ>
+hipError_t launch_cg_direction(double* p, const TZ* z, const double* scal, int i_num, int i_den,
+                               int flexible, int i_zq, int i_an, int i_ad, int64_t len, const Bat& bt,
+                               hipStream_t st);
 // Start of a solve: s[kS_TOL] = rtol, iters = 0; pairs with b = 0 are done, pairs with a
 // non-finite b . b broken, all others active.
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,

@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace ndmg {
 
@@ -187,7 +188,6 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   // y-neighbour exchange: F_y, G_z, G_x, T_z x, T_x z of the current step
   typedef typename RowVec<T, R>::type V;
   __shared__ V sB[5][NW][64];
-  __shared__ double sred[NW];
 
   const int pair = blockIdx.y;
   if (bt.act != nullptr && bt.act[pair] == 0) return;
@@ -454,15 +454,10 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   // no ring load may be left in flight when the workgroup ends
   wait_vm<0>();
   if (MODE == 2) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
-    if (lane == 0) sred[wave] = dot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < NW; ++w) t += sred[w];
-      part[(int64_t)pair * pstride + blockIdx.x] = t;
-    }
+    // partial sum of this tile (indexed by tile: padding workgroups write none)
+    __shared__ double sh[NW];
+    const double t = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[(int64_t)pair * pstride + tile] = t;
   }
 }
 
@@ -485,11 +480,13 @@ Tiling tiling(int n, int NW, int KZ) {
 
 template <typename T, int R, int NW, int D, int MODE>
 hipError_t launch_m(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int KZ, double* part,
-                    int64_t pstride, hipStream_t st) {
+                    int64_t pstride, double* dot, hipStream_t st) {
   const Tiling tl = tiling(g.n, NW, KZ);
+  if (MODE == 2 && (dot == nullptr || part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tl.nblocks, (unsigned)bt.count);
   hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g), bt,
                      g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
+  if (MODE == 2) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
   return hipGetLastError();
 }
 
@@ -574,37 +571,37 @@ bool pick(int n, int count, int mode, int* which, int* kz, Variant* var) {
 
 template <typename T, int R, int MODE>
 hipError_t launch_mode(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, double* part,
-                       int64_t pstride, hipStream_t st) {
+                       int64_t pstride, double* dot, hipStream_t st) {
   constexpr bool f64 = std::is_same<T, double>::value;
   int which = 0, kz = 8;
   Variant var{};
   if (!pick<T, R>(g.n, bt.count, MODE, &which, &kz, &var)) return hipErrorNotSupported;
   if constexpr (R == 2) {
-    if constexpr (f64 && MODE == 1) return launch_m<T, R, 6, 3, MODE>(x, b, y, g, bt, kz, part, pstride, st);
+    if constexpr (f64 && MODE == 1) return launch_m<T, R, 6, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     if constexpr (f64 && MODE != 1) {
-      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, st);
+      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
     if constexpr (!f64 && MODE == 1) {
-      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, st);
+      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
     if constexpr (!f64 && MODE != 1) {
-      if (which == 0) return launch_m<T, R, 10, 4, MODE>(x, b, y, g, bt, kz, part, pstride, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, st);
+      if (which == 0) return launch_m<T, R, 10, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
   } else {
-    if constexpr (!(f64 && MODE == 1)) return launch_m<T, R, 4, 4, MODE>(x, b, y, g, bt, kz, part, pstride, st);
+    if constexpr (!(f64 && MODE == 1)) return launch_m<T, R, 4, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
   }
   return hipErrorNotSupported;
 }
 
 template <typename T, int R>
 hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
-                    double* part, int64_t pstride, hipStream_t st) {
-  if (mode == 0) return launch_mode<T, R, 0>(x, b, y, g, bt, part, pstride, st);
-  if (mode == 1) return launch_mode<T, R, 1>(x, b, y, g, bt, part, pstride, st);
-  return launch_mode<T, R, 2>(x, b, y, g, bt, part, pstride, st);
+                    double* part, int64_t pstride, double* dot, hipStream_t st) {
+  if (mode == 0) return launch_mode<T, R, 0>(x, b, y, g, bt, part, pstride, dot, st);
+  if (mode == 1) return launch_mode<T, R, 1>(x, b, y, g, bt, part, pstride, dot, st);
+  return launch_mode<T, R, 2>(x, b, y, g, bt, part, pstride, dot, st);
 }
 
 }  // namespace
@@ -612,29 +609,29 @@ hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, 
 int stencil_max_n() { return 256; }
 int stencil_min_n() { return 64; }
 
-// partial sums per pair of the dot mode (FP64): the workgroups of the chosen launch
+// partial sums per pair of the dot mode (FP64): one per tile of the chosen launch
 int stencil_blocks(const Geom& g, int count) {
   if (g.n <= stencil_min_n() || g.n > stencil_max_n()) return 0;
   int which = 0, kz = 8;
   Variant var{};
   const bool ok = (g.n <= 128) ? pick<double, 2>(g.n, count, 2, &which, &kz, &var)
                                : pick<double, 4>(g.n, count, 2, &which, &kz, &var);
-  return ok ? tiling(g.n, var.nw, kz).nblocks : 0;
+  return ok ? tiling(g.n, var.nw, kz).ntiles : 0;
 }
 
 template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
-                          double* part, int64_t pstride, hipStream_t st) {
+                          double* part, int64_t pstride, double* dot, hipStream_t st) {
   // rows span 64 R positions: R = 2 up to n = 128, R = 4 up to 256
   if (g.n <= stencil_min_n()) return hipErrorInvalidValue;
-  if (g.n <= 128) return launch_r<T, 2>(x, b, y, g, bt, mode, part, pstride, st);
-  if (g.n <= 256) return launch_r<T, 4>(x, b, y, g, bt, mode, part, pstride, st);
+  if (g.n <= 128) return launch_r<T, 2>(x, b, y, g, bt, mode, part, pstride, dot, st);
+  if (g.n <= 256) return launch_r<T, 4>(x, b, y, g, bt, mode, part, pstride, dot, st);
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_stencil<double>(const double*, const double*, double*, const Geom&,
-                                           const Bat&, int, double*, int64_t, hipStream_t);
+                                           const Bat&, int, double*, int64_t, double*, hipStream_t);
 template hipError_t launch_stencil<float>(const float*, const float*, float*, const Geom&, const Bat&,
-                                          int, double*, int64_t, hipStream_t);
+                                          int, double*, int64_t, double*, hipStream_t);
 
 }  // namespace ndmg

@@ -1,0 +1,105 @@
+"""GPU parity of the plane-marching operator kernel (meshes with 64 < n <= 128) against
+the FP64 oracle: the apply on sampled rows (element definition, up to the 128^3 bench
+size), the FP64 V-cycle (its residuals use the kernel's residual mode), and PCG (its
+p^T A p uses the dot mode) in FP64 and mixed precision against the exact discrete
+solution.  n = 80 and 112 give tile counts that leave padding workgroups."""
+import numpy as np
+import pytest
+
+from layout import boundary_mask, from_padded, to_padded
+from oracle import assemble, exact, mesh, pcg, rhs, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _solver(n, alpha=1.0, **kw):
+    from paper_2205_05840_amd import Solver
+    print(f"[case] n={n} alpha={alpha} {kw}", flush=True)
+    return Solver(n, alpha, **kw)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("n,alpha", [(80, 1.0), (96, 0.01), (112, 37.0), (128, 1.0)])
+def test_apply_sampled_rows(n, alpha):
+    S = _solver(n, alpha)
+    h = 1.0 / n
+    x = np.random.default_rng(n).standard_normal(mesh.ndof(n))
+    y = _host(S.apply(torch.from_numpy(to_padded(n, S.P, S.B, x)).cuda()))
+    # random rows plus every row next to a tile edge in y and z (rows 0, 1, 7, 8, ...)
+    rng = np.random.default_rng(1)
+    d, p = mesh.edge_coords(n)
+    edge = np.nonzero((p[:, 1] % 8 <= 1) | (p[:, 1] % 8 == 7) | (p[:, 2] % 8 <= 1) |
+                      (p[:, 2] % 8 == 7))[0]
+    rows = np.unique(np.concatenate([rng.choice(mesh.ndof(n), 20000, replace=False),
+                                     rng.choice(edge, 20000, replace=False)]))
+    ref = assemble.apply_rows(n, h, alpha, x, rows)
+    got = from_padded(n, S.P, S.B, y)[rows]
+    assert _rel(got, ref) <= 1e-14
+    assert np.all(y[boundary_mask(n, S.P, S.B)] == 0.0)
+
+
+@pytest.mark.parametrize("n,alpha", [(80, 1.0), (96, 40.0)])
+def test_vcycle_fp64(n, alpha):
+    S = _solver(n, alpha)
+    H = vcycle.Hierarchy(n, alpha, factored=True)
+    H2 = vcycle.Hierarchy(n, alpha, factored=True, inverse="cholesky")
+    g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
+    z = _host(S.vcycle(torch.from_numpy(to_padded(n, S.P, S.B, g)).cuda()))
+    ref = H.precondition(g)
+    tol = max(1e-12, 20 * _rel(H2.precondition(g), ref))
+    print(f"V-cycle tolerance {tol:.2e}")
+    assert _rel(from_padded(n, S.P, S.B, z), ref) <= tol
+
+
+@pytest.mark.parametrize("n,alpha,precision", [(80, 1.0, "fp64"), (80, 1.0, "fp32"),
+                                               (112, 0.05, "fp32")])
+def test_pcg(n, alpha, precision):
+    from paper_2205_05840_amd import synth
+    S = _solver(n, alpha, precision=precision)
+    h = 1.0 / n
+    f = synth.normal_samples(n, 0)
+    b_o = rhs.load_from_samples(n, h, f)
+    b = S.assemble_rhs(torch.from_numpy(f))
+    u, it, rel = S.solve(b, rtol=1e-10)
+    assert rel <= 1e-10
+    u_c = from_padded(n, S.P, S.B, _host(u))
+    ue = exact.solve_fft(n, h, alpha, b_o)
+    ev = exact.eigenvalues(n, h, alpha)
+    # error bound from the residual (plus the recursive/true residual gap)
+    assert np.linalg.norm(u_c - ue) <= 3e-10 * np.linalg.norm(b_o) / ev.min()
+    if precision == "fp64" and n == 80:
+        A = assemble.matrix_kron(n, h, alpha)
+        H = vcycle.Hierarchy(n, alpha)
+        _, it_o, _, _ = pcg.pcg(A, b_o, H.precondition, rtol=1e-10)
+        assert abs(it - it_o) <= 1, (it, it_o)
+    print(f"{precision} n={n}: {it} iterations, relres {rel:.2e}")
+
+
+def test_pcg_bench_size_mixed():
+    """The 128^3 bench configuration (alpha = 1, f ~ N(0, 1) at the Gauss points, seed 2,
+    FP32 V-cycle in FP64 CG): relative residual and solution against the exact discrete
+    solution (FFT)."""
+    from paper_2205_05840_amd import synth
+    n = 128
+    h = 1.0 / n
+    S = _solver(n, 1.0, precision="fp32")
+    f = synth.normal_samples(n, 2)
+    b = S.assemble_rhs(torch.from_numpy(f))
+    u, it, rel = S.solve(b, rtol=1e-10)
+    assert rel <= 1e-10 and it <= 30
+    b_o = rhs.load_from_samples(n, h, f)
+    ue = exact.solve_fft(n, h, 1.0, b_o)
+    ev_min = h ** 3 / 9.0   # lower bound of the spectrum (symbol of A)
+    err = np.linalg.norm(from_padded(n, S.P, S.B, _host(u)) - ue)
+    print(f"128^3 mixed: {it} iterations, relres {rel:.2e}, |u - u_exact| / |u_exact| "
+          f"{err / np.linalg.norm(ue):.2e}")
+    assert err <= 3e-10 * np.linalg.norm(b_o) / ev_min

@@ -137,3 +137,16 @@ def test_manufactured_first_order():
         errs.append(np.sqrt(aa - b @ u))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(0.95 < r < 1.1 for r in rates), (errs, rates)
+
+
+@pytest.mark.parametrize("n,alpha", [(4, 1.0), (7, 0.3), (10, 25.0)])
+def test_apply_rows_equals_assembled(n, alpha):
+    """The sampled-row product (element definition, used at sizes too large to assemble)
+    equals the Kronecker-assembled matrix on every row."""
+    from oracle import assemble, mesh
+    h = 1.0 / n
+    x = np.random.default_rng(n).standard_normal(mesh.ndof(n))
+    rows = np.random.default_rng(1).permutation(mesh.ndof(n))
+    y = assemble.apply_rows(n, h, alpha, x, rows)
+    ref = (assemble.matrix_kron(n, h, alpha) @ x)[rows]
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
