@@ -70,6 +70,10 @@ typedef struct ndmg_opts {
   int flexible;         /* 1: Polak-Ribiere beta in PCG (default for FP32)          */
   int use_graphs;       /* 1 (default): replay each CG iteration from a captured HIP
                            graph when the stream is not the null stream; 0: eager   */
+  int bottom_n;         /* levels with n_k <= bottom_n (at most 64) and the coarsest
+                           solve run as one launch with one workgroup per (problem,
+                           right-hand side); 0 (default): every level launches its
+                           own kernels (faster on MI355X for every size measured)   */
 } ndmg_opts;
 
 /* Fill *o with the defaults above. */

@@ -37,6 +37,7 @@ class ndmg_opts(ctypes.Structure):
         ("boundary_patches", ctypes.c_int),
         ("flexible", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("bottom_n", ctypes.c_int),
     ]
 
 

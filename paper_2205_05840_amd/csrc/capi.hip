@@ -66,7 +66,7 @@ struct LevelHost {
   int nB = 0;
   // workspace offsets; per-pair arrays hold `count` copies, factors `nprob` copies
   size_t o_z = 0, o_g = 0, o_r = 0, o_zi = 0, o_gg = 0, o_w = 0, o_Y = 0;
-  size_t o_ATinv = 0, o_XT = 0, o_Sinv = 0, o_A0 = 0;
+  size_t o_ATinv = 0, o_XT = 0, o_Sinv = 0, o_A0 = 0, o_G = 0;
   size_t o_lut = 0, o_slots = 0, o_segs = 0, o_chunks = 0, o_bofs = 0, o_map = 0;
   size_t nY = 0;
   size_t blk_ATinv = 0, blk_XT = 0, blk_Sinv = 0, blk_A0 = 0;   // elements per problem
@@ -74,6 +74,7 @@ struct LevelHost {
 
 struct Cls {
   int n = 0, nprob = 0, nrhs = 1, count = 0;
+  int small_top = -1;              // levels 0 .. small_top run as one launch
   std::vector<int> probs;          // problem indices, input order
   std::vector<double> alpha;       // per problem
   std::vector<LevelHost> lv;       // coarsest first
@@ -124,6 +125,7 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
     return fail(NDMG_EINVAL, "unsupported precision");
   if (o->subdomain != 2) return fail(NDMG_EINVAL, "subdomain size must be 2");
   if (o->eta <= 0.0) o->eta = 1.0 / 9.0;
+  if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
   return NDMG_OK;
 }
 
@@ -171,6 +173,8 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       const size_t nv = (size_t)(L.sub.nH + 1);
       L.nY = nv * nv * nv * (size_t)L.sub.npad;
       L.o_Y = take(L.nY * el * cnt);
+      // gathered patch inputs of the one-launch bottom of the V-cycle (small levels)
+      if (sizes[k] <= pl.opts.bottom_n) L.o_G = take(L.nY * el * cnt);
       L.nB = (int)ndmg::boundary_dofs(L.sub.s).size();
       L.blk_ATinv = (size_t)L.sub.nI * L.sub.nI;
       L.blk_XT = (size_t)L.sub.nI * L.nB;
@@ -185,6 +189,12 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       L.o_chunks = take(std::max<size_t>(1, L.chunks.size()) * sizeof(int));
     }
     C.lv.push_back(std::move(L));
+  }
+  {
+    const int bn = pl.opts.bottom_n;
+    C.small_top = -1;
+    for (size_t k = 0; k < C.lv.size(); ++k)
+      if (C.lv[k].g.n <= bn && C.lv[k].g.n <= 64 && (int)k < ndmg::kSmallMaxLevels) C.small_top = (int)k;
   }
   const ndmg::Geom& gf = C.lv.back().g;
   C.vlen = gf.len;
@@ -415,11 +425,56 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
   return NDMG_OK;
 }
 
+// Levels 0 .. top of a class for the one-launch bottom of the V-cycle.
+template <typename T>
+ndmg::SmallArgs<T> small_args(ndmg_ctx* c, Cls& C, int top) {
+  ndmg::SmallArgs<T> a{};
+  a.top = top;
+  a.m = c->plan.opts.m;
+  a.eta = c->plan.opts.eta;
+  for (int k = 0; k <= top; ++k) {
+    LevelHost& L = C.lv[k];
+    ndmg::SmallLevel<T>& s = a.lv[k];
+    s.g = ndmg::dgeom(L.g);
+    s.h = L.g.h;
+    s.z = at<T>(c, L.o_z);
+    s.gv = at<T>(c, L.o_g);
+    if (L.smoothed) {
+      s.nH = L.sub.nH;
+      s.bpatch = c->plan.opts.boundary_patches != 0;
+      s.r = at<T>(c, L.o_r);
+      s.zi = at<T>(c, L.o_zi);
+      s.gg = at<T>(c, L.o_gg);
+      s.w = at<T>(c, L.o_w);
+      s.Y = at<T>(c, L.o_Y);
+      s.G = at<T>(c, L.o_G);
+      s.ATinv = at<T>(c, L.o_ATinv);
+      s.Sinv = at<T>(c, L.o_Sinv);
+      s.XT = at<T>(c, L.o_XT);
+      s.bofs = at<int64_t>(c, L.o_bofs);
+      s.lut = at<int>(c, L.o_lut);
+      s.slots = at<int>(c, L.o_slots);
+    } else {
+      s.A0inv = at<T>(c, L.o_A0);
+      s.map = at<int64_t>(c, L.o_map);
+      s.N0 = (int)L.map.size();
+    }
+  }
+  return a;
+}
+
 // z = MG(k, g, 0, m) (Fig. 1) for the pairs of a class.
 template <typename T>
 int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt, hipStream_t st) {
   Plan& pl = c->plan;
   LevelHost& L = C.lv[k];
+  if (k <= C.small_top) {
+    ndmg::SmallArgs<T> a = small_args<T>(c, C, k);
+    a.lv[k].gv = const_cast<T*>(g);
+    a.lv[k].z = z;
+    NDMG_HIP(ndmg::launch_vcycle_small<T>(a, bt, st));
+    return NDMG_OK;
+  }
   if (k == 0) {
     NDMG_HIP(ndmg::launch_coarse<T>(g, z, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map), (int)L.map.size(),
                                     L.g.len, bt, st));
@@ -792,6 +847,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->boundary_patches = 1;
   o->flexible = -1;
   o->use_graphs = 1;
+  o->bottom_n = 0;
 }
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }

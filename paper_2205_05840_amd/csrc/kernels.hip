@@ -72,18 +72,11 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, i
 // ---------------------------------------------------------------------------------
 // operator apply / residual (one thread per node position, small levels)
 // ---------------------------------------------------------------------------------
+// y (or b - A x) at the three edges of node (i, j, k)
 template <typename T, int MODE>
-__global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
-  const int pair = blockIdx.x / nbx;
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i > g.n || inactive(bt, pair)) return;
-  const int64_t off = (int64_t)pair * vlen(g);
-  x += off;
-  y += off;
-  if (MODE == 1) b += off;
-  const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
+__device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __restrict__ b,
+                                           T* __restrict__ y, const DGeom& g, T ah, T h3, int i, int j,
+                                           int k) {
   const int64_t p = lin(g, i, j, k);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -96,18 +89,28 @@ __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* 
   }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > g.n || inactive(bt, pair)) return;
+  const int64_t off = (int64_t)pair * vlen(g);
+  x += off;
+  y += off;
+  if (MODE == 1) b += off;
+  const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
+  apply_node<T, MODE>(x, b, y, g, ah, h3, i, j, k);
+}
+
 // ---------------------------------------------------------------------------------
 // grid transfers (Sec. 3.1): per direction P0 (x) P1 (x) P1
 // ---------------------------------------------------------------------------------
+// gc at the three edges of coarse node (I, J, K)
 template <typename T>
-__global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
-                                                 DGeom f, DGeom c, Bat bt, int nbx) {
-  const int pair = blockIdx.x / nbx;
-  const int I = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y, K = blockIdx.z;
-  if (I > c.n || inactive(bt, pair)) return;
-  rf += (int64_t)pair * vlen(f);
-  gc += (int64_t)pair * vlen(c);
+__device__ __forceinline__ void restrict_node(const T* __restrict__ rf, T* __restrict__ gc, const DGeom& f,
+                                              const DGeom& c, int I, int J, int K) {
   const int64_t stf[3] = {1, (int64_t)f.P, f.plane};
   const int64_t pc = lin(c, I, J, K);
   const int64_t pf = lin(f, 2 * I, 2 * J, 2 * K);
@@ -133,14 +136,19 @@ __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
-                                                    DGeom f, DGeom c, Bat bt, int nbx) {
+__global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
+                                                 DGeom f, DGeom c, Bat bt, int nbx) {
   const int pair = blockIdx.x / nbx;
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i > f.n || inactive(bt, pair)) return;
-  ec += (int64_t)pair * vlen(c);
-  zf += (int64_t)pair * vlen(f);
+  const int I = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y, K = blockIdx.z;
+  if (I > c.n || inactive(bt, pair)) return;
+  restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K);
+}
+
+// zf += I_{k-1}^k ec at the three edges of fine node (i, j, k)
+template <typename T>
+__device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __restrict__ zf, const DGeom& f,
+                                             const DGeom& c, int i, int j, int k) {
   const int o[3] = {i, j, k};
   const int64_t stc[3] = {1, (int64_t)c.P, c.plane};
   const int64_t pf = lin(f, i, j, k);
@@ -163,6 +171,16 @@ __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T*
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
+                                                    DGeom f, DGeom c, Bat bt, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i > f.n || inactive(bt, pair)) return;
+  prolong_node(ec + (int64_t)pair * vlen(c), zf + (int64_t)pair * vlen(f), f, c, i, j, k);
+}
+
 // ---------------------------------------------------------------------------------
 // vertex-based smoother (Sec. 3.2.2), s = 2
 // ---------------------------------------------------------------------------------
@@ -179,17 +197,11 @@ __device__ __forceinline__ void interior_offsets_s2(const DGeom& g, int64_t base
   off[5] = 2 * g.B + base + sx + sy + sz;
 }
 
+// zi = A_T^{-1} r on the interior unknowns of subdomain (a, b, c)
 template <typename T>
-__global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, T* __restrict__ zi,
-                                                       const T* __restrict__ ATinv, DGeom g,
-                                                       int nH, Bat bt, int nbx) {
-  const int pair = blockIdx.x / nbx;
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH || inactive(bt, pair)) return;
-  r += (int64_t)pair * vlen(g);
-  zi += (int64_t)pair * vlen(g);
-  ATinv += (int64_t)(pair / bt.nrhs) * 36;
+__device__ __forceinline__ void interior_sub_s2(const T* __restrict__ r, T* __restrict__ zi,
+                                                const T* __restrict__ ATinv, const DGeom& g, int a, int b,
+                                                int c) {
   int64_t off[6];
   interior_offsets_s2(g, lin(g, 2 * a, 2 * b, 2 * c), off);
   T rv[6];
@@ -202,6 +214,18 @@ __global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, 
     for (int t = 0; t < 6; ++t) s += ATinv[q * 6 + t] * rv[t];
     zi[off[q]] = s;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, T* __restrict__ zi,
+                                                       const T* __restrict__ ATinv, DGeom g,
+                                                       int nH, Bat bt, int nbx) {
+  const int pair = blockIdx.x / nbx;
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH || inactive(bt, pair)) return;
+  interior_sub_s2(r + (int64_t)pair * vlen(g), zi + (int64_t)pair * vlen(g),
+                  ATinv + (int64_t)(pair / bt.nrhs) * 36, g, a, b, c);
 }
 
 // Operands of the 16x16x4 MFMAs: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
@@ -339,27 +363,13 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   }
 }
 
-// w = sum_V R_V^T y_V on interface unknowns; z (assign ? =, +=) eta w there.
+// w = sum_V R_V^T y_V on the interface unknowns of node (i, j, k), i < n; z (assign ? =,
+// +=) eta w there.  Y is slot-major ([slot][vertex], NV vertices); slut the slot lookup.
 template <typename T, int S>
-__global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
-                                                 T* __restrict__ z, DGeom g, DSub sub, T eta,
-                                                 int assign, Bat bt, int nbx) {
+__device__ __forceinline__ void pull_node(const T* __restrict__ Y, T* __restrict__ w, T* __restrict__ z,
+                                          const DGeom& g, const int* slut, int nv, int64_t NV, T eta,
+                                          int assign, int i, int j, int k) {
   constexpr int W = 2 * S + 1;
-  constexpr int NG = 6 * S * (4 * S - 3);
-  constexpr int NPAD = (NG + 15) / 16 * 16;
-  __shared__ int slut[3 * W * W * W];
-  const int pair = blockIdx.x / nbx;
-  if (inactive(bt, pair)) return;
-  for (int e = threadIdx.x; e < 3 * W * W * W; e += blockDim.x) slut[e] = sub.lut[e];
-  __syncthreads();
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= g.n) return;   // i = n is never an unknown
-  const int nv = sub.nH + 1;
-  const int64_t NV = (int64_t)nv * nv * nv;
-  Y += (int64_t)pair * NV * NPAD;
-  w += (int64_t)pair * vlen(g);
-  z += (int64_t)pair * vlen(g);
   const int o[3] = {i, j, k};
   const int64_t p = lin(g, i, j, k);
 #pragma unroll
@@ -393,29 +403,37 @@ __global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __r
   }
 }
 
+template <typename T, int S>
+__global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
+                                                 T* __restrict__ z, DGeom g, DSub sub, T eta,
+                                                 int assign, Bat bt, int nbx) {
+  constexpr int W = 2 * S + 1;
+  constexpr int NG = 6 * S * (4 * S - 3);
+  constexpr int NPAD = (NG + 15) / 16 * 16;
+  __shared__ int slut[3 * W * W * W];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
+  for (int e = threadIdx.x; e < 3 * W * W * W; e += blockDim.x) slut[e] = sub.lut[e];
+  __syncthreads();
+  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.n) return;   // i = n is never an unknown
+  const int nv = sub.nH + 1;
+  const int64_t NV = (int64_t)nv * nv * nv;
+  pull_node<T, S>(Y + (int64_t)pair * NV * NPAD, w + (int64_t)pair * vlen(g), z + (int64_t)pair * vlen(g), g,
+                  slut, nv, NV, eta, assign, i, j, k);
+}
+
 // Harmonic extension into subdomain interiors and the final interior update:
 // z_I (assign ? =, +=) eta (zi_I - X_T w_dT), X_T = A_T^{-1} A_{I, dT} (6 x 48 for s = 2),
 // w_dT the interface correction on the 48 edges of the subdomain's boundary (zero where
 // they lie on the boundary of the domain).
+// z_I of subdomain (a, b, c) (assign ? =, +=) eta (zi_I - X_T w_dT); sX = X_T (6 x 48),
+// sofs the offsets of the 48 boundary edges from the subdomain's lower node
 template <typename T>
-__global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
-                                                     T* __restrict__ z, const T* __restrict__ XT,
-                                                     const int64_t* __restrict__ bofs, DGeom g,
-                                                     int nH, T eta, int assign, Bat bt, int nbx) {
-  __shared__ T sX[6 * 48];
-  __shared__ int64_t sofs[48];
-  const int pair = blockIdx.x / nbx;
-  if (inactive(bt, pair)) return;
-  XT += (int64_t)(pair / bt.nrhs) * 6 * 48;
-  for (int e = threadIdx.x; e < 6 * 48; e += blockDim.x) sX[e] = XT[e];
-  for (int e = threadIdx.x; e < 48; e += blockDim.x) sofs[e] = bofs[e];
-  __syncthreads();
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH) return;
-  w += (int64_t)pair * vlen(g);
-  zi += (int64_t)pair * vlen(g);
-  z += (int64_t)pair * vlen(g);
+__device__ __forceinline__ void extend_sub_s2(const T* __restrict__ w, const T* __restrict__ zi,
+                                              T* __restrict__ z, const T* sX, const int64_t* sofs,
+                                              const DGeom& g, T eta, int assign, int a, int b, int c) {
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
   T wv[48];
 #pragma unroll
@@ -434,6 +452,26 @@ __global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, co
     const T old = assign ? T(0) : z[off];
     z[off] = old + eta * (zi[off] - q);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
+                                                     T* __restrict__ z, const T* __restrict__ XT,
+                                                     const int64_t* __restrict__ bofs, DGeom g,
+                                                     int nH, T eta, int assign, Bat bt, int nbx) {
+  __shared__ T sX[6 * 48];
+  __shared__ int64_t sofs[48];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
+  XT += (int64_t)(pair / bt.nrhs) * 6 * 48;
+  for (int e = threadIdx.x; e < 6 * 48; e += blockDim.x) sX[e] = XT[e];
+  for (int e = threadIdx.x; e < 48; e += blockDim.x) sofs[e] = bofs[e];
+  __syncthreads();
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH) return;
+  const int64_t off = (int64_t)pair * vlen(g);
+  extend_sub_s2(w + off, zi + off, z + off, sX, sofs, g, eta, assign, a, b, c);
 }
 
 // ---------------------------------------------------------------------------------
@@ -456,6 +494,206 @@ __global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __re
     T s = T(0);
     for (int j = 0; j < N0; ++j) s += A0inv[(int64_t)i * N0 + j] * gl[j];
     z[map[i]] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// the bottom of the V-cycle in one workgroup per pair
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(512) k_vcycle_small(SmallArgs<T> a, Bat bt) {
+  constexpr int NG = 60, NPAD = 64;
+  __shared__ int sslot[NPAD][4];
+  __shared__ int64_t soff[NPAD];
+  __shared__ int slut[3 * 125];
+  __shared__ T sX[6 * 48];
+  __shared__ int64_t sofs[48];
+  __shared__ T sg0[1024];
+  const int pair = blockIdx.x;
+  if (inactive(bt, pair)) return;
+  const int prob = pair / bt.nrhs;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const T alpha = (T)bt.alpha[prob];
+
+  // pointers of this pair / problem on level k
+  struct Lv {
+    DGeom g;
+    T ah, h3;
+    int nH, nv, bpatch;
+    int64_t NV;
+    T *z, *gv, *r, *zi, *gg, *w, *Y, *G;
+    const T *ATinv, *Sinv, *XT, *A0inv;
+    const int64_t *bofs, *map;
+    const int *lut, *slots;
+    int N0;
+  };
+  auto level = [&](int k) {
+    const SmallLevel<T>& L = a.lv[k];
+    Lv v;
+    v.g = L.g;
+    v.ah = alpha * (T)L.h;
+    v.h3 = (T)(L.h * L.h * L.h);
+    v.nH = L.nH;
+    v.bpatch = L.bpatch;
+    v.nv = L.nH + 1;
+    v.NV = (int64_t)v.nv * v.nv * v.nv;
+    const int64_t vo = (int64_t)pair * vlen(L.g), yo = (int64_t)pair * v.NV * NPAD;
+    v.z = L.z + vo;
+    v.gv = L.gv + vo;
+    v.r = L.r ? L.r + vo : nullptr;
+    v.zi = L.zi ? L.zi + vo : nullptr;
+    v.gg = L.gg ? L.gg + vo : nullptr;
+    v.w = L.w ? L.w + vo : nullptr;
+    v.Y = L.Y ? L.Y + yo : nullptr;
+    v.G = L.G ? L.G + yo : nullptr;
+    v.ATinv = L.ATinv ? L.ATinv + (int64_t)prob * 36 : nullptr;
+    v.Sinv = L.Sinv ? L.Sinv + (int64_t)prob * 27 * NPAD * NPAD : nullptr;
+    v.XT = L.XT ? L.XT + (int64_t)prob * 6 * 48 : nullptr;
+    v.A0inv = L.A0inv ? L.A0inv + (int64_t)prob * L.N0 * L.N0 : nullptr;
+    v.bofs = L.bofs;
+    v.map = L.map;
+    v.lut = L.lut;
+    v.slots = L.slots;
+    v.N0 = L.N0;
+    return v;
+  };
+  // y = A x (mode 0) or b - A x (mode 1) on every node of the level
+  auto apply = [&](const Lv& L, const T* x, const T* b, T* y, int mode) {
+    const int n1 = L.g.n + 1;
+    for (int e = tid; e < n1 * n1 * n1; e += nth) {
+      const int i = e % n1, j = (e / n1) % n1, k = e / (n1 * n1);
+      if (mode) apply_node<T, 1>(x, b, y, L.g, L.ah, L.h3, i, j, k);
+      else apply_node<T, 0>(x, b, y, L.g, L.ah, L.h3, i, j, k);
+    }
+    __syncthreads();
+  };
+  // vertex type (per axis 0 on the low face, 1 inside, 2 on the high face)
+  auto vtype = [&](int nH, int vx, int vy, int vz) {
+    const int tx = vx == 0 ? 0 : (vx == nH ? 2 : 1), ty = vy == 0 ? 0 : (vy == nH ? 2 : 1),
+              tz = vz == 0 ? 0 : (vz == nH ? 2 : 1);
+    return tx + 3 * ty + 9 * tz;
+  };
+  // z (assign ? =, +=) M^{-1} r, the vertex-based smoother (eq. Preconditioner P), in six
+  // phases separated by workgroup barriers
+  auto smooth = [&](const Lv& L, const T* r, T* z, int assign) {
+    const DGeom& g = L.g;
+    const int nH = L.nH, nv = L.nv;
+    const T eta = (T)a.eta;
+    // tables of the level (read after the first barrier below)
+    for (int e = tid; e < NPAD; e += nth) {
+      if (e < NG) {
+        const int* sl = L.slots + 4 * e;
+        sslot[e][0] = sl[0]; sslot[e][1] = sl[1]; sslot[e][2] = sl[2]; sslot[e][3] = sl[3];
+        soff[e] = sl[0] * g.B + (int64_t)sl[3] * g.plane + (int64_t)sl[2] * g.P + sl[1];
+      } else {
+        sslot[e][0] = -1; sslot[e][1] = sslot[e][2] = sslot[e][3] = 0;
+        soff[e] = 0;
+      }
+    }
+    for (int e = tid; e < 3 * 125; e += nth) slut[e] = L.lut[e];
+    for (int e = tid; e < 6 * 48; e += nth) sX[e] = L.XT[e];
+    for (int e = tid; e < 48; e += nth) sofs[e] = L.bofs[e];
+    // 1. interior solves
+    for (int e = tid; e < nH * nH * nH; e += nth)
+      interior_sub_s2(r, L.zi, L.ATinv, g, e % nH, (e / nH) % nH, e / (nH * nH));
+    __syncthreads();
+    // 2. condensed interface residual gg = r - A zi (zi vanishes off subdomain interiors)
+    apply(L, L.zi, r, L.gg, 1);
+    // 3. gather the interface residual of every vertex patch (absent slots of boundary
+    //    patches are zero)
+    for (int e = tid; e < L.NV * NPAD; e += nth) {
+      const int v = e / NPAD, slot = e % NPAD;
+      const int vx = v % nv, vy = (v / nv) % nv, vz = v / (nv * nv);
+      T val = T(0);
+      if (slot < NG) {
+        const int d = sslot[slot][0];
+        const int o[3] = {2 * vx + sslot[slot][1], 2 * vy + sslot[slot][2], 2 * vz + sslot[slot][3]};
+        bool ok = true;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          if (ax == d) ok = ok && (o[ax] >= 0 && o[ax] < g.n);
+          else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
+        }
+        if (ok) val = L.gg[lin(g, 2 * vx, 2 * vy, 2 * vz) + soff[slot]];
+      }
+      L.G[e] = val;
+    }
+    __syncthreads();
+    // 4. patch solves y_V = S_type^{-1} g_V (slot-major Y; no patch: zero)
+    for (int e = tid; e < L.NV * NPAD; e += nth) {
+      const int v = e / NPAD, row = e % NPAD;
+      const int vx = v % nv, vy = (v / nv) % nv, vz = v / (nv * nv);
+      const int type = vtype(nH, vx, vy, vz);
+      T acc = T(0);
+      if (type == 13 || L.bpatch) {
+        const T* srow = L.Sinv + ((int64_t)type * NPAD + row) * NPAD;
+        const T* gv = L.G + (int64_t)v * NPAD;
+#pragma unroll 4
+        for (int col = 0; col < NG; ++col) acc += srow[col] * gv[col];
+      }
+      L.Y[(int64_t)row * L.NV + v] = acc;
+    }
+    __syncthreads();
+    // 5. interface correction w and z on the interface
+    {
+      const int n1 = g.n + 1;
+      for (int e = tid; e < n1 * n1 * n1; e += nth) {
+        const int i = e % n1, j = (e / n1) % n1, k = e / (n1 * n1);
+        if (i < g.n) pull_node<T, 2>(L.Y, L.w, z, g, slut, nv, L.NV, eta, assign, i, j, k);
+      }
+    }
+    __syncthreads();
+    // 6. harmonic extension into the subdomain interiors
+    for (int e = tid; e < nH * nH * nH; e += nth)
+      extend_sub_s2(L.w, L.zi, z, sX, sofs, g, eta, assign, e % nH, (e / nH) % nH, e / (nH * nH));
+    __syncthreads();
+  };
+  auto restrict_to = [&](const Lv& F, const Lv& C, const T* rf, T* gc) {
+    const int n1 = C.g.n + 1;
+    for (int e = tid; e < n1 * n1 * n1; e += nth)
+      restrict_node(rf, gc, F.g, C.g, e % n1, (e / n1) % n1, e / (n1 * n1));
+    __syncthreads();
+  };
+  auto prolong_add = [&](const Lv& F, const Lv& C, const T* ec, T* zf) {
+    const int n1 = F.g.n + 1;
+    for (int e = tid; e < n1 * n1 * n1; e += nth)
+      prolong_node(ec, zf, F.g, C.g, e % n1, (e / n1) % n1, e / (n1 * n1));
+    __syncthreads();
+  };
+  auto coarse = [&](const Lv& L) {
+    for (int i = tid; i < L.N0; i += nth) sg0[i] = L.gv[L.map[i]];
+    __syncthreads();
+    for (int i = tid; i < L.N0; i += nth) {
+      T s = T(0);
+      for (int j = 0; j < L.N0; ++j) s += L.A0inv[(int64_t)i * L.N0 + j] * sg0[j];
+      L.z[L.map[i]] = s;
+    }
+    __syncthreads();
+  };
+
+  const int top = a.top, m = a.m;
+  // descend: pre-smoothing from z = 0, restriction of the residual
+  for (int k = top; k >= 1; --k) {
+    const Lv L = level(k);
+    smooth(L, L.gv, L.z, 1);
+    for (int l = 1; l < m; ++l) {
+      apply(L, L.z, L.gv, L.r, 1);
+      smooth(L, L.r, L.z, 0);
+    }
+    apply(L, L.z, L.gv, L.r, 1);
+    const Lv C = level(k - 1);
+    restrict_to(L, C, L.r, C.gv);
+  }
+  coarse(level(0));
+  // ascend: prolongation of the correction, post-smoothing
+  for (int k = 1; k <= top; ++k) {
+    const Lv L = level(k);
+    const Lv C = level(k - 1);
+    prolong_add(L, C, C.z, L.z);
+    for (int l = 0; l < m; ++l) {
+      apply(L, L.z, L.gv, L.r, 1);
+      smooth(L, L.r, L.z, 0);
+    }
   }
 }
 
@@ -792,6 +1030,19 @@ hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, i
                      len, bt);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_vcycle_small(const SmallArgs<T>& a, const Bat& bt, hipStream_t st) {
+  if (a.top < 0 || a.top >= kSmallMaxLevels) return hipErrorInvalidValue;
+  for (int k = 1; k <= a.top; ++k)
+    if (a.lv[k].g.n / 2 < 2 || a.lv[k].nH * 2 != a.lv[k].g.n) return hipErrorInvalidValue;
+  if (a.lv[0].N0 > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_vcycle_small<T>), dim3((unsigned)bt.count), dim3(512), 0, st, a, bt);
+  return hipGetLastError();
+}
+
+template hipError_t launch_vcycle_small<double>(const SmallArgs<double>&, const Bat&, hipStream_t);
+template hipError_t launch_vcycle_small<float>(const SmallArgs<float>&, const Bat&, hipStream_t);
 
 template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, hipStream_t st) {

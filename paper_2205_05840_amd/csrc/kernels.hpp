@@ -95,6 +95,43 @@ template <typename T>
 hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
                          const Geom& g, const Bat& bt, double eta, int assign, hipStream_t st);
 
+// ---- the bottom of the V-cycle in one launch ---------------------------------------
+// Levels 0 .. top (coarsest first) of one size class, described for the first pair and
+// the first problem (pairs follow with the strides of the level vectors, of Y and of the
+// factor blocks, as in the per-level launchers).
+constexpr int kSmallMaxLevels = 8;
+
+template <typename T>
+struct SmallLevel {
+  DGeom g;
+  double h;
+  int nH;                        // subdomains per axis (smoothed levels)
+  int bpatch;                    // vertex spaces at boundary coarse vertices too
+  T *z, *gv, *r, *zi, *gg, *w, *Y;
+  T* G;                          // gathered patch inputs, vertex-major [NV][64]
+  const T *ATinv, *Sinv, *XT;
+  const int64_t* bofs;
+  const int *lut, *slots;
+  const T* A0inv;                // coarsest level
+  const int64_t* map;
+  int N0;
+};
+
+template <typename T>
+struct SmallArgs {
+  SmallLevel<T> lv[kSmallMaxLevels];
+  int top;      // z_top = MG(top, g_top, 0, m) (Fig. 1), g_top and z_top in lv[top]
+  int m;
+  double eta;
+};
+
+// One workgroup per pair runs MG(top, g, 0, m) over the levels 0 .. top: smoothing,
+// residuals, transfers and the exact coarsest solve, with workgroup barriers between the
+// steps (one launch instead of a dozen per level; a single compute unit per pair is
+// slower than the per-level launches on the sizes measured, so it is an option).
+template <typename T>
+hipError_t launch_vcycle_small(const SmallArgs<T>& a, const Bat& bt, hipStream_t st);
+
 // z = A_0^{-1} g on the coarsest level (A0inv: N0 x N0 per problem).
 template <typename T>
 hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,

@@ -230,3 +230,21 @@ def test_multi_rhs_solver_and_autograd():
     assert abs(Lv - L1v) <= 1e-10 * abs(L1v)
     assert abs(float(a.grad) - float(a1.grad)) <= 1e-8 * abs(float(a1.grad))
     assert _rel(_host(Bg.grad), _host(Bh.grad)) <= 1e-9
+
+
+def test_batched_bottom_levels_one_launch():
+    """The one-launch bottom of the V-cycle (levels n_k <= 16 in one workgroup per pair)
+    gives the same solves as the per-level launches, to rounding."""
+    ns, alphas, nrhs = [8, 12, 16, 24], [1.0, 0.2, 30.0, 3.0], 2
+    b = _loads(ns, nrhs, 120)
+    Bs = [_batch(ns, alphas, nrhs, "fp64", bottom_n=bn) for bn in (0, 16)]
+    out = []
+    for BS in Bs:
+        U, it, rel = BS.solve(_pack(BS, b), rtol=1e-12)
+        assert (rel <= 1e-12).all()
+        out.append((_unpack(BS, U), it))
+    for p, n in enumerate(ns):
+        ue = exact.solve_fft(n, 1.0 / n, alphas[p], b[p])
+        for r in range(nrhs):
+            assert abs(int(out[0][1][p, r]) - int(out[1][1][p, r])) <= 1
+            assert _rel(out[1][0][p][r], ue[r]) <= 1e-9, (p, r)

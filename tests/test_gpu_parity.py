@@ -117,7 +117,19 @@ def test_coarse_only(n):
                                                 (8, 0.01, 2, True), (10, 1.0, 1, True),
                                                 (12, 100.0, 1, False), (16, 1.0, 1, True)])
 def test_vcycle(n, alpha, m, boundary):
-    S = _solver(n, alpha, m=m, boundary_patches=boundary)
+    _check_vcycle(n, alpha, m, boundary, None)
+
+
+@pytest.mark.parametrize("n,alpha,m,bottom", [(8, 1.0, 1, 0), (12, 3.0, 2, 0), (16, 0.5, 1, 16),
+                                              (24, 1.0, 1, 12), (32, 20.0, 1, 16)])
+def test_vcycle_bottom_levels(n, alpha, m, bottom):
+    """The bottom of the V-cycle as one launch (bottom levels n_k <= bottom) and as one
+    launch per step (bottom = 0) both match the oracle."""
+    _check_vcycle(n, alpha, m, True, bottom)
+
+
+def _check_vcycle(n, alpha, m, boundary, bottom):
+    S = _solver(n, alpha, m=m, boundary_patches=boundary, bottom_n=bottom)
     H = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True)
     H2 = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True, inverse="cholesky")
     g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
