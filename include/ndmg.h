@@ -74,6 +74,13 @@ typedef struct ndmg_opts {
                            solve run as one launch with one workgroup per (problem,
                            right-hand side); 0 (default): every level launches its
                            own kernels (faster on MI355X for every size measured)   */
+  int dense_n;          /* with z_0 = 0 the V-cycle MG(k, g, 0, m) of Fig. 1 is a
+                           linear map of g: from the finest level with n_k <= dense_n
+                           (at most 8, i.e. at most 1176 unknowns) down, it is applied
+                           as one dense matrix per problem, built at setup by the
+                           recursive V-cycle on unit vectors (the same map, rounded
+                           differently; the matrices take nprob N_k^2 scalars of the
+                           workspace).  Default 8; 0: the recursion all the way down. */
 } ndmg_opts;
 
 /* Fill *o with the defaults above. */

@@ -38,6 +38,7 @@ class ndmg_opts(ctypes.Structure):
         ("flexible", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
         ("bottom_n", ctypes.c_int),
+        ("dense_n", ctypes.c_int),
     ]
 
 

@@ -70,11 +70,15 @@ struct LevelHost {
   size_t o_lut = 0, o_slots = 0, o_segs = 0, o_chunks = 0, o_bofs = 0, o_map = 0;
   size_t nY = 0;
   size_t blk_ATinv = 0, blk_XT = 0, blk_Sinv = 0, blk_A0 = 0;   // elements per problem
+  size_t o_Bd = 0, blk_Bd = 0;         // dense V-cycle matrix of the level (dense level only)
+  int Nd = 0;                          // its unknowns
 };
 
 struct Cls {
   int n = 0, nprob = 0, nrhs = 1, count = 0;
   int small_top = -1;              // levels 0 .. small_top run as one launch
+  int dense_k = -1;                // MG(dense_k, ., 0, m) applied as a dense matrix (-1: none)
+  int dense_K = 1;                 // matrix columns per problem built per V-cycle launch
   std::vector<int> probs;          // problem indices, input order
   std::vector<double> alpha;       // per problem
   std::vector<LevelHost> lv;       // coarsest first
@@ -126,6 +130,7 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
   if (o->subdomain != 2) return fail(NDMG_EINVAL, "subdomain size must be 2");
   if (o->eta <= 0.0) o->eta = 1.0 / 9.0;
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
+  if (o->dense_n < 0 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be in [0, 8]");
   return NDMG_OK;
 }
 
@@ -136,11 +141,27 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 2) sizes.push_back(sizes.back() / 2);
   std::reverse(sizes.begin(), sizes.end());
-  const size_t cnt = (size_t)C.count, np = (size_t)C.nprob, el = pl.elem;
+  const size_t np = (size_t)C.nprob, el = pl.elem;
+  // dense bottom: the finest level with n_k <= dense_n, if above the coarsest
+  C.dense_k = -1;
+  for (size_t k = 1; k < sizes.size(); ++k)
+    if (sizes[k] <= pl.opts.dense_n) C.dense_k = (int)k;
+  int64_t Nd = 0;
+  if (C.dense_k >= 1) {
+    const int64_t nk = sizes[C.dense_k];
+    Nd = 3 * nk * (nk - 1) * (nk - 1);
+    if (Nd > ndmg::kDenseMaxN) return fail(NDMG_EINVAL, "dense level too large");
+    // the level vectors at and below the dense level serve the build at setup (nprob x
+    // dense_K pairs); at run time only its g and z are used, by count pairs
+    C.dense_K = (int)std::max<int64_t>(C.nrhs, std::min<int64_t>(Nd, 256 / C.nprob));
+  } else {
+    C.dense_K = C.nrhs;
+  }
   C.lv.clear();
   for (size_t k = 0; k < sizes.size(); ++k) {
     LevelHost L;
     L.g = ndmg::make_geom(sizes[k], pl.length);
+    const size_t cnt = ((int)k <= C.dense_k) ? np * (size_t)C.dense_K : (size_t)C.count;
     const size_t vb = (size_t)L.g.len * el * cnt;
     L.o_z = take(vb);
     L.o_g = take(vb);
@@ -187,6 +208,12 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       L.o_slots = take((size_t)L.sub.nG * 4 * sizeof(int));
       L.o_segs = take(std::max<size_t>(1, L.segs.size()) * 8 * sizeof(int));
       L.o_chunks = take(std::max<size_t>(1, L.chunks.size()) * sizeof(int));
+      if ((int)k == C.dense_k) {
+        L.Nd = (int)Nd;
+        L.blk_Bd = (size_t)Nd * Nd;
+        L.o_Bd = take(L.blk_Bd * el * np);
+        L.o_map = take((size_t)Nd * sizeof(int64_t));
+      }
     }
     C.lv.push_back(std::move(L));
   }
@@ -198,6 +225,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   }
   const ndmg::Geom& gf = C.lv.back().g;
   C.vlen = gf.len;
+  const size_t cnt = (size_t)C.count;
   const size_t v8 = (size_t)gf.len * sizeof(double) * cnt;
   C.o_pr = take(v8);
   C.o_pz = take(v8);
@@ -420,6 +448,11 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
     }
     NDMG_TRY(stg.put_vec(c, L.o_segs, sg));
     NDMG_TRY(stg.put_vec(c, L.o_chunks, L.chunks));
+    if (k == C.dense_k) {
+      L.map = ndmg::unknown_offsets(L.g);
+      if ((int)L.map.size() != L.Nd) return fail(NDMG_EINVAL, "internal: dense level size mismatch");
+      NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
+    }
   }
   NDMG_TRY(stg.put_vec(c, C.o_alpha, C.alpha));
   return NDMG_OK;
@@ -480,6 +513,13 @@ int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt
                                     L.g.len, bt, st));
     return NDMG_OK;
   }
+  if (k == C.dense_k) {
+    // z may be a caller's vector at the finest level: clear its non-unknown entries
+    const bool top = (k == (int)C.lv.size() - 1);
+    NDMG_HIP(ndmg::launch_dense_vcycle<T>(g, z, at<T>(c, L.o_Bd), at<int64_t>(c, L.o_map), L.Nd, L.g.len, bt,
+                                          top, st));
+    return NDMG_OK;
+  }
   const int m = pl.opts.m;
   const double eta = pl.opts.eta;
   auto P = level_ptrs<T>(c, L);
@@ -503,6 +543,36 @@ int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt
     NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, bt, eta, 0, st));
   }
   return NDMG_OK;
+}
+
+// Matrix of MG(dense_k, ., 0, m) for every problem of a class: columns from the recursive
+// V-cycle applied to unit vectors, dense_K columns per problem per pass.
+template <typename T>
+int build_dense(ndmg_ctx* c, Cls& C) {
+  const int kd = C.dense_k;
+  if (kd < 1) return NDMG_OK;
+  LevelHost& L = C.lv[kd];
+  const int N = L.Nd, K = C.dense_K;
+  const ndmg::Bat bt{C.nprob * K, K, at<double>(c, C.o_alpha), nullptr};
+  T* g = at<T>(c, L.o_g);
+  T* z = at<T>(c, L.o_z);
+  const int64_t* map = at<int64_t>(c, L.o_map);
+  T* Bm = at<T>(c, L.o_Bd);
+  C.dense_k = -1;   // the recursion, not the matrix being built
+  int rc = NDMG_OK;
+  for (int j0 = 0; j0 < N && rc == NDMG_OK; j0 += K) {
+    hipError_t e = ndmg::launch_unit_cols<T>(g, map, N, j0, L.g.len, bt, c->st);
+    if (e != hipSuccess) {
+      rc = fail(NDMG_EHIP, std::string("dense build: ") + hipGetErrorString(e));
+      break;
+    }
+    rc = vcycle_rec<T>(c, C, kd, g, z, bt, c->st);
+    if (rc != NDMG_OK) break;
+    e = ndmg::launch_gather_cols<T>(z, Bm, map, N, j0, L.g.len, bt, c->st);
+    if (e != hipSuccess) rc = fail(NDMG_EHIP, std::string("dense build: ") + hipGetErrorString(e));
+  }
+  C.dense_k = kd;
+  return rc;
 }
 
 // z = B g for FP64 vectors of the finest level of a class, in the context's precision.
@@ -813,6 +883,9 @@ int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const 
                             : build_class_factors<float>(c.get(), C, stg));
     NDMG_HIP(hipStreamSynchronize(c->st));   // staging buffers die with stg
   }
+  for (auto& C : pl.cls)
+    NDMG_TRY(pl.elem == 8 ? build_dense<double>(c.get(), C) : build_dense<float>(c.get(), C));
+  NDMG_HIP(hipStreamSynchronize(c->st));
   const size_t nc = pl.cls.size();
   for (size_t i = 1; i < nc; ++i) {
     hipStream_t s = nullptr;
@@ -848,6 +921,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->flexible = -1;
   o->use_graphs = 1;
   o->bottom_n = 0;
+  o->dense_n = 8;
 }
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }

@@ -420,26 +420,41 @@ bool build_level_factors(double h, double alpha, const SubInfo& sub, bool bounda
   return true;
 }
 
-bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
-                  std::vector<int64_t>* map, std::string* err) {
+std::vector<int64_t> unknown_offsets(const Geom& g) {
   const int n = g.n;
-  // unknowns: interior edges in padded-layout order
-  std::map<Key, int> idx;
-  map->clear();
+  std::vector<int64_t> off;
+  off.reserve((size_t)3 * n * (n - 1) * (n - 1));
   for (int d = 0; d < 3; ++d)
     for (int z = 0; z <= n; ++z)
       for (int y = 0; y <= n; ++y)
         for (int x = 0; x <= n; ++x) {
-          int o[3] = {x, y, z};
+          const int o[3] = {x, y, z};
           bool ok = true;
           for (int ax = 0; ax < 3; ++ax) {
             if (ax == d) ok &= (o[ax] < n);
             else ok &= (o[ax] >= 1 && o[ax] <= n - 1);
           }
-          if (!ok) continue;
-          idx[Key(d, x, y, z)] = (int)map->size();
-          map->push_back(d * g.B + (int64_t)z * g.plane + (int64_t)y * g.P + x);
+          if (ok) off.push_back(d * g.B + (int64_t)z * g.plane + (int64_t)y * g.P + x);
         }
+  return off;
+}
+
+bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
+                  std::vector<int64_t>* map, std::string* err) {
+  const int n = g.n;
+  // unknowns: interior edges in padded-layout order
+  *map = unknown_offsets(g);
+  std::map<Key, int> idx;
+  for (size_t u = 0; u < map->size(); ++u) {
+    int64_t r = (*map)[u];
+    const int d = (int)(r / g.B);
+    r -= d * g.B;
+    const int z = (int)(r / g.plane);
+    r -= (int64_t)z * g.plane;
+    const int y = (int)(r / g.P);
+    const int x = (int)(r - (int64_t)y * g.P);
+    idx[Key(d, x, y, z)] = (int)u;
+  }
   const int N = (int)map->size();
   if (N > 1024) {
     *err = "coarsest level too large for the dense solve (over 1024 unknowns)";

@@ -498,6 +498,108 @@ __global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __re
 }
 
 // ---------------------------------------------------------------------------------
+// the V-cycle from one level down as a dense matrix per problem
+// ---------------------------------------------------------------------------------
+// With z_0 = 0, MG(k, g, 0, m) (Fig. 1) is a linear map of g; its matrix over the
+// unknowns of level k is built column by column from unit vectors by the recursive
+// V-cycle itself and then applied instead of the recursion.
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// pair p (problem p / K, column col = j0 + p % K): g = e_col (zero when col >= N)
+template <typename T>
+__global__ void k_unit_cols(T* __restrict__ g, const int64_t* __restrict__ map, int N, int j0,
+                            int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  const int col = j0 + pair % bt.nrhs;
+  const int64_t t = (col < N) ? map[col] : -1;
+  g += (int64_t)pair * len;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    g[e] = (e == t) ? T(1) : T(0);
+}
+
+// column col of the matrix of problem p / K: Bm[i][col] = z[map[i]]
+template <typename T>
+__global__ void k_gather_cols(const T* __restrict__ z, T* __restrict__ Bm, const int64_t* __restrict__ map,
+                              int N, int j0, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  const int col = j0 + pair % bt.nrhs;
+  if (col >= N) return;
+  z += (int64_t)pair * len;
+  Bm += (int64_t)(pair / bt.nrhs) * N * N;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    Bm[(int64_t)i * N + col] = z[map[i]];
+}
+
+// z[map[i]] = sum_j Bm[i][j] g[map[j]] for every pair of a problem.  Block (x, problem):
+// the problem's right-hand sides, RC at a time, are gathered into LDS; wave w takes rows
+// (4 x + w) rpw .. + rpw - 1, lanes stride over j and the row sums are wave reductions,
+// so each row of Bm is read once per RC right-hand sides.  Non-unknown entries of z are
+// not written (zero by the layout contract).
+template <typename T, int RC>
+__global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T* __restrict__ z,
+                                                      const T* __restrict__ Bm,
+                                                      const int64_t* __restrict__ map, int N, int64_t len,
+                                                      int rpw, Bat bt) {
+  extern __shared__ __align__(16) unsigned char dense_smem[];
+  T* sg = reinterpret_cast<T*>(dense_smem);
+  const int prob = blockIdx.y;
+  const int nr = bt.nrhs;
+  const T* __restrict__ Bp = Bm + (int64_t)prob * N * N;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + wave) * rpw;
+  for (int rc = 0; rc < nr; rc += RC) {
+    const int nrc = min(RC, nr - rc);
+    __syncthreads();   // the previous chunk's rows are done with sg
+    for (int e = threadIdx.x; e < RC * N; e += blockDim.x) {
+      const int r = e / N, j = e - r * N;
+      const int pair = prob * nr + rc + r;
+      sg[e] = (r < nrc && !inactive(bt, pair)) ? g[(int64_t)pair * len + map[j]] : T(0);
+    }
+    __syncthreads();
+    for (int ii = 0; ii < rpw; ++ii) {
+      const int i = row0 + ii;
+      if (i >= N) break;
+      const T* __restrict__ Brow = Bp + (int64_t)i * N;
+      T acc[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) acc[r] = T(0);
+      for (int j = lane; j < N; j += 64) {
+        const T b = Brow[j];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] += b * sg[r * N + j];
+      }
+      T mine = T(0);
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        const T v = wave_sum(acc[r]);
+        if (lane == r) mine = v;
+      }
+      if (lane < nrc) {
+        const int pair = prob * nr + rc + lane;
+        if (!inactive(bt, pair)) z[(int64_t)pair * len + map[i]] = mine;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ y, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  y += (int64_t)pair * len;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = T(0);
+}
+
+// ---------------------------------------------------------------------------------
 // the bottom of the V-cycle in one workgroup per pair
 // ---------------------------------------------------------------------------------
 template <typename T>
@@ -1032,6 +1134,44 @@ hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, i
 }
 
 template <typename T>
+hipError_t launch_unit_cols(T* g, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
+                            hipStream_t st) {
+  hipLaunchKernelGGL((k_unit_cols<T>), dim3(vec_blocks(len, bt.count, 64), (unsigned)bt.count), dim3(256), 0, st,
+                     g, map, N, j0, len, bt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((k_gather_cols<T>), dim3((unsigned)((N + 255) / 256), (unsigned)bt.count), dim3(256), 0, st,
+                     z, Bm, map, N, j0, len, bt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_vcycle(const T* g, T* z, const T* Bm, const int64_t* map, int N, int64_t len,
+                               const Bat& bt, bool clear, hipStream_t st) {
+  if (N < 1 || N > kDenseMaxN || bt.nrhs < 1 || bt.count % bt.nrhs) return hipErrorInvalidValue;
+  if (clear)
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0,
+                       st, z, len, bt);
+  const int nprob = bt.count / bt.nrhs;
+  // rows per wave: about 2048 workgroups over all problems, 1 .. 16 rows per wave
+  const int64_t want = (int64_t)N * nprob / (4 * 2048);
+  const int rpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, want));
+  const unsigned nbx = (unsigned)((N + 4 * rpw - 1) / (4 * rpw));
+  if (bt.nrhs == 1) {
+    hipLaunchKernelGGL((k_dense_vcycle<T, 1>), dim3(nbx, (unsigned)nprob), dim3(256), (size_t)N * sizeof(T), st, g,
+                       z, Bm, map, N, len, rpw, bt);
+  } else {
+    hipLaunchKernelGGL((k_dense_vcycle<T, 4>), dim3(nbx, (unsigned)nprob), dim3(256), (size_t)4 * N * sizeof(T),
+                       st, g, z, Bm, map, N, len, rpw, bt);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_vcycle_small(const SmallArgs<T>& a, const Bat& bt, hipStream_t st) {
   if (a.top < 0 || a.top >= kSmallMaxLevels) return hipErrorInvalidValue;
   for (int k = 1; k <= a.top; ++k)
@@ -1150,7 +1290,13 @@ hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& 
   template hipError_t launch_smooth<T>(const T*, T*, const LevelPtrs<T>&, const DSub&,            \
                                        const Geom&, const Bat&, double, int, hipStream_t);       \
   template hipError_t launch_coarse<T>(const T*, T*, const T*, const int64_t*, int, int64_t,      \
-                                       const Bat&, hipStream_t);
+                                       const Bat&, hipStream_t);                                  \
+  template hipError_t launch_unit_cols<T>(T*, const int64_t*, int, int, int64_t, const Bat&,      \
+                                          hipStream_t);                                           \
+  template hipError_t launch_gather_cols<T>(const T*, T*, const int64_t*, int, int, int64_t,      \
+                                            const Bat&, hipStream_t);                             \
+  template hipError_t launch_dense_vcycle<T>(const T*, T*, const T*, const int64_t*, int, int64_t, \
+                                             const Bat&, bool, hipStream_t);
 NDMG_INST(double)
 NDMG_INST(float)
 #undef NDMG_INST

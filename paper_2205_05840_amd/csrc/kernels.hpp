@@ -137,6 +137,23 @@ template <typename T>
 hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,
                          int64_t len, const Bat& bt, hipStream_t st);
 
+// The V-cycle from one level down as a dense matrix per problem (MG(k, g, 0, m) is linear
+// in g).  Build, per chunk of columns j0 .. j0 + K - 1 (K = bt.nrhs, pair = problem * K +
+// column - j0): g = unit vectors, then the recursive V-cycle, then the results become
+// columns of Bm (N x N per problem, row-major, over the unknowns listed in map).
+constexpr int kDenseMaxN = 1536;
+template <typename T>
+hipError_t launch_unit_cols(T* g, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len,
+                              const Bat& bt, hipStream_t st);
+// z = Bm g for every pair (Bm of problem pair / nrhs); clear: zero all of z first (for
+// output vectors whose non-unknown entries the caller may not have zeroed).
+template <typename T>
+hipError_t launch_dense_vcycle(const T* g, T* z, const T* Bm, const int64_t* map, int N, int64_t len,
+                               const Bat& bt, bool clear, hipStream_t st);
+
 template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, hipStream_t st);
 

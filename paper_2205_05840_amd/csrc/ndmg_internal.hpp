@@ -76,7 +76,12 @@ struct LevelFactors {
 bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
                          LevelFactors* out, std::string* err);
 
-// Coarsest level: dense inverse of A_0 over its unknowns and the padded offset of each.
+// Padded-layout offsets of the interior edges (the unknowns) of a level, direction-major
+// and then in layout order.
+std::vector<int64_t> unknown_offsets(const Geom& g);
+
+// Coarsest level: dense inverse of A_0 over its unknowns and the padded offset of each
+// (the order of unknown_offsets).
 bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
                   std::vector<int64_t>* map, std::string* err);
 

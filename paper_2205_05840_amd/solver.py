@@ -11,7 +11,7 @@ from . import _lib
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
-def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None):
+def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None, dense_n=None):
     o = _lib.ndmg_default_opts()
     o.m = int(m)
     if eta is not None:
@@ -22,6 +22,8 @@ def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=No
     o.use_graphs = 1 if use_graphs else 0
     if bottom_n is not None:
         o.bottom_n = int(bottom_n)
+    if dense_n is not None:
+        o.dense_n = int(dense_n)
     return o
 
 
@@ -68,9 +70,9 @@ class Solver(_Context):
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
-                 bottom_n=None):
+                 bottom_n=None, dense_n=None):
         self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
-        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n)
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:
@@ -195,11 +197,11 @@ class BatchedSolver(_Context):
 
     def __init__(self, ns, alphas, nrhs=1, length=1.0, m=1, eta=None, precision="fp32",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0",
-                 bottom_n=None):
+                 bottom_n=None, dense_n=None):
         self.ns = [int(v) for v in ns]
         self.alphas = [float(v) for v in alphas]
         self.nrhs, self.length, self.precision = int(nrhs), float(length), precision
-        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n)
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n)
         self.opts = o
         ws_bytes, self.total_len = _lib.ndmg_plan_batched(self.ns, self.length, self.nrhs, o)
         self._alloc(ws_bytes, device)

@@ -248,3 +248,44 @@ def test_batched_bottom_levels_one_launch():
         for r in range(nrhs):
             assert abs(int(out[0][1][p, r]) - int(out[1][1][p, r])) <= 1
             assert _rel(out[1][0][p][r], ue[r]) <= 1e-9, (p, r)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_dense_bottom_matches_recursion(precision):
+    """The bottom of the V-cycle as one dense matrix per problem (levels n_k <= 8, the
+    default) against the recursion all the way down: V-cycle outputs agree to rounding
+    and both solve every pair to the exact discrete solution."""
+    ns, alphas, nrhs = [8, 12, 16, 6, 24, 8], [1.0, 0.2, 30.0, 3.0, 0.05, 7.0], 3
+    b = _loads(ns, nrhs, 140)
+    Bd = _batch(ns, alphas, nrhs, precision)
+    Br = _batch(ns, alphas, nrhs, precision, dense_n=0)
+    rng = np.random.default_rng(6)
+    blocks = [rng.standard_normal((nrhs, mesh.ndof(n))) for n in ns]
+    Zd = _unpack(Bd, Bd.vcycle(_pack(Bd, blocks)))
+    Zr = _unpack(Br, Br.vcycle(_pack(Br, blocks)))
+    if precision == "fp64":
+        for p in range(len(ns)):
+            for r in range(nrhs):
+                assert _rel(Zd[p][r], Zr[p][r]) <= 1e-11, (p, r, _rel(Zd[p][r], Zr[p][r]))
+    else:
+        # FP32 rounding is amplified by the conditioning of the local solves (up to
+        # 1e-3 relative at alpha h^-2 ~ 1e4): the dense form must be as close to the FP64
+        # V-cycle as the recursion is
+        B64 = _batch(ns, alphas, nrhs, "fp64", dense_n=0)
+        Z64 = _unpack(B64, B64.vcycle(_pack(B64, blocks)))
+        for p in range(len(ns)):
+            for r in range(nrhs):
+                ed, er = _rel(Zd[p][r], Z64[p][r]), _rel(Zr[p][r], Z64[p][r])
+                assert ed <= 3.0 * max(er, 1e-6), (p, r, ed, er)
+    rtol = 1e-12 if precision == "fp64" else 1e-11
+    sols = []
+    for BS in (Bd, Br):
+        U, it, rel = BS.solve(_pack(BS, b), rtol=rtol)
+        assert (rel <= rtol).all()
+        sols.append((_unpack(BS, U), it))
+    for p, n in enumerate(ns):
+        ue = exact.solve_fft(n, 1.0 / n, alphas[p], b[p])
+        for r in range(nrhs):
+            assert abs(int(sols[0][1][p, r]) - int(sols[1][1][p, r])) <= 1
+            for k in range(2):
+                assert _rel(sols[k][0][p][r], ue[r]) <= 1e-7, (k, p, r)

@@ -128,8 +128,31 @@ def test_vcycle_bottom_levels(n, alpha, m, bottom):
     _check_vcycle(n, alpha, m, True, bottom)
 
 
-def _check_vcycle(n, alpha, m, boundary, bottom):
-    S = _solver(n, alpha, m=m, boundary_patches=boundary, bottom_n=bottom)
+@pytest.mark.parametrize("n,alpha,m,dense", [(4, 1.0, 1, 8), (8, 0.01, 2, 8), (12, 100.0, 1, 8),
+                                             (16, 1.0, 1, 8), (16, 1.0, 1, 4), (32, 3.0, 1, 8),
+                                             (8, 1.0, 1, 0), (16, 1.0, 1, 0), (12, 100.0, 1, 0)])
+def test_vcycle_dense_bottom(n, alpha, m, dense):
+    """The V-cycle with its bottom (from the finest level with n_k <= dense down) applied
+    as one dense matrix per problem, and with the recursion all the way (dense = 0),
+    against the oracle."""
+    _check_vcycle(n, alpha, m, True, None, dense)
+
+
+def test_vcycle_dense_top_clears_output():
+    """At n = 8 the whole V-cycle is the dense matrix; entries of the output that are not
+    unknowns come out zero whatever the buffer held."""
+    n = 8
+    S = _solver(n, 1.0)
+    g = np.random.default_rng(5).standard_normal(mesh.ndof(n))
+    z = torch.full((S.vec_len,), 7.0, dtype=torch.float64, device="cuda")
+    z = _host(S.vcycle(_dev(to_padded(n, S.P, S.B, g)), z))
+    assert not z[boundary_mask(n, S.P, S.B)].any()
+    ref = vcycle.Hierarchy(n, 1.0, m=1, boundary=True, factored=True).precondition(g)
+    assert _rel(from_padded(n, S.P, S.B, z), ref) <= 1e-12
+
+
+def _check_vcycle(n, alpha, m, boundary, bottom, dense=None):
+    S = _solver(n, alpha, m=m, boundary_patches=boundary, bottom_n=bottom, dense_n=dense)
     H = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True)
     H2 = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True, inverse="cholesky")
     g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
