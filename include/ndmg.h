@@ -148,7 +148,7 @@ int ndmg_batch_layout(const ndmg_ctx* ctx, int prob, int64_t info[6]);
  * vectors.  iters and relres (host, may be NULL) receive nprob * nrhs entries, entry
  * p * nrhs + r for right-hand side r of problem p.  The stream is synchronised once per
  * iteration of the slowest pair; with use_graphs one iteration of the whole batch (all
- * sizes) is replayed from one captured graph.
+ * sizes) is replayed from one captured graph.  d_b and d_u must be 16-byte aligned.
  * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (some pair reached maxit; every output
  * still written), NDMG_EBREAKDOWN (some pair broke down). */
 int ndmg_pcg_solve_batched(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
@@ -174,7 +174,8 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
  * test.  With use_graphs, the iterations after the first
  * are replayed from two HIP graphs captured on first use (and again whenever d_u
  * changes); the stream must then not be the null stream and must not be captured by
- * the caller.
+ * the caller.  d_b and d_u must be 16-byte aligned (the CG vector kernels move four
+ * values per access).
  * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (u still written), NDMG_EBREAKDOWN. */
 int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
                    int* iters, double* relres);

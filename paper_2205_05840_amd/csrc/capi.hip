@@ -1022,6 +1022,8 @@ int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol,
                            int* iters, double* relres) {
   if (int rc = check_ctx(c)) return rc;
   if (!b || !u) return fail(NDMG_EINVAL, "null vector");
+  if (reinterpret_cast<uintptr_t>(b) % 16 || reinterpret_cast<uintptr_t>(u) % 16)
+    return fail(NDMG_EINVAL, "d_b and d_u must be 16-byte aligned");
   if (!(rtol >= 0.0) || maxit < 1) return fail(NDMG_EINVAL, "bad rtol or maxit");
   const int np = c->plan.npairs;
   if (iters) std::fill(iters, iters + np, 0);

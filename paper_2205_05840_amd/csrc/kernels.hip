@@ -45,6 +45,15 @@ __device__ __forceinline__ bool is_unknown(const DGeom& g, int d, int i, int j, 
   return ok;
 }
 
+// Workgroups go to the 8 XCDs (each with its own L2) round-robin by linear index;
+// renumbered with this bijection, each XCD takes a contiguous range of logical indices,
+// so neighbouring tiles, which share halo data, meet in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
   return bt.act != nullptr && bt.act[pair] == 0;
 }
@@ -269,14 +278,15 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   __shared__ T sA[NPAD * LDA];
   __shared__ int sslot[NPAD][4];
   __shared__ int64_t soff[NPAD];
-  const int pair = blockIdx.y;
+  const int lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const int pair = lb / gridDim.x;
   if (inactive(bt, pair)) return;
   const int tid = threadIdx.x;
   const int nv = sub.nH + 1;
   const int64_t NV = (int64_t)nv * nv * nv;
   gg += (int64_t)pair * vlen(g);
   Y += (int64_t)pair * NV * NPAD;
-  const int chunk = blockIdx.x;
+  const int chunk = lb - pair * gridDim.x;
   const int seg = sub.chunks[2 * chunk];
   const int first = sub.chunks[2 * chunk + 1];
   const int* sg = sub.segs + 8 * seg;
@@ -554,13 +564,31 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
   const T* __restrict__ Bp = Bm + (int64_t)prob * N * N;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = (blockIdx.x * 4 + wave) * rpw;
+  constexpr int kPer = (RC * kDenseMaxN + 255) / 256;   // gathered values per thread
   for (int rc = 0; rc < nr; rc += RC) {
     const int nrc = min(RC, nr - rc);
+    bool live[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) live[r] = r < nrc && !inactive(bt, prob * nr + rc + r);
+    // offsets first, then values: each phase's loads are independent and go out together
+    int64_t src[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      src[t] = -1;
+      if (e < RC * N) {
+        const int r = e / N, j = e - r * N;
+        if (live[r]) src[t] = (int64_t)(prob * nr + rc + r) * len + map[j];
+      }
+    }
+    T val[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) val[t] = (src[t] >= 0) ? g[src[t]] : T(0);
     __syncthreads();   // the previous chunk's rows are done with sg
-    for (int e = threadIdx.x; e < RC * N; e += blockDim.x) {
-      const int r = e / N, j = e - r * N;
-      const int pair = prob * nr + rc + r;
-      sg[e] = (r < nrc && !inactive(bt, pair)) ? g[(int64_t)pair * len + map[j]] : T(0);
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      if (e < RC * N) sg[e] = val[t];
     }
     __syncthreads();
     for (int ii = 0; ii < rpw; ++ii) {
@@ -581,10 +609,10 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
         const T v = wave_sum(acc[r]);
         if (lane == r) mine = v;
       }
-      if (lane < nrc) {
-        const int pair = prob * nr + rc + lane;
-        if (!inactive(bt, pair)) z[(int64_t)pair * len + map[i]] = mine;
-      }
+      bool w = false;
+#pragma unroll
+      for (int r = 0; r < RC; ++r) w = w || (lane == r && live[r]);
+      if (w) z[(int64_t)(prob * nr + rc + lane) * len + map[i]] = mine;
     }
   }
 }
@@ -813,6 +841,40 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, in
 // ---------------------------------------------------------------------------------
 // reductions (FP64)
 // ---------------------------------------------------------------------------------
+// Four consecutive values per access (16-byte vector loads and stores): vectors are
+// padded to multiples of 8 values and start 32-byte aligned, which the launchers check.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Quad;
+template <>
+struct Quad<double> {
+  static __device__ __forceinline__ void load(const double* __restrict__ p, double (&v)[4]) {
+    const d2v a = *reinterpret_cast<const d2v*>(p);
+    const d2v b = *reinterpret_cast<const d2v*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+  static __device__ __forceinline__ void store(double* __restrict__ p, const double (&v)[4]) {
+    d2v a, b;
+    a.x = v[0]; a.y = v[1]; b.x = v[2]; b.y = v[3];
+    *reinterpret_cast<d2v*>(p) = a;
+    *reinterpret_cast<d2v*>(p + 2) = b;
+  }
+};
+template <>
+struct Quad<float> {
+  static __device__ __forceinline__ void load(const float* __restrict__ p, float (&v)[4]) {
+    const f4v a = *reinterpret_cast<const f4v*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  static __device__ __forceinline__ void store(float* __restrict__ p, const float (&v)[4]) {
+    f4v a;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    *reinterpret_cast<f4v*>(p) = a;
+  }
+};
+
 template <typename TA>
 __global__ void __launch_bounds__(256) k_dot(const TA* __restrict__ a, const double* __restrict__ b,
                                              const double* __restrict__ c, double* __restrict__ part,
@@ -825,11 +887,22 @@ __global__ void __launch_bounds__(256) k_dot(const TA* __restrict__ a, const dou
   if (c) c += (int64_t)pair * len;
   part += (int64_t)pair * pstride;
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+  const int64_t n4 = len >> 2;
+#pragma unroll 2
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double av = (double)a[e];
-    s1 += av * b[e];
-    if (c) s2 += av * c[e];
+    TA av[4];
+    double bv[4];
+    Quad<TA>::load(a + 4 * e, av);
+    Quad<double>::load(b + 4 * e, bv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s1 += (double)av[k] * bv[k];
+    if (c) {
+      double cv[4];
+      Quad<double>::load(c + 4 * e, cv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s2 += (double)av[k] * cv[k];
+    }
   }
   s1 = block_sum(s1, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s1;
@@ -876,13 +949,29 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   part += (int64_t)pair * pstride;
   const double alpha = scal[i_num] / scal[i_den];
   double s = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+  const int64_t n4 = len >> 2;
+#pragma unroll 2
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
        e += (int64_t)gridDim.x * blockDim.x) {
-    u[e] += alpha * p[e];
-    const double rv = r[e] - alpha * q[e];
-    r[e] = rv;
-    if (r32) r32[e] = (float)rv;
-    s += rv * rv;
+    double uv[4], rv[4], pv[4], qv[4];
+    Quad<double>::load(u + 4 * e, uv);
+    Quad<double>::load(r + 4 * e, rv);
+    Quad<double>::load(p + 4 * e, pv);
+    Quad<double>::load(q + 4 * e, qv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uv[k] += alpha * pv[k];
+      rv[k] -= alpha * qv[k];
+      s += rv[k] * rv[k];
+    }
+    Quad<double>::store(u + 4 * e, uv);
+    Quad<double>::store(r + 4 * e, rv);
+    if (r32) {
+      float rf[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rf[k] = (float)rv[k];
+      Quad<float>::store(r32 + 4 * e, rf);
+    }
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -901,9 +990,18 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
   double beta;
   if (flexible) beta = -(scal[i_an] / scal[i_ad]) * scal[i_zq] / scal[i_den];
   else beta = scal[i_num] / scal[i_den];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
-       e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = (double)z[e] + beta * p[e];
+  const int64_t n4 = len >> 2;
+#pragma unroll 2
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    TZ zv[4];
+    double pv[4];
+    Quad<TZ>::load(z + 4 * e, zv);
+    Quad<double>::load(p + 4 * e, pv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = (double)zv[k] + beta * pv[k];
+    Quad<double>::store(p + 4 * e, pv);
+  }
 }
 
 __global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, int* __restrict__ act,
@@ -1048,6 +1146,12 @@ inline dim3 node_grid(const Geom& g, int nbx, int count) {
 }
 
 inline int nbx64(int n) { return (n + 1 + 63) / 64; }
+
+// the four-value vector kernels: every pair's vector starts 16-byte aligned
+template <typename T>
+inline bool quad_ok(int64_t len, const T* ptr) {
+  return len % 4 == 0 && reinterpret_cast<uintptr_t>(ptr) % 16 == 0;
+}
 
 // blocks per pair of the grid-stride vector kernels: enough for a level, fewer for many pairs
 inline unsigned vec_blocks(int64_t len, int count, unsigned cap) {
@@ -1194,6 +1298,7 @@ hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, 
 template <typename TA>
 hipError_t launch_dot(const TA* a, const double* b, const double* c, double* part, int64_t pstride,
                       double* out, int64_t len, const Bat& bt, hipStream_t st) {
+  if (!quad_ok(len, a) || !quad_ok(len, b) || (c && !quad_ok(len, c))) return hipErrorInvalidValue;
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
   hipLaunchKernelGGL((k_dot<TA>), dim3(nb, (unsigned)bt.count), dim3(256), 0, st, a, b, c, part, pstride,
                      len, bt);
@@ -1212,6 +1317,8 @@ hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nou
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
                             int i_num, int i_den, int i_out, float* r32, double* part,
                             int64_t pstride, int64_t len, const Bat& bt, hipStream_t st) {
+  if (!quad_ok(len, u) || !quad_ok(len, r) || !quad_ok(len, p) || !quad_ok(len, q) || (r32 && !quad_ok(len, r32)))
+    return hipErrorInvalidValue;
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
   hipLaunchKernelGGL(k_cg_update, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal, i_num,
                      i_den, r32, part, pstride, len, bt);
@@ -1224,6 +1331,7 @@ template <typename TZ>
 hipError_t launch_cg_direction(double* p, const TZ* z, const double* scal, int i_num, int i_den,
                                int flexible, int i_zq, int i_an, int i_ad, int64_t len, const Bat& bt,
                                hipStream_t st) {
+  if (!quad_ok(len, p) || !quad_ok(len, z)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_cg_direction<TZ>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count),
                      dim3(256), 0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, len, bt);
   return hipGetLastError();

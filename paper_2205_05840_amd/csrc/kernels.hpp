@@ -141,7 +141,7 @@ hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, i
 // in g).  Build, per chunk of columns j0 .. j0 + K - 1 (K = bt.nrhs, pair = problem * K +
 // column - j0): g = unit vectors, then the recursive V-cycle, then the results become
 // columns of Bm (N x N per problem, row-major, over the unknowns listed in map).
-constexpr int kDenseMaxN = 1536;
+constexpr int kDenseMaxN = 1176;   // the unknowns of an 8^3 level
 template <typename T>
 hipError_t launch_unit_cols(T* g, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
                             hipStream_t st);

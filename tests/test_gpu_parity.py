@@ -214,6 +214,11 @@ def test_pcg_edge_cases():
     with pytest.raises(_lib.NdmgError) as e:
         S.solve(bn)
     assert e.value.code == _lib.NDMG_EBREAKDOWN
+    # vectors one double off 16-byte alignment are refused before any work
+    buf = torch.zeros(S.vec_len + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.NdmgError) as e:
+        S.solve(b, u=buf[1:])
+    assert e.value.code == _lib.NDMG_EINVAL
 
 
 def test_curlcurl_form():
