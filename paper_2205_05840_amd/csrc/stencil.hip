@@ -607,7 +607,7 @@ hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, 
 }  // namespace
 
 int stencil_max_n() { return 256; }
-int stencil_min_n() { return 64; }
+int stencil_min_n() { return 32; }
 
 // partial sums per pair of the dot mode (FP64): one per tile of the chosen launch
 int stencil_blocks(const Geom& g, int count) {
