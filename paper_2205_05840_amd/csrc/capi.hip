@@ -431,6 +431,8 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
       NDMG_TRY(stg.put_vec(c, L.o_bofs, bo));
     }
     NDMG_TRY(stg.put_vec(c, L.o_lut, ndmg::slot_lookup(L.sub.s)));
+    if (!ndmg::boundary_patches_match(ndmg::boundary_patch_table()))
+      return fail(NDMG_EINVAL, "internal: subdomain boundary patch table differs from the kernels'");
     std::vector<int> sl;
     for (auto& q : ndmg::vertex_slots(L.sub.s)) {
       sl.push_back(q.d);
@@ -613,7 +615,7 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt
   double* q = at<double>(c, C.o_pq);
   double* part = at<double>(c, C.o_part);
   double* sc = at<double>(c, C.o_scal);
-  if (g.n > ndmg::stencil_min_n() && g.n <= ndmg::stencil_max_n()) {
+  if (g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n()) {
     NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, sc + kS_PQ, st));
   } else {
     NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));

@@ -105,6 +105,35 @@ std::vector<Slot> boundary_dofs(int s) {
   return out;
 }
 
+std::vector<int> boundary_patch_table() {
+  const std::vector<Slot> bd = boundary_dofs(2);
+  const std::vector<int> lut = slot_lookup(2);
+  std::vector<int> tab(bd.size() * 4, -1);
+  for (size_t e = 0; e < bd.size(); ++e) {
+    const int o[3] = {bd[e].dx, bd[e].dy, bd[e].dz};
+    const int d = bd[e].d;
+    int n = 0;
+    // candidate vertices: two along the edge, and across each transverse axis one where
+    // the offset is even (the edge lies on that plane) or two where it is odd
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const int c[3] = {cx, cy, cz};
+          bool cand = true;
+          for (int ax = 0; ax < 3; ++ax)
+            if (ax != d && o[ax] % 2 == 0 && c[ax] != o[ax] / 2) cand = false;
+          if (!cand) continue;
+          const int rel[3] = {o[0] - 2 * cx, o[1] - 2 * cy, o[2] - 2 * cz};
+          const int slot = lut[((d * 5 + rel[0] + 2) * 5 + rel[1] + 2) * 5 + rel[2] + 2];
+          if (slot < 0) continue;
+          if (n < 4) tab[e * 4 + n] = (cx + 2 * cy + 4 * cz) + 8 * slot;
+          ++n;
+        }
+    if (o[0] <= 1 && o[1] <= 1 && o[2] <= 1) tab[e * 4] |= 1 << 30;
+  }
+  return tab;
+}
+
 std::vector<Segment> vertex_segments(int nH, bool boundary_patches) {
   std::vector<Segment> out;
   for (int tz = 0; tz < 3; ++tz)

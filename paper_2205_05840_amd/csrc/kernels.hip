@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "kernels.hpp"
 #include "reduce.hpp"
@@ -504,6 +505,143 @@ __global__ void __launch_bounds__(256) k_coarse(const T* __restrict__ g, T* __re
     T s = T(0);
     for (int j = 0; j < N0; ++j) s += A0inv[(int64_t)i * N0 + j] * gl[j];
     z[map[i]] = s;
+  }
+}
+
+// Patches holding each boundary edge of a 2 x 2 x 2 subdomain, computed at compile time
+// by the rules of the host tables (vertex_slots, boundary_dofs, boundary_patch_table),
+// which setup compares against them: the boundary edges in order (direction, then z, y,
+// x offsets from the lower node, x fastest); per edge the corners cx + 2 cy + 4 cz and
+// patch slots of its 2 or 4 candidate vertices (two along the edge; across each
+// transverse axis the one the edge lies on, or both where the offset is odd).
+struct BoundaryPatches {
+  int n = 0;
+  int d[48] = {}, o[48][3] = {}, ncand[48] = {}, corner[48][4] = {}, slot[48][4] = {};
+  bool owned[48] = {};
+};
+
+constexpr int vertex_slot_index(int d, int dx, int dy, int dz) {
+  int idx = 0;
+  for (int dd = 0; dd < 3; ++dd)
+    for (int z = -2; z <= 2; ++z)
+      for (int y = -2; y <= 2; ++y)
+        for (int x = -2; x <= 2; ++x) {
+          const int o[3] = {x, y, z};
+          if (o[dd] < -2 || o[dd] > 1) continue;
+          const int a = (dd + 1) % 3, b = (dd + 2) % 3;
+          const int oa = o[a], ob = o[b];
+          const bool ok = (oa == 0 && ob > -2 && ob < 2) || (ob == 0 && oa != 0 && oa > -2 && oa < 2);
+          if (!ok) continue;
+          if (dd == d && x == dx && y == dy && z == dz) return idx;
+          ++idx;
+        }
+  return -1;
+}
+
+constexpr BoundaryPatches make_boundary_patches() {
+  BoundaryPatches t;
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z <= 2; ++z)
+      for (int y = 0; y <= 2; ++y)
+        for (int x = 0; x <= 2; ++x) {
+          const int o[3] = {x, y, z};
+          bool edge = true, interior = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            if (ax == d) edge = edge && (o[ax] >= 0 && o[ax] < 2);
+            else interior = interior && (o[ax] == 1);
+          }
+          if (!edge || interior) continue;
+          const int e = t.n++;
+          t.d[e] = d;
+          t.o[e][0] = x; t.o[e][1] = y; t.o[e][2] = z;
+          t.owned[e] = (x <= 1 && y <= 1 && z <= 1);
+          int nc = 0;
+          for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+              for (int cx = 0; cx < 2; ++cx) {
+                const int c[3] = {cx, cy, cz};
+                bool cand = true;
+                for (int ax = 0; ax < 3; ++ax)
+                  if (ax != d && o[ax] % 2 == 0 && c[ax] != o[ax] / 2) cand = false;
+                if (!cand) continue;
+                const int sl = vertex_slot_index(d, x - 2 * cx, y - 2 * cy, z - 2 * cz);
+                if (sl < 0 || nc >= 4) continue;
+                t.corner[e][nc] = cx + 2 * cy + 4 * cz;
+                t.slot[e][nc] = sl;
+                ++nc;
+              }
+          t.ncand[e] = nc;
+        }
+  return t;
+}
+
+constexpr BoundaryPatches kBP = make_boundary_patches();
+static_assert(kBP.n == 48, "48 boundary edges of a 2 x 2 x 2 subdomain");
+
+// Interface sum and harmonic extension in one pass, one thread per subdomain T: every
+// edge on the boundary of T lies in the patches of corners of T only, so the thread
+// forms w on its 48 boundary edges straight from the patch results of its 8 corners
+// (as the interface sum takes them, kBP), then z_I (assign ? =, +=) eta (zi_I -
+// X_T w_dT) on its 6 interior unknowns and z (assign ? =, +=) eta w on the interface
+// unknowns it owns (offsets in {0, 1} from its lower node): every unknown of the level
+// is written exactly once and w never goes to memory.  Edges on the domain boundary sum
+// to zero (their slots are absent from every patch that lists them).  All table lookups
+// are compile-time constants, so the 160 loads of a thread go out together.
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, const T* __restrict__ zi,
+                                                       T* __restrict__ z, const T* __restrict__ XT, DGeom g,
+                                                       DSub sub, T eta, int assign, Bat bt, int nbx) {
+  constexpr int NB = 48, NPAD = 64;
+  __shared__ T sX[6 * NB];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
+  XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
+  for (int e = threadIdx.x; e < 6 * NB; e += blockDim.x) sX[e] = XT[e];
+  __syncthreads();
+  const int nH = sub.nH;
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH) return;
+  const int nv = nH + 1;
+  const int64_t NV = (int64_t)nv * nv * nv;
+  const int64_t voff = (int64_t)pair * vlen(g);
+  zi += voff;
+  z += voff;
+  const int64_t vrow0 = ((int64_t)c * nv + b) * nv + a;
+  const T* __restrict__ Yp = Y + (int64_t)pair * NV * NPAD + vrow0;
+  const int64_t cofs[8] = {0, 1, nv, nv + 1, (int64_t)nv * nv, (int64_t)nv * nv + 1, (int64_t)nv * nv + nv,
+                           (int64_t)nv * nv + nv + 1};
+  T wv[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < kBP.ncand[e]) acc += Yp[(int64_t)kBP.slot[e][t] * NV + cofs[kBP.corner[e][t]]];
+    wv[e] = acc;
+  }
+  const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
+  // interior unknown t: direction d = t / 2 at offset 1 across d and (t & 1) along d
+  // (the order of interior_offsets_s2)
+  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
+  const int64_t all1 = st[0] + st[1] + st[2];
+#pragma unroll 1
+  for (int t = 0; t < 6; ++t) {
+    const int d = t >> 1;
+    const int64_t off = d * g.B + base + all1 - (1 - (t & 1)) * (d == 0 ? st[0] : (d == 1 ? st[1] : st[2]));
+    T q = T(0);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) q += sX[t * NB + e] * wv[e];
+    const T old = assign ? T(0) : z[off];
+    z[off] = old + eta * (zi[off] - q);
+  }
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    if (kBP.owned[e]) {
+      const int64_t off = kBP.d[e] * g.B + base + lin(g, kBP.o[e][0], kBP.o[e][1], kBP.o[e][2]);
+      const T old = assign ? T(0) : z[off];
+      z[off] = old + eta * wv[e];
+    }
   }
 }
 
@@ -1169,7 +1307,7 @@ inline unsigned vec_blocks(int64_t len, int count, unsigned cap) {
 template <typename T>
 hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st) {
-  if (g.n > stencil_min_n() && g.n <= stencil_max_n()) {
+  if (g.n > stencil_min_n(bt.count) && g.n <= stencil_max_n()) {
     const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, nullptr, st);
     if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
   }
@@ -1216,15 +1354,8 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
   if (sub.nchunks > 0)
     hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks, (unsigned)bt.count), dim3(256), 0,
                        st, L.gg, L.Y, L.Sinv, dg, sub, bt);
-  {
-    const int bx = (g.n <= 64) ? 64 : 128;
-    const int nbp = (g.n + bx - 1) / bx;
-    const dim3 pg((unsigned)(nbp * bt.count), (unsigned)(g.n + 1), (unsigned)(g.n + 1));
-    hipLaunchKernelGGL((k_sm_pull<T, 2>), pg, dim3(bx), 0, st, L.Y, L.w, z, dg, sub, (T)eta, assign, bt,
-                       nbp);
-  }
-  hipLaunchKernelGGL((k_sm_extend_s2<T>), eg, dim3(64), 0, st, L.w, L.zi, z, L.XT, sub.bofs, dg, sub.nH,
-                     (T)eta, assign, bt, nbs);
+  hipLaunchKernelGGL((k_sm_pull_extend<T>), eg, dim3(64), 0, st, L.Y, L.zi, z, L.XT, dg, sub, (T)eta, assign, bt,
+                     nbs);
   return hipGetLastError();
 }
 
@@ -1385,6 +1516,18 @@ hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& 
   hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, nparts, (int64_t)0, 1, out,
                      Bat{1, 1, nullptr, nullptr});
   return hipGetLastError();
+}
+
+// The compile-time table of the interface-sum-and-extension kernel against the host's.
+bool boundary_patches_match(const std::vector<int>& tab) {
+  if ((int)tab.size() != 4 * kBP.n) return false;
+  for (int e = 0; e < kBP.n; ++e)
+    for (int t = 0; t < 4; ++t) {
+      int want = (t < kBP.ncand[e]) ? kBP.corner[e][t] + 8 * kBP.slot[e][t] : -1;
+      if (t == 0 && kBP.owned[e]) want |= 1 << 30;
+      if (tab[e * 4 + t] != want) return false;
+    }
+  return true;
 }
 
 // explicit instantiations

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "ndmg_internal.hpp"
 
@@ -47,6 +48,10 @@ struct DSub {
   const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };
 
+// True when the kernels' compile-time table of the patches holding each subdomain
+// boundary edge equals the host's boundary_patch_table().
+bool boundary_patches_match(const std::vector<int>& tab);
+
 template <typename T>
 struct LevelPtrs {
   T* z;       // solution / correction
@@ -61,7 +66,7 @@ struct LevelPtrs {
 };
 
 int stencil_max_n();
-int stencil_min_n();   // the plane-marching kernel serves stencil_min_n() < n <= stencil_max_n()
+int stencil_min_n(int count);   // the plane-marching kernel serves stencil_min_n(pairs) < n <= stencil_max_n()
 int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the dot mode
 // groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
 // S^{-1} stagings), one on small levels (more workgroups)

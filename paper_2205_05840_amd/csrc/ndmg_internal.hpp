@@ -54,6 +54,14 @@ std::vector<Slot> interior_dofs(int s);
 // node offsets in [0, s] across, not interior), same ordering: 3 (s+1)^2 s - nI of them.
 std::vector<Slot> boundary_dofs(int s);
 
+// For each boundary dof of a subdomain (order of boundary_dofs) the vertex patches that
+// hold it, as the sum of the interface correction w = sum_V R_V^T y_V takes them: four
+// codes per dof, corner + 8 slot (corner = cx + 2 cy + 4 cz of the subdomain's corners,
+// slot in the patch order of vertex_slots), -1 where there are fewer than four; bit 30
+// marks dofs the subdomain owns (local offsets all in {0, 1}: each interface unknown is
+// owned by exactly one subdomain, the one at floor(o / 2)).  Subdomain size 2 only.
+std::vector<int> boundary_patch_table();
+
 // Segment of vertices sharing a patch type: a box of the vertex grid (0..nH)^3.
 struct Segment {
   int type;        // tx + 3 ty + 9 tz, t = 0 low face, 1 inside, 2 high face

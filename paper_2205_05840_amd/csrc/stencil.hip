@@ -607,11 +607,14 @@ hipError_t launch_r(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, 
 }  // namespace
 
 int stencil_max_n() { return 256; }
-int stencil_min_n() { return 32; }
+// Below this size the one-thread-per-node kernel is used: n <= 32 for a single pair (the
+// plane kernel's few tiles lose to its launch there), n <= 16 for batches of four or more
+// pairs, where the tiles of all pairs fill the chip.
+int stencil_min_n(int count) { return count >= 4 ? 16 : 32; }
 
 // partial sums per pair of the dot mode (FP64): one per tile of the chosen launch
 int stencil_blocks(const Geom& g, int count) {
-  if (g.n <= stencil_min_n() || g.n > stencil_max_n()) return 0;
+  if (g.n <= stencil_min_n(count) || g.n > stencil_max_n()) return 0;
   int which = 0, kz = 8;
   Variant var{};
   const bool ok = (g.n <= 128) ? pick<double, 2>(g.n, count, 2, &which, &kz, &var)
@@ -623,7 +626,7 @@ template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                           double* part, int64_t pstride, double* dot, hipStream_t st) {
   // rows span 64 R positions: R = 2 up to n = 128, R = 4 up to 256
-  if (g.n <= stencil_min_n()) return hipErrorInvalidValue;
+  if (g.n <= stencil_min_n(bt.count)) return hipErrorInvalidValue;
   if (g.n <= 128) return launch_r<T, 2>(x, b, y, g, bt, mode, part, pstride, dot, st);
   if (g.n <= 256) return launch_r<T, 4>(x, b, y, g, bt, mode, part, pstride, dot, st);
   return hipErrorInvalidValue;
