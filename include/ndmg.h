@@ -146,9 +146,11 @@ int ndmg_batch_layout(const ndmg_ctx* ctx, int prob, int64_t info[6]);
  * ndmg_pcg_solve, each pair with its own CG scalars and stopping test: a pair that has
  * converged (or broken down) is left out of every later kernel.  d_b and d_u are batch
  * vectors.  iters and relres (host, may be NULL) receive nprob * nrhs entries, entry
- * p * nrhs + r for right-hand side r of problem p.  The stream is synchronised once per
- * iteration of the slowest pair; with use_graphs one iteration of the whole batch (all
- * sizes) is replayed from one captured graph.  d_b and d_u must be 16-byte aligned.
+ * p * nrhs + r for right-hand side r of problem p.  The host waits once per iteration
+ * for the count of pairs still active after the previous iteration, with the next
+ * iteration already enqueued (so one iteration with every pair inactive, whose kernels
+ * return at once, follows the last convergence); with use_graphs one iteration of the
+ * whole batch (all sizes) is replayed from one captured graph.  d_b and d_u must be 16-byte aligned.
  * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV (some pair reached maxit; every output
  * still written), NDMG_EBREAKDOWN (some pair broke down). */
 int ndmg_pcg_solve_batched(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
@@ -170,8 +172,9 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
  * iterations.  iters and relres (host pointers, may be NULL) receive the iteration
  * count and the final relative residual ||r|| / ||b|| (computed on the device, the
  * value the stopping test used).  The context must hold one pair (one problem, one
- * right-hand side).  The stream is synchronised once per iteration for the convergence
- * test.  With use_graphs, the iterations after the first
+ * right-hand side).  The host waits once per iteration for the convergence test of the
+ * previous iteration while the next one is already enqueued.  With use_graphs, the
+ * iterations after the first
  * are replayed from two HIP graphs captured on first use (and again whenever d_u
  * changes); the stream must then not be the null stream and must not be captured by
  * the caller.  d_b and d_u must be 16-byte aligned (the CG vector kernels move four

@@ -98,7 +98,6 @@ struct Plan {
   std::vector<int> prob_cls, prob_pos;
   int64_t total_len = 0;           // batch vector length
   int npairs = 0;
-  size_t o_nact = 0;               // one int per class
   size_t bytes = 0;
 };
 
@@ -111,7 +110,9 @@ struct ndmg_ctx {
   std::vector<hipStream_t> side;           // class i >= 1 runs on side[i - 1]
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
-  int* host_nact = nullptr;                // pinned, one per class
+  int* host_nact = nullptr;                // pinned (coherent, mapped), two sets of one per class
+  int* dev_nact = nullptr;                 // its device address: the convergence kernel writes it
+  hipEvent_t ev_nact[2] = {nullptr, nullptr};   // recorded after the writes of each set
   double* host_scal = nullptr;             // pinned, kScalStride per pair
   int* host_int = nullptr;                 // pinned, iters and status per pair
   hipGraphExec_t gexec[2] = {nullptr, nullptr};   // CG iteration body, by scalar-slot parity
@@ -289,7 +290,6 @@ int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts
     pl->npairs += C.count;
   }
   pl->total_len = voff;
-  pl->o_nact = take(pl->cls.size() * sizeof(int));
   pl->bytes = off;
   return NDMG_OK;
 }
@@ -630,11 +630,13 @@ bool flexible_beta(const Plan& pl) {
   return pl.opts.flexible > 0 || (pl.opts.flexible < 0 && pl.opts.precision == NDMG_PREC_FP32);
 }
 
-int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, hipStream_t st) {
+// The convergence test of an iteration; its count of active pairs goes straight to host
+// set `set` (iterations alternate between the two sets).
+int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, int set, hipStream_t st) {
   Cls& C = c->plan.cls[ci];
   NDMG_HIP(ndmg::launch_pcg_check(at<double>(c, C.o_scal), at<int>(c, C.o_act), at<int>(c, C.o_iters),
                                   at<int>(c, C.o_status), C.count, i_rz,
-                                  at<int>(c, c->plan.o_nact) + ci, st));
+                                  c->dev_nact + set * c->plan.cls.size() + ci, st));
   return NDMG_OK;
 }
 
@@ -665,7 +667,7 @@ int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol
     NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
   }
   NDMG_TRY(cg_apply_update(c, C, u, kS_RZA, act, st));
-  return pcg_check(c, ci, kS_RZA, st);
+  return pcg_check(c, ci, kS_RZA, 0, st);
 }
 
 // One CG iteration after the first for one class: z = B r; s[nxt] = r . z (and
@@ -694,7 +696,7 @@ int pcg_body(ndmg_ctx* c, size_t ci, double* u, int cur, int nxt, hipStream_t st
                                                st));
   }
   NDMG_TRY(cg_apply_update(c, C, u, nxt, act, st));
-  return pcg_check(c, ci, nxt, st);
+  return pcg_check(c, ci, nxt, cur == kS_RZA ? 1 : 0, st);
 }
 
 // Run fn(ci, stream) for every class: class 0 on the context's stream, class i >= 1 on
@@ -758,14 +760,19 @@ int body_all(ndmg_ctx* c, double* u, int cur, int nxt) {
   return NDMG_OK;
 }
 
-// Pairs still active, summed over the classes (synchronises the stream).
-int active_pairs(ndmg_ctx* c, int* out) {
+// Marks the end of the writes of host set `set` (the counts of active pairs, one per
+// class, written by the convergence test of the iteration just enqueued).
+int post_active(ndmg_ctx* c, int set) {
+  NDMG_HIP(hipEventRecord(c->ev_nact[set], c->st));
+  return NDMG_OK;
+}
+
+// Pairs still active in host set `set`, summed over the classes (waits for its event).
+int active_pairs(ndmg_ctx* c, int set, int* out) {
   const size_t nc = c->plan.cls.size();
-  NDMG_HIP(hipMemcpyAsync(c->host_nact, at<int>(c, c->plan.o_nact), nc * sizeof(int),
-                          hipMemcpyDeviceToHost, c->st));
-  NDMG_HIP(hipStreamSynchronize(c->st));
+  NDMG_HIP(hipEventSynchronize(c->ev_nact[set]));
   int t = 0;
-  for (size_t i = 0; i < nc; ++i) t += c->host_nact[i];
+  for (size_t i = 0; i < nc; ++i) t += c->host_nact[set * nc + i];
   *out = t;
   return NDMG_OK;
 }
@@ -778,13 +785,21 @@ int pcg_all(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int
     const Cls& C = pl.cls[ci];
     return pcg_prologue(c, ci, b + C.vec_off, u + C.vec_off, rtol, st);
   }));
-  int nact = 0;
-  NDMG_TRY(active_pairs(c, &nact));
+  // Iteration it is enqueued before the host reads the count after iteration it - 1, so
+  // the device never waits for the host; when that count is zero, iteration it runs with
+  // every pair inactive (each kernel returns at once) and the loop ends.
+  NDMG_TRY(post_active(c, 0));
   int cur = kS_RZA, nxt = kS_RZB;
-  for (int it = 2; it <= maxit && nact > 0; ++it) {
-    NDMG_TRY(body_all(c, u, cur, nxt));
-    std::swap(cur, nxt);
-    NDMG_TRY(active_pairs(c, &nact));
+  for (int it = 2, set = 0;; ++it, set ^= 1) {
+    const bool launch = it <= maxit;
+    if (launch) {
+      NDMG_TRY(body_all(c, u, cur, nxt));
+      std::swap(cur, nxt);
+      NDMG_TRY(post_active(c, set ^ 1));
+    }
+    int nact = 0;
+    NDMG_TRY(active_pairs(c, set, &nact));
+    if (!launch || nact == 0) break;
   }
   // per-pair results
   int nbroken = 0, nrun = 0, first_bad = -1;
@@ -840,10 +855,16 @@ void release(ndmg_ctx* c) {
   for (auto e : c->ev_join)
     if (e) (void)hipEventDestroy(e);
   c->ev_join.clear();
+  for (auto& e : c->ev_nact)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   if (c->host_nact) (void)hipHostFree(c->host_nact);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   if (c->host_int) (void)hipHostFree(c->host_int);
   c->host_nact = nullptr;
+  c->dev_nact = nullptr;
   c->host_scal = nullptr;
   c->host_int = nullptr;
 }
@@ -900,7 +921,9 @@ int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const 
   if (nc > 1) NDMG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   int maxcount = 0;
   for (auto& C : pl.cls) maxcount = std::max(maxcount, C.count);
-  NDMG_HIP(hipHostMalloc((void**)&c->host_nact, nc * sizeof(int), hipHostMallocDefault));
+  NDMG_HIP(hipHostMalloc((void**)&c->host_nact, 2 * nc * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  NDMG_HIP(hipHostGetDevicePointer((void**)&c->dev_nact, c->host_nact, 0));
+  for (auto& e : c->ev_nact) NDMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   NDMG_HIP(hipHostMalloc((void**)&c->host_scal, (size_t)maxcount * kScalStride * sizeof(double),
                          hipHostMallocDefault));
   NDMG_HIP(hipHostMalloc((void**)&c->host_int, (size_t)maxcount * 2 * sizeof(int), hipHostMallocDefault));

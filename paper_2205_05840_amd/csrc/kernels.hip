@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __
   const int pair = blockIdx.x / nbx;
   const int I = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int J = blockIdx.y, K = blockIdx.z;
-  if (I > c.n || inactive(bt, pair)) return;
+  if (I >= c.n || inactive(bt, pair)) return;
   restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K);
 }
 
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T*
   const int pair = blockIdx.x / nbx;
   const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
-  if (i > f.n || inactive(bt, pair)) return;
+  if (i >= f.n || inactive(bt, pair)) return;
   prolong_node(ec + (int64_t)pair * vlen(c), zf + (int64_t)pair * vlen(f), f, c, i, j, k);
 }
 
@@ -226,17 +226,6 @@ __device__ __forceinline__ void interior_sub_s2(const T* __restrict__ r, T* __re
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) k_sm_interior_s2(const T* __restrict__ r, T* __restrict__ zi,
-                                                       const T* __restrict__ ATinv, DGeom g,
-                                                       int nH, Bat bt, int nbx) {
-  const int pair = blockIdx.x / nbx;
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH || inactive(bt, pair)) return;
-  interior_sub_s2(r + (int64_t)pair * vlen(g), zi + (int64_t)pair * vlen(g),
-                  ATinv + (int64_t)(pair / bt.nrhs) * 36, g, a, b, c);
-}
 
 // Operands of the 16x16x4 MFMAs: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result register q of lane l holds D[row(l / 16, q)][l % 16], where (measured on
@@ -414,26 +403,6 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ Y, T* __restrict
   }
 }
 
-template <typename T, int S>
-__global__ void __launch_bounds__(128) k_sm_pull(const T* __restrict__ Y, T* __restrict__ w,
-                                                 T* __restrict__ z, DGeom g, DSub sub, T eta,
-                                                 int assign, Bat bt, int nbx) {
-  constexpr int W = 2 * S + 1;
-  constexpr int NG = 6 * S * (4 * S - 3);
-  constexpr int NPAD = (NG + 15) / 16 * 16;
-  __shared__ int slut[3 * W * W * W];
-  const int pair = blockIdx.x / nbx;
-  if (inactive(bt, pair)) return;
-  for (int e = threadIdx.x; e < 3 * W * W * W; e += blockDim.x) slut[e] = sub.lut[e];
-  __syncthreads();
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= g.n) return;   // i = n is never an unknown
-  const int nv = sub.nH + 1;
-  const int64_t NV = (int64_t)nv * nv * nv;
-  pull_node<T, S>(Y + (int64_t)pair * NV * NPAD, w + (int64_t)pair * vlen(g), z + (int64_t)pair * vlen(g), g,
-                  slut, nv, NV, eta, assign, i, j, k);
-}
 
 // Harmonic extension into subdomain interiors and the final interior update:
 // z_I (assign ? =, +=) eta (zi_I - X_T w_dT), X_T = A_T^{-1} A_{I, dT} (6 x 48 for s = 2),
@@ -465,25 +434,6 @@ __device__ __forceinline__ void extend_sub_s2(const T* __restrict__ w, const T* 
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) k_sm_extend_s2(const T* __restrict__ w, const T* __restrict__ zi,
-                                                     T* __restrict__ z, const T* __restrict__ XT,
-                                                     const int64_t* __restrict__ bofs, DGeom g,
-                                                     int nH, T eta, int assign, Bat bt, int nbx) {
-  __shared__ T sX[6 * 48];
-  __shared__ int64_t sofs[48];
-  const int pair = blockIdx.x / nbx;
-  if (inactive(bt, pair)) return;
-  XT += (int64_t)(pair / bt.nrhs) * 6 * 48;
-  for (int e = threadIdx.x; e < 6 * 48; e += blockDim.x) sX[e] = XT[e];
-  for (int e = threadIdx.x; e < 48; e += blockDim.x) sofs[e] = bofs[e];
-  __syncthreads();
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH) return;
-  const int64_t off = (int64_t)pair * vlen(g);
-  extend_sub_s2(w + off, zi + off, z + off, sX, sofs, g, eta, assign, a, b, c);
-}
 
 // ---------------------------------------------------------------------------------
 // coarsest level: dense inverse (one workgroup per pair)
@@ -578,6 +528,100 @@ constexpr BoundaryPatches make_boundary_patches() {
 constexpr BoundaryPatches kBP = make_boundary_patches();
 static_assert(kBP.n == 48, "48 boundary edges of a 2 x 2 x 2 subdomain");
 
+// The interface unknowns a subdomain owns (offsets in {0, 1} from its lower node, not
+// interior), with the subdomains whose boundary holds each: T + q for q in {-1, 0}^3
+// (step -1 across each transverse axis where the offset is 0, i.e. the edge lies on that
+// face plane), and the edge's index among the boundary edges of T + q.
+struct OwnedInterface {
+  int n = 0;
+  int d[18] = {}, o[18][3] = {}, nadj[18] = {}, q[18][4] = {}, e[18][4] = {};
+};
+constexpr OwnedInterface make_owned_interface() {
+  OwnedInterface t;
+  for (int e = 0; e < kBP.n; ++e) {
+    if (!kBP.owned[e]) continue;
+    const int k = t.n++;
+    const int d = kBP.d[e];
+    t.d[k] = d;
+    for (int ax = 0; ax < 3; ++ax) t.o[k][ax] = kBP.o[e][ax];
+    const int b = (d + 1) % 3, c = (d + 2) % 3;
+    int na = 0;
+    for (int sb = 0; sb < 2; ++sb)
+      for (int sc = 0; sc < 2; ++sc) {
+        if ((sb && kBP.o[e][b] != 0) || (sc && kBP.o[e][c] != 0)) continue;
+        int qv[3] = {0, 0, 0};
+        qv[b] = -sb;
+        qv[c] = -sc;
+        // offsets of the edge from the lower node of T + q
+        const int l[3] = {kBP.o[e][0] - 2 * qv[0], kBP.o[e][1] - 2 * qv[1], kBP.o[e][2] - 2 * qv[2]};
+        int idx = -1;
+        for (int f = 0; f < kBP.n; ++f)
+          if (kBP.d[f] == d && kBP.o[f][0] == l[0] && kBP.o[f][1] == l[1] && kBP.o[f][2] == l[2]) idx = f;
+        t.q[k][na] = (-qv[0]) + 2 * (-qv[1]) + 4 * (-qv[2]);
+        t.e[k][na] = idx;
+        ++na;
+      }
+    t.nadj[k] = na;
+  }
+  return t;
+}
+constexpr OwnedInterface kOI = make_owned_interface();
+static_assert(kOI.n == 18, "18 interface unknowns owned per subdomain");
+
+// Condensed interface residual g_G = r_G - (A z_I)_G with z_I = A_T^{-1} r_I on every
+// subdomain: the interior unknowns of T couple only to edges of T, so (A z_I)_e is the
+// sum over the subdomains T whose boundary holds e of (X_T^T r_I(T))_e, X_T^T =
+// A_{dT,I} A_T^{-1} (A_T symmetric).  One thread per subdomain T writes g on the 18
+// interface unknowns T owns, from r there and the interior residuals of T and its
+// neighbours T - e_x, T - e_y, T - e_z and their pairwise sums (all tables compile-time).
+// Other entries of g are left untouched (never read).
+template <typename T>
+__global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* __restrict__ gg,
+                                                    const T* __restrict__ XT, DGeom g, int nH, Bat bt, int nbx) {
+  constexpr int NB = 48;
+  __shared__ T sX[6 * NB];
+  const int pair = blockIdx.x / nbx;
+  if (inactive(bt, pair)) return;
+  XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
+  for (int e = threadIdx.x; e < 6 * NB; e += blockDim.x) sX[e] = XT[e];
+  __syncthreads();
+  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, c = blockIdx.z;
+  if (a >= nH) return;
+  const int64_t voff = (int64_t)pair * vlen(g);
+  r += voff;
+  gg += voff;
+  // interior residuals of T - q (q = bits x, y, z; not all three: never needed), from a
+  // clamped subdomain where T - q leaves the domain (those values are never used)
+  T rI[8][6];
+#pragma unroll
+  for (int qq = 0; qq < 7; ++qq) {
+    const int sa = max(a - (qq & 1), 0), sb = max(b - ((qq >> 1) & 1), 0), sc = max(c - (qq >> 2), 0);
+    int64_t off[6];
+    interior_offsets_s2(g, lin(g, 2 * sa, 2 * sb, 2 * sc), off);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) rI[qq][t] = r[off[t]];
+  }
+  const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const int d = kOI.d[k];
+    const int gi = 2 * a + kOI.o[k][0], gj = 2 * b + kOI.o[k][1], gk = 2 * c + kOI.o[k][2];
+    if (!is_unknown(g, d, gi, gj, gk)) continue;   // on the domain boundary
+    const int64_t off = d * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2]);
+    T acc = r[off];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (m < kOI.nadj[k]) {
+        const int qq = kOI.q[k][m], e = kOI.e[k][m];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc -= sX[t * NB + e] * rI[qq][t];
+      }
+    }
+    gg[off] = acc;
+  }
+}
+
 // Interface sum and harmonic extension in one pass, one thread per subdomain T: every
 // edge on the boundary of T lies in the patches of corners of T only, so the thread
 // forms w on its 48 boundary edges straight from the patch results of its 8 corners
@@ -588,15 +632,19 @@ static_assert(kBP.n == 48, "48 boundary edges of a 2 x 2 x 2 subdomain");
 // to zero (their slots are absent from every patch that lists them).  All table lookups
 // are compile-time constants, so the 160 loads of a thread go out together.
 template <typename T>
-__global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, const T* __restrict__ zi,
-                                                       T* __restrict__ z, const T* __restrict__ XT, DGeom g,
-                                                       DSub sub, T eta, int assign, Bat bt, int nbx) {
+__global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, const T* __restrict__ r,
+                                                       T* __restrict__ z, const T* __restrict__ XT,
+                                                       const T* __restrict__ ATinv, DGeom g, DSub sub, T eta,
+                                                       int assign, Bat bt, int nbx) {
   constexpr int NB = 48, NPAD = 64;
   __shared__ T sX[6 * NB];
+  __shared__ T sA[36];
   const int pair = blockIdx.x / nbx;
   if (inactive(bt, pair)) return;
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
+  ATinv += (int64_t)(pair / bt.nrhs) * 36;
   for (int e = threadIdx.x; e < 6 * NB; e += blockDim.x) sX[e] = XT[e];
+  for (int e = threadIdx.x; e < 36; e += blockDim.x) sA[e] = ATinv[e];
   __syncthreads();
   const int nH = sub.nH;
   const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
@@ -605,7 +653,7 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   const int nv = nH + 1;
   const int64_t NV = (int64_t)nv * nv * nv;
   const int64_t voff = (int64_t)pair * vlen(g);
-  zi += voff;
+  r += voff;
   z += voff;
   const int64_t vrow0 = ((int64_t)c * nv + b) * nv + a;
   const T* __restrict__ Yp = Y + (int64_t)pair * NV * NPAD + vrow0;
@@ -621,19 +669,22 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
     wv[e] = acc;
   }
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
-  // interior unknown t: direction d = t / 2 at offset 1 across d and (t & 1) along d
-  // (the order of interior_offsets_s2)
-  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
-  const int64_t all1 = st[0] + st[1] + st[2];
+  // interior unknowns (the order of interior_offsets_s2): z_I += eta (A_T^{-1} r_I - X_T w)
+  int64_t ioff[6];
+  interior_offsets_s2(g, base, ioff);
+  T rI[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) rI[t] = r[ioff[t]];
 #pragma unroll 1
   for (int t = 0; t < 6; ++t) {
-    const int d = t >> 1;
-    const int64_t off = d * g.B + base + all1 - (1 - (t & 1)) * (d == 0 ? st[0] : (d == 1 ? st[1] : st[2]));
     T q = T(0);
 #pragma unroll
     for (int e = 0; e < NB; ++e) q += sX[t * NB + e] * wv[e];
-    const T old = assign ? T(0) : z[off];
-    z[off] = old + eta * (zi[off] - q);
+    T zi = T(0);
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2) zi += sA[t * 6 + s2] * rI[s2];
+    const T old = assign ? T(0) : z[ioff[t]];
+    z[ioff[t]] = old + eta * (zi - q);
   }
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
@@ -687,9 +738,10 @@ __global__ void k_gather_cols(const T* __restrict__ z, T* __restrict__ Bm, const
 
 // z[map[i]] = sum_j Bm[i][j] g[map[j]] for every pair of a problem.  Block (x, problem):
 // the problem's right-hand sides, RC at a time, are gathered into LDS; wave w takes rows
-// (4 x + w) rpw .. + rpw - 1, lanes stride over j and the row sums are wave reductions,
-// so each row of Bm is read once per RC right-hand sides.  Non-unknown entries of z are
-// not written (zero by the layout contract).
+// (4 x + w) rpw .. + rpw - 1, lane l holds the entries j = l + 64 jj of a row (all its
+// loads issued at once; the first row's before the gather) and the row sums are wave
+// reductions, so each row of Bm is read once per RC right-hand sides.  Non-unknown
+// entries of z are not written (zero by the layout contract).
 template <typename T, int RC>
 __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T* __restrict__ z,
                                                       const T* __restrict__ Bm,
@@ -697,17 +749,41 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
                                                       int rpw, Bat bt) {
   extern __shared__ __align__(16) unsigned char dense_smem[];
   T* sg = reinterpret_cast<T*>(dense_smem);
+  constexpr int NJ = (kDenseMaxN + 63) / 64;           // row entries per lane
+  constexpr int kPer = (RC * kDenseMaxN + 255) / 256;   // gathered values per thread
   const int prob = blockIdx.y;
   const int nr = bt.nrhs;
   const T* __restrict__ Bp = Bm + (int64_t)prob * N * N;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = (blockIdx.x * 4 + wave) * rpw;
-  constexpr int kPer = (RC * kDenseMaxN + 255) / 256;   // gathered values per thread
+  // entries of row i (rows past N and entries past N read entry 0 and are masked)
+  auto load_row = [&](int i, T (&bv)[NJ]) {
+    const T* __restrict__ Brow = Bp + (int64_t)(i < N ? i : 0) * N;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int j = lane + 64 * jj;
+      bv[jj] = Brow[j < N ? j : 0];
+    }
+  };
+  auto row_sums = [&](const T (&bv)[NJ], int rc, T (&acc)[RC]) {
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = T(0);
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int j = lane + 64 * jj;
+      if (j < N) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] += bv[jj] * sg[r * N + j];
+      }
+    }
+  };
   for (int rc = 0; rc < nr; rc += RC) {
     const int nrc = min(RC, nr - rc);
     bool live[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) live[r] = r < nrc && !inactive(bt, prob * nr + rc + r);
+    T bcur[NJ];
+    load_row(row0, bcur);
     // offsets first, then values: each phase's loads are independent and go out together
     int64_t src[kPer];
 #pragma unroll
@@ -732,15 +808,10 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
     for (int ii = 0; ii < rpw; ++ii) {
       const int i = row0 + ii;
       if (i >= N) break;
-      const T* __restrict__ Brow = Bp + (int64_t)i * N;
+      T bnext[NJ];
+      if (ii + 1 < rpw) load_row(i + 1, bnext);
       T acc[RC];
-#pragma unroll
-      for (int r = 0; r < RC; ++r) acc[r] = T(0);
-      for (int j = lane; j < N; j += 64) {
-        const T b = Brow[j];
-#pragma unroll
-        for (int r = 0; r < RC; ++r) acc[r] += b * sg[r * N + j];
-      }
+      row_sums(bcur, rc, acc);
       T mine = T(0);
 #pragma unroll
       for (int r = 0; r < RC; ++r) {
@@ -751,6 +822,8 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
 #pragma unroll
       for (int r = 0; r < RC; ++r) w = w || (lane == r && live[r]);
       if (w) z[(int64_t)(prob * nr + rc + lane) * len + map[i]] = mine;
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) bcur[jj] = bnext[jj];
     }
   }
 }
@@ -1285,6 +1358,13 @@ inline dim3 node_grid(const Geom& g, int nbx, int count) {
 
 inline int nbx64(int n) { return (n + 1 + 63) / 64; }
 
+// Grid over the nodes [0, n)^3 only: every unknown has all coordinates below n (the
+// transfers leave the other entries, zero by the layout contract, untouched).
+inline dim3 inner_grid(const Geom& g, int nbx, int count) {
+  return dim3((unsigned)(nbx * count), (unsigned)g.n, (unsigned)g.n);
+}
+inline int nbx_inner(int n) { return (n + 63) / 64; }
+
 // the four-value vector kernels: every pair's vector starts 16-byte aligned
 template <typename T>
 inline bool quad_ok(int64_t len, const T* ptr) {
@@ -1324,8 +1404,8 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
 template <typename T>
 hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, const Bat& bt,
                            hipStream_t st) {
-  const int nbx = nbx64(c.n);
-  hipLaunchKernelGGL((k_restrict<T>), node_grid(c, nbx, bt.count), dim3(64), 0, st, rf, gc, dgeom(f),
+  const int nbx = nbx_inner(c.n);
+  hipLaunchKernelGGL((k_restrict<T>), inner_grid(c, nbx, bt.count), dim3(64), 0, st, rf, gc, dgeom(f),
                      dgeom(c), bt, nbx);
   return hipGetLastError();
 }
@@ -1333,8 +1413,8 @@ hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, con
 template <typename T>
 hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
                               hipStream_t st) {
-  const int nbx = nbx64(f.n);
-  hipLaunchKernelGGL((k_prolong_add<T>), node_grid(f, nbx, bt.count), dim3(64), 0, st, ec, zf, dgeom(f),
+  const int nbx = nbx_inner(f.n);
+  hipLaunchKernelGGL((k_prolong_add<T>), inner_grid(f, nbx, bt.count), dim3(64), 0, st, ec, zf, dgeom(f),
                      dgeom(c), bt, nbx);
   return hipGetLastError();
 }
@@ -1344,18 +1424,15 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
                          const Geom& g, const Bat& bt, double eta, int assign, hipStream_t st) {
   if (sub.s != 2) return hipErrorInvalidValue;
   const DGeom dg = dgeom(g);
+  // condensed interface residual gg = r - A A_T^{-1} r_I on the interface unknowns
   const int nbs = (sub.nH + 63) / 64;
   const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, (unsigned)sub.nH);
-  hipLaunchKernelGGL((k_sm_interior_s2<T>), eg, dim3(64), 0, st, r, L.zi, L.ATinv, dg, sub.nH, bt, nbs);
-  // condensed interface residual gg = r - A zi (zi vanishes off subdomain interiors;
-  // the interior entries of gg come out as rounding-level values and are never read)
-  hipError_t e = launch_apply<T>(L.zi, r, L.gg, g, bt, 1, st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sm_condense<T>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs);
   if (sub.nchunks > 0)
     hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks, (unsigned)bt.count), dim3(256), 0,
                        st, L.gg, L.Y, L.Sinv, dg, sub, bt);
-  hipLaunchKernelGGL((k_sm_pull_extend<T>), eg, dim3(64), 0, st, L.Y, L.zi, z, L.XT, dg, sub, (T)eta, assign, bt,
-                     nbs);
+  hipLaunchKernelGGL((k_sm_pull_extend<T>), eg, dim3(64), 0, st, L.Y, r, z, L.XT, L.ATinv, dg, sub, (T)eta, assign,
+                     bt, nbs);
   return hipGetLastError();
 }
 
@@ -1392,8 +1469,8 @@ hipError_t launch_dense_vcycle(const T* g, T* z, const T* Bm, const int64_t* map
     hipLaunchKernelGGL((k_fill_zero<T>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0,
                        st, z, len, bt);
   const int nprob = bt.count / bt.nrhs;
-  // rows per wave: about 2048 workgroups over all problems, 1 .. 16 rows per wave
-  const int64_t want = (int64_t)N * nprob / (4 * 2048);
+  // rows per wave: about 1024 workgroups over all problems, 1 .. 16 rows per wave
+  const int64_t want = (int64_t)N * nprob / (4 * 1024);
   const int rpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, want));
   const unsigned nbx = (unsigned)((N + 4 * rpw - 1) / (4 * rpw));
   if (bt.nrhs == 1) {
