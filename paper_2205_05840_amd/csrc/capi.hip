@@ -235,7 +235,9 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   const int64_t cc_parts = (int64_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
   C.pstride = std::max<int64_t>(std::max<int64_t>(2 * ndmg::kRedBlocks, cc_parts),
                                 (int64_t)ndmg::stencil_blocks(gf, C.count));
-  C.o_part = take((size_t)C.pstride * sizeof(double) * cnt);
+  // three regions of partial sums per pair (dot, operator p^T A p, update r . r): each
+  // is read by the kernel after its producer, so none overwrites another still unread
+  C.o_part = take((size_t)3 * C.pstride * sizeof(double) * cnt);
   C.o_scal = take((size_t)kScalStride * sizeof(double) * cnt);
   C.o_alpha = take(np * sizeof(double));
   C.o_act = take(cnt * sizeof(int));
@@ -607,22 +609,35 @@ int precondition_cg(ndmg_ctx* c, Cls& C, const ndmg::Bat& bt, hipStream_t st) {
 
 // q = A p with p^T q (slot PQ), then u += a p, r -= a q (a = s[num] / s[PQ]) and r . r
 // (and the FP32 copy of r when mixed).
+// Regions of partial sums of a class: 0 the dot products, 1 p^T A p, 2 r . r; stride
+// part_stride per pair.
+double* part_region(ndmg_ctx* c, const Cls& C, int region) {
+  return at<double>(c, C.o_part) + region * C.pstride;
+}
+int64_t part_stride(const Cls& C) { return 3 * C.pstride; }
+
+// q = A p with partial sums of p^T q, then (reducing them) u += a p, r -= a q
+// (a = s[num] / p^T q) with partial sums of r . r (and the FP32 copy of r when mixed).
 int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt, hipStream_t st) {
   const ndmg::Geom& g = C.lv.back().g;
   const int64_t len = g.len;
   double* r = at<double>(c, C.o_pr);
   double* p = at<double>(c, C.o_pp);
   double* q = at<double>(c, C.o_pq);
-  double* part = at<double>(c, C.o_part);
   double* sc = at<double>(c, C.o_scal);
+  double* pq_part = part_region(c, C, 1);
+  const int64_t ps = part_stride(C);
+  int pq_n = 0;
   if (g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n()) {
-    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, part, C.pstride, sc + kS_PQ, st));
+    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, pq_part, ps, nullptr, st));
+    pq_n = ndmg::stencil_blocks(g, bt.count);
   } else {
     NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));
-    NDMG_HIP(ndmg::launch_dot<double>(p, q, nullptr, part, C.pstride, sc + kS_PQ, len, bt, st));
+    NDMG_HIP(ndmg::launch_dot<double>(p, q, nullptr, pq_part, ps, nullptr, len, bt, st));
+    pq_n = ndmg::dot_parts(len, bt.count);
   }
-  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, kS_PQ, kS_RR, r32_of(c, C), part, C.pstride, len,
-                                  bt, st));
+  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, pq_part, pq_n, r32_of(c, C), part_region(c, C, 2), ps,
+                                  len, bt, st));
   return NDMG_OK;
 }
 
@@ -636,7 +651,8 @@ int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, int set, hipStream_t st) {
   Cls& C = c->plan.cls[ci];
   NDMG_HIP(ndmg::launch_pcg_check(at<double>(c, C.o_scal), at<int>(c, C.o_act), at<int>(c, C.o_iters),
                                   at<int>(c, C.o_status), C.count, i_rz,
-                                  c->dev_nact + set * c->plan.cls.size() + ci, st));
+                                  c->dev_nact + set * c->plan.cls.size() + ci, part_region(c, C, 2),
+                                  ndmg::dot_parts(C.vlen, C.count), part_stride(C), st));
   return NDMG_OK;
 }
 
@@ -648,22 +664,23 @@ int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol
   double* r = at<double>(c, C.o_pr);
   double* z = at<double>(c, C.o_pz);
   double* p = at<double>(c, C.o_pp);
-  double* part = at<double>(c, C.o_part);
+  double* part = part_region(c, C, 0);
+  const int64_t ps = part_stride(C);
   double* sc = at<double>(c, C.o_scal);
   const ndmg::Bat all = class_batch(c, C, false), act = class_batch(c, C, true);
   NDMG_HIP(ndmg::launch_copy(b, r, len, all, st));
   NDMG_HIP(ndmg::launch_zero(u, len, all, st));
-  NDMG_HIP(ndmg::launch_dot<double>(b, b, nullptr, part, C.pstride, sc + kS_BB, len, all, st));
+  NDMG_HIP(ndmg::launch_dot<double>(b, b, nullptr, part, ps, sc + kS_BB, len, all, st));
   NDMG_HIP(ndmg::launch_pcg_init(sc, at<int>(c, C.o_act), at<int>(c, C.o_iters), at<int>(c, C.o_status),
                                  C.count, rtol, st));
   if (mixed(c->plan)) NDMG_HIP((ndmg::launch_convert<double, float>(r, r32_of(c, C), len, act, st)));
   NDMG_TRY(precondition_cg(c, C, act, st));
   if (mixed(c->plan)) {
     const float* zf = at<float>(c, C.lv.back().o_z);
-    NDMG_HIP(ndmg::launch_dot<float>(zf, r, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
+    NDMG_HIP(ndmg::launch_dot<float>(zf, r, nullptr, part, ps, sc + kS_RZA, len, act, st));
     NDMG_HIP((ndmg::launch_convert<float, double>(zf, p, len, act, st)));
   } else {
-    NDMG_HIP(ndmg::launch_dot<double>(z, r, nullptr, part, C.pstride, sc + kS_RZA, len, act, st));
+    NDMG_HIP(ndmg::launch_dot<double>(z, r, nullptr, part, ps, sc + kS_RZA, len, act, st));
     NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
   }
   NDMG_TRY(cg_apply_update(c, C, u, kS_RZA, act, st));
@@ -680,20 +697,23 @@ int pcg_body(ndmg_ctx* c, size_t ci, double* u, int cur, int nxt, hipStream_t st
   double* z = at<double>(c, C.o_pz);
   double* p = at<double>(c, C.o_pp);
   double* q = at<double>(c, C.o_pq);
-  double* part = at<double>(c, C.o_part);
+  double* part = part_region(c, C, 0);
+  const int64_t ps = part_stride(C);
+  const int nd = ndmg::dot_parts(len, C.count);
   double* sc = at<double>(c, C.o_scal);
   const bool flex = flexible_beta(c->plan);
   const ndmg::Bat act = class_batch(c, C, true);
   NDMG_TRY(precondition_cg(c, C, act, st));
+  // dot partials; the direction kernel reduces them (s[nxt] = r . z, s[nxt + 1] = z . q)
   if (mixed(c->plan)) {
     const float* zf = at<float>(c, C.lv.back().o_z);
-    NDMG_HIP(ndmg::launch_dot<float>(zf, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
-    NDMG_HIP(ndmg::launch_cg_direction<float>(p, zf, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act,
-                                              st));
+    NDMG_HIP(ndmg::launch_dot<float>(zf, r, flex ? q : nullptr, part, ps, nullptr, len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<float>(p, zf, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part, nd, ps,
+                                              len, act, st));
   } else {
-    NDMG_HIP(ndmg::launch_dot<double>(z, r, flex ? q : nullptr, part, C.pstride, sc + nxt, len, act, st));
-    NDMG_HIP(ndmg::launch_cg_direction<double>(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, len, act,
-                                               st));
+    NDMG_HIP(ndmg::launch_dot<double>(z, r, flex ? q : nullptr, part, ps, nullptr, len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<double>(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part, nd,
+                                               ps, len, act, st));
   }
   NDMG_TRY(cg_apply_update(c, C, u, nxt, act, st));
   return pcg_check(c, ci, nxt, cur == kS_RZA ? 1 : 0, st);

@@ -283,7 +283,8 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   const int type = sg[0], count = sg[7];
   const bool inner = (type == 13);
   const T* __restrict__ Sm = Sinv + ((int64_t)(pair / bt.nrhs) * 27 + type) * NPAD * NPAD;
-  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[(e / NPAD) * LDA + e % NPAD] = Sm[e];
+  // the slot table first; S^{-1} is staged after the first group's gathers are issued, so
+  // that its loads and theirs are in flight together
   for (int e = tid; e < NPAD; e += blockDim.x) {
     if (e < NG) {
       const int* sl = sub.slots + 4 * e;
@@ -336,11 +337,13 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   int ngroups = 0;
   for (int c = 0; c < gpw; ++c)
     if (wfirst + 16 * c < count) ngroups = c + 1;
-  if (ngroups == 0) return;   // no barrier below
   T bcur[NKS], bnext[NKS];
-  int64_t vrow, vrow_n = 0;
-  bool vok, vok_n = false;
-  gather(0, bcur, vrow, vok);
+  int64_t vrow = 0, vrow_n = 0;
+  bool vok = false, vok_n = false;
+  if (ngroups > 0) gather(0, bcur, vrow, vok);
+  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[(e / NPAD) * LDA + e % NPAD] = Sm[e];
+  __syncthreads();
+  if (ngroups == 0) return;   // no barrier below
   for (int c = 0; c < ngroups; ++c) {
     if (c + 1 < ngroups) gather(c + 1, bnext, vrow_n, vok_n);
 #pragma unroll
@@ -1144,10 +1147,11 @@ __global__ void __launch_bounds__(256) k_final(const double* __restrict__ part, 
 __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, double* __restrict__ r,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ q,
-                                                   double* __restrict__ scal, int i_num, int i_den,
+                                                   double* __restrict__ scal, int i_num,
+                                                   const double* __restrict__ pq_part, int pq_n,
                                                    float* __restrict__ r32, double* __restrict__ part,
                                                    int64_t pstride, int64_t len, Bat bt) {
-  __shared__ double sh[8];
+  __shared__ double sh[17];
   const int pair = blockIdx.y;
   if (inactive(bt, pair)) return;
   const int64_t off = (int64_t)pair * len;
@@ -1158,7 +1162,10 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   if (r32) r32 += off;
   scal += (int64_t)pair * kScalStride;
   part += (int64_t)pair * pstride;
-  const double alpha = scal[i_num] / scal[i_den];
+  // p^T A p from the partials of the operator kernel (every block the same value)
+  const double pq = reduce_partials(pq_part + (int64_t)pair * pstride, pq_n, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[kS_PQ] = pq;
+  const double alpha = scal[i_num] / pq;
   double s = 0.0;
   const int64_t n4 = len >> 2;
 #pragma unroll 2
@@ -1190,17 +1197,27 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
 
 template <typename TZ>
 __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const TZ* __restrict__ z,
-                                                      const double* __restrict__ scal, int i_num,
+                                                      double* __restrict__ scal, int i_num,
                                                       int i_den, int flexible, int i_zq, int i_an,
-                                                      int i_ad, int64_t len, Bat bt) {
+                                                      int i_ad, const double* __restrict__ dot_part,
+                                                      int dot_n, int64_t pstride, int64_t len, Bat bt) {
+  __shared__ double sh[17];
   const int pair = blockIdx.y;
   if (inactive(bt, pair)) return;
   p += (int64_t)pair * len;
   z += (int64_t)pair * len;
   scal += (int64_t)pair * kScalStride;
+  // r . z (and z . q) from the partials of the dot kernel; block 0 keeps them
+  const double* dp = dot_part + (int64_t)pair * pstride;
+  const double rz = reduce_partials(dp, dot_n, sh);
+  const double zq = flexible ? reduce_partials(dp + dot_n, dot_n, sh) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[i_num] = rz;
+    if (flexible) scal[i_zq] = zq;
+  }
   double beta;
-  if (flexible) beta = -(scal[i_an] / scal[i_ad]) * scal[i_zq] / scal[i_den];
-  else beta = scal[i_num] / scal[i_den];
+  if (flexible) beta = -(scal[i_an] / scal[i_ad]) * zq / scal[i_den];
+  else beta = rz / scal[i_den];
   const int64_t n4 = len >> 2;
 #pragma unroll 2
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
@@ -1239,8 +1256,28 @@ __global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, in
 
 __global__ void __launch_bounds__(1024) k_pcg_check(double* __restrict__ scal, int* __restrict__ act,
                                                     int* __restrict__ iters, int* __restrict__ status,
-                                                    int count, int i_rz, int* __restrict__ nact) {
+                                                    int count, int i_rz, int* __restrict__ nact,
+                                                    const double* __restrict__ rr_part, int rr_n,
+                                                    int64_t pstride) {
   __shared__ int sh[16];
+  __shared__ double shd[17];
+  // r . r of each active pair from the update's partials: the block together for few
+  // pairs (many partials each), one thread per pair otherwise
+  if (count <= 8) {
+    for (int p = 0; p < count; ++p) {
+      if (act[p] == 0) continue;   // uniform over the block
+      const double rr = reduce_partials(rr_part + (int64_t)p * pstride, rr_n, shd);
+      if (threadIdx.x == 0) scal[(int64_t)p * kScalStride + kS_RR] = rr;
+    }
+    __syncthreads();
+  } else {
+    for (int p = threadIdx.x; p < count; p += blockDim.x) {
+      if (act[p] == 0) continue;
+      double rr = 0.0;
+      for (int e = 0; e < rr_n; ++e) rr += rr_part[(int64_t)p * pstride + e];
+      scal[(int64_t)p * kScalStride + kS_RR] = rr;
+    }
+  }
   int c = 0;
   for (int p = threadIdx.x; p < count; p += blockDim.x) {
     if (act[p] == 0) continue;
@@ -1508,12 +1545,16 @@ hipError_t launch_dot(const TA* a, const double* b, const double* c, double* par
                       double* out, int64_t len, const Bat& bt, hipStream_t st) {
   if (!quad_ok(len, a) || !quad_ok(len, b) || (c && !quad_ok(len, c))) return hipErrorInvalidValue;
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
+  if ((c ? 2 : 1) * (int64_t)nb > pstride) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_dot<TA>), dim3(nb, (unsigned)bt.count), dim3(256), 0, st, a, b, c, part, pstride,
                      len, bt);
-  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, c ? 2 : 1,
-                     out, bt);
+  if (out)
+    hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, c ? 2 : 1,
+                       out, bt);
   return hipGetLastError();
 }
+
+int dot_parts(int64_t len, int count) { return (int)vec_blocks(len, count, kRedBlocks); }
 
 hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nout, double* out,
                         const Bat& bt, hipStream_t st) {
@@ -1523,25 +1564,25 @@ hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nou
 }
 
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
-                            int i_num, int i_den, int i_out, float* r32, double* part,
+                            int i_num, const double* pq_part, int pq_n, float* r32, double* part,
                             int64_t pstride, int64_t len, const Bat& bt, hipStream_t st) {
   if (!quad_ok(len, u) || !quad_ok(len, r) || !quad_ok(len, p) || !quad_ok(len, q) || (r32 && !quad_ok(len, r32)))
     return hipErrorInvalidValue;
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
+  if ((int64_t)nb > pstride || pq_n > pstride) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cg_update, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal, i_num,
-                     i_den, r32, part, pstride, len, bt);
-  hipLaunchKernelGGL(k_final, dim3((unsigned)bt.count), dim3(256), 0, st, part, (int)nb, pstride, 1,
-                     scal + i_out, bt);
+                     pq_part, pq_n, r32, part, pstride, len, bt);
   return hipGetLastError();
 }
 
 template <typename TZ>
-hipError_t launch_cg_direction(double* p, const TZ* z, const double* scal, int i_num, int i_den,
-                               int flexible, int i_zq, int i_an, int i_ad, int64_t len, const Bat& bt,
-                               hipStream_t st) {
+hipError_t launch_cg_direction(double* p, const TZ* z, double* scal, int i_num, int i_den, int flexible,
+                               int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n, int64_t pstride,
+                               int64_t len, const Bat& bt, hipStream_t st) {
   if (!quad_ok(len, p) || !quad_ok(len, z)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_cg_direction<TZ>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count),
-                     dim3(256), 0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, len, bt);
+                     dim3(256), 0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, dot_part, dot_n,
+                     pstride, len, bt);
   return hipGetLastError();
 }
 
@@ -1549,10 +1590,10 @@ template hipError_t launch_dot<double>(const double*, const double*, const doubl
                                        double*, int64_t, const Bat&, hipStream_t);
 template hipError_t launch_dot<float>(const float*, const double*, const double*, double*, int64_t,
                                       double*, int64_t, const Bat&, hipStream_t);
-template hipError_t launch_cg_direction<double>(double*, const double*, const double*, int, int, int,
-                                                int, int, int, int64_t, const Bat&, hipStream_t);
-template hipError_t launch_cg_direction<float>(double*, const float*, const double*, int, int, int, int,
-                                               int, int, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<double>(double*, const double*, double*, int, int, int, int, int, int,
+                                                const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<float>(double*, const float*, double*, int, int, int, int, int, int,
+                                               const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
 
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
                            hipStream_t st) {
@@ -1561,9 +1602,9 @@ hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int 
 }
 
 hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
-                            int* nact, hipStream_t st) {
+                            int* nact, const double* rr_part, int rr_n, int64_t pstride, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1024), 0, st, scal, act, iters, status, count, i_rz,
-                     nact);
+                     nact, rr_part, rr_n, pstride);
   return hipGetLastError();
 }
 

@@ -72,10 +72,11 @@ int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the 
 // S^{-1} stagings), one on small levels (more workgroups)
 inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
 
-// Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and
-// dot[pair * kScalStride] = x . y (partial sums per tile in part[pair * pstride + tile],
-// then reduced by a second small kernel).  Returns hipErrorNotSupported (launching
-// nothing) for a mode and size it does not serve.
+// Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and partial
+// sums of x . y per tile in part[pair * pstride + tile] (stencil_blocks(g, count) of
+// them; with dot != nullptr a second small kernel reduces them into dot[pair *
+// kScalStride]).  Returns hipErrorNotSupported (launching nothing) for a mode and size
+// it does not serve.
 template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                           double* part, int64_t pstride, double* dot, hipStream_t st);
@@ -182,35 +183,40 @@ enum : int {
 // per-pair PCG state
 enum : int { kPairRun = 0, kPairDone = 1, kPairBroken = 2 };
 
-// out[pair*kScalStride + 0] = a . b (and [+1] = a . c when c != nullptr): partial sums
-// per block, then one block per pair reduces them (a second small kernel: a reduction
-// inside the first kernel would need a device-wide fence per block, which costs more).
+// Partial sums a . b (and a . c when c != nullptr) per block and pair at part[pair *
+// pstride + blk] (a . c at + nparts), nparts = dot_parts(len, count); with out != nullptr
+// a second small kernel also reduces them into out[pair*kScalStride + 0 (, 1)].  In the
+// CG iteration the next kernel reduces the partials itself (every block in the same
+// order, so all get the same value) instead of a separate launch.
 template <typename TA>
 hipError_t launch_dot(const TA* a, const double* b, const double* c, double* part, int64_t pstride,
                       double* out, int64_t len, const Bat& bt, hipStream_t st);
+int dot_parts(int64_t len, int count);
 // per pair: out[pair*kScalStride + o] = sum of nparts partials (o < nout)
 hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nout, double* out,
                         const Bat& bt, hipStream_t st);
-// alpha = s[i_num] / s[i_den]; u += alpha p; r -= alpha q; s[i_out] = r . r; r32 (may be
-// null) receives r in FP32
+// pq = sum of the pq_n partials pq_part[pair * pstride + ..] (kept in s[kS_PQ]);
+// alpha = s[i_num] / pq; u += alpha p; r -= alpha q; partial sums of r . r at
+// part[pair * pstride + blk] (dot_parts(len, count) of them); r32 (may be null) receives
+// r in FP32
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
-                            int i_num, int i_den, int i_out, float* r32, double* part,
+                            int i_num, const double* pq_part, int pq_n, float* r32, double* part,
                             int64_t pstride, int64_t len, const Bat& bt, hipStream_t st);
-// beta = s[i_num] / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) s[i_zq] / s[i_den]);
-// p = z + beta p
+// rz (and zq when flexible) = sums of the dot partials (kept in s[i_num], s[i_zq]);
+// beta = rz / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) zq / s[i_den]); p = z + beta p
 template <typename TZ>
-hipError_t launch_cg_direction(double* p, const TZ* z, const double* scal, int i_num, int i_den,
-                               int flexible, int i_zq, int i_an, int i_ad, int64_t len, const Bat& bt,
-                               hipStream_t st);
+hipError_t launch_cg_direction(double* p, const TZ* z, double* scal, int i_num, int i_den, int flexible,
+                               int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n, int64_t pstride,
+                               int64_t len, const Bat& bt, hipStream_t st);
 // Start of a solve: s[kS_TOL] = rtol, iters = 0; pairs with b = 0 are done, pairs with a
 // non-finite b . b broken, all others active.
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
                            hipStream_t st);
-// End of an iteration, per active pair: iters += 1; broken if s[kS_PQ] <= 0 or a scalar is
-// not finite; done if ||r|| / ||b|| <= rtol (s[kS_REL] = that ratio).  *nact = pairs still
-// active.
+// End of an iteration, per active pair: s[kS_RR] = sum of the update's rr_n partials;
+// iters += 1; broken if s[kS_PQ] <= 0 or a scalar is not finite; done if ||r|| / ||b|| <=
+// rtol (s[kS_REL] = that ratio).  *nact = pairs still active.
 hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
-                            int* nact, hipStream_t st);
+                            int* nact, const double* rr_part, int rr_n, int64_t pstride, hipStream_t st);
 hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, hipStream_t st);
 hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st);
 

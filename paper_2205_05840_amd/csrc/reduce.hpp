@@ -21,4 +21,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Sum of v over the block, returned to every thread (sh: 17 doubles of LDS).
+__device__ __forceinline__ double block_sum_all(double v, double* sh) {
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) sh[16] = t;
+  __syncthreads();
+  const double r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+// Sum of the n per-block partials part[0 .. n) in a fixed order, returned to every
+// thread of the block: every block that reduces the same partials gets the same value.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n, double* sh) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) s += part[e];
+  return block_sum_all(s, sh);
+}
+
 }  // namespace ndmg

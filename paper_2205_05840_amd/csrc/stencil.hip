@@ -482,11 +482,11 @@ template <typename T, int R, int NW, int D, int MODE>
 hipError_t launch_m(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int KZ, double* part,
                     int64_t pstride, double* dot, hipStream_t st) {
   const Tiling tl = tiling(g.n, NW, KZ);
-  if (MODE == 2 && (dot == nullptr || part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
+  if (MODE == 2 && (part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tl.nblocks, (unsigned)bt.count);
   hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g), bt,
                      g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
-  if (MODE == 2) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
+  if (MODE == 2 && dot != nullptr) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
   return hipGetLastError();
 }
 
