@@ -79,6 +79,7 @@ struct Cls {
   int small_top = -1;              // levels 0 .. small_top run as one launch
   int dense_k = -1;                // MG(dense_k, ., 0, m) applied as a dense matrix (-1: none)
   int dense_K = 1;                 // matrix columns per problem built per V-cycle launch
+  bool dense_t = false;            // matrices stored transposed (classes of many problems)
   std::vector<int> probs;          // problem indices, input order
   std::vector<double> alpha;       // per problem
   std::vector<LevelHost> lv;       // coarsest first
@@ -155,6 +156,9 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
     // the level vectors at and below the dense level serve the build at setup (nprob x
     // dense_K pairs); at run time only its g and z are used, by count pairs
     C.dense_K = (int)std::max<int64_t>(C.nrhs, std::min<int64_t>(Nd, 256 / C.nprob));
+    // many problems: one thread per row over the transposed matrix (coalesced, no
+    // cross-lane sums); few: waves over rows, more workgroups per problem
+    C.dense_t = C.nprob >= 8;
   } else {
     C.dense_K = C.nrhs;
   }
@@ -521,7 +525,7 @@ int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt
     // z may be a caller's vector at the finest level: clear its non-unknown entries
     const bool top = (k == (int)C.lv.size() - 1);
     NDMG_HIP(ndmg::launch_dense_vcycle<T>(g, z, at<T>(c, L.o_Bd), at<int64_t>(c, L.o_map), L.Nd, L.g.len, bt,
-                                          top, st));
+                                          top, C.dense_t, st));
     return NDMG_OK;
   }
   const int m = pl.opts.m;
@@ -572,7 +576,7 @@ int build_dense(ndmg_ctx* c, Cls& C) {
     }
     rc = vcycle_rec<T>(c, C, kd, g, z, bt, c->st);
     if (rc != NDMG_OK) break;
-    e = ndmg::launch_gather_cols<T>(z, Bm, map, N, j0, L.g.len, bt, c->st);
+    e = ndmg::launch_gather_cols<T>(z, Bm, map, N, j0, L.g.len, C.dense_t, bt, c->st);
     if (e != hipSuccess) rc = fail(NDMG_EHIP, std::string("dense build: ") + hipGetErrorString(e));
   }
   C.dense_k = kd;

@@ -726,17 +726,74 @@ __global__ void k_unit_cols(T* __restrict__ g, const int64_t* __restrict__ map, 
     g[e] = (e == t) ? T(1) : T(0);
 }
 
-// column col of the matrix of problem p / K: Bm[i][col] = z[map[i]]
+// column col of the matrix of problem p / K: Bm[i][col] = z[map[i]] (row-major), or
+// stored transposed, Bm[col][i] (colmajor)
 template <typename T>
 __global__ void k_gather_cols(const T* __restrict__ z, T* __restrict__ Bm, const int64_t* __restrict__ map,
-                              int N, int j0, int64_t len, Bat bt) {
+                              int N, int j0, int64_t len, int colmajor, Bat bt) {
   const int pair = blockIdx.y;
   const int col = j0 + pair % bt.nrhs;
   if (col >= N) return;
   z += (int64_t)pair * len;
   Bm += (int64_t)(pair / bt.nrhs) * N * N;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
-    Bm[(int64_t)i * N + col] = z[map[i]];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const int64_t at = colmajor ? (int64_t)col * N + i : (int64_t)i * N + col;
+    Bm[at] = z[map[i]];
+  }
+}
+
+// z = Bm g with the matrix stored transposed (Bt[j][i] = Bm[i][j]), for classes of many
+// problems: block (x, problem), one row i per thread; the right-hand sides, RC at a time,
+// are gathered into LDS and each thread runs over j with coalesced loads of Bt[j][.]
+// (no cross-lane sums).  Non-unknown entries of z are not written.
+template <typename T, int RC>
+__global__ void __launch_bounds__(256) k_dense_vcycle_t(const T* __restrict__ g, T* __restrict__ z,
+                                                        const T* __restrict__ Bt,
+                                                        const int64_t* __restrict__ map, int N, int64_t len,
+                                                        Bat bt) {
+  extern __shared__ __align__(16) unsigned char dense_smem[];
+  T* sg = reinterpret_cast<T*>(dense_smem);
+  const int prob = blockIdx.y;
+  const int nr = bt.nrhs;
+  const T* __restrict__ Bp = Bt + (int64_t)prob * N * N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ic = i < N ? i : 0;
+  for (int rc = 0; rc < nr; rc += RC) {
+    const int nrc = min(RC, nr - rc);
+    bool live[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) live[r] = r < nrc && !inactive(bt, prob * nr + rc + r);
+    __syncthreads();   // the previous chunk is done with sg
+    for (int e = threadIdx.x; e < RC * N; e += blockDim.x) {
+      const int r = e / N, j = e - r * N;
+      sg[e] = live[r] ? g[(int64_t)(prob * nr + rc + r) * len + map[j]] : T(0);
+    }
+    __syncthreads();
+    T acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = T(0);
+    int j = 0;
+    for (; j + 8 <= N; j += 8) {
+      T b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = Bp[(int64_t)(j + u) * N + ic];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] += b[u] * sg[r * N + j + u];
+    }
+    for (; j < N; ++j) {
+      const T b = Bp[(int64_t)j * N + ic];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) acc[r] += b * sg[r * N + j];
+    }
+    if (i < N) {
+      const int64_t zi = map[i];
+#pragma unroll
+      for (int r = 0; r < RC; ++r)
+        if (live[r]) z[(int64_t)(prob * nr + rc + r) * len + zi] = acc[r];
+    }
+  }
 }
 
 // z[map[i]] = sum_j Bm[i][j] g[map[j]] for every pair of a problem.  Block (x, problem):
@@ -1491,21 +1548,31 @@ hipError_t launch_unit_cols(T* g, const int64_t* map, int N, int j0, int64_t len
 }
 
 template <typename T>
-hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
-                              hipStream_t st) {
+hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len, bool colmajor,
+                              const Bat& bt, hipStream_t st) {
   hipLaunchKernelGGL((k_gather_cols<T>), dim3((unsigned)((N + 255) / 256), (unsigned)bt.count), dim3(256), 0, st,
-                     z, Bm, map, N, j0, len, bt);
+                     z, Bm, map, N, j0, len, colmajor ? 1 : 0, bt);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_dense_vcycle(const T* g, T* z, const T* Bm, const int64_t* map, int N, int64_t len,
-                               const Bat& bt, bool clear, hipStream_t st) {
+                               const Bat& bt, bool clear, bool colmajor, hipStream_t st) {
   if (N < 1 || N > kDenseMaxN || bt.nrhs < 1 || bt.count % bt.nrhs) return hipErrorInvalidValue;
   if (clear)
     hipLaunchKernelGGL((k_fill_zero<T>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0,
                        st, z, len, bt);
   const int nprob = bt.count / bt.nrhs;
+  if (colmajor) {
+    const dim3 grid((unsigned)((N + 255) / 256), (unsigned)nprob);
+    if (bt.nrhs == 1)
+      hipLaunchKernelGGL((k_dense_vcycle_t<T, 1>), grid, dim3(256), (size_t)N * sizeof(T), st, g, z, Bm, map, N,
+                         len, bt);
+    else
+      hipLaunchKernelGGL((k_dense_vcycle_t<T, 4>), grid, dim3(256), (size_t)4 * N * sizeof(T), st, g, z, Bm, map,
+                         N, len, bt);
+    return hipGetLastError();
+  }
   // rows per wave: about 1024 workgroups over all problems, 1 .. 16 rows per wave
   const int64_t want = (int64_t)N * nprob / (4 * 1024);
   const int rpw = (int)std::max<int64_t>(1, std::min<int64_t>(16, want));
@@ -1662,10 +1729,10 @@ bool boundary_patches_match(const std::vector<int>& tab) {
                                        const Bat&, hipStream_t);                                  \
   template hipError_t launch_unit_cols<T>(T*, const int64_t*, int, int, int64_t, const Bat&,      \
                                           hipStream_t);                                           \
-  template hipError_t launch_gather_cols<T>(const T*, T*, const int64_t*, int, int, int64_t,      \
+  template hipError_t launch_gather_cols<T>(const T*, T*, const int64_t*, int, int, int64_t, bool, \
                                             const Bat&, hipStream_t);                             \
   template hipError_t launch_dense_vcycle<T>(const T*, T*, const T*, const int64_t*, int, int64_t, \
-                                             const Bat&, bool, hipStream_t);
+                                             const Bat&, bool, bool, hipStream_t);
 NDMG_INST(double)
 NDMG_INST(float)
 #undef NDMG_INST

@@ -152,13 +152,14 @@ template <typename T>
 hipError_t launch_unit_cols(T* g, const int64_t* map, int N, int j0, int64_t len, const Bat& bt,
                             hipStream_t st);
 template <typename T>
-hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len,
+hipError_t launch_gather_cols(const T* z, T* Bm, const int64_t* map, int N, int j0, int64_t len, bool colmajor,
                               const Bat& bt, hipStream_t st);
-// z = Bm g for every pair (Bm of problem pair / nrhs); clear: zero all of z first (for
+// z = Bm g for every pair (Bm of problem pair / nrhs, stored transposed when colmajor:
+// one thread per row, for classes of many problems); clear: zero all of z first (for
 // output vectors whose non-unknown entries the caller may not have zeroed).
 template <typename T>
 hipError_t launch_dense_vcycle(const T* g, T* z, const T* Bm, const int64_t* map, int N, int64_t len,
-                               const Bat& bt, bool clear, hipStream_t st);
+                               const Bat& bt, bool clear, bool colmajor, hipStream_t st);
 
 template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin* in, Tout* out, int64_t len, const Bat& bt, hipStream_t st);

@@ -289,3 +289,38 @@ def test_batched_dense_bottom_matches_recursion(precision):
             assert abs(int(sols[0][1][p, r]) - int(sols[1][1][p, r])) <= 1
             for k in range(2):
                 assert _rel(sols[k][0][p][r], ue[r]) <= 1e-7, (k, p, r)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_dense_bottom_many_problems(precision):
+    """Classes of eight or more problems keep the dense bottom transposed (one thread per
+    row); the V-cycle agrees with the recursion and solves reach the exact solution."""
+    ns = [8] * 9 + [16] * 8 + [12] * 8
+    alphas = [10.0 ** (-1.5 + 3.0 * p / (len(ns) - 1)) for p in range(len(ns))]
+    nrhs = 2
+    Bd = _batch(ns, alphas, nrhs, precision)
+    Br = _batch(ns, alphas, nrhs, precision, dense_n=0)
+    rng = np.random.default_rng(8)
+    blocks = [rng.standard_normal((nrhs, mesh.ndof(n))) for n in ns]
+    Zd = _unpack(Bd, Bd.vcycle(_pack(Bd, blocks)))
+    Zr = _unpack(Br, Br.vcycle(_pack(Br, blocks)))
+    if precision == "fp64":
+        for p in range(len(ns)):
+            for r in range(nrhs):
+                assert _rel(Zd[p][r], Zr[p][r]) <= 1e-11, (p, r, _rel(Zd[p][r], Zr[p][r]))
+    else:
+        B64 = _batch(ns, alphas, nrhs, "fp64", dense_n=0)
+        Z64 = _unpack(B64, B64.vcycle(_pack(B64, blocks)))
+        for p in range(len(ns)):
+            for r in range(nrhs):
+                ed, er = _rel(Zd[p][r], Z64[p][r]), _rel(Zr[p][r], Z64[p][r])
+                assert ed <= 3.0 * max(er, 1e-6), (p, r, ed, er)
+    b = _loads(ns, nrhs, 160)
+    rtol = 1e-12 if precision == "fp64" else 1e-11
+    U, it, rel = Bd.solve(_pack(Bd, b), rtol=rtol)
+    assert (rel <= rtol).all()
+    sol = _unpack(Bd, U)
+    for p, n in enumerate(ns):
+        ue = exact.solve_fft(n, 1.0 / n, alphas[p], b[p])
+        for r in range(nrhs):
+            assert _rel(sol[p][r], ue[r]) <= 1e-7, (p, r)
