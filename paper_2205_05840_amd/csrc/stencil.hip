@@ -534,12 +534,12 @@ Choice choose_kz(int n, int count, Variant v) {
 // Candidate variants per precision, row length and mode (index 0 or 1 of the
 // instantiated pair below); returns the chosen one and its KZ.
 template <typename T, int R>
-void variants(int mode, Variant (&vs)[2], int* nv) {
+void variants(int mode, Variant (&vs)[3], int* nv) {
   constexpr bool f64 = std::is_same<T, double>::value;
   if (R == 2) {
     if (f64) {
       if (mode == 1) { vs[0] = {6, 3}; *nv = 1; }
-      else { vs[0] = {10, 3}; vs[1] = {8, 4}; *nv = 2; }
+      else { vs[0] = {10, 3}; vs[1] = {8, 4}; vs[2] = {6, 4}; *nv = 3; }
     } else {
       if (mode == 1) { vs[0] = {10, 3}; vs[1] = {8, 4}; *nv = 2; }
       else { vs[0] = {10, 4}; vs[1] = {8, 4}; *nv = 2; }
@@ -552,7 +552,7 @@ void variants(int mode, Variant (&vs)[2], int* nv) {
 
 template <typename T, int R>
 bool pick(int n, int count, int mode, int* which, int* kz, Variant* var) {
-  Variant vs[2];
+  Variant vs[3];
   int nv = 0;
   variants<T, R>(mode, vs, &nv);
   if (nv == 0) return false;
@@ -580,7 +580,8 @@ hipError_t launch_mode(const T* x, const T* b, T* y, const Geom& g, const Bat& b
     if constexpr (f64 && MODE == 1) return launch_m<T, R, 6, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     if constexpr (f64 && MODE != 1) {
       if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 6, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
     if constexpr (!f64 && MODE == 1) {
       if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
