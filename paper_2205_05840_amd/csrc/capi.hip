@@ -62,6 +62,7 @@ struct LevelHost {
   ndmg::SubInfo sub{};
   std::vector<ndmg::Segment> segs;
   std::vector<int> chunks;             // (segment, first) pairs
+  int gpw = 1;                         // 16-vertex groups per wave of the patch kernel
   std::vector<int64_t> map;            // coarsest level: padded offset of each unknown
   int nB = 0;
   // workspace offsets; per-pair arrays hold `count` copies, factors `nprob` copies
@@ -187,8 +188,11 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       L.sub = ndmg::make_sub(s, sizes[k]);
       L.segs = ndmg::vertex_segments(L.sub.nH, pl.opts.boundary_patches != 0);
       L.chunks.clear();
+      int64_t groups = 0;
+      for (const auto& sg : L.segs) groups += (sg.count + 15) / 16;
+      L.gpw = ndmg::patch_groups(groups * C.count, el);
       for (size_t si = 0; si < L.segs.size(); ++si)
-        for (int f = 0; f < L.segs[si].count; f += 64 * ndmg::patch_groups(L.sub.nH)) {
+        for (int f = 0; f < L.segs[si].count; f += 64 * L.gpw) {
           L.chunks.push_back((int)si);
           L.chunks.push_back(f);
         }
@@ -334,7 +338,7 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.segs = at<int>(c, L.o_segs);
   d.chunks = at<int>(c, L.o_chunks);
   d.nchunks = (int)(L.chunks.size() / 2);
-  d.gpw = ndmg::patch_groups(L.sub.nH);
+  d.gpw = L.gpw;
   d.bofs = at<int64_t>(c, L.o_bofs);
   return d;
 }

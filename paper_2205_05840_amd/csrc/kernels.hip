@@ -254,20 +254,44 @@ struct Mfma<float> {
 // Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
 // segment (one patch type) of one pair (blockIdx.y).  S_type^{-1} is staged in LDS; wave w
 // then walks its gpw groups of 16 vertices: lane l gathers the B-operand column values
-// g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (prefetching the next
-// group), reads the A-operand fragment S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and
-// accumulates the 16 x 16 output tile per mb; results go to the slot-major Y.
+// g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (the next group's gathers
+// are in flight while the current group's products run), reads the A-operand fragments
+// S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and accumulates the 16 x 16 output tile
+// per mb; results go to the slot-major Y.
+// - Slots are direction-major (NG / 3 per edge direction, a multiple of 4), so the edge
+//   direction of k-step ks is fixed and its block offset d B is uniform; a lane adds a
+//   32-bit offset to a per-group scalar base.
+// - Which slots a patch lacks depends only on its type (a vertex inside the box has every
+//   slot, one on a face of the box lacks the same slots wherever it lies on that face), so
+//   each lane holds one bit mask of present slots for the whole block.
+// - Lanes past the segment's end take the group's first vertex: they gather and compute
+//   exactly what lane 0 does and store the same values to the same places.  So every load
+//   and store is issued unconditionally; predicated memory operations would make the
+//   compiler's wait counters conservative, and each product would then wait for the loads
+//   and stores of the groups around it.
+// - S^{-1} sits in LDS fragment-major: the A operands of one lane for VE consecutive
+//   k-steps are one 16-byte word, and the 64 lanes read 64 consecutive words.
+// FP64: at least 3 waves per SIMD (168 registers), the residency patch_groups assumes;
+// FP32 fits 4 waves without the bound (asking for it makes the compiler spill).
 template <typename T, int S>
-__global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* __restrict__ Y,
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const T* __restrict__ gg, T* __restrict__ Y,
                                                   const T* __restrict__ Sinv, DGeom g, DSub sub,
                                                   Bat bt) {
   constexpr int NG = 6 * S * (4 * S - 3);
   constexpr int NPAD = (NG + 15) / 16 * 16;
   constexpr int NKS = NPAD / 4, NMB = NPAD / 16;
-  constexpr int LDA = NPAD + 1;   // odd row stride: the 16 rows a wave reads hit distinct banks
-  __shared__ T sA[NPAD * LDA];
-  __shared__ int sslot[NPAD][4];
-  __shared__ int64_t soff[NPAD];
+  constexpr int NKE = (NG + 3) / 4;                // k-steps that hold a slot
+  constexpr int KD = NG / 12;                      // k-steps per edge direction
+  static_assert(NG % 12 == 0, "slots of one direction fill whole k-steps");
+  constexpr int VE = 16 / (int)sizeof(T);          // elements per 16-byte word
+  constexpr int NL = NPAD * NPAD / VE / 256;       // 16-byte loads of S^{-1} per thread
+  constexpr int NKV = NKS / VE;                    // A words per mb and lane
+  constexpr int NKVE = (NKE + VE - 1) / VE;        // of which hold a slot
+  static_assert(NPAD * NPAD % (VE * 256) == 0, "S^{-1} staging shape");
+  typedef T vec_t __attribute__((ext_vector_type(VE)));
+  __shared__ vec_t sA[NMB * NKV * 64];
+  __shared__ int srel[NPAD];    // node offset of the slot's edge from the vertex's node
+  __shared__ int spres[NPAD];   // 1 if this patch type has the slot
   const int lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   const int pair = lb / gridDim.x;
   if (inactive(bt, pair)) return;
@@ -279,91 +303,120 @@ __global__ void __launch_bounds__(256) k_sm_patch(const T* __restrict__ gg, T* _
   const int chunk = lb - pair * gridDim.x;
   const int seg = sub.chunks[2 * chunk];
   const int first = sub.chunks[2 * chunk + 1];
+  // segment parameters, read once: inside the loop the compiler could not keep them
+  // across the stores to Y, and a reload would wait for every load and store in flight
   const int* sg = sub.segs + 8 * seg;
-  const int type = sg[0], count = sg[7];
-  const bool inner = (type == 13);
+  const int type = __builtin_amdgcn_readfirstlane(sg[0]);
+  const int lo0 = __builtin_amdgcn_readfirstlane(sg[1]);
+  const int lo1 = __builtin_amdgcn_readfirstlane(sg[2]);
+  const int lo2 = __builtin_amdgcn_readfirstlane(sg[3]);
+  const int d0 = __builtin_amdgcn_readfirstlane(sg[4]);
+  const int d1 = __builtin_amdgcn_readfirstlane(sg[5]);
+  const int count = __builtin_amdgcn_readfirstlane(sg[7]);
   const T* __restrict__ Sm = Sinv + ((int64_t)(pair / bt.nrhs) * 27 + type) * NPAD * NPAD;
-  // the slot table first; S^{-1} is staged after the first group's gathers are issued, so
-  // that its loads and theirs are in flight together
   for (int e = tid; e < NPAD; e += blockDim.x) {
+    int rel = 0, pres = 0;
     if (e < NG) {
       const int* sl = sub.slots + 4 * e;
-      sslot[e][0] = sl[0]; sslot[e][1] = sl[1]; sslot[e][2] = sl[2]; sslot[e][3] = sl[3];
-      soff[e] = sl[0] * g.B + (int64_t)sl[3] * g.plane + (int64_t)sl[2] * g.P + sl[1];
-    } else {
-      sslot[e][0] = -1; sslot[e][1] = sslot[e][2] = sslot[e][3] = 0;
-      soff[e] = 0;
+      const int d = sl[0], dx = sl[1], dy = sl[2], dz = sl[3];
+      rel = (int)((int64_t)dz * g.plane + (int64_t)dy * g.P + dx);
+      // the edge's node must satisfy 0 <= o <= n - 1 along its direction and
+      // 1 <= o <= n - 1 across it; checked at the segment's first vertex
+      const int ox = S * lo0 + dx, oy = S * lo1 + dy, oz = S * lo2 + dz, nmax = g.n - 1;
+      pres = (ox >= (d != 0)) & (ox <= nmax) & (oy >= (d != 1)) & (oy <= nmax) & (oz >= (d != 2)) &
+             (oz <= nmax);
     }
+    srel[e] = rel;
+    spres[e] = pres;
   }
+  // S^{-1}: all of this thread's 16-byte loads go out together, before the first gathers
+  vec_t sv[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) sv[l] = reinterpret_cast<const vec_t*>(Sm)[l * 256 + tid];
   __syncthreads();
   const int gpw = sub.gpw;
   const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int wfirst = first + wave * gpw * 16;
+  int rl[NKE];
+  unsigned lmask = 0;
+#pragma unroll
+  for (int ks = 0; ks < NKE; ++ks) {
+    rl[ks] = srel[4 * ks + lk];
+    lmask |= (unsigned)spres[4 * ks + lk] << ks;
+  }
 
-  auto gather = [&](int c, T (&bcol)[NKS], int64_t& vrow, bool& vok) {
-    const int v = wfirst + 16 * c + lr;
-    vok = v < count;
-    int vx = 0, vy = 0, vz = 0;
-    if (vok) {
-      vx = sg[1] + v % sg[4];
-      vy = sg[2] + (v / sg[4]) % sg[5];
-      vz = sg[3] + v / (sg[4] * sg[5]);
+  // group c: lane's vertex (clamped), node offset from lane 0's node, Y row offsets
+  auto gather = [&](int c, T (&bcol)[NKS], int64_t& y0, int& yoff) {
+    const int v0 = min(wfirst + 16 * c, count - 1);
+    int v = wfirst + 16 * c + lr;
+    if (v >= count) v = v0;
+    const int vx = lo0 + v % d0, vy = lo1 + (v / d0) % d1, vz = lo2 + v / (d0 * d1);
+    const int64_t node = lin(g, S * vx, S * vy, S * vz);
+    const int64_t vrow = ((int64_t)vz * nv + vy) * nv + vx;
+    // lane 0 holds v0, the smallest vertex of the group: the offsets are >= 0
+    const int64_t node0 = __builtin_amdgcn_readfirstlane((unsigned)(node & 0xffffffff)) |
+                          ((int64_t)__builtin_amdgcn_readfirstlane((int)(node >> 32)) << 32);
+    y0 = __builtin_amdgcn_readfirstlane((unsigned)(vrow & 0xffffffff)) |
+         ((int64_t)__builtin_amdgcn_readfirstlane((int)(vrow >> 32)) << 32);
+    const int loff = (int)(node - node0);
+    yoff = (int)(vrow - y0);
+#pragma unroll
+    for (int ks = 0; ks < NKE; ++ks) {
+      // absent slots read entry 0 (an x-edge on the boundary: zero), so that no select
+      // waits for the loaded value
+      const T* gb = gg + (int64_t)(ks / KD) * g.B + node0;
+      const bool ok = (lmask >> ks) & 1u;
+      bcol[ks] = *(ok ? gb + (loff + rl[ks]) : gg);
     }
-    vrow = ((int64_t)vz * nv + vy) * nv + vx;
-    const int64_t base = lin(g, S * vx, S * vy, S * vz);
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      const int slot = 4 * ks + lk;
-      T val = T(0);
-      if (vok && slot < NG) {
-        bool ok = true;
-        if (!inner) {
-          // absent slots of boundary patches (outside the domain or on its boundary)
-          const int d = sslot[slot][0];
-          const int o[3] = {S * vx + sslot[slot][1], S * vy + sslot[slot][2], S * vz + sslot[slot][3]};
+    for (int ks = NKE; ks < NKS; ++ks) bcol[ks] = T(0);
+  };
+  auto product_store = [&](const T (&bcol)[NKS], int64_t y0, int yoff) {
+    T* yl = Y + y0 + yoff;
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax) {
-            if (ax == d) ok = ok && (o[ax] >= 0 && o[ax] < g.n);
-            else ok = ok && (o[ax] >= 1 && o[ax] <= g.n - 1);
-          }
-        }
-        if (ok) val = gg[base + soff[slot]];
-      }
-      bcol[ks] = val;
+    for (int mb = 0; mb < NMB; ++mb) {
+      // keep the A fragments in LDS (read per use) instead of registers: occupancy
+      __asm__ volatile("" ::: "memory");
+      vec_t a[NKVE];
+#pragma unroll
+      for (int kv = 0; kv < NKVE; ++kv) a[kv] = sA[(mb * NKV + kv) * 64 + lane];
+      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int ks = 0; ks < NKE; ++ks) acc = Mfma<T>::mma(a[ks / VE][ks % VE], bcol[ks], acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV] = acc[q];
     }
   };
 
   int ngroups = 0;
   for (int c = 0; c < gpw; ++c)
     if (wfirst + 16 * c < count) ngroups = c + 1;
-  T bcur[NKS], bnext[NKS];
-  int64_t vrow = 0, vrow_n = 0;
-  bool vok = false, vok_n = false;
-  if (ngroups > 0) gather(0, bcur, vrow, vok);
-  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) sA[(e / NPAD) * LDA + e % NPAD] = Sm[e];
+  T b0[NKS], b1[NKS];
+  int64_t y0a, y0b;
+  int yoa, yob;
+  gather(0, b0, y0a, yoa);   // with no group, every lane takes the segment's last vertex
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int u = 0; u < VE; ++u) {
+      const int e = (l * 256 + tid) * VE + u;
+      const int r = e / NPAD, col = e % NPAD;
+      const int ks = col / 4, ln = (col % 4) * 16 + r % 16;
+      sA[((r / 16) * NKV + ks / VE) * 64 + ln][ks % VE] = sv[l][u];
+    }
   __syncthreads();
   if (ngroups == 0) return;   // no barrier below
-  for (int c = 0; c < ngroups; ++c) {
-    if (c + 1 < ngroups) gather(c + 1, bnext, vrow_n, vok_n);
-#pragma unroll
-    for (int mb = 0; mb < NMB; ++mb) {
-      // keep the A fragments in LDS (read per use) instead of registers: occupancy
-      __asm__ volatile("" ::: "memory");
-      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks)
-        acc = Mfma<T>::mma(sA[(16 * mb + lr) * LDA + 4 * ks + lk], bcur[ks], acc);
-      if (vok) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Y[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV + vrow] = acc[q];
-      }
-    }
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) bcur[ks] = bnext[ks];
-    vrow = vrow_n;
-    vok = vok_n;
+  // two buffers used in turn, so that no buffer is copied (a copy would wait for the
+  // loads in flight); past the last group the gathers repeat it
+  int c = 0;
+  for (; c + 2 <= ngroups; c += 2) {
+    gather(c + 1, b1, y0b, yob);
+    product_store(b0, y0a, yoa);
+    gather(min(c + 2, ngroups - 1), b0, y0a, yoa);
+    product_store(b1, y0b, yob);
   }
+  if (c < ngroups) product_store(b0, y0a, yoa);
 }
 
 // w = sum_V R_V^T y_V on the interface unknowns of node (i, j, k), i < n; z (assign ? =,

@@ -6,6 +6,7 @@
 // problem p and share its alpha and its local factors (which follow each other with a
 // stride of one factor block).  A single solve is the batch of one pair.
 #pragma once
+#include <algorithm>
 
 #include <hip/hip_runtime.h>
 
@@ -70,7 +71,15 @@ int stencil_min_n(int count);   // the plane-marching kernel serves stencil_min_
 int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the dot mode
 // groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
 // S^{-1} stagings), one on small levels (more workgroups)
-inline int patch_groups(int nH) { return nH >= 48 ? 4 : (nH >= 24 ? 2 : 1); }
+// 16-vertex groups per wave of the patch kernel for a level with `groups` groups in all
+// (summed over the segments and the pairs of a class): the fewest that let the whole grid
+// be resident at once, given the workgroups per CU that the kernel's registers allow
+// (4 in FP32, 3 in FP64 on a 256-CU MI355X), at most 8.
+inline int patch_groups(int64_t groups, size_t elem) {
+  const int64_t resident = (elem == 4 ? 4 : 3) * 256 * 4;   // waves
+  const int64_t g = (groups + resident - 1) / resident;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, g));
+}
 
 // Plane-marching operator kernel: mode 0 y = A x, 1 y = b - A x, 2 y = A x and partial
 // sums of x . y per tile in part[pair * pstride + tile] (stencil_blocks(g, count) of
