@@ -631,6 +631,18 @@ static_assert(kOI.n == 18, "18 interface unknowns owned per subdomain");
 // interface unknowns T owns, from r there and the interior residuals of T and its
 // neighbours T - e_x, T - e_y, T - e_z and their pairwise sums (all tables compile-time).
 // Other entries of g are left untouched (never read).
+// Copy n (<= 64 * R) values from global memory into LDS with one batch of loads per
+// thread (a loop that stores each value before loading the next waits for every load).
+template <typename T, int R>
+__device__ __forceinline__ void stage_lds(T* __restrict__ dst, const T* __restrict__ src, int n) {
+  T v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = src[min((int)threadIdx.x + 64 * i, n - 1)];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if ((int)threadIdx.x + 64 * i < n) dst[threadIdx.x + 64 * i] = v[i];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* __restrict__ gg,
                                                     const T* __restrict__ XT, DGeom g, int nH, Bat bt, int nbx) {
@@ -639,7 +651,7 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
   const int pair = blockIdx.x / nbx;
   if (inactive(bt, pair)) return;
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
-  for (int e = threadIdx.x; e < 6 * NB; e += blockDim.x) sX[e] = XT[e];
+  stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
   __syncthreads();
   const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, c = blockIdx.z;
@@ -659,13 +671,19 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
     for (int t = 0; t < 6; ++t) rI[qq][t] = r[off[t]];
   }
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
+  // every owned slot is read and written (its node lies inside the grid); a slot on the
+  // domain boundary gets 0, which keeps the zero there.  No branch around a load or
+  // store: predicated memory operations make the compiler's wait counters conservative.
+  T rO[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k)
+    rO[k] = r[kOI.d[k] * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2])];
 #pragma unroll
   for (int k = 0; k < 18; ++k) {
     const int d = kOI.d[k];
     const int gi = 2 * a + kOI.o[k][0], gj = 2 * b + kOI.o[k][1], gk = 2 * c + kOI.o[k][2];
-    if (!is_unknown(g, d, gi, gj, gk)) continue;   // on the domain boundary
     const int64_t off = d * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2]);
-    T acc = r[off];
+    T acc = rO[k];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       if (m < kOI.nadj[k]) {
@@ -674,7 +692,7 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
         for (int t = 0; t < 6; ++t) acc -= sX[t * NB + e] * rI[qq][t];
       }
     }
-    gg[off] = acc;
+    gg[off] = is_unknown(g, d, gi, gj, gk) ? acc : T(0);
   }
 }
 
@@ -699,8 +717,8 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   if (inactive(bt, pair)) return;
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
   ATinv += (int64_t)(pair / bt.nrhs) * 36;
-  for (int e = threadIdx.x; e < 6 * NB; e += blockDim.x) sX[e] = XT[e];
-  for (int e = threadIdx.x; e < 36; e += blockDim.x) sA[e] = ATinv[e];
+  stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
+  stage_lds<T, 1>(sA, ATinv, 36);
   __syncthreads();
   const int nH = sub.nH;
   const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
@@ -715,6 +733,23 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   const T* __restrict__ Yp = Y + (int64_t)pair * NV * NPAD + vrow0;
   const int64_t cofs[8] = {0, 1, nv, nv + 1, (int64_t)nv * nv, (int64_t)nv * nv + 1, (int64_t)nv * nv + nv,
                            (int64_t)nv * nv + nv + 1};
+  const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
+  int64_t ioff[6];
+  interior_offsets_s2(g, base, ioff);
+  // the old values of z (accumulating form) and r_I first: issued before the patch
+  // results, they are in hand when those are, and no store waits for a load
+  T zo[6 + NB], rI[6];
+#pragma unroll
+  for (int t = 0; t < 6 + NB; ++t) zo[t] = T(0);
+  if (!assign) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) zo[t] = z[ioff[t]];
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+      if (kBP.owned[e]) zo[6 + e] = z[kBP.d[e] * g.B + base + lin(g, kBP.o[e][0], kBP.o[e][1], kBP.o[e][2])];
+  }
+#pragma unroll
+  for (int t = 0; t < 6; ++t) rI[t] = r[ioff[t]];
   T wv[NB];
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
@@ -724,14 +759,8 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
       if (t < kBP.ncand[e]) acc += Yp[(int64_t)kBP.slot[e][t] * NV + cofs[kBP.corner[e][t]]];
     wv[e] = acc;
   }
-  const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
   // interior unknowns (the order of interior_offsets_s2): z_I += eta (A_T^{-1} r_I - X_T w)
-  int64_t ioff[6];
-  interior_offsets_s2(g, base, ioff);
-  T rI[6];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) rI[t] = r[ioff[t]];
-#pragma unroll 1
   for (int t = 0; t < 6; ++t) {
     T q = T(0);
 #pragma unroll
@@ -739,15 +768,13 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
     T zi = T(0);
 #pragma unroll
     for (int s2 = 0; s2 < 6; ++s2) zi += sA[t * 6 + s2] * rI[s2];
-    const T old = assign ? T(0) : z[ioff[t]];
-    z[ioff[t]] = old + eta * (zi - q);
+    z[ioff[t]] = zo[t] + eta * (zi - q);
   }
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
     if (kBP.owned[e]) {
       const int64_t off = kBP.d[e] * g.B + base + lin(g, kBP.o[e][0], kBP.o[e][1], kBP.o[e][2]);
-      const T old = assign ? T(0) : z[off];
-      z[off] = old + eta * wv[e];
+      z[off] = zo[6 + e] + eta * wv[e];
     }
   }
 }
