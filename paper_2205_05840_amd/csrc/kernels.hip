@@ -59,11 +59,14 @@ __device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
   return bt.act != nullptr && bt.act[pair] == 0;
 }
 
+// (A u) at edge (a, p).  With on = false every neighbour stride is 0, so all loads read
+// position p (in bounds wherever p is) and the result is meaningless: callers take that
+// form for positions that hold no unknown, to keep loads out of branches.
 template <typename T>
 __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
-                                      T ah, T h3) {
+                                      T ah, T h3, bool on = true) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
-  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
+  const int64_t st[3] = {on ? 1 : 0, on ? (int64_t)g.P : 0, on ? g.plane : 0};
   const int64_t sa = st[a], sb = st[b], sc = st[c];
   const T* __restrict__ ua = u + a * g.B;
   const T* __restrict__ ub = u + b * g.B;
@@ -88,19 +91,22 @@ __device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __r
                                            T* __restrict__ y, const DGeom& g, T ah, T h3, int i, int j,
                                            int k) {
   const int64_t p = lin(g, i, j, k);
+  // no branch around the loads: predicated memory operations make the compiler's wait
+  // counters conservative
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    T v = T(0);
-    if (is_unknown(g, d, i, j, k)) {
-      const T ax = apply_at(x, g, d, p, ah, h3);
-      v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
-    }
-    y[d * g.B + p] = v;
+    const bool on = is_unknown(g, d, i, j, k);
+    const T ax = apply_at(x, g, d, p, ah, h3, on);
+    const T v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
+    y[d * g.B + p] = on ? v : T(0);
   }
 }
 
+// At most 4 waves per SIMD: the scheduler may then keep all loads of a thread in flight
+// (aiming at more waves it issues them two at a time); these launches are small and
+// latency-bound.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 4))) k_apply(const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
   const int pair = blockIdx.x / nbx;
   const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
@@ -162,9 +168,13 @@ __device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __rest
   const int o[3] = {i, j, k};
   const int64_t stc[3] = {1, (int64_t)c.P, c.plane};
   const int64_t pf = lin(f, i, j, k);
+  // branch-free: across each axis the coarse neighbour enters with weight 1/2 at an odd
+  // fine index, else with weight 0 and stride 0 (so its load stays in bounds); off the
+  // unknowns the increment is 0.  (i, j, k) is an inner node, so every coarse node read
+  // lies inside the coarse grid.
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (!is_unknown(f, a, i, j, k)) continue;
+    const bool on = is_unknown(f, a, i, j, k);
     const int b = (a + 1) % 3, cc = (a + 2) % 3;
     int C[3];
     C[a] = o[a] >> 1;
@@ -172,12 +182,15 @@ __device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __rest
     C[cc] = o[cc] >> 1;
     const T* __restrict__ e = ec + a * c.B + lin(c, C[0], C[1], C[2]);
     const bool ob = o[b] & 1, oc = o[cc] & 1;
-    T v;
-    if (!ob && !oc) v = e[0];
-    else if (ob && !oc) v = T(0.5) * (e[0] + e[stc[b]]);
-    else if (!ob && oc) v = T(0.5) * (e[0] + e[stc[cc]]);
-    else v = T(0.25) * ((e[0] + e[stc[b]]) + (e[stc[cc]] + e[stc[b] + stc[cc]]));
-    zf[a * f.B + pf] += v;
+    const int64_t sb = ob ? stc[b] : 0, sc = oc ? stc[cc] : 0;
+    // scaling by 1/2 is exact: the same roundings as 0.5 (x + y) and 0.25 ((.) + (.))
+    const T wb0 = ob ? T(0.5) : T(1), wb1 = ob ? T(0.5) : T(0);
+    const T wc0 = oc ? T(0.5) : T(1), wc1 = oc ? T(0.5) : T(0);
+    const T rowlo = wb0 * e[0] + wb1 * e[sb];
+    const T rowhi = wb0 * e[sc] + wb1 * e[sb + sc];
+    const T v = wc0 * rowlo + wc1 * rowhi;
+    const T old = zf[a * f.B + pf];
+    zf[a * f.B + pf] = on ? old + v : old;
   }
 }
 
