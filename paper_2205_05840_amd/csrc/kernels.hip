@@ -59,14 +59,11 @@ __device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
   return bt.act != nullptr && bt.act[pair] == 0;
 }
 
-// (A u) at edge (a, p).  With on = false every neighbour stride is 0, so all loads read
-// position p (in bounds wherever p is) and the result is meaningless: callers take that
-// form for positions that hold no unknown, to keep loads out of branches.
 template <typename T>
 __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
-                                      T ah, T h3, bool on = true) {
+                                      T ah, T h3) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
-  const int64_t st[3] = {on ? 1 : 0, on ? (int64_t)g.P : 0, on ? g.plane : 0};
+  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
   const int64_t sa = st[a], sb = st[b], sc = st[c];
   const T* __restrict__ ua = u + a * g.B;
   const T* __restrict__ ub = u + b * g.B;
@@ -91,22 +88,19 @@ __device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __r
                                            T* __restrict__ y, const DGeom& g, T ah, T h3, int i, int j,
                                            int k) {
   const int64_t p = lin(g, i, j, k);
-  // no branch around the loads: predicated memory operations make the compiler's wait
-  // counters conservative
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const bool on = is_unknown(g, d, i, j, k);
-    const T ax = apply_at(x, g, d, p, ah, h3, on);
-    const T v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
-    y[d * g.B + p] = on ? v : T(0);
+    T v = T(0);
+    if (is_unknown(g, d, i, j, k)) {
+      const T ax = apply_at(x, g, d, p, ah, h3);
+      v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
+    }
+    y[d * g.B + p] = v;
   }
 }
 
-// At most 4 waves per SIMD: the scheduler may then keep all loads of a thread in flight
-// (aiming at more waves it issues them two at a time); these launches are small and
-// latency-bound.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 4))) k_apply(const T* __restrict__ x, const T* __restrict__ b,
+__global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
   const int pair = blockIdx.x / nbx;
   const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
