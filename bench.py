@@ -269,7 +269,7 @@ def kernel_probe(torch, Solver, precision, reps):
     torch.cuda.synchronize()
     S = Solver(N_ELEM, 1.0, precision=precision)
     t = time_apply(torch, S, reps=reps)
-    # a few fine-level smoother applications (interior, condensation, patch, pull, extend)
+    # a few fine-level smoother applications (condensation, patch products, pull/extend)
     r = torch.randn(S.vec_len, dtype=torch.float64, device=S.device) * S.unknown_mask()
     for _ in range(4):
         S.level_op(-1, "smooth", r)
