@@ -191,11 +191,24 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       int64_t groups = 0;
       for (const auto& sg : L.segs) groups += (sg.count + 15) / 16;
       L.gpw = ndmg::patch_groups(groups * C.count, el);
-      for (size_t si = 0; si < L.segs.size(); ++si)
-        for (int f = 0; f < L.segs[si].count; f += 64 * L.gpw) {
-          L.chunks.push_back((int)si);
+      // Boundary-type segments check every slot against the domain, so their groups cost
+      // more: they get the fewest groups per wave that still let the whole grid be
+      // resident at once (else as many as the interior), so that they do not finish last.
+      auto nchunks_with = [&](int gb) {
+        int64_t nch = 0;
+        for (const auto& sg : L.segs) nch += (sg.count + 64 * (sg.type == 13 ? L.gpw : gb) - 1) / (64 * (sg.type == 13 ? L.gpw : gb));
+        return nch * C.count;
+      };
+      int gpw_b = L.gpw;
+      for (int gb = 1; gb < L.gpw; ++gb)
+        if (nchunks_with(gb) <= ndmg::patch_resident_blocks(el)) { gpw_b = gb; break; }
+      for (size_t si = 0; si < L.segs.size(); ++si) {
+        const int gs = L.segs[si].type == 13 ? L.gpw : gpw_b;
+        for (int f = 0; f < L.segs[si].count; f += 64 * gs) {
+          L.chunks.push_back((int)si | gs << 16);
           L.chunks.push_back(f);
         }
+      }
       L.o_r = take(vb);
       L.o_zi = take(vb);
       L.o_gg = take(vb);
@@ -338,7 +351,6 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.segs = at<int>(c, L.o_segs);
   d.chunks = at<int>(c, L.o_chunks);
   d.nchunks = (int)(L.chunks.size() / 2);
-  d.gpw = L.gpw;
   d.bofs = at<int64_t>(c, L.o_bofs);
   return d;
 }

@@ -259,7 +259,7 @@ struct Mfma<float> {
 };
 
 // Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
-// segment (one patch type) of one pair (blockIdx.y).  S_type^{-1} is staged in LDS; wave w
+// segment (one patch type) of one pair (blockIdx.y); gpw comes with the chunk.  S_type^{-1} is staged in LDS; wave w
 // then walks its gpw groups of 16 vertices: lane l gathers the B-operand column values
 // g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (the next group's gathers
 // are in flight while the current group's products run), reads the A-operand fragments
@@ -308,7 +308,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   gg += (int64_t)pair * vlen(g);
   Y += (int64_t)pair * NV * NPAD;
   const int chunk = lb - pair * gridDim.x;
-  const int seg = sub.chunks[2 * chunk];
+  const int seg = sub.chunks[2 * chunk] & 0xffff;
+  const int gpw = sub.chunks[2 * chunk] >> 16;   // 16-vertex groups per wave in this chunk
   const int first = sub.chunks[2 * chunk + 1];
   // segment parameters, read once: inside the loop the compiler could not keep them
   // across the stores to Y, and a reload would wait for every load and store in flight
@@ -341,7 +342,6 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 #pragma unroll
   for (int l = 0; l < NL; ++l) sv[l] = reinterpret_cast<const vec_t*>(Sm)[l * 256 + tid];
   __syncthreads();
-  const int gpw = sub.gpw;
   const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int wfirst = first + wave * gpw * 16;

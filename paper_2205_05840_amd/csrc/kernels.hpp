@@ -43,9 +43,8 @@ struct DSub {
   const int* lut;       // [3][w][w][w] slot lookup
   const int* slots;     // [nG][4]: d, dx, dy, dz
   const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, d2, count
-  const int* chunks;    // [nchunks][2]: segment, first vertex
+  const int* chunks;    // [nchunks][2]: segment | groups per wave << 16, first vertex
   int nchunks;
-  int gpw;              // 16-vertex groups per wave in the patch kernel
   const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };
 
@@ -75,8 +74,9 @@ int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the 
 // (summed over the segments and the pairs of a class): the fewest that let the whole grid
 // be resident at once, given the workgroups per CU that the kernel's registers allow
 // (4 in FP32, 3 in FP64 on a 256-CU MI355X), at most 8.
+inline int64_t patch_resident_blocks(size_t elem) { return (elem == 4 ? 4 : 3) * 256; }
 inline int patch_groups(int64_t groups, size_t elem) {
-  const int64_t resident = (elem == 4 ? 4 : 3) * 256 * 4;   // waves
+  const int64_t resident = patch_resident_blocks(elem) * 4;   // waves
   const int64_t g = (groups + resident - 1) / resident;
   return (int)std::max<int64_t>(1, std::min<int64_t>(8, g));
 }
