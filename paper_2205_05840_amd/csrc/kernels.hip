@@ -1306,20 +1306,25 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   if (r32) r32 += off;
   scal += (int64_t)pair * kScalStride;
   part += (int64_t)pair * pstride;
+  // this lane's first quads do not depend on alpha: loaded before the partial sums are
+  // read (index clamped, no branch), so the two latencies overlap
+  const int64_t n4 = len >> 2, step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double u0[4], r0[4], p0[4], q0[4];
+  {
+    const int64_t ec = 4 * (e0 < n4 ? e0 : 0);
+    Quad<double>::load(u + ec, u0);
+    Quad<double>::load(r + ec, r0);
+    Quad<double>::load(p + ec, p0);
+    Quad<double>::load(q + ec, q0);
+  }
   // p^T A p from the partials of the operator kernel (every block the same value)
   const double pq = reduce_partials(pq_part + (int64_t)pair * pstride, pq_n, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[kS_PQ] = pq;
   const double alpha = scal[i_num] / pq;
   double s = 0.0;
-  const int64_t n4 = len >> 2;
-#pragma unroll 2
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double uv[4], rv[4], pv[4], qv[4];
-    Quad<double>::load(u + 4 * e, uv);
-    Quad<double>::load(r + 4 * e, rv);
-    Quad<double>::load(p + 4 * e, pv);
-    Quad<double>::load(q + 4 * e, qv);
+  auto update = [&](int64_t e, double (&uv)[4], double (&rv)[4], const double (&pv)[4],
+                    const double (&qv)[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       uv[k] += alpha * pv[k];
@@ -1334,6 +1339,16 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
       for (int k = 0; k < 4; ++k) rf[k] = (float)rv[k];
       Quad<float>::store(r32 + 4 * e, rf);
     }
+  };
+  if (e0 < n4) update(e0, u0, r0, p0, q0);
+#pragma unroll 2
+  for (int64_t e = e0 + step; e < n4; e += step) {
+    double uv[4], rv[4], pv[4], qv[4];
+    Quad<double>::load(u + 4 * e, uv);
+    Quad<double>::load(r + 4 * e, rv);
+    Quad<double>::load(p + 4 * e, pv);
+    Quad<double>::load(q + 4 * e, qv);
+    update(e, uv, rv, pv, qv);
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -1351,6 +1366,14 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
   p += (int64_t)pair * len;
   z += (int64_t)pair * len;
   scal += (int64_t)pair * kScalStride;
+  // this lane's first quads of z and p do not depend on beta: their loads go out before
+  // the partial sums are read, so the two latencies overlap (index clamped, no branch)
+  const int64_t n4 = len >> 2, step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  TZ z0[4];
+  double p0[4];
+  Quad<TZ>::load(z + 4 * (e0 < n4 ? e0 : 0), z0);
+  Quad<double>::load(p + 4 * (e0 < n4 ? e0 : 0), p0);
   // r . z (and z . q) from the partials of the dot kernel; block 0 keeps them
   const double* dp = dot_part + (int64_t)pair * pstride;
   const double rz = reduce_partials(dp, dot_n, sh);
@@ -1362,10 +1385,13 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
   double beta;
   if (flexible) beta = -(scal[i_an] / scal[i_ad]) * zq / scal[i_den];
   else beta = rz / scal[i_den];
-  const int64_t n4 = len >> 2;
+  if (e0 < n4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p0[k] = (double)z0[k] + beta * p0[k];
+    Quad<double>::store(p + 4 * e0, p0);
+  }
 #pragma unroll 2
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = e0 + step; e < n4; e += step) {
     TZ zv[4];
     double pv[4];
     Quad<TZ>::load(z + 4 * e, zv);
