@@ -236,13 +236,31 @@ def diff_leg(torch, steps, warmup):
     return res
 
 
-def cpu_baseline(f, iters_expected, sample_iters=3):
+def cpu_baseline(f, iters_expected, gpu_solutions=None, sample_iters=3):
     """The FP64 CPU oracle (assembled sparse matrices, factored vertex smoother) on a
     bounded sample of the same 128^3 solve: setup untimed, then `sample_iters` PCG
-    iterations timed and scaled to a full solve of `iters_expected` iterations."""
-    from oracle import pcg, rhs, vcycle
+    iterations timed and scaled to a full solve of `iters_expected` iterations.
+
+    Also the second CPU reference: the oracle's exact solve of the same discrete system
+    (sine/cosine transforms diagonalise A on the box into 3 x 3 blocks), timed, and the
+    relative error of the GPU solutions (padded layout, host copies) against it."""
+    import numpy as np
+    from oracle import exact, mesh, pcg, rhs, vcycle
     h = 1.0 / N_ELEM
     b = rhs.load_from_samples(N_ELEM, h, f)
+    t0 = time.perf_counter()
+    ue = exact.solve_fft(N_ELEM, h, 1.0, b)
+    t_fft = time.perf_counter() - t0
+    exact_ref = {"s_per_solve": t_fft, "method": "oracle exact solve (DST/DCT, 3x3 blocks)"}
+    if gpu_solutions:
+        P = (N_ELEM + 1 + 7) // 8 * 8
+        B = (N_ELEM + 1) ** 2 * P
+        d, pc = mesh.edge_coords(N_ELEM)
+        idx = d * B + (pc[:, 2] * (N_ELEM + 1) + pc[:, 1]) * P + pc[:, 0]
+        nrm = float(np.linalg.norm(ue))
+        for name, u in gpu_solutions.items():
+            exact_ref[f"rel_error_{name}"] = float(np.linalg.norm(u[idx] - ue)) / nrm
+    del ue
     t0 = time.perf_counter()
     H = vcycle.Hierarchy(N_ELEM, 1.0)
     t_setup = time.perf_counter() - t0
@@ -257,7 +275,8 @@ def cpu_baseline(f, iters_expected, sample_iters=3):
                        f"({t:.1f} s, setup {t_setup:.1f} s untimed), scaled to "
                        f"{iters_expected} iterations; SciPy SpMV single-threaded"),
             "s_per_solve_est": s_solve,
-            "affinity_cpus": len(os.sched_getaffinity(0))}
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "exact": exact_ref}
 
 
 def kernel_probe(torch, Solver, precision, reps):
@@ -355,7 +374,8 @@ def main():
         out["forms"] = {"batched": batched_leg(torch, max(1, args.steps // 2), 1),
                         "differentiation": diff_leg(torch, 1, 1)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"])
+        host = {"fp32": sols[(1.0, "fp32")].cpu().numpy(), "fp64": sols[(1.0, "fp64")].cpu().numpy()}
+        out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"], host)
     print(json.dumps(out), flush=True)
     del np
 
