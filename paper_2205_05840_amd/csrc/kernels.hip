@@ -718,15 +718,31 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
                                                        const T* __restrict__ ATinv, DGeom g, DSub sub, T eta,
                                                        int assign, Bat bt, int nbx) {
   constexpr int NB = 48, NPAD = 64;
-  __shared__ T sX[6 * NB];
-  __shared__ T sA[36];
+  constexpr bool kInPlace = sizeof(T) == 4;
+  __shared__ T lX[kInPlace ? 1 : 6 * NB];
+  __shared__ T lA[kInPlace ? 1 : 36];
   const int pair = blockIdx.x / nbx;
   if (inactive(bt, pair)) return;
-  XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
-  ATinv += (int64_t)(pair / bt.nrhs) * 36;
-  stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
-  stage_lds<T, 1>(sA, ATinv, 36);
-  __syncthreads();
+  // FP32: X_T and A_T^{-1} are read in place (uniform, constant indices: scalar loads that
+  // overlap the vector loads; no barrier in front of the patch-result loads).  FP64:
+  // staged in LDS (read in place, the compiler keeps too many of them in registers).
+  // (k_sm_condense stages them: its products interleave with the loads, and scalar
+  // loads on demand there measured slower.)
+  const T* __restrict__ gX = XT + (int64_t)(pair / bt.nrhs) * 6 * NB;
+  const T* __restrict__ gA = ATinv + (int64_t)(pair / bt.nrhs) * 36;
+  if constexpr (!kInPlace) {
+    stage_lds<T, (6 * NB + 63) / 64>(lX, gX, 6 * NB);
+    stage_lds<T, 1>(lA, gA, 36);
+    __syncthreads();
+  }
+  auto sX = [&](int i) -> T {
+    if constexpr (kInPlace) return gX[i];
+    else return lX[i];
+  };
+  auto sA = [&](int i) -> T {
+    if constexpr (kInPlace) return gA[i];
+    else return lA[i];
+  };
   const int nH = sub.nH;
   const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, c = blockIdx.z;
@@ -771,10 +787,10 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   for (int t = 0; t < 6; ++t) {
     T q = T(0);
 #pragma unroll
-    for (int e = 0; e < NB; ++e) q += sX[t * NB + e] * wv[e];
+    for (int e = 0; e < NB; ++e) q += sX(t * NB + e) * wv[e];
     T zi = T(0);
 #pragma unroll
-    for (int s2 = 0; s2 < 6; ++s2) zi += sA[t * 6 + s2] * rI[s2];
+    for (int s2 = 0; s2 < 6; ++s2) zi += sA(t * 6 + s2) * rI[s2];
     z[ioff[t]] = zo[t] + eta * (zi - q);
   }
 #pragma unroll
