@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
       bv[jj] = Brow[j < N ? j : 0];
     }
   };
-  auto row_sums = [&](const T (&bv)[NJ], int rc, T (&acc)[RC]) {
+  auto row_sums = [&](const T (&bv)[NJ], T (&acc)[RC]) {
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = T(0);
 #pragma unroll
@@ -974,7 +974,7 @@ __global__ void __launch_bounds__(256) k_dense_vcycle(const T* __restrict__ g, T
       T bnext[NJ];
       if (ii + 1 < rpw) load_row(i + 1, bnext);
       T acc[RC];
-      row_sums(bcur, rc, acc);
+      row_sums(bcur, acc);
       T mine = T(0);
 #pragma unroll
       for (int r = 0; r < RC; ++r) {
