@@ -203,7 +203,9 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       for (int gb = 1; gb < L.gpw; ++gb)
         if (nchunks_with(gb) <= ndmg::patch_resident_blocks(el)) { gpw_b = gb; break; }
       for (size_t si = 0; si < L.segs.size(); ++si) {
-        const int gs = L.segs[si].type == 13 ? L.gpw : gpw_b;
+        // and no more per wave than spreads a small segment over the 4 waves of one chunk
+        const int gseg = (L.segs[si].count + 15) / 16;
+        const int gs = std::max(1, std::min(L.segs[si].type == 13 ? L.gpw : gpw_b, (gseg + 3) / 4));
         for (int f = 0; f < L.segs[si].count; f += 64 * gs) {
           L.chunks.push_back((int)si | gs << 16);
           L.chunks.push_back(f);
