@@ -658,6 +658,24 @@ static_assert(kOI.n == 18, "18 interface unknowns owned per subdomain");
 // interface unknowns T owns, from r there and the interior residuals of T and its
 // neighbours T - e_x, T - e_y, T - e_z and their pairwise sums (all tables compile-time).
 // Other entries of g are left untouched (never read).
+// Subdomain (a, b, c) of this thread in the per-subdomain smoother kernels: blocks of 64
+// lanes along a row (grid (nbx * pairs, nH, nH)), or, packed (grid (nbx * pairs, nH)),
+// over consecutive positions of the (a, b) plane, so that rows shorter than a wave leave
+// no lane idle.  False past the row (or plane).
+__device__ __forceinline__ bool subdomain_of(int nH, int nbx, int packed, int& a, int& b, int& c) {
+  const int t = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  if (packed) {
+    a = t % nH;
+    b = t / nH;
+    c = blockIdx.y;
+    return t < nH * nH;
+  }
+  a = t;
+  b = blockIdx.y;
+  c = blockIdx.z;
+  return t < nH;
+}
+
 // Copy n (<= 64 * R) values from global memory into LDS with one batch of loads per
 // thread (a loop that stores each value before loading the next waits for every load).
 template <typename T, int R>
@@ -672,7 +690,8 @@ __device__ __forceinline__ void stage_lds(T* __restrict__ dst, const T* __restri
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* __restrict__ gg,
-                                                    const T* __restrict__ XT, DGeom g, int nH, Bat bt, int nbx) {
+                                                    const T* __restrict__ XT, DGeom g, int nH, Bat bt, int nbx,
+                                                    int packed) {
   constexpr int NB = 48;
   __shared__ T sX[6 * NB];
   const int pair = blockIdx.x / nbx;
@@ -680,9 +699,8 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
   stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
   __syncthreads();
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH) return;
+  int a, b, c;
+  if (!subdomain_of(nH, nbx, packed, a, b, c)) return;
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
   gg += voff;
@@ -736,7 +754,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, const T* __restrict__ r,
                                                        T* __restrict__ z, const T* __restrict__ XT,
                                                        const T* __restrict__ ATinv, DGeom g, DSub sub, T eta,
-                                                       int assign, Bat bt, int nbx) {
+                                                       int assign, Bat bt, int nbx, int packed) {
   constexpr int NB = 48, NPAD = 64;
   constexpr bool kInPlace = sizeof(T) == 4;
   __shared__ T lX[kInPlace ? 1 : 6 * NB];
@@ -764,9 +782,8 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
     else return lA[i];
   };
   const int nH = sub.nH;
-  const int a = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y, c = blockIdx.z;
-  if (a >= nH) return;
+  int a, b, c;
+  if (!subdomain_of(nH, nbx, packed, a, b, c)) return;
   const int nv = nH + 1;
   const int64_t NV = (int64_t)nv * nv * nv;
   const int64_t voff = (int64_t)pair * vlen(g);
@@ -1683,14 +1700,17 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
   if (sub.s != 2) return hipErrorInvalidValue;
   const DGeom dg = dgeom(g);
   // condensed interface residual gg = r - A A_T^{-1} r_I on the interface unknowns
-  const int nbs = (sub.nH + 63) / 64;
-  const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, (unsigned)sub.nH);
-  hipLaunchKernelGGL((k_sm_condense<T>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs);
+  // batches of rows shorter than a wave: lanes packed over the subdomain plane (a single
+  // pair keeps more, partly filled waves, which hide more latency)
+  const int packed = (sub.nH < 64 && bt.count >= 4) ? 1 : 0;
+  const int nbs = packed ? (sub.nH * sub.nH + 63) / 64 : (sub.nH + 63) / 64;
+  const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, packed ? 1u : (unsigned)sub.nH);
+  hipLaunchKernelGGL((k_sm_condense<T>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs, packed);
   if (sub.nchunks > 0)
     hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks, (unsigned)bt.count), dim3(256), 0,
                        st, L.gg, L.Y, L.Sinv, dg, sub, bt);
   hipLaunchKernelGGL((k_sm_pull_extend<T>), eg, dim3(64), 0, st, L.Y, r, z, L.XT, L.ATinv, dg, sub, (T)eta, assign,
-                     bt, nbs);
+                     bt, nbs, packed);
   return hipGetLastError();
 }
 
