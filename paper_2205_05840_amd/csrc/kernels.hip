@@ -59,6 +59,25 @@ __device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
   return bt.act != nullptr && bt.act[pair] == 0;
 }
 
+// Position (a, b, c) of this thread in a w x w x w box of work items (subdomains, or
+// nodes of the transfers): blocks of 64 lanes along a row (grid (nbx * pairs, w, w)), or,
+// packed (grid (nbx * pairs, w)), over consecutive positions of the (a, b) plane, so that
+// rows shorter than a wave leave no lane idle.  False past the row (or plane).
+__device__ __forceinline__ bool box_position(int w, int nbx, int packed, int& a, int& b, int& c) {
+  const int t = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+  if (packed) {
+    a = t % w;
+    b = t / w;
+    c = blockIdx.y;
+    return t < w * w;
+  }
+  a = t;
+  b = blockIdx.y;
+  c = blockIdx.z;
+  return t < w;
+}
+
+
 template <typename T>
 __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
                                       T ah, T h3) {
@@ -167,11 +186,10 @@ __device__ __forceinline__ void restrict_node(const T* __restrict__ rf, T* __res
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
-                                                 DGeom f, DGeom c, Bat bt, int nbx) {
+                                                 DGeom f, DGeom c, Bat bt, int nbx, int packed) {
   const int pair = blockIdx.x / nbx;
-  const int I = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y, K = blockIdx.z;
-  if (I >= c.n || inactive(bt, pair)) return;
+  int I, J, K;
+  if (!box_position(c.n, nbx, packed, I, J, K) || inactive(bt, pair)) return;
   restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K);
 }
 
@@ -210,11 +228,10 @@ __device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __rest
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
-                                                    DGeom f, DGeom c, Bat bt, int nbx) {
+                                                    DGeom f, DGeom c, Bat bt, int nbx, int packed) {
   const int pair = blockIdx.x / nbx;
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= f.n || inactive(bt, pair)) return;
+  int i, j, k;
+  if (!box_position(f.n, nbx, packed, i, j, k) || inactive(bt, pair)) return;
   prolong_node(ec + (int64_t)pair * vlen(c), zf + (int64_t)pair * vlen(f), f, c, i, j, k);
 }
 
@@ -658,24 +675,6 @@ static_assert(kOI.n == 18, "18 interface unknowns owned per subdomain");
 // interface unknowns T owns, from r there and the interior residuals of T and its
 // neighbours T - e_x, T - e_y, T - e_z and their pairwise sums (all tables compile-time).
 // Other entries of g are left untouched (never read).
-// Subdomain (a, b, c) of this thread in the per-subdomain smoother kernels: blocks of 64
-// lanes along a row (grid (nbx * pairs, nH, nH)), or, packed (grid (nbx * pairs, nH)),
-// over consecutive positions of the (a, b) plane, so that rows shorter than a wave leave
-// no lane idle.  False past the row (or plane).
-__device__ __forceinline__ bool subdomain_of(int nH, int nbx, int packed, int& a, int& b, int& c) {
-  const int t = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  if (packed) {
-    a = t % nH;
-    b = t / nH;
-    c = blockIdx.y;
-    return t < nH * nH;
-  }
-  a = t;
-  b = blockIdx.y;
-  c = blockIdx.z;
-  return t < nH;
-}
-
 // Copy n (<= 64 * R) values from global memory into LDS with one batch of loads per
 // thread (a loop that stores each value before loading the next waits for every load).
 template <typename T, int R>
@@ -700,7 +699,7 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
   stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
   __syncthreads();
   int a, b, c;
-  if (!subdomain_of(nH, nbx, packed, a, b, c)) return;
+  if (!box_position(nH, nbx, packed, a, b, c)) return;
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
   gg += voff;
@@ -783,7 +782,7 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   };
   const int nH = sub.nH;
   int a, b, c;
-  if (!subdomain_of(nH, nbx, packed, a, b, c)) return;
+  if (!box_position(nH, nbx, packed, a, b, c)) return;
   const int nv = nH + 1;
   const int64_t NV = (int64_t)nv * nv * nv;
   const int64_t voff = (int64_t)pair * vlen(g);
@@ -1679,18 +1678,21 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
 template <typename T>
 hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, const Bat& bt,
                            hipStream_t st) {
-  const int nbx = nbx_inner(c.n);
-  hipLaunchKernelGGL((k_restrict<T>), inner_grid(c, nbx, bt.count), dim3(64), 0, st, rf, gc, dgeom(f),
-                     dgeom(c), bt, nbx);
+  // batches of short rows: lanes packed over the (I, J) plane of inner nodes
+  const int packed = (c.n < 64 && bt.count >= 4) ? 1 : 0;
+  const int nbx = packed ? (c.n * c.n + 63) / 64 : nbx_inner(c.n);
+  const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), (unsigned)c.n) : inner_grid(c, nbx, bt.count);
+  hipLaunchKernelGGL((k_restrict<T>), grid, dim3(64), 0, st, rf, gc, dgeom(f), dgeom(c), bt, nbx, packed);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
                               hipStream_t st) {
-  const int nbx = nbx_inner(f.n);
-  hipLaunchKernelGGL((k_prolong_add<T>), inner_grid(f, nbx, bt.count), dim3(64), 0, st, ec, zf, dgeom(f),
-                     dgeom(c), bt, nbx);
+  const int packed = (f.n < 64 && bt.count >= 4) ? 1 : 0;
+  const int nbx = packed ? (f.n * f.n + 63) / 64 : nbx_inner(f.n);
+  const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), (unsigned)f.n) : inner_grid(f, nbx, bt.count);
+  hipLaunchKernelGGL((k_prolong_add<T>), grid, dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c), bt, nbx, packed);
   return hipGetLastError();
 }
 
