@@ -1654,9 +1654,8 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
     const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, nullptr, st);
     if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
   }
-  // batches: lanes packed over the plane (a single pair keeps more, partly filled waves,
-  // which hide more latency at these tiny sizes)
-  if (g.n + 1 < 64 && bt.count >= 4) {
+  // rows shorter than a wave: lanes packed over the plane
+  if (g.n + 1 < 64) {
     const int w = g.n + 1, nbp = (w * w + 63) / 64;
     const dim3 grid((unsigned)(nbp * bt.count), (unsigned)w);
     if (mode == 0)
@@ -1678,8 +1677,8 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
 template <typename T>
 hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, const Bat& bt,
                            hipStream_t st) {
-  // batches of short rows: lanes packed over the (I, J) plane of inner nodes
-  const int packed = (c.n < 64 && bt.count >= 4) ? 1 : 0;
+  // rows shorter than a wave: lanes packed over the (I, J) plane of inner nodes
+  const int packed = (c.n < 64) ? 1 : 0;
   const int nbx = packed ? (c.n * c.n + 63) / 64 : nbx_inner(c.n);
   const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), (unsigned)c.n) : inner_grid(c, nbx, bt.count);
   hipLaunchKernelGGL((k_restrict<T>), grid, dim3(64), 0, st, rf, gc, dgeom(f), dgeom(c), bt, nbx, packed);
@@ -1689,7 +1688,7 @@ hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, con
 template <typename T>
 hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
                               hipStream_t st) {
-  const int packed = (f.n < 64 && bt.count >= 4) ? 1 : 0;
+  const int packed = (f.n < 64) ? 1 : 0;
   const int nbx = packed ? (f.n * f.n + 63) / 64 : nbx_inner(f.n);
   const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), (unsigned)f.n) : inner_grid(f, nbx, bt.count);
   hipLaunchKernelGGL((k_prolong_add<T>), grid, dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c), bt, nbx, packed);
@@ -1702,9 +1701,8 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
   if (sub.s != 2) return hipErrorInvalidValue;
   const DGeom dg = dgeom(g);
   // condensed interface residual gg = r - A A_T^{-1} r_I on the interface unknowns
-  // batches of rows shorter than a wave: lanes packed over the subdomain plane (a single
-  // pair keeps more, partly filled waves, which hide more latency)
-  const int packed = (sub.nH < 64 && bt.count >= 4) ? 1 : 0;
+  // rows shorter than a wave: lanes packed over the subdomain plane
+  const int packed = (sub.nH < 64) ? 1 : 0;
   const int nbs = packed ? (sub.nH * sub.nH + 63) / 64 : (sub.nH + 63) / 64;
   const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, packed ? 1u : (unsigned)sub.nH);
   hipLaunchKernelGGL((k_sm_condense<T>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs, packed);
