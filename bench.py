@@ -307,6 +307,8 @@ def main():
                     help="skip the batched and differentiated forms")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only run the calibration copy and the apply kernel (counter runs)")
+    ap.add_argument("--solve-probe", choices=["fp32", "fp64"],
+                    help="only run one warm-up and one timed 128^3 solve in this precision (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -322,6 +324,12 @@ def main():
 
     if args.kernel_probe:
         kernel_probe(torch, Solver, "fp64", 10)
+        return
+    if args.solve_probe:
+        f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
+        _, _, _, res = run_leg(torch, Solver, f, 1.0, args.solve_probe, 1, 1)
+        print(json.dumps({"probe": "solve", "precision": args.solve_probe, "n": N_ELEM,
+                          "s_per_solve": res["s_per_solve_total"], "iters": res["iters"]}), flush=True)
         return
     f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
     ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
