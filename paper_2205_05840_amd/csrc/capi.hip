@@ -216,7 +216,9 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       L.o_gg = take(vb);
       L.o_w = take(vb);
       const size_t nv = (size_t)(L.sub.nH + 1);
-      L.nY = nv * nv * nv * (size_t)L.sub.npad;
+      // row positions in bytes fit in 32 bits (the smoother's reads of Y assume it)
+      if (ndmg::y_row_len(L.sub.nH) * 8 > UINT32_MAX) return fail(NDMG_EINVAL, "level too large for the patch result rows");
+      L.nY = std::max<size_t>(nv * nv * nv, (size_t)ndmg::y_row_len(L.sub.nH)) * (size_t)L.sub.npad;
       L.o_Y = take(L.nY * el * cnt);
       // gathered patch inputs of the one-launch bottom of the V-cycle (small levels)
       if (sizes[k] <= pl.opts.bottom_n) L.o_G = take(L.nY * el * cnt);
@@ -348,6 +350,7 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.npad = L.sub.npad;
   d.lut_w = L.sub.lut_w;
   d.nB = L.nB;
+  d.bpatch = c->plan.opts.boundary_patches != 0;
   d.lut = at<int>(c, L.o_lut);
   d.slots = at<int>(c, L.o_slots);
   d.segs = at<int>(c, L.o_segs);
@@ -469,7 +472,11 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
     for (auto& q : L.segs) {
       sg.push_back(q.type);
       for (int a = 0; a < 3; ++a) sg.push_back(q.lo[a]);
-      for (int a = 0; a < 3; ++a) sg.push_back(q.dims[a]);
+      for (int a = 0; a < 2; ++a) sg.push_back(q.dims[a]);
+      const int nH = L.sub.nH;
+      const int yb = ndmg::y_pos(nH, c->plan.opts.boundary_patches != 0, q.lo[0], q.lo[1], q.lo[2]);
+      if (yb % 16) return fail(NDMG_EINVAL, "internal: patch result region not on a 16-entry run");
+      sg.push_back((int)yb);
       sg.push_back(q.count);
     }
     NDMG_TRY(stg.put_vec(c, L.o_segs, sg));

@@ -301,7 +301,8 @@ struct Mfma<float> {
 // g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (the next group's gathers
 // are in flight while the current group's products run), reads the A-operand fragments
 // S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and accumulates the 16 x 16 output tile
-// per mb; results go to the slot-major Y.
+// per mb; results go to Y (layout at y_pos: a group's 16 vertices fill one aligned run
+// of each row).
 // - Slots are direction-major (NG / 3 per edge direction, a multiple of 4), so the edge
 //   direction of k-step ks is fixed and its block offset d B is uniform; a lane adds a
 //   32-bit offset to a per-group scalar base.
@@ -340,10 +341,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   const int pair = lb / gridDim.x;
   if (inactive(bt, pair)) return;
   const int tid = threadIdx.x;
-  const int nv = sub.nH + 1;
-  const int64_t NV = (int64_t)nv * nv * nv;
+  const int64_t NVY = y_row_len(sub.nH);
   gg += (int64_t)pair * vlen(g);
-  Y += (int64_t)pair * NV * NPAD;
+  Y += (int64_t)pair * NVY * NPAD;
   const int chunk = lb - pair * gridDim.x;
   const int seg = sub.chunks[2 * chunk] & 0xffff;
   const int gpw = sub.chunks[2 * chunk] >> 16;   // 16-vertex groups per wave in this chunk
@@ -357,6 +357,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   const int lo2 = __builtin_amdgcn_readfirstlane(sg[3]);
   const int d0 = __builtin_amdgcn_readfirstlane(sg[4]);
   const int d1 = __builtin_amdgcn_readfirstlane(sg[5]);
+  const int ybase = __builtin_amdgcn_readfirstlane(sg[6]);
   const int count = __builtin_amdgcn_readfirstlane(sg[7]);
   const T* __restrict__ Sm = Sinv + ((int64_t)(pair / bt.nrhs) * 27 + type) * NPAD * NPAD;
   for (int e = tid; e < NPAD; e += blockDim.x) {
@@ -397,14 +398,12 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
     if (v >= count) v = v0;
     const int vx = lo0 + v % d0, vy = lo1 + (v / d0) % d1, vz = lo2 + v / (d0 * d1);
     const int64_t node = lin(g, S * vx, S * vy, S * vz);
-    const int64_t vrow = ((int64_t)vz * nv + vy) * nv + vx;
     // lane 0 holds v0, the smallest vertex of the group: the offsets are >= 0
     const int64_t node0 = __builtin_amdgcn_readfirstlane((unsigned)(node & 0xffffffff)) |
                           ((int64_t)__builtin_amdgcn_readfirstlane((int)(node >> 32)) << 32);
-    y0 = __builtin_amdgcn_readfirstlane((unsigned)(vrow & 0xffffffff)) |
-         ((int64_t)__builtin_amdgcn_readfirstlane((int)(vrow >> 32)) << 32);
+    y0 = (int64_t)ybase + v0;
     const int loff = (int)(node - node0);
-    yoff = (int)(vrow - y0);
+    yoff = v - v0;
 #pragma unroll
     for (int ks = 0; ks < NKE; ++ks) {
       // absent slots read entry 0 (an x-edge on the boundary: zero), so that no select
@@ -429,7 +428,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 #pragma unroll
       for (int ks = 0; ks < NKE; ++ks) acc = Mfma<T>::mma(a[ks / VE][ks % VE], bcol[ks], acc);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NV] = acc[q];
+      for (int q = 0; q < 4; ++q) yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NVY] = acc[q];
     }
   };
 
@@ -461,6 +460,16 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
     product_store(b1, y0b, yob);
   }
   if (c < ngroups) product_store(b0, y0a, yoa);
+  // the zero run that vertices without a patch read (row `lane`): the buffer is shared
+  // with the small-level kernel's layout
+  if (chunk == 0 && wave == 0) {
+#pragma unroll
+    for (int row = lane; row < NPAD; row += 64) {
+      T* yz = Y + (int64_t)row * NVY + y_zero_run(sub.nH);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) yz[i] = T(0);
+    }
+  }
 }
 
 // w = sum_V R_V^T y_V on the interface unknowns of node (i, j, k), i < n; z (assign ? =,
@@ -783,15 +792,20 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   const int nH = sub.nH;
   int a, b, c;
   if (!box_position(nH, nbx, packed, a, b, c)) return;
-  const int nv = nH + 1;
-  const int64_t NV = (int64_t)nv * nv * nv;
+  const int64_t NVY = y_row_len(nH);
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
   z += voff;
-  const int64_t vrow0 = ((int64_t)c * nv + b) * nv + a;
-  const T* __restrict__ Yp = Y + (int64_t)pair * NV * NPAD + vrow0;
-  const int64_t cofs[8] = {0, 1, nv, nv + 1, (int64_t)nv * nv, (int64_t)nv * nv + 1, (int64_t)nv * nv + nv,
-                           (int64_t)nv * nv + nv + 1};
+  // Y rows as a uniform base per slot plus a 32-bit byte offset per corner (corner
+  // i + 2 j + 4 k at vertex (a + i, b + j, c + k)): 8 offset registers serve every load
+  const char* __restrict__ Yb = reinterpret_cast<const char*>(Y + (int64_t)pair * NVY * NPAD);
+  const int64_t rowb = NVY * (int64_t)sizeof(T);
+  unsigned cb[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int x = a + (q & 1), y = b + ((q >> 1) & 1), zc = c + (q >> 2);
+    cb[q] = (unsigned)y_pos(nH, sub.bpatch, x, y, zc) * (unsigned)sizeof(T);
+  }
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
   int64_t ioff[6];
   interior_offsets_s2(g, base, ioff);
@@ -815,7 +829,8 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-      if (t < kBP.ncand[e]) acc += Yp[(int64_t)kBP.slot[e][t] * NV + cofs[kBP.corner[e][t]]];
+      if (t < kBP.ncand[e])
+        acc += *reinterpret_cast<const T*>(Yb + kBP.slot[e][t] * rowb + cb[kBP.corner[e][t]]);
     wv[e] = acc;
   }
   // interior unknowns (the order of interior_offsets_s2): z_I += eta (A_T^{-1} r_I - X_T w)

@@ -40,13 +40,55 @@ inline Bat single_batch(const double* d_alpha) { return Bat{1, 1, d_alpha, nullp
 // Smoother tables of one level on the device (shared by all pairs of a class).
 struct DSub {
   int s, nH, nI, nG, npad, lut_w, nB;
+  int bpatch;           // boundary vertices carry patches
   const int* lut;       // [3][w][w][w] slot lookup
   const int* slots;     // [nG][4]: d, dx, dy, dz
-  const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, d2, count
+  const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, row position of the
+                        // segment's first vertex in Y (y_pos), count
   const int* chunks;    // [nchunks][2]: segment | groups per wave << 16, first vertex
   int nchunks;
   const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };
+
+// ---- Y, the vertex patch results of the large-level smoother --------------------------
+// Slot-major: npad rows per pair, row `slot` holding y_V[slot] of every vertex V at
+// y_pos(V).  The vertices of one patch type (inside the box, on one of its 6 faces, on
+// one of its 12 edges) lie together, in the order of their segment, each type in a
+// region of whole 16-entry runs: 16 consecutive vertices of a segment from a multiple of
+// 16 fill one aligned run, so each store of the patch kernel writes whole cache lines.
+// Vertices with no patch (the box corners; all boundary vertices when those carry none)
+// share the zero run at the end of the row, which the patch kernel clears.
+__host__ __device__ inline int64_t y_run16(int64_t x) { return (x + 15) / 16 * 16; }
+__host__ __device__ inline int64_t y_zero_run(int nH) {
+  const int64_t m = nH - 1;
+  return y_run16(m * m * m) + 6 * y_run16(m * m) + 12 * y_run16(m);
+}
+__host__ __device__ inline int64_t y_row_len(int nH) { return y_zero_run(nH) + 16; }
+// row position of vertex (x, y, z), 0 <= x, y, z <= nH.  Plain arithmetic on 0/1 flags,
+// no selects between expressions: a kernel computes it between loads that it wants in
+// flight together, and branches there would make it wait for them.  Row positions fit in
+// 32 bits (the host checks y_row_len).
+__host__ __device__ inline int y_pos(int nH, int bpatch, int x, int y, int z) {
+  const int m = nH - 1;
+  // per axis: inside the box (i), on its upper face (h); on the lower face otherwise
+  const int ix = (x > 0) & (x < nH), iy = (y > 0) & (y < nH), iz = (z > 0) & (z < nH);
+  const int hx = x == nH, hy = y == nH, hz = z == nH;
+  const int nb = 3 - ix - iy - iz;   // axes on which the vertex lies on the box boundary
+  // the segment's order: x fastest, then y, then z, over the axes inside the box
+  const int dx = 1 + ix * (m - 1), dy = 1 + iy * (m - 1);
+  const int local = ix * (x - 1) + dx * (iy * (y - 1) + dy * (iz * (z - 1)));
+  const int r3 = (int)y_run16((int64_t)m * m * m), r2 = (int)y_run16((int64_t)m * m), r1 = (int)y_run16(m);
+  // a face (nb = 1) by its normal axis and side: 2 axis + side
+  const int f = (1 - ix) * hx + (1 - iy) * (2 + hy) + (1 - iz) * (4 + hz);
+  // an edge (nb = 2) by the axis along it, then the sides of the other two, lower axis
+  // first: 4 axis + 2 side1 + side2
+  const int e = 4 * (iy + 2 * iz) + 2 * (ix * hy + (1 - ix) * hx) + (iz * hy + (1 - iz) * hz);
+  const int base = (nb == 1) * (r3 + f * r2) + (nb == 2) * (r3 + 6 * r2 + e * r1);
+  // no patch: the box corners, and every boundary vertex when those carry none
+  const int none = (nb == 3) | ((nb > 0) & (bpatch == 0));
+  const int pos = base + local;
+  return pos + none * (r3 + 6 * r2 + 12 * r1 - pos);
+}
 
 // True when the kernels' compile-time table of the patches holding each subdomain
 // boundary edge equals the host's boundary_patch_table().
@@ -59,7 +101,8 @@ struct LevelPtrs {
   T* zi;      // interior solves (only interior-of-subdomain entries ever written)
   T* gg;      // condensed interface residual
   T* w;       // interface correction (only interface entries ever written)
-  T* Y;       // vertex patch results, slot-major [npad][(nH+1)^3] per pair
+  T* Y;       // vertex patch results, [npad][y_row_len(nH)] per pair (the small-level
+              // kernel uses [npad][(nH+1)^3] in the same buffer)
   const T* ATinv;   // nI x nI per problem
   const T* Sinv;    // 27 x npad x npad per problem
   const T* XT;      // nI x nB per problem
