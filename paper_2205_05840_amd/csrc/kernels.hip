@@ -59,21 +59,33 @@ __device__ __forceinline__ bool inactive(const Bat& bt, int pair) {
   return bt.act != nullptr && bt.act[pair] == 0;
 }
 
+// This block's coordinates in the grid, renumbered so that consecutive blocks of the
+// grid's x-y-z order run on one XCD (the hardware deals blocks to the 8 XCDs in turn, and
+// each XCD has its own L2): neighbouring rows of a box, which read each other's halo,
+// then share an L2.
+__device__ __forceinline__ int3 xcd_grid_block() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int lb = xcd_block(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  return make_int3(lb % gx, (lb / gx) % gy, lb / (gx * gy));
+}
+
 // Position (a, b, c) of this thread in a w x w x w box of work items (subdomains, or
-// nodes of the transfers): blocks of 64 lanes along a row (grid (nbx * pairs, w, w)), or,
-// packed (grid (nbx * pairs, w)), over consecutive positions of the (a, b) plane, so that
-// rows shorter than a wave leave no lane idle.  False past the row (or plane).
-__device__ __forceinline__ bool box_position(int w, int nbx, int packed, int& a, int& b, int& c) {
-  const int t = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
+// nodes of the transfers), for block coordinates bk (xcd_grid_block; pair bk.x / nbx):
+// blocks of 64 lanes along a row (grid (nbx * pairs, w, w)), or, packed (grid (nbx *
+// pairs, w)), over consecutive positions of the (a, b) plane, so that rows shorter than a
+// wave leave no lane idle.  False past the row (or plane).
+__device__ __forceinline__ bool box_position(const int3& bk, int w, int nbx, int packed, int& a, int& b,
+                                             int& c) {
+  const int t = (bk.x % nbx) * blockDim.x + threadIdx.x;
   if (packed) {
     a = t % w;
     b = t / w;
-    c = blockIdx.y;
+    c = bk.y;
     return t < w * w;
   }
   a = t;
-  b = blockIdx.y;
-  c = blockIdx.z;
+  b = bk.y;
+  c = bk.z;
   return t < w;
 }
 
@@ -121,9 +133,10 @@ __device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __r
 template <typename T, int MODE>
 __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
-  const int pair = blockIdx.x / nbx;
-  const int i = (blockIdx.x % nbx) * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
+  const int3 bk = xcd_grid_block();
+  const int pair = bk.x / nbx;
+  const int i = (bk.x % nbx) * blockDim.x + threadIdx.x;
+  const int j = bk.y, k = bk.z;
   if (i > g.n || inactive(bt, pair)) return;
   const int64_t off = (int64_t)pair * vlen(g);
   x += off;
@@ -187,9 +200,10 @@ __device__ __forceinline__ void restrict_node(const T* __restrict__ rf, T* __res
 template <typename T>
 __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __restrict__ gc,
                                                  DGeom f, DGeom c, Bat bt, int nbx, int packed) {
-  const int pair = blockIdx.x / nbx;
+  const int3 bk = xcd_grid_block();
+  const int pair = bk.x / nbx;
   int I, J, K;
-  if (!box_position(c.n, nbx, packed, I, J, K) || inactive(bt, pair)) return;
+  if (!box_position(bk, c.n, nbx, packed, I, J, K) || inactive(bt, pair)) return;
   restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K);
 }
 
@@ -229,9 +243,10 @@ __device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __rest
 template <typename T>
 __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
                                                     DGeom f, DGeom c, Bat bt, int nbx, int packed) {
-  const int pair = blockIdx.x / nbx;
+  const int3 bk = xcd_grid_block();
+  const int pair = bk.x / nbx;
   int i, j, k;
-  if (!box_position(f.n, nbx, packed, i, j, k) || inactive(bt, pair)) return;
+  if (!box_position(bk, f.n, nbx, packed, i, j, k) || inactive(bt, pair)) return;
   prolong_node(ec + (int64_t)pair * vlen(c), zf + (int64_t)pair * vlen(f), f, c, i, j, k);
 }
 
@@ -702,13 +717,14 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
                                                     int packed) {
   constexpr int NB = 48;
   __shared__ T sX[6 * NB];
-  const int pair = blockIdx.x / nbx;
+  const int3 bk = xcd_grid_block();
+  const int pair = bk.x / nbx;
   if (inactive(bt, pair)) return;
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
   stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
   __syncthreads();
   int a, b, c;
-  if (!box_position(nH, nbx, packed, a, b, c)) return;
+  if (!box_position(bk, nH, nbx, packed, a, b, c)) return;
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
   gg += voff;
@@ -767,7 +783,8 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   constexpr bool kInPlace = sizeof(T) == 4;
   __shared__ T lX[kInPlace ? 1 : 6 * NB];
   __shared__ T lA[kInPlace ? 1 : 36];
-  const int pair = blockIdx.x / nbx;
+  const int3 bk = xcd_grid_block();
+  const int pair = bk.x / nbx;
   if (inactive(bt, pair)) return;
   // FP32: X_T and A_T^{-1} are read in place (uniform, constant indices: scalar loads that
   // overlap the vector loads; no barrier in front of the patch-result loads).  FP64:
@@ -791,7 +808,7 @@ __global__ void __launch_bounds__(64) k_sm_pull_extend(const T* __restrict__ Y, 
   };
   const int nH = sub.nH;
   int a, b, c;
-  if (!box_position(nH, nbx, packed, a, b, c)) return;
+  if (!box_position(bk, nH, nbx, packed, a, b, c)) return;
   const int64_t NVY = y_row_len(nH);
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
