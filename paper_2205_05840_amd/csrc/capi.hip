@@ -61,7 +61,7 @@ struct LevelHost {
   bool smoothed = false;
   ndmg::SubInfo sub{};
   std::vector<ndmg::Segment> segs;
-  std::vector<int> chunks;             // (segment, first) pairs
+  std::vector<int> chunks;             // per chunk: segment | gpw << 16, first, wave step, group step
   int gpw = 1;                         // 16-vertex groups per wave of the patch kernel
   std::vector<int64_t> map;            // coarsest level: padded offset of each unknown
   int nB = 0;
@@ -209,6 +209,34 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
         for (int f = 0; f < L.segs[si].count; f += 64 * gs) {
           L.chunks.push_back((int)si | gs << 16);
           L.chunks.push_back(f);
+          L.chunks.push_back(16 * gs);   // wave w starts at f + w * 16 gs
+          L.chunks.push_back(16);        // and takes consecutive groups
+        }
+      }
+      // One pair: the interior segment's chunks that run on one XCD (the kernel numbers
+      // blocks with xcd_block: XCD x takes a contiguous range of chunks) share their
+      // vertex range with the groups dealt out in turn, wave after wave, so that at any
+      // time the XCD's waves work on one band of vertices whose gathered entries fit its
+      // L2, instead of each wave on its own stretch across the XCD's whole range.
+      if (C.count == 1) {
+        const int nch = (int)(L.chunks.size() / 4);
+        int c0 = -1, c1 = -1;
+        for (int j = 0; j < nch; ++j)
+          if (L.segs[L.chunks[4 * j] & 0xffff].type == 13) {
+            if (c0 < 0) c0 = j;
+            c1 = j + 1;
+          }
+        const int q = nch / 8, rem = nch % 8;
+        for (int x = 0; x < 8 && c0 >= 0; ++x) {
+          const int s0 = x * q + std::min(x, rem), s1 = s0 + q + (x < rem ? 1 : 0);
+          const int j0 = std::max(c0, s0), j1 = std::min(c1, s1);
+          if (j1 - j0 < 2) continue;
+          const int start = L.chunks[4 * j0 + 1], nw = 4 * (j1 - j0);
+          for (int j = j0; j < j1; ++j) {
+            L.chunks[4 * j + 1] = start + 64 * (j - j0);
+            L.chunks[4 * j + 2] = 16;
+            L.chunks[4 * j + 3] = 16 * nw;
+          }
         }
       }
       L.o_r = take(vb);
@@ -355,7 +383,7 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
   d.slots = at<int>(c, L.o_slots);
   d.segs = at<int>(c, L.o_segs);
   d.chunks = at<int>(c, L.o_chunks);
-  d.nchunks = (int)(L.chunks.size() / 2);
+  d.nchunks = (int)(L.chunks.size() / 4);
   d.bofs = at<int64_t>(c, L.o_bofs);
   return d;
 }

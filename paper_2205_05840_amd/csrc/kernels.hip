@@ -310,9 +310,11 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
 };
 
-// Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw * 16 vertices of one
-// segment (one patch type) of one pair (blockIdx.y); gpw comes with the chunk.  S_type^{-1} is staged in LDS; wave w
-// then walks its gpw groups of 16 vertices: lane l gathers the B-operand column values
+// Vertex patch solves on MFMA.  A workgroup (4 waves) takes 4 * gpw groups of 16 vertices
+// of one segment (one patch type) of one pair (blockIdx.y); the chunk gives gpw, wave 0's
+// first vertex and the vertex steps between waves and between a wave's groups (groups
+// consecutive per wave, or dealt out in turn among the waves of one XCD).  S_type^{-1} is
+// staged in LDS; wave w then walks its gpw groups: lane l gathers the B-operand column values
 // g[slot = 4 ks + l / 16] of vertex l % 16 straight from memory (the next group's gathers
 // are in flight while the current group's products run), reads the A-operand fragments
 // S^{-1}[16 mb + l % 16][4 ks + l / 16] from LDS and accumulates the 16 x 16 output tile
@@ -360,9 +362,11 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   gg += (int64_t)pair * vlen(g);
   Y += (int64_t)pair * NVY * NPAD;
   const int chunk = lb - pair * gridDim.x;
-  const int seg = sub.chunks[2 * chunk] & 0xffff;
-  const int gpw = sub.chunks[2 * chunk] >> 16;   // 16-vertex groups per wave in this chunk
-  const int first = sub.chunks[2 * chunk + 1];
+  const int seg = sub.chunks[4 * chunk] & 0xffff;
+  const int gpw = sub.chunks[4 * chunk] >> 16;   // 16-vertex groups per wave in this chunk
+  const int first = sub.chunks[4 * chunk + 1];
+  const int wstep = sub.chunks[4 * chunk + 2];   // wave w's first group at first + w wstep
+  const int cstep = sub.chunks[4 * chunk + 3];   // its group c at that + c cstep
   // segment parameters, read once: inside the loop the compiler could not keep them
   // across the stores to Y, and a reload would wait for every load and store in flight
   const int* sg = sub.segs + 8 * seg;
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const int wfirst = first + wave * gpw * 16;
+  const int wfirst = first + wave * wstep;
   int rl[NKE];
   unsigned lmask = 0;
 #pragma unroll
@@ -408,8 +412,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 
   // group c: lane's vertex (clamped), node offset from lane 0's node, Y row offsets
   auto gather = [&](int c, T (&bcol)[NKS], int64_t& y0, int& yoff) {
-    const int v0 = min(wfirst + 16 * c, count - 1);
-    int v = wfirst + 16 * c + lr;
+    const int v0 = min(wfirst + cstep * c, count - 1);
+    int v = wfirst + cstep * c + lr;
     if (v >= count) v = v0;
     const int vx = lo0 + v % d0, vy = lo1 + (v / d0) % d1, vz = lo2 + v / (d0 * d1);
     const int64_t node = lin(g, S * vx, S * vy, S * vz);
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 
   int ngroups = 0;
   for (int c = 0; c < gpw; ++c)
-    if (wfirst + 16 * c < count) ngroups = c + 1;
+    if (wfirst + cstep * c < count) ngroups = c + 1;
   T b0[NKS], b1[NKS];
   int64_t y0a, y0b;
   int yoa, yob;

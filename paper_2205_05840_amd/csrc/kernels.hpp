@@ -45,7 +45,9 @@ struct DSub {
   const int* slots;     // [nG][4]: d, dx, dy, dz
   const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, row position of the
                         // segment's first vertex in Y (y_pos), count
-  const int* chunks;    // [nchunks][2]: segment | groups per wave << 16, first vertex
+  const int* chunks;    // [nchunks][4]: segment | groups per wave << 16, first vertex of
+                        // wave 0, vertex step between waves, vertex step between a wave's
+                        // groups (all multiples of 16)
   int nchunks;
   const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };

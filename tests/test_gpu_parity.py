@@ -91,6 +91,24 @@ def test_smoother(n, alpha, boundary):
         assert _rel(from_padded(n, S.P, S.B, z), ref2) <= tol
 
 
+@pytest.mark.parametrize("boundary", [True, False])
+def test_smoother_after_small_level_kernel(boundary):
+    """The one-launch small-level kernel and the per-level smoother share a level's buffer
+    of patch results in different layouts; vertices without a patch must still read
+    zeros in the per-level smoother after the small-level kernel has filled the buffer."""
+    n, alpha = 16, 0.5
+    S = _solver(n, alpha, boundary_patches=boundary, bottom_n=n)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(mesh.ndof(n))
+    S.vcycle(_dev(to_padded(n, S.P, S.B, g)))   # fills the buffers in the small-level layout
+    A = assemble.matrix_kron(n, 1.0 / n, alpha)
+    r = rng.standard_normal(mesh.ndof(n))
+    z = _host(S.level_op(S.levels - 1, "smooth", _dev(to_padded(n, S.P, S.B, r))))
+    ref = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary)(r)
+    alt = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary, inverse="cholesky")(r)
+    assert _rel(from_padded(n, S.P, S.B, z), ref) <= max(1e-13, 20 * _rel(alt, ref))
+
+
 def test_exported_factors_match_patch_matrices():
     n, alpha = 8, 0.7
     S = _solver(n, alpha)
