@@ -208,46 +208,83 @@ __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __
 }
 
 // zf += I_{k-1}^k ec at the three edges of fine node (i, j, k)
+// Inputs of the prolongation at one fine node: per direction the 4 coarse values that
+// enter and the old fine value.
 template <typename T>
-__device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __restrict__ zf, const DGeom& f,
-                                             const DGeom& c, int i, int j, int k) {
+struct ProlongIn {
+  T e[3][4];
+  T old[3];
+};
+
+// branch-free: across each axis the coarse neighbour enters with weight 1/2 at an odd
+// fine index, else with weight 0 and stride 0 (so its load stays in bounds).  (i, j, k) is
+// an inner node, so every coarse node read lies inside the coarse grid.
+template <typename T>
+__device__ __forceinline__ void prolong_load(const T* __restrict__ ec, const T* zf, const DGeom& f,
+                                             const DGeom& c, int i, int j, int k, ProlongIn<T>& in) {
   const int o[3] = {i, j, k};
   const int64_t stc[3] = {1, (int64_t)c.P, c.plane};
   const int64_t pf = lin(f, i, j, k);
-  // branch-free: across each axis the coarse neighbour enters with weight 1/2 at an odd
-  // fine index, else with weight 0 and stride 0 (so its load stays in bounds); off the
-  // unknowns the increment is 0.  (i, j, k) is an inner node, so every coarse node read
-  // lies inside the coarse grid.
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, cc = (a + 2) % 3;
+    const T* __restrict__ e = ec + a * c.B + lin(c, o[0] >> 1, o[1] >> 1, o[2] >> 1);
+    const int64_t sb = (o[b] & 1) ? stc[b] : 0, sc = (o[cc] & 1) ? stc[cc] : 0;
+    in.e[a][0] = e[0];
+    in.e[a][1] = e[sb];
+    in.e[a][2] = e[sc];
+    in.e[a][3] = e[sb + sc];
+    in.old[a] = zf[a * f.B + pf];
+  }
+}
+
+// zf += I_{k-1}^k ec at node (i, j, k) from its loaded inputs; off the unknowns the
+// increment is 0
+template <typename T>
+__device__ __forceinline__ void prolong_store(T* zf, const DGeom& f, int i, int j, int k,
+                                              const ProlongIn<T>& in) {
+  const int o[3] = {i, j, k};
+  const int64_t pf = lin(f, i, j, k);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const bool on = is_unknown(f, a, i, j, k);
-    const int b = (a + 1) % 3, cc = (a + 2) % 3;
-    int C[3];
-    C[a] = o[a] >> 1;
-    C[b] = o[b] >> 1;
-    C[cc] = o[cc] >> 1;
-    const T* __restrict__ e = ec + a * c.B + lin(c, C[0], C[1], C[2]);
-    const bool ob = o[b] & 1, oc = o[cc] & 1;
-    const int64_t sb = ob ? stc[b] : 0, sc = oc ? stc[cc] : 0;
+    const bool ob = o[(a + 1) % 3] & 1, oc = o[(a + 2) % 3] & 1;
     // scaling by 1/2 is exact: the same roundings as 0.5 (x + y) and 0.25 ((.) + (.))
     const T wb0 = ob ? T(0.5) : T(1), wb1 = ob ? T(0.5) : T(0);
     const T wc0 = oc ? T(0.5) : T(1), wc1 = oc ? T(0.5) : T(0);
-    const T rowlo = wb0 * e[0] + wb1 * e[sb];
-    const T rowhi = wb0 * e[sc] + wb1 * e[sb + sc];
+    const T rowlo = wb0 * in.e[a][0] + wb1 * in.e[a][1];
+    const T rowhi = wb0 * in.e[a][2] + wb1 * in.e[a][3];
     const T v = wc0 * rowlo + wc1 * rowhi;
-    const T old = zf[a * f.B + pf];
-    zf[a * f.B + pf] = on ? old + v : old;
+    zf[a * f.B + pf] = on ? in.old[a] + v : in.old[a];
   }
 }
 
 template <typename T>
+__device__ __forceinline__ void prolong_node(const T* __restrict__ ec, T* __restrict__ zf, const DGeom& f,
+                                             const DGeom& c, int i, int j, int k) {
+  ProlongIn<T> in;
+  prolong_load(ec, zf, f, c, i, j, k, in);
+  prolong_store(zf, f, i, j, k, in);
+}
+
+// KP consecutive planes per lane (the grid's plane coordinate counts blocks of KP
+// planes), every load before any store: a fine level has few nodes per lane otherwise,
+// and its waves would wait on one round trip after another.  Planes past the level
+// repeat the last one (which then stores the same values twice).
+template <typename T, int KP>
 __global__ void __launch_bounds__(64) k_prolong_add(const T* __restrict__ ec, T* __restrict__ zf,
                                                     DGeom f, DGeom c, Bat bt, int nbx, int packed) {
   const int3 bk = xcd_grid_block();
   const int pair = bk.x / nbx;
-  int i, j, k;
-  if (!box_position(bk, f.n, nbx, packed, i, j, k) || inactive(bt, pair)) return;
-  prolong_node(ec + (int64_t)pair * vlen(c), zf + (int64_t)pair * vlen(f), f, c, i, j, k);
+  int i, j, kb;
+  if (!box_position(bk, f.n, nbx, packed, i, j, kb) || inactive(bt, pair)) return;
+  ec += (int64_t)pair * vlen(c);
+  zf += (int64_t)pair * vlen(f);
+  ProlongIn<T> in[KP];
+#pragma unroll
+  for (int q = 0; q < KP; ++q) prolong_load(ec, zf, f, c, i, j, min(KP * kb + q, f.n - 1), in[q]);
+#pragma unroll
+  for (int q = 0; q < KP; ++q) prolong_store(zf, f, i, j, min(KP * kb + q, f.n - 1), in[q]);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1724,10 +1761,12 @@ hipError_t launch_restrict(const T* rf, T* gc, const Geom& f, const Geom& c, con
 template <typename T>
 hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, const Bat& bt,
                               hipStream_t st) {
+  constexpr int KP = sizeof(T) == 4 ? 4 : 2;   // FP64: 4 planes leave 3 waves per SIMD
   const int packed = (f.n < 64) ? 1 : 0;
   const int nbx = packed ? (f.n * f.n + 63) / 64 : nbx_inner(f.n);
-  const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), (unsigned)f.n) : inner_grid(f, nbx, bt.count);
-  hipLaunchKernelGGL((k_prolong_add<T>), grid, dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c), bt, nbx, packed);
+  const unsigned nkb = (unsigned)((f.n + KP - 1) / KP);
+  const dim3 grid = packed ? dim3((unsigned)(nbx * bt.count), nkb) : dim3((unsigned)(nbx * bt.count), (unsigned)f.n, nkb);
+  hipLaunchKernelGGL((k_prolong_add<T, KP>), grid, dim3(64), 0, st, ec, zf, dgeom(f), dgeom(c), bt, nbx, packed);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def test_apply(n, alpha):
     assert np.all(y[boundary_mask(n, S.P, S.B)] == 0.0)
 
 
-@pytest.mark.parametrize("n", [8, 12, 32])
+@pytest.mark.parametrize("n", [8, 10, 12, 14, 32])
 def test_transfers(n):
     S = _solver(n, 1.0)
     J = S.levels - 1
@@ -70,7 +70,9 @@ def test_transfers(n):
     zf0 = rng.standard_normal(mesh.ndof(nf))
     zf = _dev(to_padded(nf, Pf, Bf, zf0))
     S.level_op(J, "prolong", _dev(to_padded(nc, Pc, Bc, ec)), out=zf)
-    assert _rel(from_padded(nf, Pf, Bf, _host(zf)), zf0 + Pm @ ec) <= 1e-15
+    zh = _host(zf)
+    assert _rel(from_padded(nf, Pf, Bf, zh), zf0 + Pm @ ec) <= 1e-15
+    assert not zh[boundary_mask(nf, Pf, Bf)].any()   # non-unknown entries untouched (zero)
 
 
 @pytest.mark.parametrize("n,alpha,boundary", [(4, 1.0, True), (8, 0.3, True), (8, 3.0, False),
