@@ -484,7 +484,13 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 #pragma unroll
       for (int ks = 0; ks < NKE; ++ks) acc = Mfma<T>::mma(a[ks / VE][ks % VE], bcol[ks], acc);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NVY] = acc[q];
+      for (int q = 0; q < 4; ++q) {
+        // FP64: register q holds rows 16 mb + 4 q .. + 3 in every lane, so a register of
+        // padding rows only (>= NG, never read) is not stored; in FP32 the padding rows
+        // share registers with real ones
+        if (sizeof(T) == 8 && 16 * mb + 4 * q >= NG) continue;
+        yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NVY] = acc[q];
+      }
     }
   };
 
