@@ -749,13 +749,21 @@ static_assert(kOI.n == 18, "18 interface unknowns owned per subdomain");
 // Copy n (<= 64 * R) values from global memory into LDS with one batch of loads per
 // thread (a loop that stores each value before loading the next waits for every load).
 template <typename T, int R>
-__device__ __forceinline__ void stage_lds(T* __restrict__ dst, const T* __restrict__ src, int n) {
-  T v[R];
+__device__ __forceinline__ void stage_load(T (&v)[R], const T* __restrict__ src, int n) {
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = src[min((int)threadIdx.x + 64 * i, n - 1)];
+}
+template <typename T, int R>
+__device__ __forceinline__ void stage_store(T* __restrict__ dst, const T (&v)[R], int n) {
 #pragma unroll
   for (int i = 0; i < R; ++i)
     if ((int)threadIdx.x + 64 * i < n) dst[threadIdx.x + 64 * i] = v[i];
+}
+template <typename T, int R>
+__device__ __forceinline__ void stage_lds(T* __restrict__ dst, const T* __restrict__ src, int n) {
+  T v[R];
+  stage_load(v, src, n);
+  stage_store(dst, v, n);
 }
 
 template <typename T>
@@ -768,10 +776,15 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
   const int pair = bk.x / nbx;
   if (inactive(bt, pair)) return;
   XT += (int64_t)(pair / bt.nrhs) * 6 * NB;
-  stage_lds<T, (6 * NB + 63) / 64>(sX, XT, 6 * NB);
-  __syncthreads();
+  // X_T's loads first, then this thread's residual loads, then X_T into LDS and the
+  // barrier: the residual loads are in flight across the staging (lanes past the box
+  // load subdomain 0's values and return after the barrier)
+  constexpr int RX = (6 * NB + 63) / 64;
+  T xv[RX];
+  stage_load(xv, XT, 6 * NB);
   int a, b, c;
-  if (!box_position(bk, nH, nbx, packed, a, b, c)) return;
+  const bool valid = box_position(bk, nH, nbx, packed, a, b, c);
+  if (!valid) a = b = c = 0;
   const int64_t voff = (int64_t)pair * vlen(g);
   r += voff;
   gg += voff;
@@ -794,6 +807,9 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
 #pragma unroll
   for (int k = 0; k < 18; ++k)
     rO[k] = r[kOI.d[k] * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2])];
+  stage_store(sX, xv, 6 * NB);
+  __syncthreads();
+  if (!valid) return;
 #pragma unroll
   for (int k = 0; k < 18; ++k) {
     const int d = kOI.d[k];
