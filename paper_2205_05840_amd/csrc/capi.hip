@@ -206,6 +206,16 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
         // and no more per wave than spreads a small segment over the 4 waves of one chunk
         const int gseg = (L.segs[si].count + 15) / 16;
         const int gs = std::max(1, std::min(L.segs[si].type == 13 ? L.gpw : gpw_b, (gseg + 3) / 4));
+        // A segment of one group (a short edge of the box) in a class of several
+        // right-hand sides: one workgroup per 4 right-hand sides of a problem, one per
+        // wave (they share S^{-1}), instead of a workgroup per pair with 3 idle waves.
+        if (C.nrhs > 1 && gseg == 1) {
+          L.chunks.push_back((int)si | 1 << 16 | ndmg::kChunkRhsWaves);
+          L.chunks.push_back(0);
+          L.chunks.push_back(0);
+          L.chunks.push_back(16);
+          continue;
+        }
         for (int f = 0; f < L.segs[si].count; f += 64 * gs) {
           L.chunks.push_back((int)si | gs << 16);
           L.chunks.push_back(f);
@@ -222,7 +232,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
         const int nch = (int)(L.chunks.size() / 4);
         int c0 = -1, c1 = -1;
         for (int j = 0; j < nch; ++j)
-          if (L.segs[L.chunks[4 * j] & 0xffff].type == 13) {
+          if (L.segs[L.chunks[4 * j] & 0xffff].type == 13) {   // (no right-hand-side chunks: one pair)
             if (c0 < 0) c0 = j;
             c1 = j + 1;
           }

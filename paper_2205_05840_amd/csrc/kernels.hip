@@ -393,14 +393,22 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   __shared__ int spres[NPAD];   // 1 if this patch type has the slot
   const int lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   const int pair = lb / gridDim.x;
-  if (inactive(bt, pair)) return;
-  const int tid = threadIdx.x;
-  const int64_t NVY = y_row_len(sub.nH);
-  gg += (int64_t)pair * vlen(g);
-  Y += (int64_t)pair * NVY * NPAD;
   const int chunk = lb - pair * gridDim.x;
-  const int seg = sub.chunks[4 * chunk] & 0xffff;
-  const int gpw = sub.chunks[4 * chunk] >> 16;   // 16-vertex groups per wave in this chunk
+  const int cw = sub.chunks[4 * chunk];
+  // a right-hand-side chunk runs in the workgroups of pairs whose index within their
+  // problem is a multiple of 4; wave w then takes pair + w (same problem, same S^{-1})
+  const bool rhsw = (cw & kChunkRhsWaves) != 0;
+  if (rhsw ? (pair % bt.nrhs) % 4 != 0 : inactive(bt, pair)) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const bool wact = __builtin_amdgcn_readfirstlane(
+      !rhsw || ((pair % bt.nrhs) + wave < bt.nrhs && !inactive(bt, pair + wave)));
+  const int wpair = __builtin_amdgcn_readfirstlane(rhsw && wact ? pair + wave : pair);
+  const int64_t NVY = y_row_len(sub.nH);
+  gg += (int64_t)wpair * vlen(g);
+  Y += (int64_t)wpair * NVY * NPAD;
+  const int seg = cw & 0xffff;
+  const int gpw = (cw >> 16) & 0x3fff;   // 16-vertex groups per wave in this chunk
   const int first = sub.chunks[4 * chunk + 1];
   const int wstep = sub.chunks[4 * chunk + 2];   // wave w's first group at first + w wstep
   const int cstep = sub.chunks[4 * chunk + 3];   // its group c at that + c cstep
@@ -436,7 +444,6 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 #pragma unroll
   for (int l = 0; l < NL; ++l) sv[l] = reinterpret_cast<const vec_t*>(Sm)[l * 256 + tid];
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int wfirst = first + wave * wstep;
   int rl[NKE];
@@ -496,7 +503,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 
   int ngroups = 0;
   for (int c = 0; c < gpw; ++c)
-    if (wfirst + cstep * c < count) ngroups = c + 1;
+    if (wact && wfirst + cstep * c < count) ngroups = c + 1;
   T b0[NKS], b1[NKS];
   int64_t y0a, y0b;
   int yoa, yob;
@@ -524,7 +531,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   if (c < ngroups) product_store(b0, y0a, yoa);
   // the zero run that vertices without a patch read (row `lane`): the buffer is shared
   // with the small-level kernel's layout
-  if (chunk == 0 && wave == 0) {
+  if (chunk == 0 && (rhsw || wave == 0)) {   // (a right-hand-side wave: its own pair)
 #pragma unroll
     for (int row = lane; row < NPAD; row += 64) {
       T* yz = Y + (int64_t)row * NVY + y_zero_run(sub.nH);

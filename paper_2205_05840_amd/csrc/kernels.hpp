@@ -45,9 +45,9 @@ struct DSub {
   const int* slots;     // [nG][4]: d, dx, dy, dz
   const int* segs;      // [nseg][8]: type, lo0, lo1, lo2, d0, d1, row position of the
                         // segment's first vertex in Y (y_pos), count
-  const int* chunks;    // [nchunks][4]: segment | groups per wave << 16, first vertex of
-                        // wave 0, vertex step between waves, vertex step between a wave's
-                        // groups (all multiples of 16)
+  const int* chunks;    // [nchunks][4]: segment | groups per wave << 16 (| kChunkRhsWaves),
+                        // first vertex of wave 0, vertex step between waves, vertex step
+                        // between a wave's groups (all multiples of 16)
   int nchunks;
   const int64_t* bofs;  // nB offsets of the subdomain boundary edges from its lower node
 };
@@ -91,6 +91,11 @@ __host__ __device__ inline int y_pos(int nH, int bpatch, int x, int y, int z) {
   const int pos = base + local;
   return pos + none * (r3 + 6 * r2 + 12 * r1 - pos);
 }
+
+// Patch chunk flag: the workgroup of pair p takes right-hand sides p .. p + 3 of p's
+// problem, one per wave, when p's right-hand-side index is a multiple of 4 (else it
+// does nothing); its segment has one group of 16 vertices.
+constexpr int kChunkRhsWaves = 1 << 30;
 
 // True when the kernels' compile-time table of the patches holding each subdomain
 // boundary edge equals the host's boundary_patch_table().
