@@ -136,6 +136,34 @@ def test_batched_pcg_solution_to_tight_tolerance():
             assert _rel(u[p][r], ue[r]) <= 1e-9, (p, r)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_six_rhs_with_idle_pairs(precision):
+    """Six right-hand sides per problem: the patch products of one-group segments run
+    four right-hand sides of a problem per workgroup, so the second workgroup of each
+    problem holds two.  Zero right-hand sides are done at once and idle from the first
+    iteration: one that leads a workgroup (r = 0) and one in the second (r = 5)."""
+    ns, alphas, nrhs = [16, 12, 16], [0.5, 20.0, 0.02], 6
+    BS = _batch(ns, alphas, nrhs, precision)
+    b = _loads(ns, nrhs, 70)
+    b[1][0] = 0.0
+    b[2][5] = 0.0
+    U, it, rel = BS.solve(_pack(BS, b), rtol=1e-10)
+    u = _unpack(BS, U)
+    for p, n in enumerate(ns):
+        h = 1.0 / n
+        A = assemble.matrix_kron(n, h, alphas[p])
+        ev = exact.eigenvalues(n, h, alphas[p])
+        ue = exact.solve_fft(n, h, alphas[p], b[p])
+        for r in range(nrhs):
+            if (p, r) in ((1, 0), (2, 5)):
+                assert it[p, r] == 0 and not u[p][r].any(), (p, r)
+                continue
+            bn = np.linalg.norm(b[p][r])
+            assert rel[p, r] <= 1e-10, (p, r)
+            assert _true_residual_ok(A, b[p][r], u[p][r], 1e-10), (p, r)
+            assert np.linalg.norm(u[p][r] - ue[r]) <= 2e-10 * bn / ev.min(), (p, r)
+
+
 def test_batched_mixed_precision_uneven():
     """Sizes from {8, 12, 16, 24, 32}, alpha log-uniform in [1e-2, 1e2], four N(0, 1)
     right-hand sides each, FP32 V-cycle in FP64 CG."""
