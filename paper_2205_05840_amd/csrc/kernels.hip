@@ -388,6 +388,17 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
   constexpr int NKVE = (NKE + VE - 1) / VE;        // of which hold a slot
   static_assert(NPAD * NPAD % (VE * 256) == 0, "S^{-1} staging shape");
   typedef T vec_t __attribute__((ext_vector_type(VE)));
+  // FP32 with 60 slots: S^{-1} row i of the last row block goes to the A operand's row
+  // perm_row(i) (an involution swapping 51, 55, 59 with 60, 61, 62), so that the result
+  // register 3 of that block holds the 4 padding rows in every lane
+  constexpr bool kPerm = sizeof(T) == 4 && NG == 60 && NPAD == 64;
+  auto perm_row = [](int i) {
+    if (!kPerm || i < 48) return i;
+    const int lk = (i - 48) >> 2, q = (i - 48) & 3;
+    if (q == 3 && lk < 3) return 60 + lk;
+    if (lk == 3 && q < 3) return 51 + 4 * q;
+    return i;
+  };
   __shared__ vec_t sA[NMB * NKV * 64];
   __shared__ int srel[NPAD];    // node offset of the slot's edge from the vertex's node
   __shared__ int spres[NPAD];   // 1 if this patch type has the slot
@@ -492,11 +503,15 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
       for (int ks = 0; ks < NKE; ++ks) acc = Mfma<T>::mma(a[ks / VE][ks % VE], bcol[ks], acc);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        // FP64: register q holds rows 16 mb + 4 q .. + 3 in every lane, so a register of
-        // padding rows only (>= NG, never read) is not stored; in FP32 the padding rows
-        // share registers with real ones
+        // padding rows (>= NG) are never read, so a register that holds only such rows
+        // is not stored.  FP64: register q holds rows 16 mb + 4 q .. + 3 in every lane.
+        // FP32 (row 4 lk + q): the last block's rows are permuted (kPerm) so that its
+        // register 3 holds the padding rows, and lanes lk = 3 store slots 51 + 4 q
         if (sizeof(T) == 8 && 16 * mb + 4 * q >= NG) continue;
-        yl[(int64_t)(16 * mb + Mfma<T>::row(lk, q)) * NVY] = acc[q];
+        if (kPerm && mb == NMB - 1 && q == 3) continue;
+        int row = 16 * mb + Mfma<T>::row(lk, q);
+        if (kPerm && mb == NMB - 1 && lk == 3) row = 16 * mb + 3 + 4 * q;
+        yl[(int64_t)row * NVY] = acc[q];
       }
     }
   };
@@ -513,7 +528,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 1 : 3) k_sm_patch(const 
 #pragma unroll
     for (int u = 0; u < VE; ++u) {
       const int e = (l * 256 + tid) * VE + u;
-      const int r = e / NPAD, col = e % NPAD;
+      const int r = perm_row(e / NPAD), col = e % NPAD;
       const int ks = col / 4, ln = (col % 4) * 16 + r % 16;
       sA[((r / 16) * NKV + ks / VE) * 64 + ln][ks % VE] = sv[l][u];
     }
