@@ -309,6 +309,9 @@ def main():
                     help="only run the calibration copy and the apply kernel (counter runs)")
     ap.add_argument("--solve-probe", choices=["fp32", "fp64"],
                     help="only run one warm-up and one timed 128^3 solve in this precision (counter runs)")
+    ap.add_argument("--batched-probe", choices=["fp32", "fp64"],
+                    help="only run one warm-up and one timed solve of the batched form in this "
+                         "precision (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -330,6 +333,23 @@ def main():
         _, _, _, res = run_leg(torch, Solver, f, 1.0, args.solve_probe, 1, 1)
         print(json.dumps({"probe": "solve", "precision": args.solve_probe, "n": N_ELEM,
                           "s_per_solve": res["s_per_solve_total"], "iters": res["iters"]}), flush=True)
+        return
+    if args.batched_probe:
+        from paper_2205_05840_amd import BatchedSolver
+        ns, alphas = synth.batched_problems(BATCH_NPROB, seed=BATCH_SEED)
+        BS = BatchedSolver(ns, alphas, nrhs=BATCH_NRHS, precision=args.batched_probe)
+        g = torch.Generator(device=BS.device)
+        g.manual_seed(BATCH_SEED)
+        B = BS.assemble_rhs(torch.randn(BS.sample_len(), generator=g, dtype=torch.float64, device=BS.device))
+        U = BS.zeros()
+        BS.solve(B, rtol=RTOL, U=U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, _ = BS.solve(B, rtol=RTOL, U=U)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "batched", "precision": args.batched_probe, "nprob": BATCH_NPROB,
+                          "nrhs": BATCH_NRHS, "s_per_batch": time.perf_counter() - t0,
+                          "iters_max": int(it.max())}), flush=True)
         return
     f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
     ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
