@@ -1212,45 +1212,73 @@ int ndmg_export_factor(const ndmg_ctx* c, int level, int which, int type, double
   return NDMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One step on one level in the V-cycle's precision T.  in and out are the operation's
+// input and output in T (for FP32 contexts: the level buffers holding the converted
+// vectors).
+template <typename T>
+int level_op_t(ndmg_ctx* c, Cls& C, int level, int op, const T* in, T* out, const ndmg::Bat& bt) {
+  LevelHost& L = C.lv[level];
+  switch (op) {
+    case NDMG_OP_APPLY:
+      NDMG_HIP(ndmg::launch_apply<T>(in, nullptr, out, L.g, bt, 0, c->st));
+      return NDMG_OK;
+    case NDMG_OP_SMOOTH: {
+      auto P = level_ptrs<T>(c, L);
+      auto D = level_dsub(c, L);
+      NDMG_HIP(ndmg::launch_smooth<T>(in, out, P, D, L.g, bt, c->plan.opts.eta, 1, c->st));
+      return NDMG_OK;
+    }
+    case NDMG_OP_RESTRICT:
+      NDMG_HIP(ndmg::launch_restrict<T>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
+      return NDMG_OK;
+    case NDMG_OP_PROLONG:
+      NDMG_HIP(ndmg::launch_prolong_add<T>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
+      return NDMG_OK;
+    default:   // NDMG_OP_COARSE
+      NDMG_HIP(ndmg::launch_coarse<T>(in, out, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map), (int)L.map.size(),
+                                      L.g.len, bt, c->st));
+      return NDMG_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
 int ndmg_level_op(ndmg_ctx* c, int level, int op, const double* in, double* out) {
   if (int rc = check_ctx(c)) return rc;
   if (int rc = one_class(c)) return rc;
   if (!in || !out) return fail(NDMG_EINVAL, "null vector");
   Plan& pl = c->plan;
-  if (pl.elem != 8) return fail(NDMG_EINVAL, "level operations need an FP64 context");
   Cls& C = pl.cls[0];
   const int nl = (int)C.lv.size();
   if (level < 0) level += nl;
   if (level < 0 || level >= nl) return fail(NDMG_EINVAL, "level out of range");
-  LevelHost& L = C.lv[level];
+  if (op < NDMG_OP_APPLY || op > NDMG_OP_COARSE) return fail(NDMG_EINVAL, "unknown operation");
+  if (op == NDMG_OP_SMOOTH && !C.lv[level].smoothed) return fail(NDMG_EINVAL, "the coarsest level has no smoother");
+  if ((op == NDMG_OP_RESTRICT || op == NDMG_OP_PROLONG) && level < 1)
+    return fail(NDMG_EINVAL, "transfers need level >= 1");
+  if (op == NDMG_OP_COARSE && level != 0) return fail(NDMG_EINVAL, "coarse solve needs level 0");
   const ndmg::Bat bt = class_batch(c, C, false);
-  switch (op) {
-    case NDMG_OP_APPLY:
-      NDMG_HIP(ndmg::launch_apply<double>(in, nullptr, out, L.g, bt, 0, c->st));
-      return NDMG_OK;
-    case NDMG_OP_SMOOTH: {
-      if (!L.smoothed) return fail(NDMG_EINVAL, "the coarsest level has no smoother");
-      auto P = level_ptrs<double>(c, L);
-      auto D = level_dsub(c, L);
-      NDMG_HIP(ndmg::launch_smooth<double>(in, out, P, D, L.g, bt, pl.opts.eta, 1, c->st));
-      return NDMG_OK;
-    }
-    case NDMG_OP_RESTRICT:
-      if (level < 1) return fail(NDMG_EINVAL, "restriction needs level >= 1");
-      NDMG_HIP(ndmg::launch_restrict<double>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
-      return NDMG_OK;
-    case NDMG_OP_PROLONG:
-      if (level < 1) return fail(NDMG_EINVAL, "prolongation needs level >= 1");
-      NDMG_HIP(ndmg::launch_prolong_add<double>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
-      return NDMG_OK;
-    case NDMG_OP_COARSE:
-      if (level != 0) return fail(NDMG_EINVAL, "coarse solve needs level 0");
-      NDMG_HIP(ndmg::launch_coarse<double>(in, out, at<double>(c, L.o_A0), at<int64_t>(c, L.o_map),
-                                           (int)L.map.size(), L.g.len, bt, c->st));
-      return NDMG_OK;
-    default:
-      return fail(NDMG_EINVAL, "unknown operation");
-  }
+  if (pl.elem == 8) return level_op_t<double>(c, C, level, op, in, out, bt);
+  // FP32 context: the FP64 input is rounded into a level buffer of the input's level,
+  // the step runs in FP32 into a buffer of the output's level (holding the rounded old
+  // output for the accumulating prolongation), and the result is widened into out.
+  const int lin = op == NDMG_OP_PROLONG ? level - 1 : level;
+  const int lout = op == NDMG_OP_RESTRICT ? level - 1 : level;
+  LevelHost& Li = C.lv[lin];
+  LevelHost& Lo = C.lv[lout];
+  float* fin = at<float>(c, Li.o_g);
+  float* fout = at<float>(c, Lo.o_z);
+  NDMG_HIP((ndmg::launch_convert<double, float>(in, fin, Li.g.len, bt, c->st)));
+  if (op == NDMG_OP_PROLONG) NDMG_HIP((ndmg::launch_convert<double, float>(out, fout, Lo.g.len, bt, c->st)));
+  NDMG_TRY(level_op_t<float>(c, C, level, op, fin, fout, bt));
+  NDMG_HIP((ndmg::launch_convert<float, double>(fout, out, Lo.g.len, bt, c->st)));
+  return NDMG_OK;
 }
 
 int ndmg_destroy(ndmg_ctx* c) {

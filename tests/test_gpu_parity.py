@@ -1,13 +1,17 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
 
 Tolerances (FP64, relative l2): apply 1e-14, transfers 1e-15.  The smoother and the
-V-cycle go through inverted local matrices (A_T, and Schur complements S_V with
-condition numbers up to ~1e5 at large alpha h^-2), so two correct FP64 evaluations
-already differ by rounding amplified by that conditioning.  Their tolerance is
-max(1e-13 resp. 1e-12, 20 * sens), where sens is the difference between the oracle
-evaluated with its factors from two FP64 routes (LU and Cholesky).  PCG: relative
-residual <= 1e-10 with the oracle's iteration count +-1; solution error within the
-residual bound ||e|| <= ||r|| / lambda_min(A).
+V-cycle go through inverted local matrices (A_T, and Schur complements S_V whose
+condition grows like alpha h^-2), so any two correct FP64 evaluations already differ by
+the rounding of those inverses, of relative size u kappa.  The scale of that rounding
+is measured per case as the spread between the oracle evaluated with its factors from
+two FP64 routes (LU and Cholesky).  The library's factors come from a third route (host
+Cholesky with its own Schur complement sums), so its error is a third sample of the
+same rounding: over the 29 smoother and V-cycle cases here it lies between 0.47 and
+3.5 times the spread (deterministic: no atomics on either side).  The tolerance is
+max(1e-13 resp. 1e-12, 5 * spread): 1.4 to 10.6 times every observed error.  PCG:
+relative residual <= 1e-10 with the oracle's iteration count +-1; solution error
+within the residual bound ||e|| <= ||r|| / lambda_min(A).
 """
 import numpy as np
 import pytest
@@ -17,6 +21,8 @@ from oracle import assemble, exact, mesh, pcg, rhs, smoother, transfer, vcycle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+C64 = 5.0   # tolerance / spread of the oracle's two FP64 routes (see above)
 
 
 def _solver(n, alpha=1.0, **kw):
@@ -76,7 +82,8 @@ def test_transfers(n):
 
 
 @pytest.mark.parametrize("n,alpha,boundary", [(4, 1.0, True), (8, 0.3, True), (8, 3.0, False),
-                                              (12, 10.0, True), (16, 0.01, True)])
+                                              (10, 1.0, True), (10, 2.0, False), (12, 10.0, True),
+                                              (14, 0.5, True), (14, 5.0, False), (16, 0.01, True)])
 def test_smoother(n, alpha, boundary):
     S = _solver(n, alpha, boundary_patches=boundary)
     h = 1.0 / n
@@ -85,9 +92,10 @@ def test_smoother(n, alpha, boundary):
     z = _host(S.level_op(S.levels - 1, "smooth", _dev(to_padded(n, S.P, S.B, r))))
     ref = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary)(r)
     alt = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary, inverse="cholesky")(r)
-    tol = max(1e-13, 20 * _rel(alt, ref))
-    print(f"smoother rounding sensitivity {_rel(alt, ref):.2e}, tolerance {tol:.2e}")
-    assert _rel(from_padded(n, S.P, S.B, z), ref) <= tol
+    tol = max(1e-13, C64 * _rel(alt, ref))
+    err = _rel(from_padded(n, S.P, S.B, z), ref)
+    print(f"smoother fp64: err {err:.2e}, spread {_rel(alt, ref):.2e}, ratio {err / max(_rel(alt, ref), 1e-300):.2f}")
+    assert err <= tol
     if n <= 8:
         ref2 = smoother.LiteralSmoother(A, n, 2, boundary=boundary)(r)
         assert _rel(from_padded(n, S.P, S.B, z), ref2) <= tol
@@ -108,7 +116,7 @@ def test_smoother_after_small_level_kernel(boundary):
     z = _host(S.level_op(S.levels - 1, "smooth", _dev(to_padded(n, S.P, S.B, r))))
     ref = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary)(r)
     alt = smoother.FactoredVertexSmoother(A, n, 2, boundary=boundary, inverse="cholesky")(r)
-    assert _rel(from_padded(n, S.P, S.B, z), ref) <= max(1e-13, 20 * _rel(alt, ref))
+    assert _rel(from_padded(n, S.P, S.B, z), ref) <= max(1e-13, C64 * _rel(alt, ref))
 
 
 def test_exported_factors_match_patch_matrices():
@@ -178,9 +186,11 @@ def _check_vcycle(n, alpha, m, boundary, bottom, dense=None):
     g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
     z = _host(S.vcycle(_dev(to_padded(n, S.P, S.B, g))))
     ref = H.precondition(g)
-    tol = max(1e-12, 20 * _rel(H2.precondition(g), ref))
-    print(f"V-cycle tolerance {tol:.2e}")
-    assert _rel(from_padded(n, S.P, S.B, z), ref) <= tol
+    spread = _rel(H2.precondition(g), ref)
+    tol = max(1e-12, C64 * spread)
+    err = _rel(from_padded(n, S.P, S.B, z), ref)
+    print(f"V-cycle fp64: err {err:.2e}, spread {spread:.2e}, ratio {err / max(spread, 1e-300):.2f}")
+    assert err <= tol
 
 
 @pytest.mark.parametrize("n,alpha", [(8, 1.0), (16, 0.01), (16, 100.0), (24, 1.0), (32, 1.0)])
@@ -273,7 +283,7 @@ def test_mixed_precision_pcg():
     b = S64.assemble_rhs(torch.from_numpy(f))
     u64, it64, rel64 = S64.solve(b)
     u32, it32, rel32 = S32.solve(b)
-    assert rel32 <= 1e-10 and it32 <= it64 + 3
+    assert rel32 <= 1e-10 and abs(it32 - it64) <= 1
     b_o = rhs.load_from_samples(n, h, f)
     A = assemble.matrix_kron(n, h, alpha)
     u_c = from_padded(n, S32.P, S32.B, _host(u32))
@@ -283,15 +293,11 @@ def test_mixed_precision_pcg():
     # the V-cycle itself agrees with the FP64 oracle to single precision
     g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
     z = _host(S32.vcycle(_dev(to_padded(n, S32.P, S32.B, g))))
-    H = vcycle.Hierarchy(n, alpha)
-    ref = H.precondition(g)
-    # the FP32 path rounds the FP64 factors to single precision: a relative perturbation
-    # of 2^-24 amplified by the conditioning of the vertex Schur complement
-    kappa = np.linalg.cond(H.M[-1].schur(13))
-    tol = 2.0 ** -24 * kappa
+    ref = vcycle.Hierarchy(n, alpha).precondition(g)
+    # a few roundings of relative size 2^-24 per entry (see test_gpu_precision.py)
     err32 = _rel(from_padded(n, S32.P, S32.B, z), ref)
-    print(f"FP32 V-cycle vs FP64 oracle: {err32:.2e} (tolerance {tol:.2e})")
-    assert err32 <= tol
+    print(f"FP32 V-cycle vs FP64 oracle: {err32:.2e}")
+    assert err32 <= 16 * 2.0 ** -24
 
 
 def test_graph_replays_match_eager():

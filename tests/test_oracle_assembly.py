@@ -150,3 +150,84 @@ def test_apply_rows_equals_assembled(n, alpha):
     y = assemble.apply_rows(n, h, alpha, x, rows)
     ref = (assemble.matrix_kron(n, h, alpha) @ x)[rows]
     assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_interpolate_gradient_commutes(n):
+    """Canonical interpolation (edge averages, eq. NDdof) of a gradient equals the
+    discrete gradient of the nodal values: the average of d phi / dx_d along an edge is
+    (phi(end) - phi(start)) / h, the commuting property of the de Rham sequence."""
+    L = 1.3
+    h = L / n
+    p = np.pi / L
+    phi = lambda x, y, z: np.sin(p * x) * np.sin(2 * p * y) * np.sin(p * z) * (1 + x * y)
+    grad = lambda x, y, z: (
+        np.sin(2 * p * y) * np.sin(p * z) * (p * np.cos(p * x) * (1 + x * y) + np.sin(p * x) * y),
+        np.sin(p * x) * np.sin(p * z) * (2 * p * np.cos(2 * p * y) * (1 + x * y) + np.sin(2 * p * y) * x),
+        np.sin(p * x) * np.sin(2 * p * y) * p * np.cos(p * z) * (1 + x * y))
+    ii = np.arange(1, n) * h
+    z2, y2, x2 = np.meshgrid(ii, ii, ii, indexing="ij")
+    nodal = phi(x2, y2, z2).ravel()                     # [z][y][x] over interior nodes
+    got = rhs.interpolate(n, L, grad, q=10)
+    ref = assemble.gradient(n, h) @ nodal
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_interpolate_polynomial_edge_average():
+    """Edge averages of a field polynomial along each edge, against the closed form
+    (1/h) int_{ih}^{(i+1)h} t^3 dt = h^3 ((i+1)^4 - i^4) / 4 times the transverse factors."""
+    n, L = 4, 2.0
+    h = L / n
+    f = lambda x, y, z: (x ** 3 * y, z * y ** 3, 2.0 + 0 * x)
+    got = rhs.interpolate(n, L, f, q=4)
+    d, pp = mesh.edge_coords(n)
+    c = pp.astype(float)
+    avg3 = lambda i: h ** 3 * ((i + 1) ** 4 - i ** 4) / 4.0
+    ref = np.where(d == 0, avg3(c[:, 0]) * c[:, 1] * h,
+                   np.where(d == 1, c[:, 2] * h * avg3(c[:, 1]), 2.0))
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,alpha", [(3, 1.0), (6, 0.05), (9, 40.0)])
+def test_apply_fft_equals_assembled(n, alpha):
+    """A x through the 3x3 symbols of the orthonormal DST/DCT transforms equals the
+    assembled matrix (the matrix-free reference for sizes too large to assemble)."""
+    h = 1.0 / n
+    X = np.random.default_rng(n).standard_normal((2, mesh.ndof(n)))
+    ref = (assemble.matrix_kron(n, h, alpha) @ X.T).T
+    got = exact.apply_fft(n, h, alpha, X)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,alpha", [(4, 1.0), (6, 30.0)])
+def test_fft_extended_precision(n, alpha):
+    """The extended-precision transform solve: its residual with the extended symbol
+    product is at the level of the extended unit roundoff (2^-64, far below FP64's),
+    the FP64-assembled matrix sees an FP64-level residual (its entries are rounded to
+    FP64), and it agrees with the FP64 solve within kappa * eps."""
+    h = 1.0 / n
+    b = np.random.default_rng(n).standard_normal(mesh.ndof(n))
+    ul = exact.solve_fft(n, h, alpha, b, dtype=np.longdouble)
+    assert ul.dtype == np.longdouble
+    A = assemble.matrix_kron(n, h, alpha).toarray()
+    scale = (np.abs(A) @ np.abs(ul.astype(np.float64))).max()
+    rl = exact.apply_fft(n, h, alpha, ul, dtype=np.longdouble) - b
+    assert np.abs(rl).max() <= 1e-17 * scale
+    res = np.abs(A.astype(np.longdouble) @ ul - b).max()
+    assert res <= 1e-15 * scale
+    ev = exact.eigenvalues(n, h, alpha)
+    u64 = exact.solve_fft(n, h, alpha, b)
+    assert np.linalg.norm(u64 - ul.astype(np.float64)) <= 10 * ev.max() / ev.min() * 2.2e-16 * np.linalg.norm(u64)
+
+
+def test_adjoint_extended_matches_fp64_small():
+    """At 8^3 (no strong cancellation) the extended-precision adjoint reference equals
+    the FP64 one to 1e-9 in dL/db and 1e-12 in the loss and dL/dalpha."""
+    from oracle import adjoint
+    n, h = 8, 1.0 / 8
+    B = np.random.default_rng(3).standard_normal((2, mesh.ndof(n)))
+    T = exact.solve_fft(n, h, 2.0, B)
+    l1, d1, a1 = adjoint.loss_and_grads(n, 1.0, 1.0, B, T)
+    l2, d2, a2 = adjoint.loss_and_grads(n, 1.0, 1.0, B, T, dtype=np.longdouble)
+    assert abs(l1 - l2) <= 1e-12 * l2 and abs(a1 - a2) <= 1e-12 * abs(a2)
+    assert np.linalg.norm(d1 - d2) <= 1e-9 * np.linalg.norm(d2)

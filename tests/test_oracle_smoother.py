@@ -150,3 +150,101 @@ def test_vectorized_sets_equal_per_item_sets(n, s):
         G = mesh.vertex_interface_sets(n, s, verts)
         G2 = np.stack([mesh.vertex_interface_set(n, s, v) for v in verts])
         assert np.array_equal(G, G2)
+
+
+def _edge_geometry(n):
+    """Compact indices with the doubled coordinates of each unknown's midpoint (2 p, with
+    the cell axis at 2 p + 1), so that every geometric test below is on integers."""
+    d, p = mesh.edge_coords(n)
+    mid = 2 * p.astype(np.int64)
+    mid[np.arange(d.size), d] += 1
+    return d, mid
+
+
+def _in_open_face(mid, d, normal, plane, box):
+    """Edges (doubled midpoints) lying in the open interior of the axis-parallel square
+    {x_normal = plane} x box[a] x box[b] (box in doubled coordinates, closed intervals):
+    the edge is parallel to the face, its midpoint in the open square, and it does not
+    lie on the square's boundary lines."""
+    ok = (d != normal) & (mid[:, normal] == plane)
+    for ax in range(3):
+        if ax == normal:
+            continue
+        lo, hi = box[ax]
+        ok &= (mid[:, ax] > lo) & (mid[:, ax] < hi)
+    return ok
+
+
+@pytest.mark.parametrize("s,n", [(2, 6), (2, 8), (4, 12)])
+@pytest.mark.parametrize("boundary", [True, False])
+def test_edge_sets_brute_force(s, n, boundary):
+    """Each edge interface set (eq. edge space) equals, by brute force over all unknowns,
+    the fine edges lying on the closed coarse edge E or in the open interior of one of
+    the (up to) 4 coarse faces containing E; and every face-interior unknown lies in as
+    many sets as its face has coarse edges carrying a space (4 with boundary edges, the
+    interior coarse edges of its face otherwise), every coarse-edge unknown in exactly 1."""
+    d, mid = _edge_geometry(n)
+    m = n // s
+    cover = np.zeros(mesh.ndof(n), int)
+    for axis, c in mesh.coarse_edges(n, s, boundary):
+        got = np.asarray(mesh.edge_interface_set(n, s, axis, c))
+        cover[got] += 1
+        C = 2 * np.asarray(c)
+        ea, eb = [ax for ax in range(3) if ax != axis]
+        on_e = (d == axis) & (mid[:, ea] == C[ea]) & (mid[:, eb] == C[eb]) & \
+            (mid[:, axis] > C[axis]) & (mid[:, axis] < C[axis] + 2 * s)
+        sel = on_e.copy()
+        for t, other in ((ea, eb), (eb, ea)):
+            for sign in (-1, 1):
+                box = {axis: (C[axis], C[axis] + 2 * s),
+                       t: tuple(sorted((C[t], C[t] + sign * 2 * s)))}
+                sel |= _in_open_face(mid, d, other, C[other], box)
+        np.testing.assert_array_equal(got, np.flatnonzero(sel))
+    trans = np.stack([mid[np.arange(d.size), (d + 1) % 3], mid[np.arange(d.size), (d + 2) % 3]], 1)
+    on = (trans % (2 * s) == 0).sum(1)
+    assert np.all(cover[on == 0] == 0) and np.all(cover[on == 2] == 1)
+    face = np.flatnonzero(on == 1)
+    if boundary:
+        assert np.all(cover[face] == 4)
+    else:
+        # the face of a face-interior unknown: normal axis = the transverse axis at a
+        # coarse node; its 4 coarse edges are interior unless they lie on the box boundary
+        for e in face:
+            dd = d[e]
+            a1, a2 = (dd + 1) % 3, (dd + 2) % 3
+            normal, t = (a1, a2) if trans[e, 0] % (2 * s) == 0 else (a2, a1)
+            f0 = mid[e, dd] // (2 * s) * (2 * s)
+            g0 = mid[e, t] // (2 * s) * (2 * s)
+            interior = lambda x: 0 < x < 2 * n
+            pl = mid[e, normal]
+            want = 0
+            for along, fixed, pos in ((dd, t, g0), (dd, t, g0 + 2 * s), (t, dd, f0), (t, dd, f0 + 2 * s)):
+                want += interior(pl) and interior(pos)
+            assert cover[e] == want, (e, cover[e], want)
+
+
+@pytest.mark.parametrize("s,n", [(2, 6), (4, 12)])
+@pytest.mark.parametrize("boundary", [True, False])
+def test_vertex_sets_brute_force(s, n, boundary):
+    """Each vertex interface set (eq. vertex space) equals, by brute force, the fine edges
+    on the 6 closed coarse edges through V or in the open interiors of the 12 coarse faces
+    containing V (cut to the unknowns)."""
+    d, mid = _edge_geometry(n)
+    for v in mesh.coarse_vertices(n, s, boundary):
+        V = 2 * s * np.asarray(v)
+        sel = np.zeros(d.size, bool)
+        for axis in range(3):
+            ea, eb = [ax for ax in range(3) if ax != axis]
+            sel |= (d == axis) & (mid[:, ea] == V[ea]) & (mid[:, eb] == V[eb]) & \
+                (np.abs(mid[:, axis] - V[axis]) < 2 * s)
+            for normal in range(3):
+                if normal == axis:
+                    continue
+                t = 3 - axis - normal
+                for sa in (-1, 1):
+                    for sb in (-1, 1):
+                        box = {axis: tuple(sorted((V[axis], V[axis] + sa * 2 * s))),
+                               t: tuple(sorted((V[t], V[t] + sb * 2 * s)))}
+                        sel |= _in_open_face(mid, d, normal, V[normal], box)
+        np.testing.assert_array_equal(np.asarray(mesh.vertex_interface_set(n, s, v)),
+                                      np.flatnonzero(sel))
