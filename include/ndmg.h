@@ -8,7 +8,8 @@
  * C ABI.  Every pointer argument named d_* is a device (HIP, gfx950) pointer owned by
  * the caller; every other pointer is a host pointer owned by the caller.  The library
  * allocates no device memory: the caller passes a device workspace of the size
- * ndmg_plan (or ndmg_plan_batched) reports.  A context owns host metadata, a few pinned
+ * ndmg_plan (or ndmg_plan_batched) reports (the one fixed array of the library's image,
+ * used by ndmg_curlcurl_form_noalloc, is the exception).  A context owns host metadata, a few pinned
  * host words for the convergence test and, when it holds several problem sizes, one
  * side stream and event per extra size.  All device work is enqueued on the stream
  * given at setup (work of extra sizes forks from it and joins back before a call
@@ -198,6 +199,22 @@ int ndmg_assemble_rhs(ndmg_ctx* ctx, const double* d_f, double* d_b);
  * Errors: NDMG_EINVAL, NDMG_EHIP. */
 int ndmg_curlcurl_form(ndmg_ctx* ctx, const double* d_lam, const double* d_u, int nrhs,
                        double* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the curl-curl form of
+ * ndmg_curlcurl_form without a context or workspace, for vectors of the padded layout
+ * of an n^3 mesh of the cube (0, length)^3.  out (host) = sum_r lam_r^T K u_r over nrhs
+ * vector pairs stored back to back.  Its partial sums live in a fixed 4 MiB device array
+ * inside the library (one copy per GPU, kept until the process ends); meshes whose
+ * (ceil((n+1)/64) (n+1)^2 partial sums plus a 256-byte result slot) exceed it are
+ * rejected with NDMG_EINVAL before any device work (n <= 319).  The call allocates
+ * nothing: no hipMalloc, no hipFree, no pinned host memory.  The work is enqueued on
+ * `stream` (NULL = default stream) and the call waits for it once per right-hand side.
+ * Calls that overlap on one GPU (several host threads, or a call on another stream
+ * while one is running) share that array and race; callers serialise them.
+ * Errors: NDMG_EINVAL, NDMG_EHIP. */
+int ndmg_curlcurl_form_noalloc(int n, double length, const double* d_lam, const double* d_u, int nrhs,
+                               double* out, void* stream);
 
 /* Debug export of the FP64 local factors of a level (level as in ndmg_layout, >= 1) of
  * the first problem of a context with a single problem size (rebuilt on the host):

@@ -22,6 +22,7 @@ EXPORTED = [
     "ndmg_vcycle", "ndmg_pcg_solve", "ndmg_assemble_rhs", "ndmg_curlcurl_form",
     "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
     "ndmg_plan_batched", "ndmg_setup_batched", "ndmg_batch_layout", "ndmg_pcg_solve_batched",
+    "ndmg_curlcurl_form_noalloc",
 ]
 
 NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE = range(5)
@@ -72,6 +73,7 @@ def lib():
     L.ndmg_pcg_solve.argtypes = [vp, vp, vp, d, i, P(i), P(d)]
     L.ndmg_assemble_rhs.argtypes = [vp, vp, vp]
     L.ndmg_curlcurl_form.argtypes = [vp, vp, vp, i, P(d)]
+    L.ndmg_curlcurl_form_noalloc.argtypes = [i, d, vp, vp, i, P(d), vp]
     L.ndmg_export_factor.argtypes = [vp, i, i, i, P(d), P(i)]
     L.ndmg_level_op.argtypes = [vp, i, i, vp, vp]
     L.ndmg_plan_batched.argtypes = [i, P(i), d, i, P(ndmg_opts), P(sz), P(sz)]

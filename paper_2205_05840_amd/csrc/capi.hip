@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1180,6 +1181,75 @@ int ndmg_curlcurl_form(ndmg_ctx* c, const double* lam, const double* u, int nrhs
     NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, kScalStride * sizeof(double), hipMemcpyDeviceToHost, c->st));
     NDMG_HIP(hipStreamSynchronize(c->st));
     total += c->host_scal[kS_CC];
+  }
+  *out = total;
+  return NDMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of the allocation-free curl-curl form: 256 bytes for its result slot, then
+// one partial sum per block of the form kernel.  Each GPU the library runs on holds its
+// own copy until the process ends; every call on a GPU reuses that GPU's copy.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr size_t kNoAllocResultBytes = 256;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device, looked up once per device with that
+// device current (host code never passes the array's own name to a kernel: on the host
+// it stands in for the device copy and is not a device address).
+int scratch_on_current_device(void** out) {
+  int dev = -1;
+  NDMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NDMG_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    NDMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(NDMG_EHIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return NDMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ndmg_curlcurl_form_noalloc(int n, double length, const double* lam, const double* u, int nrhs,
+                               double* out, void* stream) {
+  if (n < 2 || n > 2048) return fail(NDMG_EINVAL, "n must be in [2, 2048]");
+  if (!(length > 0.0) || !std::isfinite(length)) return fail(NDMG_EINVAL, "length must be > 0");
+  if (!lam || !u || !out || nrhs < 0) return fail(NDMG_EINVAL, "bad arguments");
+  const ndmg::Geom g = ndmg::make_geom(n, length);
+  // one partial per block of the form kernel's grid: ceil((n + 1) / 64) x (n + 1)^2
+  const size_t nparts = (size_t)((n + 1 + 63) / 64) * (size_t)(n + 1) * (size_t)(n + 1);
+  const size_t need = kNoAllocResultBytes + nparts * sizeof(double);
+  if (need > kNoAllocScratchBytes)
+    return fail(NDMG_EINVAL, "n = " + std::to_string(n) + " needs " + std::to_string(need) +
+                                 " bytes of scratch, more than the fixed " +
+                                 std::to_string(kNoAllocScratchBytes) + " of the allocation-free form");
+  void* base = nullptr;
+  NDMG_TRY(scratch_on_current_device(&base));
+  double* res = static_cast<double*>(base);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(base) + kNoAllocResultBytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double total = 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    // the form kernel writes every partial and the final sum writes the result slot, so
+    // nothing left by an earlier call is read
+    NDMG_HIP(ndmg::launch_curlcurl_form(lam + (int64_t)r * g.len, u + (int64_t)r * g.len, g, part, res, st));
+    double v = 0.0;
+    NDMG_HIP(hipMemcpyAsync(&v, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    NDMG_HIP(hipStreamSynchronize(st));
+    total += v;
   }
   *out = total;
   return NDMG_OK;
