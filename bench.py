@@ -41,18 +41,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the sources of the operator kernel (counter readings are valid for it only)."""
+def source_hash(files):
+    """Hash of library sources (a counter reading is valid for the sources it was taken on)."""
     h = hashlib.sha256()
-    for f in ("stencil.hip", "kernels.hpp", "reduce.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2205_05840_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+    """HBM bytes per launch (per solve for kernel "solve") from the committed rocprofv3
+    counter summary, if its entry was taken on the current sources it lists; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,10 +61,10 @@ def load_traffic(kernel, prec):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
     ent = rec.get("kernels", {}).get(f"{kernel}:{prec}")
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or ent.get("source_hash") != source_hash(ent.get("sources", [])):
+        return None
+    return ent.get("bytes")
 
 
 def run_leg(torch, Solver, f, alpha, precision, steps, warmup):
@@ -115,6 +115,40 @@ def time_apply(torch, S, reps=40, nbuf=8):
     e0.record(st)
     for i in range(reps):
         _lib.check(L.ndmg_apply(S.ctx, *ptrs[i % nbuf]))
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def patch_flops(n):
+    """Useful flops of one launch of the fine-level vertex patch products at n^3 (2 x 2 x 2
+    subdomains, vertex spaces at boundary coarse vertices too): 2 |Gamma_V|^2 per
+    non-empty patch.  With nH = n / 2 coarse cells per axis there are (nH - 1)^3 interior
+    vertices with 60 interface unknowns, 6 (nH - 1)^2 on the faces of the box with 18
+    (the 2 fine edges of the inward coarse edge and 4 in each of the 4 inward faces) and
+    12 (nH - 1) on its edges with 4 (the one face between the two boundary planes); the 8
+    corners have none.  The padding of the MFMA tiles is not counted."""
+    m = n // 2 - 1
+    return 2 * (m ** 3 * 60 ** 2 + 6 * m ** 2 * 18 ** 2 + 12 * m * 4 ** 2)
+
+
+def time_patch(torch, S, reps=40):
+    """Average duration of the fine-level patch products (k_sm_patch alone, one launch per
+    call), timed with HIP events on the library's stream over `reps` launches queued
+    behind a first batch, on the condensed residual left by one smoother application."""
+    from paper_2205_05840_amd import _lib
+    r = (torch.randn(S.vec_len, dtype=torch.float64, device=S.device) * S.unknown_mask()).contiguous()
+    S.level_op(-1, "smooth", r)
+    L = _lib.lib()
+    ptr = r.data_ptr()
+    torch.cuda.synchronize()
+    st = S.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(8):
+        _lib.check(L.ndmg_level_op(S.ctx, -1, _lib.NDMG_OP_PATCH, ptr, ptr))
+    e0.record(st)
+    for _ in range(reps):
+        _lib.check(L.ndmg_level_op(S.ctx, -1, _lib.NDMG_OP_PATCH, ptr, ptr))
     e1.record(st)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
@@ -279,22 +313,26 @@ def cpu_baseline(f, iters_expected, gpu_solutions=None, sample_iters=3):
             "exact": exact_ref}
 
 
-def kernel_probe(torch, Solver, precision, reps):
+def kernel_probe(torch, Solver, reps):
     """For hardware-counter runs: a device copy of 256 MiB (calibration of the byte
-    counters against a kernel of known traffic), then `reps` operator applies at 128^3."""
+    counters against a kernel of known traffic), then `reps` FP64 operator applies at
+    128^3, and 4 fine-level smoother applications (condensation, patch products,
+    pull/extend) in FP64 and in FP32."""
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    S = Solver(N_ELEM, 1.0, precision=precision)
-    t = time_apply(torch, S, reps=reps)
-    # a few fine-level smoother applications (condensation, patch products, pull/extend)
-    r = torch.randn(S.vec_len, dtype=torch.float64, device=S.device) * S.unknown_mask()
-    for _ in range(4):
-        S.level_op(-1, "smooth", r)
-    torch.cuda.synchronize()
-    print(json.dumps({"probe": "apply+smooth", "n": N_ELEM, "reps": reps, "avg_launch_us": t * 1e6,
-                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
+    out = {"probe": "apply+smooth", "n": N_ELEM, "reps": reps, "copy_bytes_each_way": src.numel() * 8}
+    for prec in ("fp64", "fp32"):
+        S = Solver(N_ELEM, 1.0, precision=prec)
+        if prec == "fp64":
+            out["apply_avg_launch_us"] = time_apply(torch, S, reps=reps) * 1e6
+        r = (torch.randn(S.vec_len, dtype=torch.float64, device=S.device) * S.unknown_mask()).contiguous()
+        for _ in range(4):
+            S.level_op(-1, "smooth", r)
+        torch.cuda.synchronize()
+        del S
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -308,7 +346,10 @@ def main():
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only run the calibration copy and the apply kernel (counter runs)")
     ap.add_argument("--solve-probe", choices=["fp32", "fp64"],
-                    help="only run one warm-up and one timed 128^3 solve in this precision (counter runs)")
+                    help="only run one warm-up and --probe-solves timed 128^3 solves in this "
+                         "precision (counter runs; the difference of runs with 2 and 1 timed "
+                         "solves is the traffic of one solve)")
+    ap.add_argument("--probe-solves", type=int, default=1)
     ap.add_argument("--batched-probe", choices=["fp32", "fp64"],
                     help="only run one warm-up and one timed solve of the batched form in this "
                          "precision (counter runs)")
@@ -326,11 +367,11 @@ def main():
     _lib.lib()   # fail loudly if the HIP library is missing
 
     if args.kernel_probe:
-        kernel_probe(torch, Solver, "fp64", 10)
+        kernel_probe(torch, Solver, 10)
         return
     if args.solve_probe:
         f = torch.from_numpy(synth.normal_samples(N_ELEM, SEED))
-        _, _, _, res = run_leg(torch, Solver, f, 1.0, args.solve_probe, 1, 1)
+        _, _, _, res = run_leg(torch, Solver, f, 1.0, args.solve_probe, args.probe_solves, 1)
         print(json.dumps({"probe": "solve", "precision": args.solve_probe, "n": N_ELEM,
                           "s_per_solve": res["s_per_solve_total"], "iters": res["iters"]}), flush=True)
         return
@@ -365,6 +406,9 @@ def main():
             sols[(alpha, prec)] = u.clone()
             if alpha == 1.0 and prec == "fp64":
                 t_apply = time_apply(torch, S)
+                t_patch64 = time_patch(torch, S)
+            if alpha == 1.0 and prec == "fp32":
+                t_patch = time_patch(torch, S)
             del S, b, u
             torch.cuda.empty_cache()
     for alpha in (1.0, 1e-3):
@@ -376,11 +420,27 @@ def main():
     fp64 = legs["fp64@alpha=1"]
     bytes_apply = 2 * ndof * 8
     achieved = bytes_apply / t_apply / 1e9
-    traffic = load_traffic("apply", "fp64")
-    roofline = {"kernel": "k_stencil (operator apply y = A x, 128^3, FP64)",
-                "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": traffic,
-                "avg_launch_us": t_apply * 1e6, "algorithmic_bytes_per_launch": bytes_apply}
+    roofline_apply = {"kernel": "k_stencil (operator apply y = A x, 128^3, FP64)",
+                      "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                      "frac": achieved / 8000.0, "traffic": load_traffic("apply", "fp64"),
+                      "avg_launch_us": t_apply * 1e6, "algorithmic_bytes_per_launch": bytes_apply}
+    # the dominant kernel of the headline (FP32 V-cycle) solve: the fine-level patch
+    # products, two launches per CG iteration, priced against the FP32 MFMA peak
+    flops = patch_flops(N_ELEM)
+    roofline = {"kernel": "k_sm_patch (vertex patch products y_V = S_V^-1 g|Gamma_V, 128^3, FP32)",
+                "bound": "mfma", "achieved": flops / t_patch / 1e12, "peak": 157.3, "unit": "TFLOP/s",
+                "frac": flops / t_patch / 1e12 / 157.3, "traffic": load_traffic("patch", "fp32"),
+                "avg_launch_us": t_patch * 1e6, "algorithmic_flops_per_launch": flops}
+    roofline_patch64 = {"kernel": "k_sm_patch (128^3, FP64)", "bound": "mfma",
+                        "achieved": flops / t_patch64 / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": flops / t_patch64 / 1e12 / 78.6, "traffic": load_traffic("patch", "fp64"),
+                        "avg_launch_us": t_patch64 * 1e6, "algorithmic_flops_per_launch": flops}
+    solve_bytes = {p: load_traffic("solve", p) for p in ("fp32", "fp64")}
+    solve_traffic = {p: (None if solve_bytes[p] is None else
+                         {"bytes_per_solve": solve_bytes[p],
+                          "achieved_GBps": solve_bytes[p] / legs[f"{p}@alpha=1"]["s_per_solve_total"] / 1e9,
+                          "frac_of_hbm_peak": solve_bytes[p] / legs[f"{p}@alpha=1"]["s_per_solve_total"] / 8e12})
+                     for p in ("fp32", "fp64")}
     out = {
         "metric": "DOF/s and s/solve to 1e-10 rel. residual at 128^3, mixed vs FP64 V-cycle-PCG",
         "value": head["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
@@ -398,6 +458,8 @@ def main():
                  "iters": fp64["iters"], "true_relres": fp64["true_relres"]},
         "speedup_mixed_vs_fp64": fp64["s_per_solve_total"] / head["s_per_solve_total"],
         "legs": legs, "roofline": roofline,
+        "roofline_other": {"apply_fp64": roofline_apply, "patch_fp64": roofline_patch64},
+        "solve_traffic": solve_traffic,
     }
     if not args.no_forms:
         out["forms"] = {"batched": batched_leg(torch, max(1, args.steps // 2), 1),

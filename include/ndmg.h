@@ -1,6 +1,7 @@
 /*
  * ndmg: V-cycle multigrid for the lowest-order hexahedral Nedelec discretisation of
- *        curl(alpha curl u) + u = f in a cube, u x n = 0 on its boundary,
+ *        curl(alpha curl u) + u = f in a box (this version: a cube), u x n = 0 on its
+ *        boundary,
  *        with the nonoverlapping substructuring smoothers of Oh, "Multigrid methods for
  *        3D H(curl) problems with nonoverlapping domain decomposition smoothers"
  *        (arXiv 2205.05840), used as a preconditioner inside conjugate gradients.
@@ -90,19 +91,24 @@ void ndmg_default_opts(ndmg_opts* o);
 /* ---- planning and setup ---------------------------------------------------------------
  * ndmg_plan: validate a problem and report the device workspace size in bytes and the
  * vector length (in elements) of the padded edge layout of the finest level.
- * n: elements per axis (>= 2); length: cube side (> 0); alpha: the constant of
- * eq. (model problem) (> 0).  The levels are n, n/2, ... while a level is even and its
- * half is >= 2 (Sec. 3.1, h_k = h_{k-1}/2); the coarsest is solved exactly.  Every
- * smoothed level must be divisible by min(s, n_k / 2).  Either output pointer may be
- * NULL.  Errors: NDMG_EINVAL.
+ * The domain is the box (0, box[0]) x (0, box[1]) x (0, box[2]) (Sec. 1: a box with
+ * axis-parallel edges) meshed by nx x ny x nz congruent cubes (box[d] / n_d equal; the
+ * uniform refinement of Sec. 3.1 keeps them cubes).  This version serves nx = ny = nz
+ * = n (>= 2) only: every other box is rejected with NDMG_EINVAL.  alpha: the constant of
+ * eq. (model problem) (> 0).  levels: 0 for all levels n, n/2, ... while a level is even
+ * and its half is >= 2 (Sec. 3.1, h_k = h_{k-1}/2), else the number of levels kept from
+ * the finest down (1 = the exact solve alone); the coarsest is solved exactly and must
+ * have at most 1024 unknowns.  Every smoothed level must be divisible by min(s, n_k / 2).
+ * Either output pointer may be NULL.  Errors: NDMG_EINVAL.
  */
-int ndmg_plan(int n, double length, double alpha, const ndmg_opts* opts,
-              size_t* workspace_bytes, size_t* vec_len);
+int ndmg_plan(int nx, int ny, int nz, const double box[3], double alpha, int levels,
+              const ndmg_opts* opts, size_t* workspace_bytes, size_t* vec_len);
 
 /* Opaque solver context. */
 typedef struct ndmg_ctx ndmg_ctx;
 
-/* ndmg_setup: build the level hierarchy and the local factors of every level (the
+/* ndmg_setup: for the problem of ndmg_plan (same box, alpha and levels), build the
+ * level hierarchy and the local factors of every level (the
  * subdomain matrices A_T of eq. ATDef and the vertex-space matrices A_V of eq. AVDef,
  * inverted in FP64 on the host), lay out the caller's workspace (d_workspace, at
  * least the planned size, 256-byte aligned), clear it and upload the factors.
@@ -110,8 +116,8 @@ typedef struct ndmg_ctx ndmg_ctx;
  * On success *out owns host metadata only; release it with ndmg_destroy.
  * Errors: NDMG_EINVAL, NDMG_EWORKSPACE, NDMG_EHIP.
  */
-int ndmg_setup(ndmg_ctx** out, int n, double length, double alpha, const ndmg_opts* opts,
-               void* d_workspace, size_t workspace_bytes, void* stream);
+int ndmg_setup(ndmg_ctx** out, int nx, int ny, int nz, const double box[3], double alpha, int levels,
+               const ndmg_opts* opts, void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* ndmg_layout: describe the padded edge layout of a level (level 0 = coarsest,
  * level -1 = finest) of a context with a single problem size.  info[0] = n,
@@ -226,21 +232,29 @@ int ndmg_curlcurl_form_noalloc(int n, double length, const double* d_lam, const 
 int ndmg_export_factor(const ndmg_ctx* ctx, int level, int which, int type, double* buf,
                        int* dims);
 
-/* ---- single steps of one level (FP64 contexts; for tests and diagnostics) ----------
+/* ---- single steps of one level (for tests and diagnostics) --------------------------
  * Vectors use the padded layout of the level(s) named (ndmg_layout), one per pair of
- * the context (a single problem size) back to back.  level as in ndmg_layout.
+ * the context (a single problem size) back to back, in FP64.  level as in ndmg_layout.
+ * In an FP32 context the input (and the old output of NDMG_OP_PROLONG) is rounded to
+ * FP32 into level buffers of the context, the step runs in FP32 as inside the V-cycle,
+ * and the result is widened to FP64 into out.
  *   NDMG_OP_APPLY     out = A_k in                                  (any level)
- *   NDMG_OP_SMOOTH    out = M_k^{-1} in, the vertex-based smoother of
- *                     eq. (Preconditioner P) including its damping eta   (level >= 1)
+ *   NDMG_OP_SMOOTH    out = M_k^{-1} in, the smoother of the context (eq. Preconditioner
+ *                     P or E) including its damping eta                 (level >= 1)
  *   NDMG_OP_RESTRICT  out (level k-1) = I_k^{k-1} in (level k), eq. (F2C)  (level >= 1)
  *   NDMG_OP_PROLONG   out (level k) += I_{k-1}^k in (level k-1)           (level >= 1)
  *   NDMG_OP_COARSE    out = A_0^{-1} in                               (level 0)
- * Errors: NDMG_EINVAL (FP32 context, bad level or op), NDMG_EHIP. */
+ *   NDMG_OP_PATCH     the patch products y_V = S_V^{-1} g|Gamma_V of the smoother alone,
+ *                     on the condensed residual left in the context's level buffers by
+ *                     the last smoothing step (for timing the kernel); in and out are
+ *                     not read or written but must not be NULL           (level >= 1)
+ * Errors: NDMG_EINVAL (bad level or op), NDMG_EHIP. */
 #define NDMG_OP_APPLY 0
 #define NDMG_OP_SMOOTH 1
 #define NDMG_OP_RESTRICT 2
 #define NDMG_OP_PROLONG 3
 #define NDMG_OP_COARSE 4
+#define NDMG_OP_PATCH 5
 int ndmg_level_op(ndmg_ctx* ctx, int level, int op, const double* d_in, double* d_out);
 
 /* Release the context (host memory only; the workspace stays the caller's). */

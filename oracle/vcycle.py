@@ -16,8 +16,14 @@ class Hierarchy:
     """All levels of the V-cycle for n elements per axis on a cube of side L."""
 
     def __init__(self, n, alpha, L=1.0, s=2, m=1, kind="vertex", eta=None,
-                 factored=None, damp_interior=True, boundary=True, inverse="lu"):
+                 factored=None, damp_interior=True, boundary=True, inverse="lu", levels=None):
+        """levels: keep only that many levels from the finest down (the coarsest kept
+        level is then solved exactly, k = 0 of Fig. 1); None keeps all of them."""
         self.sizes = mesh.level_sizes(n)          # coarsest first
+        if levels is not None:
+            if not 1 <= levels <= len(self.sizes):
+                raise ValueError("levels out of range")
+            self.sizes = self.sizes[len(self.sizes) - levels:]
         self.alpha, self.L, self.m = alpha, L, m
         self.A, self.M, self.P = [], [], [None]
         for k, nk in enumerate(self.sizes):

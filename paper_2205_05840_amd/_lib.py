@@ -25,7 +25,7 @@ EXPORTED = [
     "ndmg_curlcurl_form_noalloc",
 ]
 
-NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE = range(5)
+NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE, NDMG_OP_PATCH = range(6)
 
 
 class ndmg_opts(ctypes.Structure):
@@ -65,8 +65,8 @@ def lib():
     P = ctypes.POINTER
     L.ndmg_default_opts.argtypes = [P(ndmg_opts)]
     L.ndmg_default_opts.restype = None
-    L.ndmg_plan.argtypes = [i, d, d, P(ndmg_opts), P(sz), P(sz)]
-    L.ndmg_setup.argtypes = [P(vp), i, d, d, P(ndmg_opts), vp, sz, vp]
+    L.ndmg_plan.argtypes = [i, i, i, P(d), d, i, P(ndmg_opts), P(sz), P(sz)]
+    L.ndmg_setup.argtypes = [P(vp), i, i, i, P(d), d, i, P(ndmg_opts), vp, sz, vp]
     L.ndmg_layout.argtypes = [vp, i, P(ctypes.c_int64)]
     L.ndmg_apply.argtypes = [vp, vp, vp]
     L.ndmg_vcycle.argtypes = [vp, vp, vp]
@@ -102,16 +102,27 @@ def ndmg_default_opts():
     return o
 
 
-def ndmg_plan(n, length, alpha, opts):
+def _box(dims, box):
+    """(nx, ny, nz) and the box lengths from an int n (cube) or a triple, and a scalar
+    length or a triple."""
+    dims = (int(dims),) * 3 if isinstance(dims, (int,)) or hasattr(dims, "__index__") else tuple(int(v) for v in dims)
+    box = (float(box),) * 3 if isinstance(box, (int, float)) else tuple(float(v) for v in box)
+    return dims, (ctypes.c_double * 3)(*box)
+
+
+def ndmg_plan(dims, box, alpha, opts, levels=0):
+    (nx, ny, nz), b = _box(dims, box)
     ws, vl = ctypes.c_size_t(), ctypes.c_size_t()
-    check(lib().ndmg_plan(n, length, alpha, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(vl)))
+    check(lib().ndmg_plan(nx, ny, nz, b, alpha, int(levels), ctypes.byref(opts), ctypes.byref(ws),
+                          ctypes.byref(vl)))
     return ws.value, vl.value
 
 
-def ndmg_setup(n, length, alpha, opts, d_workspace, workspace_bytes, stream):
+def ndmg_setup(dims, box, alpha, opts, d_workspace, workspace_bytes, stream, levels=0):
+    (nx, ny, nz), b = _box(dims, box)
     ctx = ctypes.c_void_p()
-    check(lib().ndmg_setup(ctypes.byref(ctx), n, length, alpha, ctypes.byref(opts), d_workspace,
-                           workspace_bytes, stream))
+    check(lib().ndmg_setup(ctypes.byref(ctx), nx, ny, nz, b, alpha, int(levels), ctypes.byref(opts),
+                           d_workspace, workspace_bytes, stream))
     return ctx
 
 

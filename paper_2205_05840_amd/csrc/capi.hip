@@ -94,6 +94,7 @@ struct Cls {
 
 struct Plan {
   double length = 1.0;
+  int levels = 0;                  // 0: every level down to 2^3 or 3^3; else this many
   ndmg_opts opts{};
   size_t elem = 8;                 // bytes of the V-cycle scalar type
   int nprob = 0, nrhs = 1;
@@ -144,6 +145,12 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   const int n = C.n;
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 2) sizes.push_back(sizes.back() / 2);
+  if (pl.levels > 0) {
+    if (pl.levels > (int)sizes.size())
+      return fail(NDMG_EINVAL, "n = " + std::to_string(n) + " has at most " + std::to_string(sizes.size()) +
+                                   " levels (halving while a level is even and its half >= 2)");
+    sizes.resize(pl.levels);
+  }
   std::reverse(sizes.begin(), sizes.end());
   const size_t np = (size_t)C.nprob, el = pl.elem;
   // dense bottom: the finest level with n_k <= dense_n, if above the coarsest
@@ -176,9 +183,9 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       const int nc = sizes[k];
       const int64_t N0 = 3LL * nc * (nc - 1) * (nc - 1);
       if (N0 > 1024)
-        return fail(NDMG_EINVAL, "n = " + std::to_string(n) +
-                                     ": coarsest level has more than 1024 unknowns; choose n = c 2^j "
-                                     "with c <= 7");
+        return fail(NDMG_EINVAL, "n = " + std::to_string(n) + ": the coarsest level (" + std::to_string(nc) +
+                                     "^3, solved exactly) has " + std::to_string(N0) +
+                                     " unknowns, more than 1024; choose n = c 2^j with c <= 7, or more levels");
       L.blk_A0 = (size_t)N0 * N0;
       L.o_A0 = take(L.blk_A0 * el * np);
       L.o_map = take((size_t)N0 * sizeof(int64_t));
@@ -310,8 +317,11 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   return NDMG_OK;
 }
 
-int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts* o_in, Plan* pl) {
+int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts* o_in, Plan* pl,
+              int levels = 0) {
   if (nprob < 1) return fail(NDMG_EINVAL, "nprob must be >= 1");
+  if (levels < 0) return fail(NDMG_EINVAL, "levels must be >= 0 (0: all)");
+  pl->levels = levels;
   if (!ns) return fail(NDMG_EINVAL, "null size array");
   if (nrhs < 1 || nrhs > 4096) return fail(NDMG_EINVAL, "nrhs must be in [1, 4096]");
   if ((int64_t)nprob * nrhs > 65535) return fail(NDMG_EINVAL, "more than 65535 (problem, rhs) pairs");
@@ -966,12 +976,12 @@ struct CtxDeleter {
 
 int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const double* alpha,
                  int nrhs, const ndmg_opts* opts, void* d_workspace, size_t workspace_bytes,
-                 void* stream) {
+                 void* stream, int levels = 0) {
   if (!out) return fail(NDMG_EINVAL, "null output pointer");
   *out = nullptr;
   if (!alpha) return fail(NDMG_EINVAL, "null alpha array");
   std::unique_ptr<ndmg_ctx, CtxDeleter> c(new ndmg_ctx());
-  NDMG_TRY(make_plan(nprob, ns, length, nrhs, opts, &c->plan));
+  NDMG_TRY(make_plan(nprob, ns, length, nrhs, opts, &c->plan, levels));
   for (int p = 0; p < nprob; ++p)
     if (!(alpha[p] > 0.0) || !std::isfinite(alpha[p])) return fail(NDMG_EINVAL, "alpha must be > 0");
   if (!d_workspace) return fail(NDMG_EINVAL, "null workspace");
@@ -1019,6 +1029,25 @@ int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const 
   return NDMG_OK;
 }
 
+// The box (0, box[0]) x (0, box[1]) x (0, box[2]) with nx x ny x nz elements (Sec. 1: a
+// box with axis-parallel edges, meshed by congruent cubes): the elements must be cubes,
+// and the kernels serve nx = ny = nz.  On success *n and *length describe the cube.
+int check_box(int nx, int ny, int nz, const double* box, int* n, double* length) {
+  if (!box) return fail(NDMG_EINVAL, "null box");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(NDMG_EINVAL, "nx, ny, nz must be >= 2");
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0) || !std::isfinite(box[d])) return fail(NDMG_EINVAL, "box lengths must be > 0");
+  const double h[3] = {box[0] / nx, box[1] / ny, box[2] / nz};
+  for (int d = 1; d < 3; ++d)
+    if (std::fabs(h[d] - h[0]) > 1e-12 * h[0])
+      return fail(NDMG_EINVAL, "the elements must be cubes: box[d] / n_d must be equal");
+  if (nx != ny || ny != nz)
+    return fail(NDMG_EINVAL, "only cubes are supported: nx = ny = nz (the kernels take one size per axis)");
+  *n = nx;
+  *length = box[0];
+  return NDMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1039,19 +1068,27 @@ void ndmg_default_opts(ndmg_opts* o) {
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }
 
-int ndmg_plan(int n, double length, double alpha, const ndmg_opts* opts, size_t* workspace_bytes,
-              size_t* vec_len) {
+int ndmg_plan(int nx, int ny, int nz, const double box[3], double alpha, int levels,
+              const ndmg_opts* opts, size_t* workspace_bytes, size_t* vec_len) {
+  int n = 0;
+  double length = 0.0;
+  NDMG_TRY(check_box(nx, ny, nz, box, &n, &length));
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NDMG_EINVAL, "alpha must be > 0");
   Plan pl;
-  NDMG_TRY(make_plan(1, &n, length, 1, opts, &pl));
+  NDMG_TRY(make_plan(1, &n, length, 1, opts, &pl, levels));
   if (workspace_bytes) *workspace_bytes = pl.bytes;
   if (vec_len) *vec_len = (size_t)pl.total_len;
   return NDMG_OK;
 }
 
-int ndmg_setup(ndmg_ctx** out, int n, double length, double alpha, const ndmg_opts* opts,
-               void* d_workspace, size_t workspace_bytes, void* stream) {
-  return setup_common(out, 1, &n, length, &alpha, 1, opts, d_workspace, workspace_bytes, stream);
+int ndmg_setup(ndmg_ctx** out, int nx, int ny, int nz, const double box[3], double alpha, int levels,
+               const ndmg_opts* opts, void* d_workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return fail(NDMG_EINVAL, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  double length = 0.0;
+  NDMG_TRY(check_box(nx, ny, nz, box, &n, &length));
+  return setup_common(out, 1, &n, length, &alpha, 1, opts, d_workspace, workspace_bytes, stream, levels);
 }
 
 int ndmg_plan_batched(int nprob, const int* n, double length, int nrhs, const ndmg_opts* opts,
@@ -1308,6 +1345,9 @@ int level_op_t(ndmg_ctx* c, Cls& C, int level, int op, const T* in, T* out, cons
     case NDMG_OP_PROLONG:
       NDMG_HIP(ndmg::launch_prolong_add<T>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
       return NDMG_OK;
+    case NDMG_OP_PATCH:
+      NDMG_HIP(ndmg::launch_patch_products<T>(level_ptrs<T>(c, L), level_dsub(c, L), L.g, bt, c->st));
+      return NDMG_OK;
     default:   // NDMG_OP_COARSE
       NDMG_HIP(ndmg::launch_coarse<T>(in, out, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map), (int)L.map.size(),
                                       L.g.len, bt, c->st));
@@ -1328,13 +1368,15 @@ int ndmg_level_op(ndmg_ctx* c, int level, int op, const double* in, double* out)
   const int nl = (int)C.lv.size();
   if (level < 0) level += nl;
   if (level < 0 || level >= nl) return fail(NDMG_EINVAL, "level out of range");
-  if (op < NDMG_OP_APPLY || op > NDMG_OP_COARSE) return fail(NDMG_EINVAL, "unknown operation");
-  if (op == NDMG_OP_SMOOTH && !C.lv[level].smoothed) return fail(NDMG_EINVAL, "the coarsest level has no smoother");
+  if (op < NDMG_OP_APPLY || op > NDMG_OP_PATCH) return fail(NDMG_EINVAL, "unknown operation");
+  if ((op == NDMG_OP_SMOOTH || op == NDMG_OP_PATCH) && !C.lv[level].smoothed)
+    return fail(NDMG_EINVAL, "the coarsest level has no smoother");
   if ((op == NDMG_OP_RESTRICT || op == NDMG_OP_PROLONG) && level < 1)
     return fail(NDMG_EINVAL, "transfers need level >= 1");
   if (op == NDMG_OP_COARSE && level != 0) return fail(NDMG_EINVAL, "coarse solve needs level 0");
   const ndmg::Bat bt = class_batch(c, C, false);
   if (pl.elem == 8) return level_op_t<double>(c, C, level, op, in, out, bt);
+  if (op == NDMG_OP_PATCH) return level_op_t<float>(c, C, level, op, nullptr, nullptr, bt);
   // FP32 context: the FP64 input is rounded into a level buffer of the input's level,
   // the step runs in FP32 into a buffer of the output's level (holding the rounded old
   // output for the accumulating prolongation), and the result is widened into out.

@@ -1834,6 +1834,16 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
 }
 
 template <typename T>
+hipError_t launch_patch_products(const LevelPtrs<T>& L, const DSub& sub, const Geom& g, const Bat& bt,
+                                 hipStream_t st) {
+  if (sub.s != 2) return hipErrorInvalidValue;
+  if (sub.nchunks > 0)
+    hipLaunchKernelGGL((k_sm_patch<T, 2>), dim3((unsigned)sub.nchunks, (unsigned)bt.count), dim3(256), 0,
+                       st, L.gg, L.Y, L.Sinv, dgeom(g), sub, bt);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_coarse(const T* g, T* z, const T* A0inv, const int64_t* map, int N0,
                          int64_t len, const Bat& bt, hipStream_t st) {
   if (N0 > 1024) return hipErrorInvalidValue;
@@ -2028,6 +2038,8 @@ bool boundary_patches_match(const std::vector<int>& tab) {
                                             hipStream_t);                                         \
   template hipError_t launch_smooth<T>(const T*, T*, const LevelPtrs<T>&, const DSub&,            \
                                        const Geom&, const Bat&, double, int, hipStream_t);       \
+  template hipError_t launch_patch_products<T>(const LevelPtrs<T>&, const DSub&, const Geom&,     \
+                                               const Bat&, hipStream_t);                          \
   template hipError_t launch_coarse<T>(const T*, T*, const T*, const int64_t*, int, int64_t,      \
                                        const Bat&, hipStream_t);                                  \
   template hipError_t launch_unit_cols<T>(T*, const int64_t*, int, int, int64_t, const Bat&,      \

@@ -160,6 +160,12 @@ template <typename T>
 hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& sub,
                          const Geom& g, const Bat& bt, double eta, int assign, hipStream_t st);
 
+// The vertex patch products of the smoother alone (k_sm_patch): Y = S^{-1} gg per patch,
+// on the level's current condensed residual (for timing the kernel in isolation).
+template <typename T>
+hipError_t launch_patch_products(const LevelPtrs<T>& L, const DSub& sub, const Geom& g, const Bat& bt,
+                                 hipStream_t st);
+
 // ---- the bottom of the V-cycle in one launch ---------------------------------------
 // Levels 0 .. top (coarsest first) of one size class, described for the first pair and
 // the first problem (pairs follow with the strides of the level vectors, of Y and of the

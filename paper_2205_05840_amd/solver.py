@@ -70,20 +70,22 @@ class Solver(_Context):
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
-                 bottom_n=None, dense_n=None):
+                 bottom_n=None, dense_n=None, levels=0):
         self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
+        if self.nrhs > 1 and levels:
+            raise ValueError("levels applies to single right-hand-side solvers")
         o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:
-            ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o)
+            ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o, levels)
         else:
             ws_bytes, tl = _lib.ndmg_plan_batched([self.n], self.length, self.nrhs, o)
             self.vec_len = tl // self.nrhs
         self._alloc(ws_bytes, device)
         if self.nrhs == 1:
             self.ctx = _lib.ndmg_setup(self.n, self.length, self.alpha, o, self._ws_ptr, ws_bytes,
-                                       self.stream.cuda_stream)
+                                       self.stream.cuda_stream, levels)
         else:
             self.ctx = _lib.ndmg_setup_batched([self.n], self.length, [self.alpha], self.nrhs, o,
                                                self._ws_ptr, ws_bytes, self.stream.cuda_stream)

@@ -74,8 +74,10 @@ def test_null_arguments(lib):
     assert L.ndmg_layout(None, 0, None) == lib.NDMG_EINVAL
     ctx = ctypes.c_void_p()
     o = lib.ndmg_default_opts()
-    assert L.ndmg_setup(ctypes.byref(ctx), 8, 1.0, 1.0, ctypes.byref(o), None, 0, None) == \
+    box = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert L.ndmg_setup(ctypes.byref(ctx), 8, 8, 8, box, 1.0, 0, ctypes.byref(o), None, 0, None) == \
         lib.NDMG_EINVAL
+    assert L.ndmg_plan(8, 8, 8, None, 1.0, 0, ctypes.byref(o), None, None) == lib.NDMG_EINVAL
     assert L.ndmg_destroy(None) == 0
 
 
@@ -121,3 +123,42 @@ def test_batched_null_arguments(lib):
                                 None) == lib.NDMG_EINVAL
     assert L.ndmg_batch_layout(None, 0, None) == lib.NDMG_EINVAL
     assert L.ndmg_pcg_solve_batched(None, None, None, 1e-10, 10, None, None) == lib.NDMG_EINVAL
+
+
+@pytest.mark.parametrize("dims,box,msg", [((8, 8, 16), (1.0, 1.0, 2.0), b"only cubes"),
+                                          ((8, 16, 16), (1.0, 2.0, 2.0), b"only cubes"),
+                                          ((8, 8, 8), (1.0, 1.0, 1.5), b"must be cubes"),
+                                          ((8, 8, 8), (1.0, -1.0, 1.0), b"box lengths"),
+                                          ((8, 8, 1), (1.0, 1.0, 0.125), b">= 2")])
+def test_plan_box_rejections(lib, dims, box, msg):
+    """The boundary takes a box (Sec. 1) with nx x ny x nz elements; the elements must be
+    cubes, and this version serves cubes nx = ny = nz only: anything else is refused with
+    a message (no silent fallback)."""
+    o = lib.ndmg_default_opts()
+    with pytest.raises(lib.NdmgError) as e:
+        lib.ndmg_plan(dims, box, 1.0, o)
+    assert e.value.code == lib.NDMG_EINVAL
+    assert msg in lib.lib().ndmg_last_error()
+
+
+def test_plan_box_cube_equals_scalar_form(lib):
+    o = lib.ndmg_default_opts()
+    assert lib.ndmg_plan((16, 16, 16), (2.0, 2.0, 2.0), 1.0, o) == lib.ndmg_plan(16, 2.0, 1.0, o)
+
+
+@pytest.mark.parametrize("n,levels,ok", [(32, 1, False), (32, 2, False), (32, 3, False), (32, 4, True),
+                                         (32, 5, True), (32, 6, False), (12, 1, False), (12, 2, True),
+                                         (6, 1, True)])
+def test_plan_levels(lib, n, levels, ok):
+    """levels = L keeps the L finest levels n, n/2, ...; the coarsest of them is solved
+    exactly, so it must have at most 1024 unknowns (8^3 has 1176: too many); more levels
+    than the halving rule gives are refused."""
+    o = lib.ndmg_default_opts()
+    if ok:
+        ws, vl = lib.ndmg_plan(n, 1.0, 1.0, o, levels)
+        ws_all, vl_all = lib.ndmg_plan(n, 1.0, 1.0, o)
+        assert vl == vl_all and ws <= ws_all
+    else:
+        with pytest.raises(lib.NdmgError) as e:
+            lib.ndmg_plan(n, 1.0, 1.0, o, levels)
+        assert e.value.code == lib.NDMG_EINVAL

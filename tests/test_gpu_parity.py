@@ -179,10 +179,20 @@ def test_vcycle_dense_top_clears_output():
     assert _rel(from_padded(n, S.P, S.B, z), ref) <= 1e-12
 
 
-def _check_vcycle(n, alpha, m, boundary, bottom, dense=None):
-    S = _solver(n, alpha, m=m, boundary_patches=boundary, bottom_n=bottom, dense_n=dense)
-    H = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True)
-    H2 = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True, inverse="cholesky")
+@pytest.mark.parametrize("n,levels,alpha", [(12, 2, 1.0), (16, 3, 0.2), (32, 4, 5.0)])
+def test_vcycle_fewer_levels(n, levels, alpha):
+    """levels = L keeps the L finest levels; the coarsest kept level is solved exactly."""
+    _check_vcycle(n, alpha, 1, True, None, levels=levels)
+    S = _solver(n, alpha, levels=levels)
+    assert S.levels == levels and S.layout(0)[0] == n >> (levels - 1)
+
+
+def _check_vcycle(n, alpha, m, boundary, bottom, dense=None, levels=None):
+    S = _solver(n, alpha, m=m, boundary_patches=boundary, bottom_n=bottom, dense_n=dense,
+                **({"levels": levels} if levels else {}))
+    H = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True, levels=levels)
+    H2 = vcycle.Hierarchy(n, alpha, m=m, boundary=boundary, factored=True, inverse="cholesky",
+                          levels=levels)
     g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
     z = _host(S.vcycle(_dev(to_padded(n, S.P, S.B, g))))
     ref = H.precondition(g)

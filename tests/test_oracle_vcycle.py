@@ -159,3 +159,20 @@ def test_stiffness_is_alpha_derivative():
     A1 = assemble.matrix_kron(n, h, 1.0)
     A2 = assemble.matrix_kron(n, h, 3.0)
     assert abs((A2 - A1) / 2.0 - K).max() <= 1e-14 * abs(K).max()
+
+
+def test_fewer_levels_two_grid_is_exact_coarse_correction():
+    """With two levels kept, MG(1, g, 0, 1) of Fig. 1 is the two-grid cycle whose coarse
+    step is the exact solve with A_{J-1}: pre-smoothing, exact coarse correction of the
+    restricted residual, post-smoothing, written out here by hand."""
+    import numpy as np
+    import scipy.linalg as sla
+    n, alpha = 8, 0.7
+    H = vcycle.Hierarchy(n, alpha, levels=2)
+    assert H.sizes == [4, 8]
+    g = np.random.default_rng(1).standard_normal(mesh.ndof(n))
+    A, M, P = H.A[1], H.M[1], H.P[1]
+    z = M(g)
+    z = z + P @ sla.solve(H.A[0].toarray(), P.T @ (g - A @ z), assume_a="pos")
+    z = z + M(g - A @ z)
+    assert np.abs(H.precondition(g) - z).max() <= 1e-12 * np.abs(z).max()
