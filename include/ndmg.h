@@ -57,25 +57,29 @@ extern "C" {
 
 /* ---- options ----------------------------------------------------------------------- */
 #define NDMG_SMOOTHER_VERTEX 0   /* vertex-based smoother, eq. (Preconditioner P)       */
+#define NDMG_SMOOTHER_EDGE 1     /* edge-based smoother, eq. (Preconditioner E)         */
 #define NDMG_PREC_FP64 0         /* V-cycle in FP64                                     */
 #define NDMG_PREC_FP32 1         /* V-cycle in FP32 inside FP64 CG (mixed precision)    */
 
 typedef struct ndmg_opts {
-  int smoother;         /* NDMG_SMOOTHER_VERTEX                                       */
+  int smoother;         /* NDMG_SMOOTHER_VERTEX (default) or NDMG_SMOOTHER_EDGE       */
   int m;                /* smoothing steps m of MG(k, g, z0, m) (Fig. 1); default 1   */
-  double eta;           /* damping eta_V; <= 0 selects 1/9 (Sec. 5)                   */
+  double eta;           /* damping of the whole smoother sum; <= 0 (default) selects
+                           the value of Sec. 5: 1/9 (vertex), 1/13 (edge)             */
   int precision;        /* NDMG_PREC_FP64 or NDMG_PREC_FP32                           */
-  int subdomain;        /* s: subdomains are s x s x s fine cells; 2 (= T_{k-1}) or 4 */
-  int boundary_patches; /* 1: vertex spaces also at coarse vertices on the boundary,
-                           cut to the domain (default; reproduces Table 2);
-                           0: interior coarse vertices only                          */
+  int subdomain;        /* s: subdomains are s x s x s fine cells (min(s, n_k / 2) on
+                           level k); 2 (= T_{k-1}, Sec. 3.2; default) or 4             */
+  int boundary_patches; /* 1: vertex (edge) spaces also at coarse vertices (edges) on
+                           the boundary, cut to the domain (default; reproduces
+                           Table 2); 0: interior coarse vertices (edges) only         */
   int flexible;         /* 1: Polak-Ribiere beta in PCG (default for FP32)          */
   int use_graphs;       /* 1 (default): replay each CG iteration from a captured HIP
                            graph when the stream is not the null stream; 0: eager   */
   int bottom_n;         /* levels with n_k <= bottom_n (at most 64) and the coarsest
                            solve run as one launch with one workgroup per (problem,
                            right-hand side); 0 (default): every level launches its
-                           own kernels (faster on MI355X for every size measured)   */
+                           own kernels (faster on MI355X for every size measured).
+                           Vertex smoother with subdomain 2 only.                   */
   int dense_n;          /* with z_0 = 0 the V-cycle MG(k, g, 0, m) of Fig. 1 is a
                            linear map of g: from the finest level with n_k <= dense_n
                            (at most 8, i.e. at most 1176 unknowns) down, it is applied

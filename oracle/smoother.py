@@ -37,10 +37,20 @@ def _sub(A, rows, cols):
 class LiteralSmoother:
     """M^{-1} for kind='vertex' (eta defaults to 1/9) or kind='edge' (eta 1/13)."""
 
-    def __init__(self, A, n, s=2, kind="vertex", eta=None, damp_interior=True, boundary=True):
+    def __init__(self, A, n, s=2, kind="vertex", eta=None, damp_interior=True, boundary=True,
+                 inverse="lu"):
+        """inverse: 'lu' (LAPACK solves and inverses) or 'cholesky' (Cholesky solves and
+        inverses); two FP64 routes to the same local matrices whose difference measures how
+        far rounding in the setup moves the result."""
         if n % s or n // s < 2:
             raise ValueError("need n divisible by s with at least 2 subdomains per axis")
         self.A, self.n, self.s, self.kind = A.tocsr(), n, s, kind
+        if inverse == "cholesky":
+            self._inv = lambda M: sla.cho_solve(sla.cho_factor(M), np.eye(M.shape[0]))
+            self._solve = lambda M, B: sla.cho_solve(sla.cho_factor(M), B)
+        else:
+            self._inv = np.linalg.inv
+            self._solve = np.linalg.solve
         self.eta = eta if eta is not None else (1.0 / 9.0 if kind == "vertex" else 1.0 / 13.0)
         self.damp_interior = damp_interior
         self.T = []
@@ -48,7 +58,7 @@ class LiteralSmoother:
         for t in mesh.coarse_elements(n, s):
             I = mesh.interior_set(n, s, t)
             self.Iof[t] = I
-            self.T.append((I, np.linalg.inv(_sub(self.A, I, I))))
+            self.T.append((I, self._inv(_sub(self.A, I, I))))
         self.P = []
         if kind == "vertex":
             for v in mesh.coarse_vertices(n, s, boundary):
@@ -64,13 +74,14 @@ class LiteralSmoother:
 
     def _patch(self, G, elems):
         Ip = np.sort(np.concatenate([self.Iof[t] for t in elems]))
-        ext = -np.linalg.solve(_sub(self.A, Ip, Ip), _sub(self.A, Ip, G))
+        ext = -self._solve(_sub(self.A, Ip, Ip), _sub(self.A, Ip, G))
         idx = np.concatenate([G, Ip])
         Phi = np.vstack([np.eye(len(G)), ext])           # rows follow idx
         # A_V = Phi^T A Phi with A restricted to idx (Phi vanishes elsewhere)
         Aloc = _sub(self.A, idx, idx)
         AV = Phi.T @ Aloc @ Phi
-        return idx, Phi, np.linalg.inv(AV), AV
+        AV = 0.5 * (AV + AV.T)
+        return idx, Phi, self._inv(AV), AV
 
     def patch_matrices(self):
         """A_V (or A_E) of every patch, in the order of the sorted interface indices."""

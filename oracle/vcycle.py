@@ -42,7 +42,7 @@ class Hierarchy:
                 e = 1.0 / 9.0 if eta is None else eta
                 self.M.append(sm.FactoredVertexSmoother(A, nk, sk, e, boundary, inverse))
             else:
-                self.M.append(sm.LiteralSmoother(A, nk, sk, kind, eta, damp_interior, boundary))
+                self.M.append(sm.LiteralSmoother(A, nk, sk, kind, eta, damp_interior, boundary, inverse))
             self.P.append(transfer.prolongation(self.sizes[k - 1]))
 
     @property

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libndmg.so")
 
-SOURCES = ["kernels.hip", "stencil.hip", "capi.hip", "host_setup.cpp"]
+SOURCES = ["kernels.hip", "stencil.hip", "generic.hip", "capi.hip", "host_setup.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 instructions stay off in device code

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/ndmg.h"
+#include "generic.hpp"
 #include "kernels.hpp"
 #include "ndmg_internal.hpp"
 
@@ -74,6 +75,13 @@ struct LevelHost {
   size_t blk_ATinv = 0, blk_XT = 0, blk_Sinv = 0, blk_A0 = 0;   // elements per problem
   size_t o_Bd = 0, blk_Bd = 0;         // dense V-cycle matrix of the level (dense level only)
   int Nd = 0;                          // its unknowns
+  // generic smoother (edge spaces, or subdomains of size 4): tables and factors
+  bool gen = false;
+  ndmg::GenTables gt;
+  size_t o_C = 0, o_gX = 0, o_gE = 0, o_gS = 0, blk_gX = 0, blk_gE = 0, blk_gS = 0;
+  size_t o_guI = 0, o_grI = 0, o_grE = 0, o_gcI = 0, o_guP = 0, o_grP = 0, o_gcP = 0, o_ggam = 0, o_gcc = 0,
+         o_gcodes = 0;
+  int64_t ylenG = 0, clenG = 0;
 };
 
 struct Cls {
@@ -128,12 +136,15 @@ namespace {
 int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
   ndmg_default_opts(o);
   if (o_in) *o = *o_in;
-  if (o->smoother != NDMG_SMOOTHER_VERTEX) return fail(NDMG_EINVAL, "unsupported smoother");
+  if (o->smoother != NDMG_SMOOTHER_VERTEX && o->smoother != NDMG_SMOOTHER_EDGE)
+    return fail(NDMG_EINVAL, "unsupported smoother");
   if (o->m < 1 || o->m > 64) return fail(NDMG_EINVAL, "m must be in [1, 64]");
   if (o->precision != NDMG_PREC_FP64 && o->precision != NDMG_PREC_FP32)
     return fail(NDMG_EINVAL, "unsupported precision");
-  if (o->subdomain != 2) return fail(NDMG_EINVAL, "subdomain size must be 2");
-  if (o->eta <= 0.0) o->eta = 1.0 / 9.0;
+  if (o->subdomain != 2 && o->subdomain != 4) return fail(NDMG_EINVAL, "subdomain size must be 2 or 4");
+  if (!(o->eta > 0.0)) o->eta = (o->smoother == NDMG_SMOOTHER_EDGE) ? 1.0 / 13.0 : 1.0 / 9.0;
+  if (o->bottom_n > 0 && (o->smoother == NDMG_SMOOTHER_EDGE || o->subdomain != 2))
+    return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) serves the vertex smoother with subdomain 2 only");
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
   if (o->dense_n < 0 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be in [0, 8]");
   return NDMG_OK;
@@ -194,6 +205,45 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       if (sizes[k] % s) return fail(NDMG_EINVAL, "level not divisible by the subdomain size");
       L.smoothed = true;
       L.sub = ndmg::make_sub(s, sizes[k]);
+      if (pl.opts.smoother == NDMG_SMOOTHER_EDGE || s != 2) {
+        // the generic smoother: gathered products over subdomains and patches
+        L.gen = true;
+        std::string err;
+        if (!ndmg::build_gen_tables(L.g, s, pl.opts.smoother == NDMG_SMOOTHER_EDGE ? 1 : 0,
+                                    pl.opts.boundary_patches != 0, &L.gt, &err))
+          return fail(NDMG_EINVAL, err);
+        L.o_r = take(vb);
+        L.o_gg = take(vb);
+        L.o_w = take(vb);
+        L.ylenG = (int64_t)L.gt.unitsP.size() * L.gt.npadP;
+        L.clenG = (int64_t)L.gt.unitsI.size() * L.gt.npadB;
+        L.o_Y = take((size_t)L.ylenG * el * cnt);
+        L.o_C = take((size_t)L.clenG * el * cnt);
+        L.blk_gX = (size_t)L.gt.npadI * L.gt.npadB;
+        L.blk_gE = (size_t)L.gt.npadE * L.gt.npadI;
+        L.blk_gS = (size_t)L.gt.ntypes * L.gt.npadP * L.gt.npadP;
+        L.o_gX = take(L.blk_gX * el * np);
+        L.o_gE = take(L.blk_gE * el * np);
+        L.o_gS = take(L.blk_gS * el * np);
+        L.o_guI = take(L.gt.unitsI.size() * sizeof(int64_t));
+        L.o_grI = take(L.gt.relI.size() * sizeof(int64_t));
+        L.o_grE = take(L.gt.relE.size() * sizeof(int64_t));
+        L.o_gcI = take(std::max<size_t>(1, L.gt.chunksI.size()) * sizeof(int));
+        L.o_guP = take(std::max<size_t>(1, L.gt.unitsP.size()) * sizeof(int64_t));
+        L.o_grP = take(L.gt.relP.size() * sizeof(int64_t));
+        L.o_gcP = take(std::max<size_t>(1, L.gt.chunksP.size()) * sizeof(int));
+        L.o_ggam = take(std::max<size_t>(1, L.gt.gamma.size()) * sizeof(int64_t));
+        L.o_gcc = take(std::max<size_t>(1, L.gt.ccodes.size()) * sizeof(int));
+        L.o_gcodes = take(std::max<size_t>(1, L.gt.codes.size()) * sizeof(int));
+        if ((int)k == C.dense_k) {
+          L.Nd = (int)Nd;
+          L.blk_Bd = (size_t)Nd * Nd;
+          L.o_Bd = take(L.blk_Bd * el * np);
+          L.o_map = take((size_t)Nd * sizeof(int64_t));
+        }
+        C.lv.push_back(std::move(L));
+        continue;
+      }
       L.segs = ndmg::vertex_segments(L.sub.nH, pl.opts.boundary_patches != 0);
       L.chunks.clear();
       int64_t groups = 0;
@@ -429,6 +479,123 @@ struct Staging {
   }
 };
 
+// FP64 factors of one problem on a level of the generic smoother, cast to T, each stored
+// k-major (column k of the matrix is a contiguous row of the array):
+//   xc: X_T^T (rows: the nB boundary edges of a subdomain; columns: its nI interior
+//       unknowns), [npadI][npadB];
+//   ex: [A_T^{-1} | -X_T] (rows: interior unknowns; columns: interior, then boundary),
+//       [npadE][npadI];
+//   sp: S_P^{-1} of every patch type (symmetric), [27][npadP][npadP], zero for absent
+//       types and slots.
+// The slots present in each patch factor must be those of the level's gather tables.
+template <typename T>
+bool build_gen_factors(const LevelHost& L, double alpha, T* xc, T* ex, T* sp, std::string* err) {
+  const ndmg::GenTables& tb = L.gt;
+  const int s = tb.s, nI = tb.nI, nB = tb.nB;
+  std::vector<double> ai, xt;
+  if (!ndmg::subdomain_factors(s, L.g.h, alpha, &ai, &xt, err)) return false;
+  for (int k = 0; k < nI; ++k)
+    for (int r = 0; r < nB; ++r) xc[(size_t)k * tb.npadB + r] = (T)xt[(size_t)k * nB + r];
+  for (int r = 0; r < nI; ++r) {
+    for (int k = 0; k < nI; ++k) ex[(size_t)k * tb.npadI + r] = (T)ai[(size_t)r * nI + k];
+    for (int b = 0; b < nB; ++b) ex[(size_t)(nI + b) * tb.npadI + r] = (T)(-xt[(size_t)r * nB + b]);
+  }
+  std::vector<double> buf((size_t)tb.npadP * tb.npadP);
+  std::vector<char> present;
+  for (int type : tb.typesP) {
+    int t[3];
+    ndmg::patch_type_axes(tb.kind, type, t);
+    const std::vector<ndmg::Slot> slots = tb.kind == 0 ? ndmg::vertex_slots(s) : ndmg::edge_slots(s, type / 9);
+    if (!ndmg::patch_inverse(ndmg::patch_cells(tb.kind, type, s), slots, t, s, L.g.h, alpha, tb.npadP, buf.data(),
+                             &present, err))
+      return false;
+    for (size_t j = 0; j < slots.size(); ++j)
+      if (present[j] != tb.presentP[(size_t)type * tb.npadP + j]) {
+        *err = "internal: patch slots differ from the gather tables";
+        return false;
+      }
+    T* dst = sp + (size_t)type * tb.npadP * tb.npadP;
+    for (size_t i = 0; i < buf.size(); ++i) dst[i] = (T)buf[i];
+  }
+  return true;
+}
+
+template <typename T>
+ndmg::GenLevel<T> gen_level(ndmg_ctx* c, const LevelHost& L) {
+  ndmg::GenLevel<T> G{};
+  const ndmg::GenTables& tb = L.gt;
+  auto common = [&](ndmg::GemmArgs<T>& a) {
+    a.vlen = L.g.len;
+    a.scale = T(1);
+    a.assign = 1;
+  };
+  auto& Cd = G.cond;   // C_T = X_T^T r_I
+  common(Cd);
+  Cd.M = at<T>(c, L.o_gX);
+  Cd.mstride = (int64_t)L.blk_gX;
+  Cd.chunks = at<int>(c, L.o_gcI);
+  Cd.nchunks = (int)(tb.chunksI.size() / 4);
+  Cd.units = at<int64_t>(c, L.o_guI);
+  Cd.relIn = at<int64_t>(c, L.o_grI);
+  Cd.relOut = nullptr;
+  Cd.ksplit = tb.npadI;
+  Cd.npadK = tb.npadI;
+  Cd.npadR = tb.npadB;
+  Cd.nrb = (tb.npadB + 63) / 64;
+  Cd.ylen = L.clenG;
+  auto& Ex = G.ext;    // z_I = eta [A_T^{-1} | -X_T] [r_I ; w_dT]
+  common(Ex);
+  Ex.M = at<T>(c, L.o_gE);
+  Ex.mstride = (int64_t)L.blk_gE;
+  Ex.chunks = Cd.chunks;
+  Ex.nchunks = Cd.nchunks;
+  Ex.units = Cd.units;
+  Ex.relIn = at<int64_t>(c, L.o_grE);
+  Ex.relOut = at<int64_t>(c, L.o_grI);
+  Ex.ksplit = tb.nI;
+  Ex.npadK = tb.npadE;
+  Ex.npadR = tb.npadI;
+  Ex.nrb = (tb.npadI + 63) / 64;
+  Ex.ylen = 0;
+  auto& P = G.patch;   // y_P = S_P^{-1} g|Gamma_P
+  common(P);
+  P.M = at<T>(c, L.o_gS);
+  P.mstride = (int64_t)L.blk_gS;
+  P.chunks = at<int>(c, L.o_gcP);
+  P.nchunks = (int)(tb.chunksP.size() / 4);
+  P.units = at<int64_t>(c, L.o_guP);
+  P.relIn = at<int64_t>(c, L.o_grP);
+  P.relOut = nullptr;
+  P.ksplit = tb.npadP;
+  P.npadK = tb.npadP;
+  P.npadR = tb.npadP;
+  P.nrb = (tb.npadP + 63) / 64;
+  P.ylen = L.ylenG;
+  G.C = at<T>(c, L.o_C);
+  G.gg = at<T>(c, L.o_gg);
+  G.Y = at<T>(c, L.o_Y);
+  G.w = at<T>(c, L.o_w);
+  G.gamma = at<int64_t>(c, L.o_ggam);
+  G.ccodes = at<int>(c, L.o_gcc);
+  G.codes = at<int>(c, L.o_gcodes);
+  G.ngam = (int64_t)tb.gamma.size();
+  G.clen = L.clenG;
+  return G;
+}
+
+// One smoothing step z (assign ? = : +=) M^{-1} r on a smoothed level.
+template <typename T>
+int smooth_level(ndmg_ctx* c, const Cls& C, const LevelHost& L, const T* r, T* z, const ndmg::Bat& bt, int assign,
+                 hipStream_t st) {
+  const double eta = c->plan.opts.eta;
+  if (L.gen) {
+    NDMG_HIP(ndmg::launch_smooth_generic<T>(r, z, gen_level<T>(c, L), L.g, bt, eta, assign, st));
+  } else {
+    NDMG_HIP(ndmg::launch_smooth<T>(r, z, level_ptrs<T>(c, L), level_dsub(c, L), L.g, bt, eta, assign, st));
+  }
+  return NDMG_OK;
+}
+
 // Local factors of every (problem, level) of a class, built on host threads in FP64 and
 // cast to the working precision (Sec. 3.2: A_T of eq. ATDef, A_V of eq. AVDef; coarsest
 // level exact).
@@ -439,7 +606,11 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
   std::vector<std::vector<T>> ATinv(nl), XT(nl), Sinv(nl), A0(nl);
   for (int k = 0; k < nl; ++k) {
     LevelHost& L = C.lv[k];
-    if (L.smoothed) {
+    if (L.gen) {
+      ATinv[k].assign(L.blk_gE * C.nprob, T(0));
+      XT[k].assign(L.blk_gX * C.nprob, T(0));
+      Sinv[k].assign(L.blk_gS * C.nprob, T(0));
+    } else if (L.smoothed) {
       ATinv[k].assign(L.blk_ATinv * C.nprob, T(0));
       XT[k].assign(L.blk_XT * C.nprob, T(0));
       Sinv[k].assign(L.blk_Sinv * C.nprob, T(0));
@@ -469,6 +640,14 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
           if (maps[t].empty()) maps[t] = map;
           continue;
         }
+        if (L.gen) {
+          if (!build_gen_factors(L, a, XT[k].data() + (size_t)p * L.blk_gX, ATinv[k].data() + (size_t)p * L.blk_gE,
+                                 Sinv[k].data() + (size_t)p * L.blk_gS, &err)) {
+            errs[t] = err;
+            return;
+          }
+          continue;
+        }
         ndmg::LevelFactors fac;
         if (!ndmg::build_level_factors(L.g.h, a, L.sub, bp, &fac, &err)) {
           errs[t] = err;
@@ -495,6 +674,27 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
       L.map = maps[0];
       NDMG_TRY(stg.put_vec(c, L.o_A0, A0[k]));
       NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
+      continue;
+    }
+    if (L.gen) {
+      NDMG_TRY(stg.put_vec(c, L.o_gE, ATinv[k]));
+      NDMG_TRY(stg.put_vec(c, L.o_gX, XT[k]));
+      NDMG_TRY(stg.put_vec(c, L.o_gS, Sinv[k]));
+      NDMG_TRY(stg.put_vec(c, L.o_guI, L.gt.unitsI));
+      NDMG_TRY(stg.put_vec(c, L.o_grI, L.gt.relI));
+      NDMG_TRY(stg.put_vec(c, L.o_grE, L.gt.relE));
+      NDMG_TRY(stg.put_vec(c, L.o_gcI, L.gt.chunksI));
+      NDMG_TRY(stg.put_vec(c, L.o_guP, L.gt.unitsP));
+      NDMG_TRY(stg.put_vec(c, L.o_grP, L.gt.relP));
+      NDMG_TRY(stg.put_vec(c, L.o_gcP, L.gt.chunksP));
+      NDMG_TRY(stg.put_vec(c, L.o_ggam, L.gt.gamma));
+      NDMG_TRY(stg.put_vec(c, L.o_gcc, L.gt.ccodes));
+      NDMG_TRY(stg.put_vec(c, L.o_gcodes, L.gt.codes));
+      if (k == C.dense_k) {
+        L.map = ndmg::unknown_offsets(L.g);
+        if ((int)L.map.size() != L.Nd) return fail(NDMG_EINVAL, "internal: dense level size mismatch");
+        NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
+      }
       continue;
     }
     NDMG_TRY(stg.put_vec(c, L.o_ATinv, ATinv[k]));
@@ -603,15 +803,13 @@ int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt
     return NDMG_OK;
   }
   const int m = pl.opts.m;
-  const double eta = pl.opts.eta;
   auto P = level_ptrs<T>(c, L);
-  auto D = level_dsub(c, L);
   LevelHost& Lc = C.lv[k - 1];
   // z_1 .. z_m: pre-smoothing from z_0 = 0
-  NDMG_HIP(ndmg::launch_smooth<T>(g, z, P, D, L.g, bt, eta, 1, st));
+  NDMG_TRY(smooth_level<T>(c, C, L, g, z, bt, 1, st));
   for (int l = 1; l < m; ++l) {
     NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
-    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, bt, eta, 0, st));
+    NDMG_TRY(smooth_level<T>(c, C, L, P.r, z, bt, 0, st));
   }
   // gbar = I_k^{k-1} (g - A z_m)
   NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
@@ -622,7 +820,7 @@ int vcycle_rec(ndmg_ctx* c, Cls& C, int k, const T* g, T* z, const ndmg::Bat& bt
   // post-smoothing
   for (int l = 0; l < m; ++l) {
     NDMG_HIP(ndmg::launch_apply<T>(z, g, P.r, L.g, bt, 1, st));
-    NDMG_HIP(ndmg::launch_smooth<T>(P.r, z, P, D, L.g, bt, eta, 0, st));
+    NDMG_TRY(smooth_level<T>(c, C, L, P.r, z, bt, 0, st));
   }
   return NDMG_OK;
 }
@@ -1056,7 +1254,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   if (!o) return;
   o->smoother = NDMG_SMOOTHER_VERTEX;
   o->m = 1;
-  o->eta = 1.0 / 9.0;
+  o->eta = 0.0;
   o->precision = NDMG_PREC_FP64;
   o->subdomain = 2;
   o->boundary_patches = 1;
@@ -1303,6 +1501,25 @@ int ndmg_export_factor(const ndmg_ctx* c, int level, int which, int type, double
   if (which != 0 && which != 1) return fail(NDMG_EINVAL, "which must be 0 or 1");
   if (which == 1 && (type < 0 || type > 26)) return fail(NDMG_EINVAL, "type out of range");
   const LevelHost& L = C.lv[level];
+  if (L.gen) {
+    const ndmg::GenTables& tb = L.gt;
+    if (which == 1 && std::find(tb.typesP.begin(), tb.typesP.end(), type) == tb.typesP.end())
+      return fail(NDMG_EINVAL, "no patch of that type on this level");
+    dims[0] = which == 0 ? L.sub.nI : tb.npadP;
+    if (!buf) return NDMG_OK;
+    std::vector<double> xc((size_t)tb.npadI * tb.npadB), ex((size_t)tb.npadE * tb.npadI),
+        sp((size_t)tb.ntypes * tb.npadP * tb.npadP);
+    std::string err;
+    if (!build_gen_factors<double>(L, C.alpha[0], xc.data(), ex.data(), sp.data(), &err))
+      return fail(NDMG_EINVAL, err);
+    if (which == 0) {   // A_T^{-1}: columns k of ex below nI (symmetric)
+      for (int i = 0; i < L.sub.nI; ++i)
+        for (int j = 0; j < L.sub.nI; ++j) buf[(size_t)i * L.sub.nI + j] = ex[(size_t)j * tb.npadI + i];
+    } else {
+      std::memcpy(buf, sp.data() + (size_t)type * tb.npadP * tb.npadP, (size_t)tb.npadP * tb.npadP * sizeof(double));
+    }
+    return NDMG_OK;
+  }
   dims[0] = which == 0 ? L.sub.nI : L.sub.npad;
   if (!buf) return NDMG_OK;
   // rebuilt in FP64 for the first problem (the device copy is in the working precision)
@@ -1333,12 +1550,8 @@ int level_op_t(ndmg_ctx* c, Cls& C, int level, int op, const T* in, T* out, cons
     case NDMG_OP_APPLY:
       NDMG_HIP(ndmg::launch_apply<T>(in, nullptr, out, L.g, bt, 0, c->st));
       return NDMG_OK;
-    case NDMG_OP_SMOOTH: {
-      auto P = level_ptrs<T>(c, L);
-      auto D = level_dsub(c, L);
-      NDMG_HIP(ndmg::launch_smooth<T>(in, out, P, D, L.g, bt, c->plan.opts.eta, 1, c->st));
-      return NDMG_OK;
-    }
+    case NDMG_OP_SMOOTH:
+      return smooth_level<T>(c, C, L, in, out, bt, 1, c->st);
     case NDMG_OP_RESTRICT:
       NDMG_HIP(ndmg::launch_restrict<T>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
       return NDMG_OK;
@@ -1346,7 +1559,11 @@ int level_op_t(ndmg_ctx* c, Cls& C, int level, int op, const T* in, T* out, cons
       NDMG_HIP(ndmg::launch_prolong_add<T>(in, out, L.g, C.lv[level - 1].g, bt, c->st));
       return NDMG_OK;
     case NDMG_OP_PATCH:
-      NDMG_HIP(ndmg::launch_patch_products<T>(level_ptrs<T>(c, L), level_dsub(c, L), L.g, bt, c->st));
+      if (L.gen) {
+        NDMG_HIP(ndmg::launch_patch_generic<T>(gen_level<T>(c, L), bt, c->st));
+      } else {
+        NDMG_HIP(ndmg::launch_patch_products<T>(level_ptrs<T>(c, L), level_dsub(c, L), L.g, bt, c->st));
+      }
       return NDMG_OK;
     default:   // NDMG_OP_COARSE
       NDMG_HIP(ndmg::launch_coarse<T>(in, out, at<T>(c, L.o_A0), at<int64_t>(c, L.o_map), (int)L.map.size(),

@@ -449,6 +449,361 @@ bool build_level_factors(double h, double alpha, const SubInfo& sub, bool bounda
   return true;
 }
 
+// ---------------------------------------------------------------------------------
+// Generic patches (any subdomain size; vertex and edge spaces)
+// ---------------------------------------------------------------------------------
+std::vector<Slot> edge_slots(int s, int a) {
+  // Sec. 3.2.1, eq. (edge space): the fine edges on the coarse edge from the anchor node
+  // to anchor + s e_a and in the interiors of the 4 coarse faces containing it.
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  std::vector<Slot> out;
+  auto push = [&](int d, int oa, int ob, int oc) {
+    int o[3];
+    o[a] = oa;
+    o[b] = ob;
+    o[c] = oc;
+    out.push_back({d, o[0], o[1], o[2]});
+  };
+  std::vector<std::pair<int, int>> pairs{{0, 0}};
+  for (int t = 1; t < s; ++t) {
+    pairs.push_back({t, 0});
+    pairs.push_back({-t, 0});
+    pairs.push_back({0, t});
+    pairs.push_back({0, -t});
+  }
+  for (auto& pq : pairs)
+    for (int ca = 0; ca < s; ++ca) push(a, ca, pq.first, pq.second);
+  // edges across it: direction b in the face (a, b) at c-node 0, direction c in the
+  // face (a, c) at b-node 0; node offsets 1 .. s-1 along a, cells -s .. s-1 across
+  for (int na = 1; na < s; ++na)
+    for (int cb = -s; cb < s; ++cb) push(b, na, cb, 0);
+  for (int na = 1; na < s; ++na)
+    for (int cc = -s; cc < s; ++cc) push(c, na, 0, cc);
+  return out;
+}
+
+bool subdomain_factors(int s, double h, double alpha, std::vector<double>* ATinv, std::vector<double>* XT,
+                       std::string* err) {
+  std::vector<std::array<int, 3>> cells;
+  for (int z = 0; z < s; ++z)
+    for (int y = 0; y < s; ++y)
+      for (int x = 0; x < s; ++x) cells.push_back({x, y, z});
+  LocalSystem sys;
+  assemble_cells(cells, h, alpha, &sys);
+  std::vector<int> I, Bd;
+  for (auto& q : interior_dofs(s)) I.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+  for (auto& q : boundary_dofs(s)) Bd.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+  *ATinv = submatrix(sys, I, I);
+  const int nI = (int)I.size(), nB = (int)Bd.size();
+  if (!spd_inverse(*ATinv, nI)) {
+    *err = "subdomain matrix A_T is not positive definite";
+    return false;
+  }
+  const std::vector<double> AIB = submatrix(sys, I, Bd);
+  XT->assign((size_t)nI * nB, 0.0);
+  for (int i = 0; i < nI; ++i)
+    for (int k = 0; k < nI; ++k) {
+      const double a = (*ATinv)[(size_t)i * nI + k];
+      for (int j = 0; j < nB; ++j) (*XT)[(size_t)i * nB + j] += a * AIB[(size_t)k * nB + j];
+    }
+  return true;
+}
+
+namespace {
+
+// An edge (direction d, offsets o from the anchor) lies on the boundary of the domain if
+// it is in a boundary plane through the anchor: node offset 0 along an axis on which the
+// anchor lies on the boundary (t[ax] != 1).
+bool in_boundary_plane(const int t[3], int d, const int o[3]) {
+  for (int ax = 0; ax < 3; ++ax)
+    if (ax != d && t[ax] != 1 && o[ax] == 0) return true;
+  return false;
+}
+
+}  // namespace
+
+std::vector<char> patch_slots_present(const std::vector<std::array<int, 3>>& cells,
+                                      const std::vector<Slot>& slots, const int t[3]) {
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  for (auto& c : cells)
+    for (int ax = 0; ax < 3; ++ax) {
+      lo[ax] = std::min(lo[ax], c[ax]);
+      hi[ax] = std::max(hi[ax], c[ax] + 1);
+    }
+  std::vector<char> present(slots.size(), 0);
+  for (size_t j = 0; j < slots.size(); ++j) {
+    const int d = slots[j].d;
+    const int o[3] = {slots[j].dx, slots[j].dy, slots[j].dz};
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax == d) in &= (o[ax] >= lo[ax] && o[ax] < hi[ax]);
+      else in &= (o[ax] >= lo[ax] && o[ax] <= hi[ax]);
+    }
+    present[j] = in && !in_boundary_plane(t, d, o);
+  }
+  return present;
+}
+
+std::vector<std::array<int, 3>> patch_cells(int kind, int type, int s) {
+  int t[3];
+  patch_type_axes(kind, type, t);
+  int lo[3], hi[3];
+  const int a = type / 9;   // the edge's axis (edge patches)
+  for (int ax = 0; ax < 3; ++ax) {
+    if (kind == 1 && ax == a) {
+      lo[ax] = 0;
+      hi[ax] = s;
+    } else {
+      lo[ax] = (t[ax] == 0) ? 0 : -s;
+      hi[ax] = (t[ax] == 2) ? 0 : s;
+    }
+  }
+  std::vector<std::array<int, 3>> cells;
+  for (int z = lo[2]; z < hi[2]; ++z)
+    for (int y = lo[1]; y < hi[1]; ++y)
+      for (int x = lo[0]; x < hi[0]; ++x) cells.push_back({x, y, z});
+  return cells;
+}
+
+void patch_type_axes(int kind, int type, int t[3]) {
+  if (kind == 0) {
+    t[0] = type % 3;
+    t[1] = (type / 3) % 3;
+    t[2] = type / 9;
+  } else {
+    const int a = type / 9, b = (a + 1) % 3, c = (a + 2) % 3;
+    t[a] = 1;
+    t[b] = type % 3;
+    t[c] = (type / 3) % 3;
+  }
+}
+
+bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
+                   const int t[3], int s, double h, double alpha, int npad, double* out,
+                   std::vector<char>* present, std::string* err) {
+  LocalSystem sys;
+  assemble_cells(cells, h, alpha, &sys);
+  auto dirichlet = [&](int d, const int o[3]) { return in_boundary_plane(t, d, o); };
+  *present = patch_slots_present(cells, slots, t);
+  std::vector<int> G, Gslot;
+  for (size_t j = 0; j < slots.size(); ++j) {
+    if (!(*present)[j]) continue;
+    G.push_back(sys.index.at(Key(slots[j].d, slots[j].dx, slots[j].dy, slots[j].dz)));
+    Gslot.push_back((int)j);
+  }
+  for (int i = 0; i < npad * npad; ++i) out[i] = 0.0;
+  if (G.empty()) return true;
+  // interior unknowns of the subdomains in the patch, grouped by subdomain: A_II is block
+  // diagonal over subdomains, each block the same A_T up to the order of its unknowns
+  std::map<std::array<int, 3>, std::vector<int>> blocks;
+  for (int e = 0; e < sys.N; ++e) {
+    const Key& k = sys.keys[e];
+    const int d = std::get<0>(k);
+    const int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+    bool interior = true;
+    for (int ax = 0; ax < 3; ++ax)
+      if (ax != d && ((o[ax] % s) + s) % s == 0) interior = false;
+    if (!interior || dirichlet(d, o)) continue;
+    std::array<int, 3> blk;
+    for (int ax = 0; ax < 3; ++ax) blk[ax] = (o[ax] - ((o[ax] % s) + s) % s) / s;   // floor(o / s)
+    blocks[blk].push_back(e);
+  }
+  const int nG = (int)G.size();
+  std::vector<double> S = submatrix(sys, G, G);
+  for (auto& kv : blocks) {
+    const std::vector<int>& I = kv.second;
+    const int nI = (int)I.size();
+    std::vector<double> AII = submatrix(sys, I, I);
+    if (!spd_inverse(AII, nI)) {
+      *err = "patch interior block is not positive definite";
+      return false;
+    }
+    std::vector<double> AIG = submatrix(sys, I, G);
+    std::vector<double> X((size_t)nI * nG, 0.0);   // A_II^{-1} A_IG
+    for (int i = 0; i < nI; ++i)
+      for (int k = 0; k < nI; ++k) {
+        const double a = AII[(size_t)i * nI + k];
+        for (int j = 0; j < nG; ++j) X[(size_t)i * nG + j] += a * AIG[(size_t)k * nG + j];
+      }
+    for (int i = 0; i < nG; ++i)
+      for (int k = 0; k < nI; ++k) {
+        const double a = AIG[(size_t)k * nG + i];
+        if (a == 0.0) continue;
+        for (int j = 0; j < nG; ++j) S[(size_t)i * nG + j] -= a * X[(size_t)k * nG + j];
+      }
+  }
+  for (int i = 0; i < nG; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double v = 0.5 * (S[(size_t)i * nG + j] + S[(size_t)j * nG + i]);
+      S[(size_t)i * nG + j] = S[(size_t)j * nG + i] = v;
+    }
+  if (!spd_inverse(S, nG)) {
+    *err = "patch Schur complement is not positive definite";
+    return false;
+  }
+  for (int i = 0; i < nG; ++i)
+    for (int j = 0; j < nG; ++j) out[(size_t)Gslot[i] * npad + Gslot[j]] = S[(size_t)i * nG + j];
+  return true;
+}
+
+bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err) {
+  const int n = g.n, nH = n / s;
+  GenTables& tb = *out;
+  tb = GenTables{};
+  tb.kind = kind;
+  tb.s = s;
+  tb.ntypes = 27;
+  const std::vector<Slot> idofs = interior_dofs(s), bdofs = boundary_dofs(s);
+  tb.nI = (int)idofs.size();
+  tb.nB = (int)bdofs.size();
+  tb.npadI = (tb.nI + 15) / 16 * 16;
+  tb.npadB = (tb.nB + 15) / 16 * 16;
+  tb.npadE = (tb.nI + tb.nB + 15) / 16 * 16;
+  auto rel_of = [&](const Slot& q) { return q.d * g.B + (int64_t)q.dz * g.plane + (int64_t)q.dy * g.P + q.dx; };
+  auto anchor = [&](int x, int y, int z) { return (int64_t)z * g.plane + (int64_t)y * g.P + x; };
+  // subdomains: one type; every boundary edge of a subdomain lies in [0, n] (those on the
+  // boundary of the domain are zero in every vector read there)
+  tb.relI.assign(tb.npadI, kGenAbsentHost);
+  tb.relE.assign(tb.npadE, kGenAbsentHost);
+  for (int j = 0; j < tb.nI; ++j) tb.relI[j] = tb.relE[j] = rel_of(idofs[j]);
+  for (int j = 0; j < tb.nB; ++j) tb.relE[tb.nI + j] = rel_of(bdofs[j]);
+  for (int c = 0; c < nH; ++c)
+    for (int b = 0; b < nH; ++b)
+      for (int a = 0; a < nH; ++a) tb.unitsI.push_back(anchor(s * a, s * b, s * c));
+  for (size_t u = 0; u < tb.unitsI.size(); u += 64) {
+    tb.chunksI.push_back(0);
+    tb.chunksI.push_back((int)u);
+    tb.chunksI.push_back((int)std::min<size_t>(64, tb.unitsI.size() - u));
+    tb.chunksI.push_back(0);
+  }
+  // patches, grouped by type
+  const int nslots = kind == 0 ? 6 * s * (4 * s - 3) : s + 8 * s * (s - 1);
+  tb.npadP = (nslots + 15) / 16 * 16;
+  tb.relP.assign((size_t)tb.ntypes * tb.npadP, kGenAbsentHost);
+  tb.presentP.assign((size_t)tb.ntypes * tb.npadP, 0);
+  auto positions = [&](int t, int cells_axis, std::vector<int>* pos) {
+    // coarse coordinates of the given type along one axis: node axes 0 / inside / nH,
+    // the edge's own axis its cells 0 .. nH - 1
+    pos->clear();
+    if (cells_axis) {
+      for (int i = 0; i < nH; ++i) pos->push_back(i);
+    } else if (t == 0) {
+      pos->push_back(0);
+    } else if (t == 2) {
+      pos->push_back(nH);
+    } else {
+      for (int i = 1; i < nH; ++i) pos->push_back(i);
+    }
+  };
+  for (int type = 0; type < tb.ntypes; ++type) {
+    int t[3];
+    patch_type_axes(kind, type, t);
+    const int nb = (t[0] != 1) + (t[1] != 1) + (t[2] != 1);
+    if (kind == 0 && nb == 3) continue;       // box corners: no interface unknowns
+    if (kind == 1 && nb == 2) continue;       // coarse edges on the box's edges: none either
+    if (!boundary && nb > 0) continue;
+    const std::vector<Slot> slots = kind == 0 ? vertex_slots(s) : edge_slots(s, type / 9);
+    if ((int)slots.size() != nslots) {
+      *err = "internal: slot count";
+      return false;
+    }
+    const std::vector<char> pres = patch_slots_present(patch_cells(kind, type, s), slots, t);
+    bool any = false;
+    for (int j = 0; j < nslots; ++j) {
+      tb.presentP[(size_t)type * tb.npadP + j] = pres[j];
+      if (pres[j]) {
+        tb.relP[(size_t)type * tb.npadP + j] = rel_of(slots[j]);
+        any = true;
+      }
+    }
+    if (!any) continue;
+    std::vector<int> px, py, pz;
+    const int a = type / 9;
+    positions(t[0], kind == 1 && a == 0, &px);
+    positions(t[1], kind == 1 && a == 1, &py);
+    positions(t[2], kind == 1 && a == 2, &pz);
+    const size_t first = tb.unitsP.size();
+    for (int z : pz)
+      for (int y : py)
+        for (int x : px) tb.unitsP.push_back(anchor(s * x, s * y, s * z));
+    if (tb.unitsP.size() == first) continue;
+    tb.typesP.push_back(type);
+    for (size_t u = first; u < tb.unitsP.size(); u += 64) {
+      tb.chunksP.push_back(type);
+      tb.chunksP.push_back((int)u);
+      tb.chunksP.push_back((int)std::min<size_t>(64, tb.unitsP.size() - u));
+      tb.chunksP.push_back(0);
+    }
+  }
+  if ((int64_t)tb.unitsP.size() * tb.npadP >= (int64_t)1 << 31) {
+    *err = "level too large for the patch result indices";
+    return false;
+  }
+  // interface unknowns (not inside a subdomain), in layout order, and the patch results
+  // summed on each, in the order of the patches
+  std::vector<int> gpos((size_t)g.len, -1);
+  for (int64_t e : unknown_offsets(g)) {
+    const int d = (int)(e / g.B);
+    int64_t r = e - d * g.B;
+    const int z = (int)(r / g.plane);
+    r -= (int64_t)z * g.plane;
+    const int y = (int)(r / g.P), x = (int)(r - (int64_t)y * g.P);
+    const int o[3] = {x, y, z};
+    bool interior = true;
+    for (int ax = 0; ax < 3; ++ax)
+      if (ax != d && o[ax] % s == 0) interior = false;
+    if (interior) continue;
+    gpos[(size_t)e] = (int)tb.gamma.size();
+    tb.gamma.push_back(e);
+  }
+  // subdomain terms of the condensation on each interface unknown
+  tb.ccodes.assign(tb.gamma.size() * 4, -1);
+  {
+    std::vector<int> cfill(tb.gamma.size(), 0);
+    if ((int64_t)tb.unitsI.size() * tb.npadB >= (int64_t)1 << 31) {
+      *err = "level too large for the condensation indices";
+      return false;
+    }
+    for (size_t u = 0; u < tb.unitsI.size(); ++u)
+      for (int b = 0; b < tb.nB; ++b) {
+        const int64_t e = tb.unitsI[u] + tb.relE[tb.nI + b];
+        if (e < 0 || e >= g.len) {
+          *err = "internal: a subdomain boundary edge outside the level";
+          return false;
+        }
+        const int k = gpos[(size_t)e];
+        if (k < 0) continue;   // on the boundary of the domain
+        if (cfill[k] == 4) {
+          *err = "internal: more than 4 subdomains hold an interface unknown";
+          return false;
+        }
+        tb.ccodes[(size_t)k * 4 + cfill[k]++] = (int)u * tb.npadB + b;
+      }
+  }
+  tb.codes.assign(tb.gamma.size() * 4, -1);
+  std::vector<int> fill(tb.gamma.size(), 0);
+  for (size_t c = 0; c < tb.chunksP.size(); c += 4) {
+    const int type = tb.chunksP[c], u0 = tb.chunksP[c + 1], cnt = tb.chunksP[c + 2];
+    for (int u = u0; u < u0 + cnt; ++u)
+      for (int j = 0; j < tb.npadP; ++j) {
+        const int64_t ro = tb.relP[(size_t)type * tb.npadP + j];
+        if (ro == kGenAbsentHost) continue;
+        const int64_t e = tb.unitsP[u] + ro;
+        if (e < 0 || e >= g.len || gpos[(size_t)e] < 0) {
+          *err = "internal: a patch slot is not an interface unknown";
+          return false;
+        }
+        const int k = gpos[(size_t)e];
+        if (fill[k] == 4) {
+          *err = "internal: more than 4 patches hold an interface unknown";
+          return false;
+        }
+        tb.codes[(size_t)k * 4 + fill[k]++] = u * tb.npadP + j;
+      }
+  }
+  return true;
+}
+
 std::vector<int64_t> unknown_offsets(const Geom& g) {
   const int n = g.n;
   std::vector<int64_t> off;

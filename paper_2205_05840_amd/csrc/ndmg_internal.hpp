@@ -1,6 +1,8 @@
 // Internal declarations of the ndmg library (not part of the C ABI).
 #pragma once
 
+#include <array>
+#include <climits>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -83,6 +85,61 @@ struct LevelFactors {
 // Build the factors for a level (h, alpha, s).  Returns false and sets err on failure.
 bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
                          LevelFactors* out, std::string* err);
+
+// Interface slots of the edge space of a coarse edge along axis a (Sec. 3.2.1), offsets
+// from the edge's first node (a multiple of s per axis): s (4 s - 3) edges along a, then
+// 2 s (s - 1) along each of the two other axes; s + 8 s (s - 1) in all.
+std::vector<Slot> edge_slots(int s, int a);
+
+// A_T^{-1} of an s x s x s subdomain (nI x nI, order of interior_dofs) and X_T =
+// A_T^{-1} A_{I, dT} (nI x nB, columns in the order of boundary_dofs).
+bool subdomain_factors(int s, double h, double alpha, std::vector<double>* ATinv, std::vector<double>* XT,
+                       std::string* err);
+
+// Inverse Schur complement of one patch (eq. AVDef / AEDef in the discrete-harmonic basis):
+// cells are the fine cells of the patch (offsets from its anchor node), slots its
+// interface edges, t[ax] = 0 / 2 where the anchor lies on the low / high boundary plane
+// of axis ax (edges in such a plane through the anchor carry no unknown), 1 otherwise.
+// out (npad x npad, row-major) receives S^{-1} on the present slots and zeros elsewhere;
+// present[j] = 1 for the slots that hold an unknown.
+bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
+                   const int t[3], int s, double h, double alpha, int npad, double* out,
+                   std::vector<char>* present, std::string* err);
+
+// Patch types of the generic smoother.  kind 0 (vertex spaces): type = tx + 3 ty + 9 tz,
+// t = 0 / 1 / 2 for a vertex on the low boundary plane / inside / on the high plane of
+// that axis.  kind 1 (edge spaces): type = 9 a + tb + 3 tc for a coarse edge along axis
+// a, (b, c) = (a + 1, a + 2) mod 3 the axes across it; t[a] = 1.
+void patch_type_axes(int kind, int type, int t[3]);
+// The fine cells of a patch of that type (offsets from its anchor node): the 8 (vertex)
+// or 4 (edge) subdomains around the anchor that lie in the domain.
+std::vector<std::array<int, 3>> patch_cells(int kind, int type, int s);
+// Slots of a patch that hold an unknown: inside the patch's cells and not in a boundary
+// plane through the anchor.
+std::vector<char> patch_slots_present(const std::vector<std::array<int, 3>>& cells,
+                                      const std::vector<Slot>& slots, const int t[3]);
+
+// Relative offset of a slot without an unknown (the same value as the kernels' kGenAbsent).
+constexpr int64_t kGenAbsentHost = INT64_MIN;
+
+// Device tables of one level of the generic smoother (geometry only).
+struct GenTables {
+  int kind = 0, s = 2, ntypes = 27;
+  int nI = 0, nB = 0;
+  int npadI = 0, npadB = 0, npadE = 0, npadP = 0;
+  std::vector<int64_t> unitsI;         // subdomain anchors
+  std::vector<int64_t> relI;           // [npadI] interior offsets
+  std::vector<int64_t> relE;           // [npadE] interior offsets, then boundary offsets
+  std::vector<int> chunksI;            // [n][4]
+  std::vector<int64_t> unitsP, relP;   // patch anchors; [ntypes][npadP] slot offsets
+  std::vector<int> chunksP;
+  std::vector<char> presentP;          // [ntypes][npadP]
+  std::vector<int> typesP;             // the types that have patches
+  std::vector<int64_t> gamma;          // interface unknowns
+  std::vector<int> ccodes;             // [ngam][4] subdomain terms (u npadB + boundary slot)
+  std::vector<int> codes;              // [ngam][4] patch results (u npadP + slot)
+};
+bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err);
 
 // Padded-layout offsets of the interior edges (the unknowns) of a level, direction-major
 // and then in layout order.

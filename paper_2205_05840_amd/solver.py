@@ -9,10 +9,14 @@ import torch
 from . import _lib
 
 PRECISIONS = {"fp64": 0, "fp32": 1}
+SMOOTHERS = {"vertex": 0, "edge": 1}
 
 
-def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None, dense_n=None):
+def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None, dense_n=None,
+          smoother="vertex", subdomain=2):
     o = _lib.ndmg_default_opts()
+    o.smoother = SMOOTHERS[smoother]
+    o.subdomain = int(subdomain)
     o.m = int(m)
     if eta is not None:
         o.eta = float(eta)
@@ -64,17 +68,20 @@ class _Context:
 
 class Solver(_Context):
     """V-cycle-preconditioned CG for curl(alpha curl u) + u = f on (0, length)^3 with
-    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace.  With
+    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace; smoother
+    "vertex" (eq. Preconditioner P) or "edge" (eq. Preconditioner E) on subdomains of
+    subdomain^3 elements (2 or 4).  With
     nrhs > 1 every call works on nrhs vectors at once ([nrhs, vec_len] tensors), each
     right-hand side with its own CG scalars."""
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
-                 bottom_n=None, dense_n=None, levels=0):
+                 bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2):
         self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
         if self.nrhs > 1 and levels:
             raise ValueError("levels applies to single right-hand-side solvers")
-        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n)
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n,
+                  smoother, subdomain)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:
@@ -199,11 +206,12 @@ class BatchedSolver(_Context):
 
     def __init__(self, ns, alphas, nrhs=1, length=1.0, m=1, eta=None, precision="fp32",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0",
-                 bottom_n=None, dense_n=None):
+                 bottom_n=None, dense_n=None, smoother="vertex", subdomain=2):
         self.ns = [int(v) for v in ns]
         self.alphas = [float(v) for v in alphas]
         self.nrhs, self.length, self.precision = int(nrhs), float(length), precision
-        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n)
+        o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n,
+                  smoother, subdomain)
         self.opts = o
         ws_bytes, self.total_len = _lib.ndmg_plan_batched(self.ns, self.length, self.nrhs, o)
         self._alloc(ws_bytes, device)

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_default_opts(lib):
     o = lib.ndmg_default_opts()
-    assert o.m == 1 and abs(o.eta - 1 / 9) < 1e-15 and o.subdomain == 2
+    assert o.m == 1 and o.eta == 0.0 and o.subdomain == 2 and o.smoother == 0   # eta 0: Sec. 5's value
     assert o.boundary_patches == 1 and o.precision == 0
 
 
@@ -61,7 +61,7 @@ def test_plan_rejects(lib, args, code):
 
 
 def test_plan_rejects_bad_options(lib):
-    for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5)):
+    for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5), ("subdomain", 8)):
         o = lib.ndmg_default_opts()
         setattr(o, field, val)
         with pytest.raises(lib.NdmgError):
@@ -162,3 +162,24 @@ def test_plan_levels(lib, n, levels, ok):
         with pytest.raises(lib.NdmgError) as e:
             lib.ndmg_plan(n, 1.0, 1.0, o, levels)
         assert e.value.code == lib.NDMG_EINVAL
+
+
+@pytest.mark.parametrize("smoother,s,n", [(1, 2, 8), (1, 2, 16), (1, 4, 16), (0, 4, 8), (0, 4, 64),
+                                          (1, 2, 12), (0, 4, 24)])
+def test_plan_generic_smoothers(lib, smoother, s, n):
+    """The edge smoother (eq. Preconditioner E) and 4 x 4 x 4 subdomains plan; the one-launch
+    bottom is refused for them."""
+    o = lib.ndmg_default_opts()
+    o.smoother, o.subdomain = smoother, s
+    ws, vl = lib.ndmg_plan(n, 1.0, 1.0, o)
+    assert ws % 256 == 0 and vl == 3 * (n + 1) ** 2 * (((n + 1) + 7) // 8 * 8)
+    o.bottom_n = 8
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan(n, 1.0, 1.0, o)
+
+
+def test_plan_s4_needs_divisible_levels(lib):
+    o = lib.ndmg_default_opts()
+    o.subdomain = 4
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan(10, 1.0, 1.0, o)       # 10 is not divisible by min(4, 10 / 2)
