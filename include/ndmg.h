@@ -194,6 +194,23 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
 int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
                    int* iters, double* relres);
 
+/* Contraction number ||E_J||_a of the V-cycle (Sec. 4.2: E = I - B A with B = MG(J, ., 0,
+ * m) is a-symmetric positive semidefinite, so ||E||_a = 1 - lambda_min(B A); the quantity
+ * of Sec. 5, Tables 1-2), estimated by the Lanczos process of V-cycle-preconditioned CG:
+ * CG on A u = b from u = 0 (d_b any vector with components along every eigenvector, e.g.
+ * random; d_u receives the iterate and must be 16-byte aligned like d_b) runs for maxit
+ * iterations (at most 512) or until ||r|| <= rtol ||b||, and its coefficients give the
+ * tridiagonal Lanczos matrix T of B A, whose extreme eigenvalues (Sturm bisection on the
+ * host) bound those of B A from inside.  rtol = 0 runs CG past the convergence of u (the
+ * process is scale-free); the matrix then ends where r.z has fallen below 1e-200 of its
+ * first value.  *contraction = 1 - lambda_min(T) (from below,
+ * converging as the iterations grow), *lam_max = lambda_max(T) (may be NULL), *iters =
+ * the Lanczos steps used (may be NULL).  Needs a context with one right-hand side, the
+ * FP64 V-cycle and the standard CG beta (flexible = 0 or default).
+ * Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_EBREAKDOWN. */
+int ndmg_contraction(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
+                     double* contraction, double* lam_max, int* iters);
+
 /* Load vector b_e = (f, phi_e) (Sec. 2, the functional f_h) from f sampled at the
  * 2x2x2 Gauss-Legendre points of every element: d_f is [n^3][8][3] doubles, element
  * (c0, c1, c2) at row (c2 n + c1) n + c0, point q = q0 + 2 q1 + 4 q2 at local

@@ -22,7 +22,7 @@ EXPORTED = [
     "ndmg_vcycle", "ndmg_pcg_solve", "ndmg_assemble_rhs", "ndmg_curlcurl_form",
     "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
     "ndmg_plan_batched", "ndmg_setup_batched", "ndmg_batch_layout", "ndmg_pcg_solve_batched",
-    "ndmg_curlcurl_form_noalloc",
+    "ndmg_curlcurl_form_noalloc", "ndmg_contraction",
 ]
 
 NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE, NDMG_OP_PATCH = range(6)
@@ -74,6 +74,7 @@ def lib():
     L.ndmg_assemble_rhs.argtypes = [vp, vp, vp]
     L.ndmg_curlcurl_form.argtypes = [vp, vp, vp, i, P(d)]
     L.ndmg_curlcurl_form_noalloc.argtypes = [i, d, vp, vp, i, P(d), vp]
+    L.ndmg_contraction.argtypes = [vp, vp, vp, d, i, P(d), P(d), P(i)]
     L.ndmg_export_factor.argtypes = [vp, i, i, i, P(d), P(i)]
     L.ndmg_level_op.argtypes = [vp, i, i, vp, vp]
     L.ndmg_plan_batched.argtypes = [i, P(i), d, i, P(ndmg_opts), P(sz), P(sz)]
@@ -146,6 +147,12 @@ def ndmg_pcg_solve(ctx, d_b, d_u, rtol, maxit, raise_on_noconv=True):
     if code != NDMG_OK and (raise_on_noconv or code != NDMG_ENOCONV):
         check(code)
     return code, it.value, rel.value
+
+
+def ndmg_contraction(ctx, d_b, d_u, rtol, maxit):
+    c, lm, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    check(lib().ndmg_contraction(ctx, d_b, d_u, rtol, maxit, ctypes.byref(c), ctypes.byref(lm), ctypes.byref(it)))
+    return c.value, lm.value, it.value
 
 
 def ndmg_plan_batched(ns, length, nrhs, opts):

@@ -98,6 +98,7 @@ struct Cls {
   int64_t pstride = 0;             // partial sums per pair
   size_t o_pr = 0, o_pz = 0, o_pp = 0, o_pq = 0, o_part = 0, o_scal = 0;
   size_t o_alpha = 0, o_act = 0, o_iters = 0, o_status = 0;
+  size_t o_hist = 0;               // per pair: (r . z, p . A p) of the first kHistCap iterations
 };
 
 struct Plan {
@@ -364,6 +365,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   C.o_act = take(cnt * sizeof(int));
   C.o_iters = take(cnt * sizeof(int));
   C.o_status = take(cnt * sizeof(int));
+  C.o_hist = take(cnt * (size_t)ndmg::kHistCap * 2 * sizeof(double));
   return NDMG_OK;
 }
 
@@ -928,7 +930,7 @@ int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, int set, hipStream_t st) {
   NDMG_HIP(ndmg::launch_pcg_check(at<double>(c, C.o_scal), at<int>(c, C.o_act), at<int>(c, C.o_iters),
                                   at<int>(c, C.o_status), C.count, i_rz,
                                   c->dev_nact + set * c->plan.cls.size() + ci, part_region(c, C, 2),
-                                  ndmg::dot_parts(C.vlen, C.count), part_stride(C), st));
+                                  ndmg::dot_parts(C.vlen, C.count), part_stride(C), at<double>(c, C.o_hist), st));
   return NDMG_OK;
 }
 
@@ -1377,6 +1379,93 @@ int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol,
   if (iters) std::fill(iters, iters + np, 0);
   if (relres) std::fill(relres, relres + np, 0.0);
   return pcg_all(c, b, u, rtol, maxit, iters, relres);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Eigenvalues of the symmetric tridiagonal matrix (diagonal a, off-diagonal b) below x:
+// the negative pivots of its LDL^T factorisation (Sturm sequence count).
+int count_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+    q = (a[i] - x) - (i ? bb / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Smallest (which = 0) or largest (which = 1) eigenvalue by bisection on the Sturm count
+// within the Gershgorin interval.
+double tridiag_extreme(const std::vector<double>& a, const std::vector<double>& b, int which) {
+  double lo = a[0], hi = a[0];
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const int target = which == 0 ? 1 : (int)a.size();   // the first x with count_below >= target
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(a, b, mid) >= target) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ndmg_contraction(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, double* contraction,
+                     double* lam_max, int* iters) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!contraction) return fail(NDMG_EINVAL, "null output");
+  const Plan& pl = c->plan;
+  if (pl.npairs != 1) return fail(NDMG_EINVAL, "the contraction needs a context with one right-hand side");
+  if (pl.opts.precision != NDMG_PREC_FP64 || flexible_beta(pl))
+    return fail(NDMG_EINVAL, "the contraction needs the FP64 V-cycle and the standard CG beta");
+  if (maxit < 1 || maxit > ndmg::kHistCap) return fail(NDMG_EINVAL, "maxit must be in [1, 512]");
+  int it = 0;
+  double rel = 0.0;
+  const int rc = ndmg_pcg_solve_batched(c, b, u, rtol, maxit, &it, &rel);
+  if (rc != NDMG_OK && rc != NDMG_ENOCONV && rc != NDMG_EBREAKDOWN) return rc;
+  const Cls& C = pl.cls[0];
+  const int k = std::min(it, ndmg::kHistCap);
+  if (k < 1) return fail(NDMG_EINVAL, "no CG iteration ran (zero right-hand side?)");
+  std::vector<double> h((size_t)2 * k);
+  NDMG_HIP(hipMemcpy(h.data(), at<double>(c, C.o_hist), h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // CG with preconditioner B is the Lanczos process for B A: alpha_j = r_j.z_j / p_j.A p_j,
+  // beta_j = r_{j+1}.z_{j+1} / r_j.z_j give its tridiagonal matrix T with diagonal
+  // 1/alpha_j + beta_{j-1}/alpha_{j-1} and off-diagonal sqrt(beta_j)/alpha_j.  The process
+  // is scale-free, so CG may run past the convergence of u; the matrix ends at a breakdown
+  // (scalars not finite and positive) or once r.z has fallen below 1e-200 of its first
+  // value, before the products of the shrinking vectors reach the subnormal range.
+  std::vector<double> alpha, beta;
+  const double rz0 = h[0];
+  auto usable = [&](int j) {
+    const double rz = h[2 * j], pq = h[2 * j + 1];
+    return rz > 0.0 && pq > 0.0 && std::isfinite(rz) && std::isfinite(pq) && rz >= 1e-200 * rz0 &&
+           pq >= 1e-200 * h[1];
+  };
+  for (int j = 0; j < k && usable(j); ++j) {
+    alpha.push_back(h[2 * j] / h[2 * j + 1]);
+    if (j + 1 < k && usable(j + 1)) beta.push_back(h[2 * j + 2] / h[2 * j]);
+  }
+  const size_t m = alpha.size();
+  if (m < 1) return fail(NDMG_EBREAKDOWN, "no usable CG iteration");
+  std::vector<double> d(m), e(m > 1 ? m - 1 : 0);
+  for (size_t j = 0; j < m; ++j) d[j] = 1.0 / alpha[j] + (j ? beta[j - 1] / alpha[j - 1] : 0.0);
+  for (size_t j = 0; j + 1 < m; ++j) e[j] = std::sqrt(beta[j]) / alpha[j];
+  *contraction = 1.0 - tridiag_extreme(d, e, 0);
+  if (lam_max) *lam_max = tridiag_extreme(d, e, 1);
+  if (iters) *iters = (int)m;
+  return NDMG_OK;
 }
 
 int ndmg_assemble_rhs(ndmg_ctx* c, const double* f, double* b) {

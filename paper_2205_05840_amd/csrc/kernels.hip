@@ -1597,7 +1597,7 @@ __global__ void __launch_bounds__(1024) k_pcg_check(double* __restrict__ scal, i
                                                     int* __restrict__ iters, int* __restrict__ status,
                                                     int count, int i_rz, int* __restrict__ nact,
                                                     const double* __restrict__ rr_part, int rr_n,
-                                                    int64_t pstride) {
+                                                    int64_t pstride, double* __restrict__ hist) {
   __shared__ int sh[16];
   __shared__ double shd[17];
   // r . r of each active pair from the update's partials: the block together for few
@@ -1621,8 +1621,12 @@ __global__ void __launch_bounds__(1024) k_pcg_check(double* __restrict__ scal, i
   for (int p = threadIdx.x; p < count; p += blockDim.x) {
     if (act[p] == 0) continue;
     double* s = scal + (int64_t)p * kScalStride;
-    iters[p] += 1;
     const double pq = s[kS_PQ], rr = s[kS_RR], rz = s[i_rz];
+    if (iters[p] < kHistCap) {   // (r . z, p . A p) of this iteration: the Lanczos coefficients of CG
+      hist[((int64_t)p * kHistCap + iters[p]) * 2] = rz;
+      hist[((int64_t)p * kHistCap + iters[p]) * 2 + 1] = pq;
+    }
+    iters[p] += 1;
     const double rel = sqrt(rr) / sqrt(s[kS_BB]);
     s[kS_REL] = rel;
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz)) {
@@ -1982,9 +1986,10 @@ hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int 
 }
 
 hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
-                            int* nact, const double* rr_part, int rr_n, int64_t pstride, hipStream_t st) {
+                            int* nact, const double* rr_part, int rr_n, int64_t pstride, double* hist,
+                            hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1024), 0, st, scal, act, iters, status, count, i_rz,
-                     nact, rr_part, rr_n, pstride);
+                     nact, rr_part, rr_n, pstride, hist);
   return hipGetLastError();
 }
 

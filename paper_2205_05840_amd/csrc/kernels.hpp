@@ -279,10 +279,13 @@ hipError_t launch_cg_direction(double* p, const TZ* z, double* scal, int i_num, 
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
                            hipStream_t st);
 // End of an iteration, per active pair: s[kS_RR] = sum of the update's rr_n partials;
-// iters += 1; broken if s[kS_PQ] <= 0 or a scalar is not finite; done if ||r|| / ||b|| <=
-// rtol (s[kS_REL] = that ratio).  *nact = pairs still active.
+// (s[i_rz], s[kS_PQ]) recorded at hist[pair][iters] while iters < kHistCap; iters += 1;
+// broken if s[kS_PQ] <= 0 or a scalar is not finite; done if ||r|| / ||b|| <= rtol
+// (s[kS_REL] = that ratio).  *nact = pairs still active.
+constexpr int kHistCap = 512;
 hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int count, int i_rz,
-                            int* nact, const double* rr_part, int rr_n, int64_t pstride, hipStream_t st);
+                            int* nact, const double* rr_part, int rr_n, int64_t pstride, double* hist,
+                            hipStream_t st);
 hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, hipStream_t st);
 hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st);
 

@@ -157,6 +157,12 @@ class Solver(_Context):
                                   maxit, self.nrhs, raise_on_noconv)
         return u, it, rel
 
+    def contraction(self, b, rtol=1e-13, maxit=200):
+        """V-cycle contraction number ||E||_a = 1 - lambda_min(B A) by the Lanczos process of
+        preconditioned CG started from b; returns (contraction, lambda_max(B A), steps)."""
+        u = self.zeros()
+        return self._run(_lib.ndmg_contraction, self._check(b), self._check(u), rtol, maxit)
+
     def assemble_rhs(self, f):
         """b from f sampled at the 2x2x2 Gauss points ([n^3, 8, 3] float64)."""
         f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()

@@ -1,0 +1,131 @@
+"""Tables 1-2 of Sec. 5 on the GPU: V-cycle contraction numbers ||E_k||_a on Omega =
+(-1, 1)^3 with (2^(k+1))^3 elements, k = 1..4, m = 1..5 smoothing steps, five alpha.
+
+The library estimates ||E_k||_a = 1 - lambda_min(B A) (E_k is a-symmetric positive
+semidefinite, Sec. 4.2) from the Lanczos matrix of its V-cycle-preconditioned CG
+(ndmg_contraction).  Pins:
+* vertex smoother (Table 2), k = 1: exactly (8/9)^(2m) (one vertex patch and the 8
+  interiors split N_1 a-orthogonally, so M^{-1} = eta A^{-1});
+* vertex smoother, k = 2 and 3: the oracle's contraction numbers (dense eigensolve of the
+  oracle's V-cycle at k = 2, Lanczos with exact inner solves at k = 3) to 1e-6;
+* vertex smoother, every k, m, alpha: Table 2's printed values within 1.5 % (the
+  oracle's own distance at k = 2, where its dense eigensolve is exact, reaches 1.3 %:
+  the paper's digits scatter between levels, e.g. 0.312 at k = 2 and 0.308 at k = 3 for
+  alpha = 0.01, m = 5), never below the bubble bound (8/9)^(2m);
+* edge smoother (Table 1, eta_E = 1/13): the oracle's dense values at k = 1, 2 to 1e-6, and
+  never below its bubble bound (12/13)^(2m) at any k.  Table 1's printed values are
+  context only (the method as written cannot reach several of them: A15 of the readings).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from layout import to_padded
+from oracle import contraction, mesh, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALPHAS = (0.01, 0.1, 1.0, 10.0, 100.0)
+
+
+def _table(name):
+    rows = {}
+    with open(os.path.join(HERE, "golden", name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            rows[(float(v[0]), int(v[1]))] = [float(x) for x in v[2:]]
+    return rows
+
+
+TABLE2 = _table("table2_vertex.txt")
+TABLE1 = _table("table1_edge.txt")
+
+
+def _gpu_contraction(k, alpha, m, smoother="vertex", seed=0):
+    from paper_2205_05840_amd import Solver
+    n = 2 ** (k + 1)
+    S = Solver(n, alpha, length=2.0, m=m, smoother=smoother)
+    b = np.random.default_rng(seed).standard_normal(mesh.ndof(n))
+    # CG continued past convergence (rtol 0): the extreme eigenvalue sits next to the large
+    # bubble cluster and needs about 60 Lanczos steps (vertex), more for the edge smoother
+    c, lam_max, steps = S.contraction(torch.from_numpy(to_padded(n, S.P, S.B, b)).cuda(), rtol=0.0,
+                                      maxit=250 if smoother == "vertex" else 400)
+    S.close()
+    return c, lam_max, steps
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_table2_k1_exact(alpha):
+    print(f"[case] contraction k=1 alpha={alpha}", flush=True)
+    for m in range(1, 6):
+        c, lam_max, steps = _gpu_contraction(1, alpha, m)
+        assert abs(c - (8.0 / 9.0) ** (2 * m)) <= 1e-9, (m, c)
+        assert lam_max <= 1.0 + 1e-9
+        assert round(c, 3) == TABLE2[(alpha, 1)][m - 1]
+
+
+@pytest.mark.parametrize("alpha,m", [(0.01, 1), (1.0, 1), (1.0, 5), (100.0, 5)])
+def test_table2_k2_against_oracle(alpha, m):
+    print(f"[case] contraction k=2 alpha={alpha} m={m}", flush=True)
+    c, _, _ = _gpu_contraction(2, alpha, m)
+    c_o, _ = contraction.contraction_dense(vcycle.Hierarchy(8, alpha, L=2.0, m=m))
+    print(f"k=2 alpha={alpha} m={m}: GPU {c:.7f}, oracle {c_o:.7f}")
+    assert abs(c - c_o) <= 1e-6
+
+
+def test_table2_k3_against_oracle():
+    print("[case] contraction k=3 alpha=0.01 m=1", flush=True)
+    c, _, _ = _gpu_contraction(3, 0.01, 1)
+    c_o = contraction.contraction_lanczos(vcycle.Hierarchy(16, 0.01, L=2.0, m=1))
+    print(f"k=3: GPU {c:.7f}, oracle {c_o:.7f}")
+    assert abs(c - c_o) <= 1e-6
+
+
+def test_table2_all():
+    """The whole of Table 2 on the GPU (k = 1..4)."""
+    print("[case] Table 2 on the GPU", flush=True)
+    worst = 0.0
+    for alpha in ALPHAS:
+        for k in range(1, 5):
+            res = [_gpu_contraction(k, alpha, m) for m in range(1, 6)]
+            row = [r[0] for r in res]
+            print(f"alpha={alpha:6g} k={k}: " + " ".join(f"{c:.4f}" for c in row)
+                  + "   (Table 2: " + " ".join(f"{c:.3f}" for c in TABLE2[(alpha, k)]) + ")  steps "
+                  + " ".join(str(r[2]) for r in res), flush=True)
+            for m, c in enumerate(row, 1):
+                ref = TABLE2[(alpha, k)][m - 1]
+                assert c >= (8.0 / 9.0) ** (2 * m) - 1e-6, (alpha, k, m, c)
+                worst = max(worst, abs(c - ref) / ref)
+    print(f"largest relative distance from Table 2: {worst:.4f}")
+    assert worst <= 0.015
+
+
+@pytest.mark.parametrize("k,alpha,m", [(1, 1.0, 1), (1, 0.01, 3), (2, 1.0, 1), (2, 100.0, 2)])
+def test_table1_edge_against_oracle(k, alpha, m):
+    print(f"[case] edge contraction k={k} alpha={alpha} m={m}", flush=True)
+    c, _, _ = _gpu_contraction(k, alpha, m, smoother="edge")
+    H = vcycle.Hierarchy(2 ** (k + 1), alpha, L=2.0, m=m, kind="edge")
+    c_o, _ = contraction.contraction_dense(H)
+    print(f"edge k={k} alpha={alpha} m={m}: GPU {c:.7f}, oracle {c_o:.7f}")
+    assert abs(c - c_o) <= 1e-6
+    assert c >= (12.0 / 13.0) ** (2 * m) - 1e-6
+
+
+def test_table1_all():
+    """The whole of Table 1 (edge smoother) on the GPU, printed next to the paper's values
+    (context only); every entry at or above the bubble bound (12/13)^(2m)."""
+    print("[case] Table 1 on the GPU", flush=True)
+    for alpha in ALPHAS:
+        for k in range(1, 5):
+            res = [_gpu_contraction(k, alpha, m, smoother="edge") for m in range(1, 6)]
+            row = [r[0] for r in res]
+            print(f"alpha={alpha:6g} k={k}: " + " ".join(f"{c:.4f}" for c in row)
+                  + "   (Table 1: " + " ".join(f"{c:.3f}" for c in TABLE1[(alpha, k)]) + ")  steps "
+                  + " ".join(str(r[2]) for r in res), flush=True)
+            for m, c in enumerate(row, 1):
+                assert c >= (12.0 / 13.0) ** (2 * m) - 1e-6, (alpha, k, m, c)
