@@ -194,6 +194,32 @@ int ndmg_vcycle(ndmg_ctx* ctx, const double* d_g, double* d_z);
 int ndmg_pcg_solve(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
                    int* iters, double* relres);
 
+/* As ndmg_pcg_solve_batched, but every pair starts from the vector the caller put in d_u
+ * (its non-unknown entries must be 0): r_0 = b - A u_0, and the stopping test is still
+ * ||b - A u|| <= rtol ||b||.  For sequences of related right-hand sides (time stepping):
+ * a good initial guess saves iterations.  Errors: as ndmg_pcg_solve_batched. */
+int ndmg_pcg_solve_warm(ndmg_ctx* ctx, const double* d_b, double* d_u, double rtol, int maxit,
+                        int* iters, double* relres);
+
+/* One implicit time step of Maxwell's equations (Sec. 1): with H eliminated, the electric
+ * field solves eps E'' + sigma E' + curl(mu^{-1} curl E) = J' (all coefficients constant).
+ * The average-acceleration Newmark scheme (beta = 1/4, gamma = 1/2; the trapezoidal rule,
+ * which conserves the discrete energy when sigma = 0) asks in each step for
+ *   (dt^2 / 4) curl(mu^{-1} curl E_{n+1}) + (eps + sigma dt / 2) E_{n+1} = R.H.S.,
+ * the equation of eq. (Maxwell timestep), i.e. the model problem with alpha =
+ * dt^2 / (4 mu (eps + sigma dt / 2)), which must be the context's alpha (relative 1e-12).
+ * In the discrete setting (M the mass matrix, K the curl-curl matrix, padded layout):
+ *   w = u + dt v + dt^2/4 a                                  (predictor)
+ *   A u' = (dt^2/4 f + M (eps w + sigma (dt/2 u + dt^2/4 v))) / (eps + sigma dt/2)
+ *   a' = 4 / dt^2 (u' - w),   v' = v + dt/2 (a + a')
+ * with f = (J', phi_e) the load vector of the current's time derivative at the new time,
+ * and the solve by V-cycle PCG started from w (ndmg_pcg_solve_warm; rtol and maxit as
+ * there).  d_u, d_v, d_a (field, its rate and its second rate) are updated in place; every
+ * (problem, right-hand side) pair of a single-size context steps at once.  Waits for the
+ * step before returning.  Errors: NDMG_EINVAL, NDMG_EHIP, NDMG_ENOCONV, NDMG_EBREAKDOWN. */
+int ndmg_maxwell_step(ndmg_ctx* ctx, const double* d_f, double* d_u, double* d_v, double* d_a, double dt,
+                      double eps, double sigma, double mu, double rtol, int maxit, int* iters, double* relres);
+
 /* Contraction number ||E_J||_a of the V-cycle (Sec. 4.2: E = I - B A with B = MG(J, ., 0,
  * m) is a-symmetric positive semidefinite, so ||E||_a = 1 - lambda_min(B A); the quantity
  * of Sec. 5, Tables 1-2), estimated by the Lanczos process of V-cycle-preconditioned CG:

@@ -22,7 +22,7 @@ EXPORTED = [
     "ndmg_vcycle", "ndmg_pcg_solve", "ndmg_assemble_rhs", "ndmg_curlcurl_form",
     "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
     "ndmg_plan_batched", "ndmg_setup_batched", "ndmg_batch_layout", "ndmg_pcg_solve_batched",
-    "ndmg_curlcurl_form_noalloc", "ndmg_contraction",
+    "ndmg_curlcurl_form_noalloc", "ndmg_contraction", "ndmg_pcg_solve_warm", "ndmg_maxwell_step",
 ]
 
 NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE, NDMG_OP_PATCH = range(6)
@@ -75,6 +75,8 @@ def lib():
     L.ndmg_curlcurl_form.argtypes = [vp, vp, vp, i, P(d)]
     L.ndmg_curlcurl_form_noalloc.argtypes = [i, d, vp, vp, i, P(d), vp]
     L.ndmg_contraction.argtypes = [vp, vp, vp, d, i, P(d), P(d), P(i)]
+    L.ndmg_pcg_solve_warm.argtypes = [vp, vp, vp, d, i, P(i), P(d)]
+    L.ndmg_maxwell_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, d, i, P(i), P(d)]
     L.ndmg_export_factor.argtypes = [vp, i, i, i, P(d), P(i)]
     L.ndmg_level_op.argtypes = [vp, i, i, vp, vp]
     L.ndmg_plan_batched.argtypes = [i, P(i), d, i, P(ndmg_opts), P(sz), P(sz)]
@@ -153,6 +155,22 @@ def ndmg_contraction(ctx, d_b, d_u, rtol, maxit):
     c, lm, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
     check(lib().ndmg_contraction(ctx, d_b, d_u, rtol, maxit, ctypes.byref(c), ctypes.byref(lm), ctypes.byref(it)))
     return c.value, lm.value, it.value
+
+
+def ndmg_pcg_solve_warm(ctx, d_b, d_u, rtol, maxit, npairs, raise_on_noconv=True):
+    it = (ctypes.c_int * npairs)()
+    rel = (ctypes.c_double * npairs)()
+    code = lib().ndmg_pcg_solve_warm(ctx, d_b, d_u, rtol, maxit, it, rel)
+    if code != NDMG_OK and (raise_on_noconv or code != NDMG_ENOCONV):
+        check(code)
+    return code, list(it), list(rel)
+
+
+def ndmg_maxwell_step(ctx, d_f, d_u, d_v, d_a, dt, eps, sigma, mu, rtol, maxit, npairs):
+    it = (ctypes.c_int * npairs)()
+    rel = (ctypes.c_double * npairs)()
+    check(lib().ndmg_maxwell_step(ctx, d_f, d_u, d_v, d_a, dt, eps, sigma, mu, rtol, maxit, it, rel))
+    return list(it), list(rel)
 
 
 def ndmg_plan_batched(ns, length, nrhs, opts):

@@ -99,6 +99,8 @@ struct Cls {
   size_t o_pr = 0, o_pz = 0, o_pp = 0, o_pq = 0, o_part = 0, o_scal = 0;
   size_t o_alpha = 0, o_act = 0, o_iters = 0, o_status = 0;
   size_t o_hist = 0;               // per pair: (r . z, p . A p) of the first kHistCap iterations
+  size_t o_tw = 0, o_tb = 0;       // time stepping: predictor and right-hand side (FP64, per pair)
+  size_t o_alpha0 = 0;             // zeros: alpha = 0 turns the operator into the mass matrix
 };
 
 struct Plan {
@@ -366,6 +368,10 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   C.o_iters = take(cnt * sizeof(int));
   C.o_status = take(cnt * sizeof(int));
   C.o_hist = take(cnt * (size_t)ndmg::kHistCap * 2 * sizeof(double));
+  // time stepping: the predictor and the right-hand side of a step; alpha = 0 for the mass
+  C.o_tw = take(v8);
+  C.o_tb = take(v8);
+  C.o_alpha0 = take(np * sizeof(double));
   return NDMG_OK;
 }
 
@@ -936,7 +942,7 @@ int pcg_check(ndmg_ctx* c, size_t ci, int i_rz, int set, hipStream_t st) {
 
 // Start of a solve for one class: r = b, u = 0, b . b, per-pair state, z = B r,
 // s[cur] = r . z, p = z and the first update.
-int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol, hipStream_t st) {
+int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol, hipStream_t st, bool warm) {
   Cls& C = c->plan.cls[ci];
   const int64_t len = C.vlen;
   double* r = at<double>(c, C.o_pr);
@@ -946,8 +952,12 @@ int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol
   const int64_t ps = part_stride(C);
   double* sc = at<double>(c, C.o_scal);
   const ndmg::Bat all = class_batch(c, C, false), act = class_batch(c, C, true);
-  NDMG_HIP(ndmg::launch_copy(b, r, len, all, st));
-  NDMG_HIP(ndmg::launch_zero(u, len, all, st));
+  if (warm) {   // r = b - A u from the caller's u
+    NDMG_HIP(ndmg::launch_apply<double>(u, b, r, C.lv.back().g, all, 1, st));
+  } else {
+    NDMG_HIP(ndmg::launch_copy(b, r, len, all, st));
+    NDMG_HIP(ndmg::launch_zero(u, len, all, st));
+  }
   NDMG_HIP(ndmg::launch_dot<double>(b, b, nullptr, part, ps, sc + kS_BB, len, all, st));
   NDMG_HIP(ndmg::launch_pcg_init(sc, at<int>(c, C.o_act), at<int>(c, C.o_iters), at<int>(c, C.o_status),
                                  C.count, rtol, st));
@@ -1077,11 +1087,11 @@ int active_pairs(ndmg_ctx* c, int set, int* out) {
 
 // Whole PCG over all pairs; per-pair results in problem order (p * nrhs + rhs).
 int pcg_all(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int* iters,
-            double* relres) {
+            double* relres, bool warm = false) {
   Plan& pl = c->plan;
   NDMG_TRY(for_classes(c, [&](size_t ci, hipStream_t st) {
     const Cls& C = pl.cls[ci];
-    return pcg_prologue(c, ci, b + C.vec_off, u + C.vec_off, rtol, st);
+    return pcg_prologue(c, ci, b + C.vec_off, u + C.vec_off, rtol, st, warm);
   }));
   // Iteration it is enqueued before the host reads the count after iteration it - 1, so
   // the device never waits for the host; when that count is zero, iteration it runs with
@@ -1368,8 +1378,12 @@ int ndmg_pcg_solve(ndmg_ctx* c, const double* b, double* u, double rtol, int max
   return ndmg_pcg_solve_batched(c, b, u, rtol, maxit, iters, relres);
 }
 
-int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit,
-                           int* iters, double* relres) {
+}  // extern "C"
+
+namespace {
+
+int pcg_entry(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int* iters, double* relres,
+              bool warm) {
   if (int rc = check_ctx(c)) return rc;
   if (!b || !u) return fail(NDMG_EINVAL, "null vector");
   if (reinterpret_cast<uintptr_t>(b) % 16 || reinterpret_cast<uintptr_t>(u) % 16)
@@ -1378,7 +1392,63 @@ int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol,
   const int np = c->plan.npairs;
   if (iters) std::fill(iters, iters + np, 0);
   if (relres) std::fill(relres, relres + np, 0.0);
-  return pcg_all(c, b, u, rtol, maxit, iters, relres);
+  return pcg_all(c, b, u, rtol, maxit, iters, relres, warm);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ndmg_pcg_solve_batched(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit,
+                           int* iters, double* relres) {
+  return pcg_entry(c, b, u, rtol, maxit, iters, relres, false);
+}
+
+int ndmg_pcg_solve_warm(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int* iters,
+                        double* relres) {
+  return pcg_entry(c, b, u, rtol, maxit, iters, relres, true);
+}
+
+int ndmg_maxwell_step(ndmg_ctx* c, const double* f, double* u, double* v, double* a, double dt, double eps,
+                      double sigma, double mu, double rtol, int maxit, int* iters, double* relres) {
+  if (int rc = check_ctx(c)) return rc;
+  if (int rc = one_class(c)) return rc;
+  if (!f || !u || !v || !a) return fail(NDMG_EINVAL, "null vector");
+  if (!(dt > 0.0) || !(eps >= 0.0) || !(sigma >= 0.0) || !(mu > 0.0) || !(eps + 0.5 * sigma * dt > 0.0) ||
+      !std::isfinite(dt) || !std::isfinite(eps) || !std::isfinite(sigma) || !std::isfinite(mu))
+    return fail(NDMG_EINVAL, "need dt > 0, mu > 0, eps >= 0, sigma >= 0 and eps + sigma dt / 2 > 0");
+  Cls& C = c->plan.cls[0];
+  const double d = eps + 0.5 * sigma * dt;
+  const double want = dt * dt / (4.0 * mu * d);
+  for (double al : C.alpha)
+    if (std::fabs(al - want) > 1e-12 * want)
+      return fail(NDMG_EINVAL, "the context's alpha must be dt^2 / (4 mu (eps + sigma dt / 2)) = " +
+                                   std::to_string(want));
+  const ndmg::Geom& g = C.lv.back().g;
+  const int64_t len = g.len;
+  const ndmg::Bat all = class_batch(c, C, false);
+  const ndmg::Bat mass{C.count, C.nrhs, at<double>(c, C.o_alpha0), nullptr};
+  double* w = at<double>(c, C.o_tw);
+  double* rhs = at<double>(c, C.o_tb);
+  double* t = at<double>(c, C.o_pz);   // CG vectors, free outside the solve
+  hipStream_t st = c->st;
+  const double h2 = 0.25 * dt * dt;
+  // predictor w = u + dt v + dt^2/4 a
+  NDMG_HIP(ndmg::launch_lincomb(w, u, 1.0, v, dt, a, h2, len, all, st));
+  // rhs = (dt^2/4 f + M (eps w + sigma (dt/2 u + dt^2/4 v))) / (eps + sigma dt/2)
+  NDMG_HIP(ndmg::launch_lincomb(t, w, eps, u, sigma * 0.5 * dt, v, sigma * h2, len, all, st));
+  NDMG_HIP(ndmg::launch_apply<double>(t, nullptr, rhs, g, mass, 0, st));
+  NDMG_HIP(ndmg::launch_lincomb(rhs, rhs, 1.0 / d, f, h2 / d, nullptr, 0.0, len, all, st));
+  // u_{n+1}: the model problem with alpha = dt^2 / (4 mu d), started from the predictor
+  NDMG_HIP(ndmg::launch_copy(w, u, len, all, st));
+  const int rc = pcg_entry(c, rhs, u, rtol, maxit, iters, relres, true);
+  if (rc != NDMG_OK) return rc;
+  // a_{n+1} = 4 / dt^2 (u_{n+1} - w);  v_{n+1} = v_n + dt/2 (a_n + a_{n+1})
+  NDMG_HIP(ndmg::launch_lincomb(t, u, 1.0 / h2, w, -1.0 / h2, nullptr, 0.0, len, all, st));
+  NDMG_HIP(ndmg::launch_lincomb(v, v, 1.0, a, 0.5 * dt, t, 0.5 * dt, len, all, st));
+  NDMG_HIP(ndmg::launch_copy(t, a, len, all, st));
+  NDMG_HIP(hipStreamSynchronize(st));
+  return NDMG_OK;
 }
 
 }  // extern "C"

@@ -1670,6 +1670,21 @@ __global__ void k_zero(double* __restrict__ y, int64_t len, Bat bt) {
     y[e] = 0.0;
 }
 
+// y = c0 x0 + c1 x1 + c2 x2 per entry (x1, x2 may be null; y may alias any x)
+__global__ void k_lincomb(double* y, const double* x0, double c0, const double* x1, double c1, const double* x2,
+                          double c2, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  const int64_t off = (int64_t)pair * len;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = c0 * x0[off + e];
+    if (x1) v += c1 * x1[off + e];
+    if (x2) v += c2 * x2[off + e];
+    y[off + e] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // load vector from 2x2x2 Gauss samples
 // ---------------------------------------------------------------------------------
@@ -2002,6 +2017,13 @@ hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, h
 hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0, st, y,
                      len, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* y, const double* x0, double c0, const double* x1, double c1, const double* x2,
+                          double c2, int64_t len, const Bat& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0, st, y, x0,
+                     c0, x1, c1, x2, c2, len, bt);
   return hipGetLastError();
 }
 

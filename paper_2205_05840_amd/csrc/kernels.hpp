@@ -288,6 +288,9 @@ hipError_t launch_pcg_check(double* scal, int* act, int* iters, int* status, int
                             hipStream_t st);
 hipError_t launch_copy(const double* x, double* y, int64_t len, const Bat& bt, hipStream_t st);
 hipError_t launch_zero(double* y, int64_t len, const Bat& bt, hipStream_t st);
+// y = c0 x0 + c1 x1 + c2 x2 entrywise for every pair (x1, x2 may be null; y may alias them)
+hipError_t launch_lincomb(double* y, const double* x0, double c0, const double* x1, double c1, const double* x2,
+                          double c2, int64_t len, const Bat& bt, hipStream_t st);
 
 // b = load vector of f sampled at the 2x2x2 Gauss points (single problem).
 hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st);

@@ -145,10 +145,15 @@ class Solver(_Context):
         self._run(_lib.ndmg_vcycle, self._check(g), self._check(z))
         return z
 
-    def solve(self, b, rtol=1e-10, maxit=500, u=None, raise_on_noconv=True):
+    def solve(self, b, rtol=1e-10, maxit=500, u=None, raise_on_noconv=True, warm=False):
         """u = A^{-1} b by V-cycle PCG; returns (u, iterations, relative residual), the
-        last two as lists over the right-hand sides when nrhs > 1."""
+        last two as lists over the right-hand sides when nrhs > 1.  warm: start from the
+        values in u instead of 0."""
         u = self.zeros() if u is None else u
+        if warm:
+            code, it, rel = self._run(_lib.ndmg_pcg_solve_warm, self._check(b), self._check(u), rtol, maxit,
+                                      self.nrhs, raise_on_noconv)
+            return (u, it[0], rel[0]) if self.nrhs == 1 else (u, it, rel)
         if self.nrhs == 1:
             code, it, rel = self._run(_lib.ndmg_pcg_solve, self._check(b), self._check(u), rtol,
                                       maxit, raise_on_noconv)
@@ -156,6 +161,14 @@ class Solver(_Context):
         code, it, rel = self._run(_lib.ndmg_pcg_solve_batched, self._check(b), self._check(u), rtol,
                                   maxit, self.nrhs, raise_on_noconv)
         return u, it, rel
+
+    def maxwell_step(self, f, u, v, a, dt, eps=1.0, sigma=0.0, mu=1.0, rtol=1e-10, maxit=500):
+        """One average-acceleration Newmark step of eps E'' + sigma E' + curl(mu^-1 curl E) = J'
+        (each step is the model problem with this solver's alpha = dt^2 / (4 mu (eps +
+        sigma dt / 2)), eq. Maxwell timestep); u, v, a updated in place; f = (J', phi) at the
+        new time.  Returns (iterations, relative residuals) per right-hand side."""
+        return self._run(_lib.ndmg_maxwell_step, self._check(f), self._check(u), self._check(v), self._check(a),
+                         dt, eps, sigma, mu, rtol, maxit, self.nrhs)
 
     def contraction(self, b, rtol=1e-13, maxit=200):
         """V-cycle contraction number ||E||_a = 1 - lambda_min(B A) by the Lanczos process of
