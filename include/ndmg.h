@@ -304,6 +304,43 @@ int ndmg_export_factor(const ndmg_ctx* ctx, int level, int which, int type, doub
 #define NDMG_OP_PATCH 5
 int ndmg_level_op(ndmg_ctx* ctx, int level, int op, const double* d_in, double* d_out);
 
+/* ---- launch shapes: the autotuner's table ------------------------------------------
+ * The plane-marching operator kernel (variant: waves per workgroup and ring depth; planes
+ * per workgroup) and the vertex patch products (16-vertex groups per wave, for the
+ * interior segment and for the segments on the box's faces and edges) take their launch
+ * shapes from a process-wide table when it holds an entry for (size n, precision, mode,
+ * class of pairs per launch: 1, 2-3, 4-15, 16-63, >= 64), else from a cost model.  The
+ * table is measured on the device by paper_2205_05840_amd/tune.py.  A context keeps the
+ * patch shapes of the table at its plan and setup; operator shapes are looked up per launch.
+ *
+ * ndmg_source_key: hash of the tuned kernels' sources, built into the library.
+ * ndmg_tuning_load: replace the table by a file: a line "key <source key>", then lines
+ *   "<stencil|patch> <n> <fp32|fp64> <mode> <pair class 0-4> <p0> <p1>" ('#' comments).
+ *   A file keyed to other sources (or malformed) is refused with NDMG_EINVAL and the table
+ *   is left as it was.
+ * ndmg_tuning_set: add or replace one entry (a line of that format, no key needed).
+ * ndmg_tuning_clear: empty the table (cost models everywhere).
+ * ndmg_time_stencil: average duration in microseconds of `reps` launches of the operator
+ *   kernel on an n^3 mesh with launch variant `variant` (0 .. count - 1 of the variants of
+ *   that precision and mode) and kz planes per workgroup, forced for these launches only,
+ *   on `count` caller vectors back to back (d_x, d_b for mode 1, d_y in the padded layout
+ *   of the precision; d_part room for the partial sums of mode 2; d_alpha `count` device
+ *   doubles), after 3 untimed launches, timed with HIP events on `stream`.  Launch r
+ *   works on vector set r mod nrot (set r starts r count vectors after d_x, d_b, d_y), so
+ *   that nrot sets larger than the last-level cache make every launch read HBM.
+ * ndmg_stencil_shape: the shape a launch of the operator kernel takes now (the table's
+ *   entry, or the cost model's choice).
+ * Errors: NDMG_EINVAL (a variant that does not exist: the tuner's end of the list),
+ * NDMG_EHIP. */
+const char* ndmg_source_key(void);
+int ndmg_tuning_load(const char* path);
+int ndmg_tuning_set(const char* line);
+int ndmg_tuning_clear(void);
+int ndmg_time_stencil(int n, int precision, int mode, int count, int variant, int kz, const void* d_x,
+                      const void* d_b, void* d_y, double* d_part, const double* d_alpha, int reps, int nrot,
+                      void* stream, double* avg_us);
+int ndmg_stencil_shape(int n, int precision, int mode, int count, int* variant, int* kz);
+
 /* Release the context (host memory only; the workspace stays the caller's). */
 int ndmg_destroy(ndmg_ctx* ctx);
 

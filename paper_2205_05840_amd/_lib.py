@@ -23,7 +23,13 @@ EXPORTED = [
     "ndmg_export_factor", "ndmg_level_op", "ndmg_destroy", "ndmg_last_error",
     "ndmg_plan_batched", "ndmg_setup_batched", "ndmg_batch_layout", "ndmg_pcg_solve_batched",
     "ndmg_curlcurl_form_noalloc", "ndmg_contraction", "ndmg_pcg_solve_warm", "ndmg_maxwell_step",
+    "ndmg_source_key", "ndmg_tuning_load", "ndmg_tuning_set", "ndmg_tuning_clear", "ndmg_time_stencil",
+    "ndmg_stencil_shape",
 ]
+
+# The autotuner's table of launch shapes (written by tune.py on the device); loaded with the
+# library when its key matches the library's kernel sources.
+TUNING_PATH = os.path.join(HERE, "tuning.txt")
 
 NDMG_OP_APPLY, NDMG_OP_SMOOTH, NDMG_OP_RESTRICT, NDMG_OP_PROLONG, NDMG_OP_COARSE, NDMG_OP_PATCH = range(6)
 
@@ -86,10 +92,20 @@ def lib():
     L.ndmg_destroy.argtypes = [vp]
     L.ndmg_last_error.argtypes = []
     L.ndmg_last_error.restype = ctypes.c_char_p
+    L.ndmg_source_key.argtypes = []
+    L.ndmg_source_key.restype = ctypes.c_char_p
+    L.ndmg_tuning_load.argtypes = [ctypes.c_char_p]
+    L.ndmg_tuning_set.argtypes = [ctypes.c_char_p]
+    L.ndmg_tuning_clear.argtypes = []
+    L.ndmg_time_stencil.argtypes = [i, i, i, i, i, i, vp, vp, vp, vp, vp, i, i, vp, P(d)]
+    L.ndmg_stencil_shape.argtypes = [i, i, i, i, P(i), P(i)]
     for name in EXPORTED:
-        if name not in ("ndmg_default_opts", "ndmg_last_error"):
+        if name not in ("ndmg_default_opts", "ndmg_last_error", "ndmg_source_key"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
+    if os.path.exists(TUNING_PATH) and L.ndmg_tuning_load(TUNING_PATH.encode()) != NDMG_OK:
+        import warnings
+        warnings.warn("launch-shape table not used: " + L.ndmg_last_error().decode())
     return L
 
 

@@ -21,6 +21,7 @@
 #include "../../include/ndmg.h"
 #include "generic.hpp"
 #include "kernels.hpp"
+#include "tuning.hpp"
 #include "ndmg_internal.hpp"
 
 namespace {
@@ -252,6 +253,10 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       int64_t groups = 0;
       for (const auto& sg : L.segs) groups += (sg.count + 15) / 16;
       L.gpw = ndmg::patch_groups(groups * C.count, el);
+      int tuned_i = 0, tuned_b = 0;
+      const bool tuned = ndmg::tune_lookup(ndmg::kTunePatch, sizes[k], (int)el, 0, C.count, &tuned_i, &tuned_b) &&
+                         tuned_i >= 1 && tuned_i <= 8 && tuned_b >= 1 && tuned_b <= 8;
+      if (tuned) L.gpw = tuned_i;
       // Boundary-type segments check every slot against the domain, so their groups cost
       // more: they get the fewest groups per wave that still let the whole grid be
       // resident at once (else as many as the interior), so that they do not finish last.
@@ -263,6 +268,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       int gpw_b = L.gpw;
       for (int gb = 1; gb < L.gpw; ++gb)
         if (nchunks_with(gb) <= ndmg::patch_resident_blocks(el)) { gpw_b = gb; break; }
+      if (tuned) gpw_b = tuned_b;
       for (size_t si = 0; si < L.segs.size(); ++si) {
         // and no more per wave than spreads a small segment over the 4 waves of one chunk
         const int gseg = (L.segs[si].count + 15) / 16;
@@ -358,7 +364,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   C.o_pq = take(v8);
   const int64_t cc_parts = (int64_t)((gf.n + 1 + 63) / 64) * (gf.n + 1) * (gf.n + 1);
   C.pstride = std::max<int64_t>(std::max<int64_t>(2 * ndmg::kRedBlocks, cc_parts),
-                                (int64_t)ndmg::stencil_blocks(gf, C.count));
+                                (int64_t)ndmg::stencil_max_blocks(gf));
   // three regions of partial sums per pair (dot, operator p^T A p, update r . r): each
   // is read by the kernel after its producer, so none overwrites another still unread
   C.o_part = take((size_t)3 * C.pstride * sizeof(double) * cnt);
@@ -1535,6 +1541,88 @@ int ndmg_contraction(ndmg_ctx* c, const double* b, double* u, double rtol, int m
   *contraction = 1.0 - tridiag_extreme(d, e, 0);
   if (lam_max) *lam_max = tridiag_extreme(d, e, 1);
   if (iters) *iters = (int)m;
+  return NDMG_OK;
+}
+
+const char* ndmg_source_key(void) { return ndmg::source_key(); }
+
+int ndmg_tuning_load(const char* path) {
+  if (!path) return fail(NDMG_EINVAL, "null path");
+  std::string err;
+  if (!ndmg::tune_load(path, &err)) return fail(NDMG_EINVAL, err);
+  return NDMG_OK;
+}
+
+int ndmg_tuning_set(const char* line) {
+  if (!line) return fail(NDMG_EINVAL, "null line");
+  std::string err;
+  if (!ndmg::tune_set_line(line, &err)) return fail(NDMG_EINVAL, err);
+  return NDMG_OK;
+}
+
+int ndmg_tuning_clear(void) {
+  ndmg::tune_clear();
+  return NDMG_OK;
+}
+
+int ndmg_stencil_shape(int n, int precision, int mode, int count, int* variant, int* kz) {
+  if (!variant || !kz) return fail(NDMG_EINVAL, "null pointer");
+  if (precision != NDMG_PREC_FP64 && precision != NDMG_PREC_FP32) return fail(NDMG_EINVAL, "bad precision");
+  if (n <= ndmg::stencil_min_n(count) || n > ndmg::stencil_max_n())
+    return fail(NDMG_EINVAL, "n outside the sizes of the plane-marching kernel");
+  if (!ndmg::stencil_shape(n, precision == NDMG_PREC_FP64 ? 8 : 4, mode, count, variant, kz))
+    return fail(NDMG_EINVAL, "no launch variant for this precision and mode");
+  return NDMG_OK;
+}
+
+int ndmg_time_stencil(int n, int precision, int mode, int count, int variant, int kz, const void* x,
+                      const void* b, void* y, double* part, const double* alpha, int reps, int nrot, void* stream,
+                      double* avg_us) {
+  if (!x || !y || !part || !alpha || !avg_us || (mode == 1 && !b)) return fail(NDMG_EINVAL, "null pointer");
+  if (nrot < 1) return fail(NDMG_EINVAL, "nrot must be >= 1");
+  if (precision != NDMG_PREC_FP64 && precision != NDMG_PREC_FP32) return fail(NDMG_EINVAL, "bad precision");
+  if (mode < 0 || mode > 2 || (mode == 2 && precision != NDMG_PREC_FP64)) return fail(NDMG_EINVAL, "bad mode");
+  if (count < 1 || reps < 1) return fail(NDMG_EINVAL, "bad count or reps");
+  if (n <= ndmg::stencil_min_n(count) || n > ndmg::stencil_max_n())
+    return fail(NDMG_EINVAL, "n outside the sizes of the plane-marching kernel");
+  const int elem = precision == NDMG_PREC_FP64 ? 8 : 4;
+  if (variant < 0 || variant >= ndmg::stencil_variant_count(elem, mode, n))
+    return fail(NDMG_EINVAL, "no such launch variant");
+  if (kz < 2 || kz > n) return fail(NDMG_EINVAL, "kz must be in [2, n]");
+  const ndmg::Geom g = ndmg::make_geom(n, 1.0);
+  const ndmg::Bat bt{count, count, alpha, nullptr};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t ps = ndmg::stencil_max_blocks(g);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NDMG_HIP(hipEventCreate(&e0));
+  NDMG_HIP(hipEventCreate(&e1));
+  // set r of the nrot rotating vector sets starts r count vectors after the first
+  const int64_t set = (int64_t)count * g.len * elem;
+  auto launch = [&](int r) -> hipError_t {
+    const int64_t o = (int64_t)(r % nrot) * set;
+    const char* xr = static_cast<const char*>(x) + o;
+    const char* br = b ? static_cast<const char*>(b) + o : nullptr;
+    char* yr = static_cast<char*>(y) + o;
+    if (elem == 8)
+      return ndmg::launch_stencil<double>((const double*)xr, (const double*)br, (double*)yr, g, bt, mode, part, ps,
+                                          nullptr, st);
+    return ndmg::launch_stencil<float>((const float*)xr, (const float*)br, (float*)yr, g, bt, mode, nullptr, 0,
+                                       nullptr, st);
+  };
+  ndmg::tune_force_stencil(variant, kz);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(r);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(r);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  ndmg::tune_force_stencil(-1, -1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(NDMG_EHIP, std::string("stencil timing: ") + hipGetErrorString(e));
+  *avg_us = 1e3 * ms / reps;
   return NDMG_OK;
 }
 

@@ -118,6 +118,11 @@ struct LevelPtrs {
 int stencil_max_n();
 int stencil_min_n(int count);   // the plane-marching kernel serves stencil_min_n(pairs) < n <= stencil_max_n()
 int stencil_blocks(const Geom& g, int count);   // partial sums per pair of the dot mode
+int stencil_max_blocks(const Geom& g);          // at most that many, whatever the launch shape
+int stencil_variant_count(int elem, int mode, int n);   // launch variants the tuner may choose from
+// the shape (variant index, planes per workgroup) a launch would take now (forced, tuned
+// or from the cost model)
+bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz);
 // groups of 16 vertices per wave in the patch kernel: more on large levels (fewer
 // S^{-1} stagings), one on small levels (more workgroups)
 // 16-vertex groups per wave of the patch kernel for a level with `groups` groups in all

@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "tuning.hpp"
 #include "reduce.hpp"
 
 namespace ndmg {
@@ -550,12 +551,24 @@ void variants(int mode, Variant (&vs)[3], int* nv) {
   }
 }
 
+// The shape of a launch: a shape forced by the tuner's timing calls, else the tuned
+// table's entry, else the cost model.
 template <typename T, int R>
 bool pick(int n, int count, int mode, int* which, int* kz, Variant* var) {
   Variant vs[3];
   int nv = 0;
   variants<T, R>(mode, vs, &nv);
   if (nv == 0) return false;
+  int w = -1, z = 0;
+  if (tune_forced_stencil(&w, &z) ||
+      tune_lookup(kTuneStencil, n, (int)sizeof(T), mode, count, &w, &z)) {
+    if (w >= 0 && w < nv && z >= 2 && z <= n) {
+      *which = w;
+      *kz = z;
+      *var = vs[w];
+      return true;
+    }
+  }
   int64_t best = INT64_MAX;
   for (int i = 0; i < nv; ++i) {
     const Choice c = choose_kz(n, count, vs[i]);
@@ -621,6 +634,36 @@ int stencil_blocks(const Geom& g, int count) {
   const bool ok = (g.n <= 128) ? pick<double, 2>(g.n, count, 2, &which, &kz, &var)
                                : pick<double, 4>(g.n, count, 2, &which, &kz, &var);
   return ok ? tiling(g.n, var.nw, kz).ntiles : 0;
+}
+
+// room for the partial sums of any launch shape (any variant, at least 2 planes per
+// workgroup): a tuned shape never overflows a buffer sized by it
+int stencil_max_blocks(const Geom& g) {
+  if (g.n > stencil_max_n()) return 0;
+  return tiling(g.n, 4, 2).ntiles;
+}
+
+bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz) {
+  Variant var{};
+  if (n <= 128) {
+    if (elem == 8) return pick<double, 2>(n, count, mode, variant, kz, &var);
+    return pick<float, 2>(n, count, mode, variant, kz, &var);
+  }
+  if (elem == 8) return pick<double, 4>(n, count, mode, variant, kz, &var);
+  return pick<float, 4>(n, count, mode, variant, kz, &var);
+}
+
+int stencil_variant_count(int elem, int mode, int n) {
+  Variant vs[3];
+  int nv = 0;
+  if (n <= 128) {
+    if (elem == 8) variants<double, 2>(mode, vs, &nv);
+    else variants<float, 2>(mode, vs, &nv);
+  } else {
+    if (elem == 8) variants<double, 4>(mode, vs, &nv);
+    else variants<float, 4>(mode, vs, &nv);
+  }
+  return nv;
 }
 
 template <typename T>

@@ -183,3 +183,40 @@ def test_plan_s4_needs_divisible_levels(lib):
     o.subdomain = 4
     with pytest.raises(lib.NdmgError):
         lib.ndmg_plan(10, 1.0, 1.0, o)       # 10 is not divisible by min(4, 10 / 2)
+
+
+def test_tuning_table(lib, tmp_path):
+    """The launch-shape table: entries set by line change the operator shape the library
+    picks; a file keyed to other kernel sources, or malformed, is refused and leaves the
+    table as it was; clearing brings back the cost model."""
+    L = lib.lib()
+    v, z = ctypes.c_int(), ctypes.c_int()
+    L.ndmg_tuning_clear()
+    assert L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z)) == 0
+    model = (v.value, z.value)
+    assert L.ndmg_tuning_set(b"stencil 96 fp64 0 0 1 12") == 0
+    assert L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z)) == 0
+    assert (v.value, z.value) == (1, 12)
+    # a variant that does not exist falls back to the model
+    assert L.ndmg_tuning_set(b"stencil 96 fp64 0 0 7 12") == 0
+    assert L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z)) == 0
+    assert (v.value, z.value) == model
+    key = L.ndmg_source_key().decode()
+    good = tmp_path / "good.txt"
+    good.write_text(f"# comment\nkey {key}\nstencil 96 fp64 0 0 2 16\n")
+    assert L.ndmg_tuning_load(str(good).encode()) == 0
+    L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z))
+    assert (v.value, z.value) == (2, 16)
+    stale = tmp_path / "stale.txt"
+    stale.write_text("key 0000000000000000\nstencil 96 fp64 0 0 0 4\n")
+    assert L.ndmg_tuning_load(str(stale).encode()) == lib.NDMG_EINVAL
+    assert b"other kernel sources" in L.ndmg_last_error()
+    L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z))
+    assert (v.value, z.value) == (2, 16)             # unchanged
+    assert L.ndmg_tuning_set(b"stencil 96 fp64") == lib.NDMG_EINVAL
+    assert L.ndmg_tuning_set(b"warp 96 fp64 0 0 1 1") == lib.NDMG_EINVAL
+    L.ndmg_tuning_clear()
+    L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z))
+    assert (v.value, z.value) == model
+    if os.path.exists(lib.TUNING_PATH):   # leave the process as the binding set it up
+        L.ndmg_tuning_load(lib.TUNING_PATH.encode())
