@@ -7,13 +7,15 @@ the setup done before the timed region.  The headline leg runs the V-cycle in FP
 inside FP64 flexible CG; the FP64 leg (V-cycle in FP64) is reported next to it, and
 both are repeated at alpha = 1e-3.
 
-Two more forms are measured next to the plain FP64 path and reported under "forms":
+More forms are measured next to the plain FP64 path and reported under "forms":
 batched (512 problems with n drawn from {8, 12, 16, 24, 32} and alpha log-uniform in
 [1e-2, 1e2], 4 right-hand sides each, FP32 V-cycle in FP64 CG, one batched solve per
-step; against single FP64 solves of a sample of the same problems) and differentiated
+step; against single FP64 solves of a sample of the same problems), differentiated
 (96^3, 16 right-hand sides, loss sum_k ||u_k - t_k||^2 with t_k the alpha = 2
 solutions, forward and adjoint solves plus dL/dalpha per step; against the same
-gradient through single-right-hand-side solves).
+gradient through single-right-hand-side solves), the 64^3 manufactured-field
+configuration (alpha 0.01, 1, 100; subdomains of 2 and 4 elements; the edge smoother at
+alpha = 1) and implicit Maxwell time stepping at 128^3 (steps per second).
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K, --warmup W,
 --no-cpu-baseline, --no-forms.
@@ -270,6 +272,58 @@ def diff_leg(torch, steps, warmup):
     return res
 
 
+def manufactured_leg(torch, steps):
+    """The 64^3 configuration: plain FP64 V-cycle PCG to 1e-10 for f = (2 pi^2 alpha + 1) u*
+    at the Gauss points plus N(0, 1e-6) noise (seed 1), alpha in {0.01, 1, 100}, subdomains
+    of 2 and of 4 elements; and the edge-based smoother (eta 1/13) on the same problem at
+    alpha = 1."""
+    from paper_2205_05840_amd import Solver, synth
+    n = 64
+    ndof = 3 * n * (n - 1) ** 2
+    out = {"n": n, "ndof": ndof, "precision": "fp64"}
+    cases = [(a, "vertex", s) for s in (2, 4) for a in (0.01, 1.0, 100.0)] + [(1.0, "edge", 2)]
+    for alpha, kind, sd in cases:
+        S = Solver(n, alpha, subdomain=sd, smoother=kind)
+        b = S.assemble_rhs(torch.from_numpy(synth.manufactured_samples(n, alpha, 1)))
+        u = S.zeros()
+        S.solve(b, rtol=RTOL, u=u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, it, rel = S.solve(b, rtol=RTOL, u=u)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        name = f"{kind}_s{sd}@alpha={alpha:g}"
+        out[name] = {"s_per_solve": t, "dof_per_s": ndof / t, "iters": it, "relres": rel}
+        log(f"64^3 {name}: {t * 1e3:.2f} ms/solve, {it} iterations")
+        del S, b, u
+    return out
+
+
+def timestep_leg(torch, nsteps=20):
+    """Implicit Maxwell time stepping at 128^3 (average-acceleration Newmark, eps = 1,
+    sigma = 1, mu = 1, dt = 0.01: each step the model problem with alpha = dt^2 / (4 (1 +
+    dt / 2))), FP32 V-cycle, solves to 1e-10 started from the predictor."""
+    from paper_2205_05840_amd import Solver, synth
+    n, dt, eps, sigma, mu = N_ELEM, 0.01, 1.0, 1.0, 1.0
+    alpha = dt * dt / (4 * mu * (eps + 0.5 * sigma * dt))
+    S = Solver(n, alpha, precision="fp32")
+    f = S.assemble_rhs(torch.from_numpy(synth.normal_samples(n, SEED)))
+    u, v, a = S.zeros(), S.zeros(), S.zeros()
+    S.maxwell_step(f, u, v, a, dt, eps, sigma, mu, rtol=RTOL)   # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(nsteps):
+        it, _ = S.maxwell_step(f, u, v, a, dt, eps, sigma, mu, rtol=RTOL)
+        iters.append(it[0])
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / nsteps
+    log(f"time stepping 128^3: {t * 1e3:.2f} ms per step, iterations {iters[0]} .. {iters[-1]}")
+    return {"n": n, "alpha": alpha, "dt": dt, "s_per_step": t, "steps_per_s": 1.0 / t,
+            "iters_first": iters[0], "iters_last": iters[-1], "iters_mean": sum(iters) / len(iters)}
+
+
 def cpu_baseline(f, iters_expected, gpu_solutions=None, sample_iters=3):
     """The FP64 CPU oracle (assembled sparse matrices, factored vertex smoother) on a
     bounded sample of the same 128^3 solve: setup untimed, then `sample_iters` PCG
@@ -463,7 +517,9 @@ def main():
     }
     if not args.no_forms:
         out["forms"] = {"batched": batched_leg(torch, max(1, args.steps // 2), 1),
-                        "differentiation": diff_leg(torch, 1, 1)}
+                        "differentiation": diff_leg(torch, 1, 1),
+                        "manufactured_64": manufactured_leg(torch, max(1, args.steps // 2)),
+                        "time_stepping": timestep_leg(torch)}
     if not args.no_cpu_baseline:
         host = {"fp32": sols[(1.0, "fp32")].cpu().numpy(), "fp64": sols[(1.0, "fp64")].cpu().numpy()}
         out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"], host)

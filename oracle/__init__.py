@@ -18,6 +18,7 @@ implementation of what the GPU library computes, written from the paper:
   * ``rhs``        load vector b = (f, phi_e) from samples at the 2x2x2 Gauss points
   * ``contraction`` V-cycle contraction number ||E_k||_a (Sec. 4.2, eq. VCycleRecursion)
   * ``adjoint``    gradients of L = sum_k ||u_k - t_k||^2 w.r.t. b_k and alpha
+  * ``coefficient`` alpha with jumps on a grid of boxes: cell-by-cell assembly (Sec. 6)
   * ``timestep``   implicit (average-acceleration Newmark) time stepping of Maxwell's
                    equations, each step the model problem (Sec. 1, eq. Maxwell timestep)
 

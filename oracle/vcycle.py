@@ -9,26 +9,35 @@ refined mesh (Sec. 3.1, eq. kthEq).
 import numpy as np
 import scipy.linalg as sla
 
-from . import assemble, mesh, smoother as sm, transfer
+from . import assemble, coefficient, mesh, smoother as sm, transfer
 
 
 class Hierarchy:
     """All levels of the V-cycle for n elements per axis on a cube of side L."""
 
     def __init__(self, n, alpha, L=1.0, s=2, m=1, kind="vertex", eta=None,
-                 factored=None, damp_interior=True, boundary=True, inverse="lu", levels=None):
+                 factored=None, damp_interior=True, boundary=True, inverse="lu", levels=None,
+                 boxes=None):
         """levels: keep only that many levels from the finest down (the coarsest kept
-        level is then solved exactly, k = 0 of Fig. 1); None keeps all of them."""
+        level is then solved exactly, k = 0 of Fig. 1); None keeps all of them.
+        boxes: alpha(x) = alpha * boxes[z][y][x] on an r x r x r grid of boxes (r divides
+        the coarsest kept level), every level assembled cell by cell
+        (``oracle.coefficient``) and smoothed by the literal smoother; None: constant."""
         self.sizes = mesh.level_sizes(n)          # coarsest first
         if levels is not None:
             if not 1 <= levels <= len(self.sizes):
                 raise ValueError("levels out of range")
             self.sizes = self.sizes[len(self.sizes) - levels:]
-        self.alpha, self.L, self.m = alpha, L, m
+        self.alpha, self.L, self.m, self.boxes = alpha, L, m, boxes
+        if boxes is not None and factored:
+            raise ValueError("the factored smoother assumes one alpha for every subdomain")
         self.A, self.M, self.P = [], [], [None]
         for k, nk in enumerate(self.sizes):
             h = L / nk
-            A = assemble.matrix_kron(nk, h, alpha)
+            if boxes is None:
+                A = assemble.matrix_kron(nk, h, alpha)
+            else:
+                A = coefficient.matrix_cells(nk, h, alpha * coefficient.cell_field(nk, boxes))
             self.A.append(A)
             if k == 0:
                 self.M.append(None)
@@ -37,7 +46,7 @@ class Hierarchy:
             sk = min(s, nk // 2)
             if nk % sk:
                 raise ValueError(f"level with {nk} elements is not divisible by {sk}")
-            use_f = factored if factored is not None else (nk >= 24)
+            use_f = (factored if factored is not None else (nk >= 24)) and boxes is None
             if kind == "vertex" and use_f and damp_interior:
                 e = 1.0 / 9.0 if eta is None else eta
                 self.M.append(sm.FactoredVertexSmoother(A, nk, sk, e, boundary, inverse))
