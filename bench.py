@@ -15,7 +15,8 @@ step; against single FP64 solves of a sample of the same problems), differentiat
 solutions, forward and adjoint solves plus dL/dalpha per step; against the same
 gradient through single-right-hand-side solves), the 64^3 manufactured-field
 configuration (alpha 0.01, 1, 100; subdomains of 2 and 4 elements; the edge smoother at
-alpha = 1) and implicit Maxwell time stepping at 128^3 (steps per second).
+alpha = 1), implicit Maxwell time stepping at 128^3 (steps per second) and a coefficient with
+jumps at 128^3 (alpha constant on each of 4^3 boxes, contrast up to 1e4).
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K, --warmup W,
 --no-cpu-baseline, --no-forms.
@@ -300,6 +301,34 @@ def manufactured_leg(torch, steps):
     return out
 
 
+def jumps_leg(torch, steps):
+    """Coefficient with jumps at 128^3: alpha = 10^U(-2, 2) on a 4 x 4 x 4 grid of boxes
+    (seed 3; contrast up to 1e4), six levels (coarsest 4^3, so that the boxes hold whole
+    coarse elements), FP32 V-cycle in FP64 CG to 1e-10; the per-cell operator kernel and the
+    gathered-product smoother on every level."""
+    import numpy as np
+    from paper_2205_05840_amd import Solver, synth
+    n = N_ELEM
+    boxes = 10.0 ** np.random.default_rng(3).uniform(-2.0, 2.0, size=(4, 4, 4))
+    t0 = time.perf_counter()
+    S = Solver(n, 1.0, precision="fp32", levels=6, coef=boxes)
+    t_setup = time.perf_counter() - t0
+    b = S.assemble_rhs(torch.from_numpy(synth.normal_samples(n, SEED)))
+    u = S.zeros()
+    S.solve(b, rtol=RTOL, u=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, it, rel = S.solve(b, rtol=RTOL, u=u)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    true_rel = float(torch.linalg.norm(b - S.apply(u)) / torch.linalg.norm(b))
+    ndof = 3 * n * (n - 1) ** 2
+    log(f"128^3 jumps (4^3 boxes): setup {t_setup:.2f} s, {t * 1e3:.2f} ms/solve, {it} iterations")
+    return {"n": n, "boxes": 4, "contrast": float(boxes.max() / boxes.min()), "setup_s": t_setup,
+            "s_per_solve": t, "dof_per_s": ndof / t, "iters": it, "relres": rel, "true_relres": true_rel}
+
+
 def timestep_leg(torch, nsteps=20):
     """Implicit Maxwell time stepping at 128^3 (average-acceleration Newmark, eps = 1,
     sigma = 1, mu = 1, dt = 0.01: each step the model problem with alpha = dt^2 / (4 (1 +
@@ -519,7 +548,8 @@ def main():
         out["forms"] = {"batched": batched_leg(torch, max(1, args.steps // 2), 1),
                         "differentiation": diff_leg(torch, 1, 1),
                         "manufactured_64": manufactured_leg(torch, max(1, args.steps // 2)),
-                        "time_stepping": timestep_leg(torch)}
+                        "time_stepping": timestep_leg(torch),
+                        "jumps_128": jumps_leg(torch, max(1, args.steps // 2))}
     if not args.no_cpu_baseline:
         host = {"fp32": sols[(1.0, "fp32")].cpu().numpy(), "fp64": sols[(1.0, "fp64")].cpu().numpy()}
         out["cpu_baseline"] = cpu_baseline(f.numpy(), fp64["iters"], host)

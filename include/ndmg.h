@@ -87,6 +87,23 @@ typedef struct ndmg_opts {
                            recursive V-cycle on unit vectors (the same map, rounded
                            differently; the matrices take nprob N_k^2 scalars of the
                            workspace).  Default 8; 0: the recursion all the way down. */
+  int coef_r;           /* a coefficient with jumps (Sec. 6, the first extension the
+                           paper names): alpha(x) = alpha * coef[(bz r + by) r + bx] on
+                           the r x r x r grid of equal boxes tiling the cube (x fastest),
+                           r = coef_r.  0 (default): alpha constant.  r must divide the
+                           coarsest level's n, and n_k / r must be a multiple of the
+                           subdomain size on every smoothed level, so that every element
+                           and every subdomain lies in one box: each level is then the
+                           cell-by-cell form of eq. (fem) with its cell's alpha, the coarse
+                           forms are the Galerkin restrictions of the fine one, and every
+                           subdomain and patch gets the factors of its own alphas (any
+                           smoother and subdomain size; the gathered-product smoother on
+                           every level).  Single problems only (ndmg_setup, or one problem
+                           in ndmg_setup_batched); bottom_n must be 0; ndmg_export_factor
+                           is refused.  ndmg_curlcurl_form then returns lam^T K_c u with
+                           K_c = sum_T coef_T K_T, the derivative of A in alpha.          */
+  const double* coef;   /* the r^3 box factors (> 0), host memory, read during ndmg_plan /
+                           ndmg_setup only (the context keeps a copy); NULL when r = 0 */
 } ndmg_opts;
 
 /* Fill *o with the defaults above. */

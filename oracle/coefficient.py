@@ -58,12 +58,16 @@ def level_matrices(sizes, L, alpha, boxes):
     return [matrix_cells(nk, L / nk, alpha * cell_field(nk, boxes)) for nk in sizes]
 
 
-def apply_rows(n, h, alpha_cells, x, rows):
+def apply_rows(n, h, alpha_cells, x, rows, absolute=False):
     """Selected entries of A x, row by row from the element definition, for sizes where
     assembling A is too costly: (A x)_e sums, over the (at most four) cubes T holding edge
-    e, alpha_T K_T + M_T's row of e's local edge times T's edge values."""
+    e, alpha_T K_T + M_T's row of e's local edge times T's edge values.  absolute: the same
+    sum of |alpha_T K_T + M_T| |x| instead, an upper bound of (|A| |x|)_e (the rounding
+    scale of the row)."""
     K = element.curl_matrix(h)
     M = element.mass_matrix(h)
+    if absolute:
+        x = np.abs(x)
     ac = np.asarray(alpha_cells, dtype=np.float64)
     rows = np.asarray(rows, dtype=np.int64)
     d_all, p_all = mesh.edge_coords(n)
@@ -95,5 +99,7 @@ def apply_rows(n, h, alpha_cells, x, rows):
                         vals[ok, element.local_edge(dd, aa, bb)] = x[idx[ok]]
             loc = 4 * d + a + 2 * b
             row = aT[:, None] * K[loc] + M[loc]
+            if absolute:
+                row = np.abs(row)
             out += np.where(inside, np.einsum("ij,ij->i", row, vals), 0.0)
     return out

@@ -46,6 +46,8 @@ class ndmg_opts(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("bottom_n", ctypes.c_int),
         ("dense_n", ctypes.c_int),
+        ("coef_r", ctypes.c_int),
+        ("coef", ctypes.POINTER(ctypes.c_double)),
     ]
 
 

@@ -102,12 +102,15 @@ struct Cls {
   size_t o_hist = 0;               // per pair: (r . z, p . A p) of the first kHistCap iterations
   size_t o_tw = 0, o_tb = 0;       // time stepping: predictor and right-hand side (FP64, per pair)
   size_t o_alpha0 = 0;             // zeros: alpha = 0 turns the operator into the mass matrix
+  size_t o_coef = 0;               // coefficient boxes (r^3 doubles), if any
 };
 
 struct Plan {
   double length = 1.0;
   int levels = 0;                  // 0: every level down to 2^3 or 3^3; else this many
-  ndmg_opts opts{};
+  ndmg_opts opts{};                // (opts.coef cleared: the values live in coef below)
+  std::vector<double> coef;        // coefficient boxes (Sec. 6), r^3 factors; empty: constant
+  ndmg::CoefBoxes boxes() const { return coef.empty() ? ndmg::CoefBoxes{} : ndmg::CoefBoxes{opts.coef_r, coef.data()}; }
   size_t elem = 8;                 // bytes of the V-cycle scalar type
   int nprob = 0, nrhs = 1;
   std::vector<Cls> cls;            // ascending n
@@ -151,6 +154,14 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
     return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) serves the vertex smoother with subdomain 2 only");
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
   if (o->dense_n < 0 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be in [0, 8]");
+  if (o->coef_r < 0 || o->coef_r > 64) return fail(NDMG_EINVAL, "coef_r must be in [0, 64]");
+  if (o->coef_r > 0) {
+    if (!o->coef) return fail(NDMG_EINVAL, "coef_r > 0 needs the coef array");
+    if (o->bottom_n > 0) return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) takes a constant alpha");
+    const size_t nb = (size_t)o->coef_r * o->coef_r * o->coef_r;
+    for (size_t b = 0; b < nb; ++b)
+      if (!(o->coef[b] > 0.0) || !std::isfinite(o->coef[b])) return fail(NDMG_EINVAL, "coef values must be > 0");
+  }
   return NDMG_OK;
 }
 
@@ -168,6 +179,10 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   }
   std::reverse(sizes.begin(), sizes.end());
   const size_t np = (size_t)C.nprob, el = pl.elem;
+  const ndmg::CoefBoxes cf = pl.boxes();
+  if (cf.r > 0 && sizes[0] % cf.r)
+    return fail(NDMG_EINVAL, "coef_r = " + std::to_string(cf.r) + " must divide the coarsest level's n (" +
+                                 std::to_string(sizes[0]) + "), so that every element of every level lies in one box");
   // dense bottom: the finest level with n_k <= dense_n, if above the coarsest
   C.dense_k = -1;
   for (size_t k = 1; k < sizes.size(); ++k)
@@ -209,12 +224,13 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
       if (sizes[k] % s) return fail(NDMG_EINVAL, "level not divisible by the subdomain size");
       L.smoothed = true;
       L.sub = ndmg::make_sub(s, sizes[k]);
-      if (pl.opts.smoother == NDMG_SMOOTHER_EDGE || s != 2) {
-        // the generic smoother: gathered products over subdomains and patches
+      if (pl.opts.smoother == NDMG_SMOOTHER_EDGE || s != 2 || cf.r > 0) {
+        // the generic smoother: gathered products over subdomains and patches (also every
+        // level of a coefficient with jumps: its factors differ from box to box)
         L.gen = true;
         std::string err;
         if (!ndmg::build_gen_tables(L.g, s, pl.opts.smoother == NDMG_SMOOTHER_EDGE ? 1 : 0,
-                                    pl.opts.boundary_patches != 0, &L.gt, &err))
+                                    pl.opts.boundary_patches != 0, &L.gt, &err, cf))
           return fail(NDMG_EINVAL, err);
         L.o_r = take(vb);
         L.o_gg = take(vb);
@@ -223,8 +239,8 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
         L.clenG = (int64_t)L.gt.unitsI.size() * L.gt.npadB;
         L.o_Y = take((size_t)L.ylenG * el * cnt);
         L.o_C = take((size_t)L.clenG * el * cnt);
-        L.blk_gX = (size_t)L.gt.npadI * L.gt.npadB;
-        L.blk_gE = (size_t)L.gt.npadE * L.gt.npadI;
+        L.blk_gX = (size_t)L.gt.ntypesI * L.gt.npadI * L.gt.npadB;
+        L.blk_gE = (size_t)L.gt.ntypesI * L.gt.npadE * L.gt.npadI;
         L.blk_gS = (size_t)L.gt.ntypes * L.gt.npadP * L.gt.npadP;
         L.o_gX = take(L.blk_gX * el * np);
         L.o_gE = take(L.blk_gE * el * np);
@@ -378,6 +394,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   C.o_tw = take(v8);
   C.o_tb = take(v8);
   C.o_alpha0 = take(np * sizeof(double));
+  if (cf.r > 0) C.o_coef = take(pl.coef.size() * sizeof(double));
   return NDMG_OK;
 }
 
@@ -391,6 +408,13 @@ int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts
   if ((int64_t)nprob * nrhs > 65535) return fail(NDMG_EINVAL, "more than 65535 (problem, rhs) pairs");
   if (!(length > 0.0) || !std::isfinite(length)) return fail(NDMG_EINVAL, "length must be > 0");
   NDMG_TRY(check_opts(o_in, &pl->opts));
+  pl->coef.clear();
+  if (pl->opts.coef_r > 0) {
+    if (nprob != 1) return fail(NDMG_EINVAL, "a coefficient with jumps (coef_r > 0) serves a single problem");
+    const size_t nb = (size_t)pl->opts.coef_r * pl->opts.coef_r * pl->opts.coef_r;
+    pl->coef.assign(pl->opts.coef, pl->opts.coef + nb);
+  }
+  pl->opts.coef = nullptr;
   for (int p = 0; p < nprob; ++p) {
     if (ns[p] < 2) return fail(NDMG_EINVAL, "n must be >= 2");
     if (ns[p] > 2048) return fail(NDMG_EINVAL, "n too large");
@@ -475,7 +499,9 @@ ndmg::DSub level_dsub(ndmg_ctx* c, const LevelHost& L) {
 
 // All pairs of a class, or only its active ones.
 ndmg::Bat class_batch(ndmg_ctx* c, const Cls& C, bool masked) {
-  return ndmg::Bat{C.count, C.nrhs, at<double>(c, C.o_alpha), masked ? at<int>(c, C.o_act) : nullptr};
+  const bool jumps = !c->plan.coef.empty();
+  return ndmg::Bat{C.count, C.nrhs, at<double>(c, C.o_alpha), masked ? at<int>(c, C.o_act) : nullptr,
+                   jumps ? at<double>(c, C.o_coef) : nullptr, jumps ? c->plan.opts.coef_r : 0};
 }
 
 // Host staging of everything uploaded at setup; freed after the stream has synchronised.
@@ -499,29 +525,47 @@ struct Staging {
 //       unknowns), [npadI][npadB];
 //   ex: [A_T^{-1} | -X_T] (rows: interior unknowns; columns: interior, then boundary),
 //       [npadE][npadI];
-//   sp: S_P^{-1} of every patch type (symmetric), [27][npadP][npadP], zero for absent
-//       types and slots.
-// The slots present in each patch factor must be those of the level's gather tables.
+//   sp: S_P^{-1} of every patch type (symmetric), [ntypes][npadP][npadP], zero for
+//       absent types and slots.
+// With a coefficient (boxes), xc and ex hold one block per subdomain type (box) and each
+// patch type has its own subdomain alphas.  The slots present in each patch factor must
+// be those of the level's gather tables.
 template <typename T>
 bool build_gen_factors(const LevelHost& L, double alpha, T* xc, T* ex, T* sp, std::string* err) {
   const ndmg::GenTables& tb = L.gt;
   const int s = tb.s, nI = tb.nI, nB = tb.nB;
   std::vector<double> ai, xt;
-  if (!ndmg::subdomain_factors(s, L.g.h, alpha, &ai, &xt, err)) return false;
-  for (int k = 0; k < nI; ++k)
-    for (int r = 0; r < nB; ++r) xc[(size_t)k * tb.npadB + r] = (T)xt[(size_t)k * nB + r];
-  for (int r = 0; r < nI; ++r) {
-    for (int k = 0; k < nI; ++k) ex[(size_t)k * tb.npadI + r] = (T)ai[(size_t)r * nI + k];
-    for (int b = 0; b < nB; ++b) ex[(size_t)(nI + b) * tb.npadI + r] = (T)(-xt[(size_t)r * nB + b]);
+  for (int tI = 0; tI < tb.ntypesI; ++tI) {
+    if (!ndmg::subdomain_factors(s, L.g.h, alpha * tb.boxI[tI], &ai, &xt, err)) return false;
+    T* xcb = xc + (size_t)tI * tb.npadI * tb.npadB;
+    T* exb = ex + (size_t)tI * tb.npadE * tb.npadI;
+    for (int k = 0; k < nI; ++k)
+      for (int r = 0; r < nB; ++r) xcb[(size_t)k * tb.npadB + r] = (T)xt[(size_t)k * nB + r];
+    for (int r = 0; r < nI; ++r) {
+      for (int k = 0; k < nI; ++k) exb[(size_t)k * tb.npadI + r] = (T)ai[(size_t)r * nI + k];
+      for (int b = 0; b < nB; ++b) exb[(size_t)(nI + b) * tb.npadI + r] = (T)(-xt[(size_t)r * nB + b]);
+    }
   }
   std::vector<double> buf((size_t)tb.npadP * tb.npadP);
   std::vector<char> present;
+  std::vector<double> cell_alpha;
   for (int type : tb.typesP) {
+    const bool jumps = !tb.geomP.empty();
+    const int geom = jumps ? tb.geomP[type] : type;
     int t[3];
-    ndmg::patch_type_axes(tb.kind, type, t);
-    const std::vector<ndmg::Slot> slots = tb.kind == 0 ? ndmg::vertex_slots(s) : ndmg::edge_slots(s, type / 9);
-    if (!ndmg::patch_inverse(ndmg::patch_cells(tb.kind, type, s), slots, t, s, L.g.h, alpha, tb.npadP, buf.data(),
-                             &present, err))
+    ndmg::patch_type_axes(tb.kind, geom, t);
+    const std::vector<ndmg::Slot> slots = tb.kind == 0 ? ndmg::vertex_slots(s) : ndmg::edge_slots(s, geom / 9);
+    const std::vector<std::array<int, 3>> cells = ndmg::patch_cells(tb.kind, geom, s);
+    if (jumps) {   // each cell takes the alpha of its subdomain (offset floor(o / s) in {-1, 0})
+      cell_alpha.clear();
+      for (const auto& c : cells) {
+        int o = 0;
+        for (int ax = 0; ax < 3; ++ax) o |= (c[ax] >= 0 ? 1 : 0) << ax;
+        cell_alpha.push_back(alpha * tb.keyP[type][o]);
+      }
+    }
+    if (!ndmg::patch_inverse(cells, slots, t, s, L.g.h, alpha, tb.npadP, buf.data(), &present, err,
+                             jumps ? &cell_alpha : nullptr))
       return false;
     for (size_t j = 0; j < slots.size(); ++j)
       if (present[j] != tb.presentP[(size_t)type * tb.npadP + j]) {
@@ -646,7 +690,7 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
         if (!L.smoothed) {
           std::vector<double> inv;
           std::vector<int64_t> map;
-          if (!ndmg::build_coarse(L.g, a, &inv, &map, &err)) {
+          if (!ndmg::build_coarse(L.g, a, &inv, &map, &err, pl.boxes())) {
             errs[t] = err;
             return;
           }
@@ -751,6 +795,7 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
     }
   }
   NDMG_TRY(stg.put_vec(c, C.o_alpha, C.alpha));
+  if (!pl.coef.empty()) NDMG_TRY(stg.put_vec(c, C.o_coef, pl.coef));
   return NDMG_OK;
 }
 
@@ -847,7 +892,9 @@ int build_dense(ndmg_ctx* c, Cls& C) {
   if (kd < 1) return NDMG_OK;
   LevelHost& L = C.lv[kd];
   const int N = L.Nd, K = C.dense_K;
-  const ndmg::Bat bt{C.nprob * K, K, at<double>(c, C.o_alpha), nullptr};
+  ndmg::Bat bt = class_batch(c, C, false);   // alpha and coefficient of the class
+  bt.count = C.nprob * K;
+  bt.nrhs = K;
   T* g = at<T>(c, L.o_g);
   T* z = at<T>(c, L.o_z);
   const int64_t* map = at<int64_t>(c, L.o_map);
@@ -918,7 +965,7 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt
   double* pq_part = part_region(c, C, 1);
   const int64_t ps = part_stride(C);
   int pq_n = 0;
-  if (g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n()) {
+  if (bt.coef == nullptr && g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n()) {
     NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, pq_part, ps, nullptr, st));
     pq_n = ndmg::stencil_blocks(g, bt.count);
   } else {
@@ -1280,6 +1327,8 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->use_graphs = 1;
   o->bottom_n = 0;
   o->dense_n = 8;
+  o->coef_r = 0;
+  o->coef = nullptr;
 }
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }
@@ -1658,8 +1707,10 @@ int ndmg_curlcurl_form(ndmg_ctx* c, const double* lam, const double* u, int nrhs
   double* sc = at<double>(c, C.o_scal);
   double total = 0.0;
   for (int r = 0; r < nrhs; ++r) {
+    const bool jumps = !c->plan.coef.empty();
     NDMG_HIP(ndmg::launch_curlcurl_form(lam + (int64_t)r * g.len, u + (int64_t)r * g.len, g, part,
-                                        sc + kS_CC, c->st));
+                                        sc + kS_CC, c->st, jumps ? at<double>(c, C.o_coef) : nullptr,
+                                        jumps ? c->plan.opts.coef_r : 0));
     NDMG_HIP(hipMemcpyAsync(c->host_scal, sc, kScalStride * sizeof(double), hipMemcpyDeviceToHost, c->st));
     NDMG_HIP(hipStreamSynchronize(c->st));
     total += c->host_scal[kS_CC];
@@ -1748,6 +1799,7 @@ int ndmg_export_factor(const ndmg_ctx* c, int level, int which, int type, double
   if (which != 0 && which != 1) return fail(NDMG_EINVAL, "which must be 0 or 1");
   if (which == 1 && (type < 0 || type > 26)) return fail(NDMG_EINVAL, "type out of range");
   const LevelHost& L = C.lv[level];
+  if (!c->plan.coef.empty()) return fail(NDMG_EINVAL, "with a coefficient (coef_r > 0) the factors differ by box: not exported");
   if (L.gen) {
     const ndmg::GenTables& tb = L.gt;
     if (which == 1 && std::find(tb.typesP.begin(), tb.typesP.end(), type) == tb.typesP.end())

@@ -273,8 +273,9 @@ Key cell_edge(const int c[3], int d, int a, int b) {
   return Key(d, o[0], o[1], o[2]);
 }
 
+// A_loc = sum over cells of alpha_T K_T + M_T, with alpha_T = cell_alpha[i] when given.
 void assemble_cells(const std::vector<std::array<int, 3>>& cells, double h, double alpha,
-                    LocalSystem* sys) {
+                    LocalSystem* sys, const std::vector<double>* cell_alpha = nullptr) {
   for (auto& c : cells)
     for (int d = 0; d < 3; ++d)
       for (int b = 0; b < 2; ++b)
@@ -289,7 +290,13 @@ void assemble_cells(const std::vector<std::array<int, 3>>& cells, double h, doub
   sys->A.assign((size_t)sys->N * sys->N, 0.0);
   double E[144];
   element_matrix(h, alpha, 1.0, E);
-  for (auto& c : cells) {
+  double Ealpha = alpha;
+  for (size_t ic = 0; ic < cells.size(); ++ic) {
+    const auto& c = cells[ic];
+    if (cell_alpha && (*cell_alpha)[ic] != Ealpha) {
+      Ealpha = (*cell_alpha)[ic];
+      element_matrix(h, Ealpha, 1.0, E);
+    }
     int loc[12];
     for (int d = 0; d < 3; ++d)
       for (int b = 0; b < 2; ++b)
@@ -580,9 +587,9 @@ void patch_type_axes(int kind, int type, int t[3]) {
 
 bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
                    const int t[3], int s, double h, double alpha, int npad, double* out,
-                   std::vector<char>* present, std::string* err) {
+                   std::vector<char>* present, std::string* err, const std::vector<double>* cell_alpha) {
   LocalSystem sys;
-  assemble_cells(cells, h, alpha, &sys);
+  assemble_cells(cells, h, alpha, &sys, cell_alpha);
   auto dirichlet = [&](int d, const int o[3]) { return in_boundary_plane(t, d, o); };
   *present = patch_slots_present(cells, slots, t);
   std::vector<int> G, Gslot;
@@ -594,7 +601,7 @@ bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vect
   for (int i = 0; i < npad * npad; ++i) out[i] = 0.0;
   if (G.empty()) return true;
   // interior unknowns of the subdomains in the patch, grouped by subdomain: A_II is block
-  // diagonal over subdomains, each block the same A_T up to the order of its unknowns
+  // diagonal over subdomains (each block A_T of its subdomain's alpha)
   std::map<std::array<int, 3>, std::vector<int>> blocks;
   for (int e = 0; e < sys.N; ++e) {
     const Key& k = sys.keys[e];
@@ -646,8 +653,15 @@ bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vect
   return true;
 }
 
-bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err) {
+bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err,
+                      const CoefBoxes& cf) {
   const int n = g.n, nH = n / s;
+  const bool jumps = cf.r > 0;
+  if (jumps && (n % cf.r || (n / cf.r) % s)) {
+    *err = "every subdomain must lie in one box of the coefficient: n_k / r must be a multiple of the "
+           "subdomain size on every smoothed level";
+    return false;
+  }
   GenTables& tb = *out;
   tb = GenTables{};
   tb.kind = kind;
@@ -661,26 +675,43 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
   tb.npadE = (tb.nI + tb.nB + 15) / 16 * 16;
   auto rel_of = [&](const Slot& q) { return q.d * g.B + (int64_t)q.dz * g.plane + (int64_t)q.dy * g.P + q.dx; };
   auto anchor = [&](int x, int y, int z) { return (int64_t)z * g.plane + (int64_t)y * g.P + x; };
-  // subdomains: one type; every boundary edge of a subdomain lies in [0, n] (those on the
-  // boundary of the domain are zero in every vector read there)
-  tb.relI.assign(tb.npadI, kGenAbsentHost);
-  tb.relE.assign(tb.npadE, kGenAbsentHost);
-  for (int j = 0; j < tb.nI; ++j) tb.relI[j] = tb.relE[j] = rel_of(idofs[j]);
-  for (int j = 0; j < tb.nB; ++j) tb.relE[tb.nI + j] = rel_of(bdofs[j]);
-  for (int c = 0; c < nH; ++c)
-    for (int b = 0; b < nH; ++b)
-      for (int a = 0; a < nH; ++a) tb.unitsI.push_back(anchor(s * a, s * b, s * c));
-  for (size_t u = 0; u < tb.unitsI.size(); u += 64) {
-    tb.chunksI.push_back(0);
-    tb.chunksI.push_back((int)u);
-    tb.chunksI.push_back((int)std::min<size_t>(64, tb.unitsI.size() - u));
-    tb.chunksI.push_back(0);
+  // subdomains: one type per box of the coefficient (one type without boxes); every
+  // boundary edge of a subdomain lies in [0, n] (those on the boundary of the domain are
+  // zero in every vector read there)
+  tb.ntypesI = jumps ? cf.r * cf.r * cf.r : 1;
+  tb.boxI.assign(tb.ntypesI, 1.0);
+  if (jumps)
+    for (int b = 0; b < tb.ntypesI; ++b) tb.boxI[b] = cf.v[b];
+  tb.relI.assign((size_t)tb.ntypesI * tb.npadI, kGenAbsentHost);
+  tb.relE.assign((size_t)tb.ntypesI * tb.npadE, kGenAbsentHost);
+  for (int t = 0; t < tb.ntypesI; ++t) {
+    for (int j = 0; j < tb.nI; ++j)
+      tb.relI[(size_t)t * tb.npadI + j] = tb.relE[(size_t)t * tb.npadE + j] = rel_of(idofs[j]);
+    for (int j = 0; j < tb.nB; ++j) tb.relE[(size_t)t * tb.npadE + tb.nI + j] = rel_of(bdofs[j]);
+  }
+  {
+    std::vector<std::vector<int64_t>> byType(tb.ntypesI);
+    const int w = jumps ? n / cf.r : n;
+    for (int c = 0; c < nH; ++c)
+      for (int b = 0; b < nH; ++b)
+        for (int a = 0; a < nH; ++a) {
+          const int t = jumps ? ((s * c / w) * cf.r + s * b / w) * cf.r + s * a / w : 0;
+          byType[t].push_back(anchor(s * a, s * b, s * c));
+        }
+    for (int t = 0; t < tb.ntypesI; ++t) {
+      const size_t first = tb.unitsI.size();
+      tb.unitsI.insert(tb.unitsI.end(), byType[t].begin(), byType[t].end());
+      for (size_t u = first; u < tb.unitsI.size(); u += 64) {
+        tb.chunksI.push_back(t);
+        tb.chunksI.push_back((int)u);
+        tb.chunksI.push_back((int)std::min<size_t>(64, tb.unitsI.size() - u));
+        tb.chunksI.push_back(0);
+      }
+    }
   }
   // patches, grouped by type
   const int nslots = kind == 0 ? 6 * s * (4 * s - 3) : s + 8 * s * (s - 1);
   tb.npadP = (nslots + 15) / 16 * 16;
-  tb.relP.assign((size_t)tb.ntypes * tb.npadP, kGenAbsentHost);
-  tb.presentP.assign((size_t)tb.ntypes * tb.npadP, 0);
   auto positions = [&](int t, int cells_axis, std::vector<int>* pos) {
     // coarse coordinates of the given type along one axis: node axes 0 / inside / nH,
     // the edge's own axis its cells 0 .. nH - 1
@@ -695,7 +726,13 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
       for (int i = 1; i < nH; ++i) pos->push_back(i);
     }
   };
-  for (int type = 0; type < tb.ntypes; ++type) {
+  // per geometric type: present slots and their offsets; the anchors of each type
+  std::vector<std::vector<char>> gpres(27);
+  std::vector<std::vector<int64_t>> grel(27);
+  std::vector<std::vector<int64_t>> byType;     // anchors per type
+  std::map<std::pair<int, std::array<double, 8>>, int> keyIndex;
+  if (!jumps) byType.assign(27, {});
+  for (int type = 0; type < 27; ++type) {
     int t[3];
     patch_type_axes(kind, type, t);
     const int nb = (t[0] != 1) + (t[1] != 1) + (t[2] != 1);
@@ -709,10 +746,12 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
     }
     const std::vector<char> pres = patch_slots_present(patch_cells(kind, type, s), slots, t);
     bool any = false;
+    gpres[type].assign(tb.npadP, 0);
+    grel[type].assign(tb.npadP, kGenAbsentHost);
     for (int j = 0; j < nslots; ++j) {
-      tb.presentP[(size_t)type * tb.npadP + j] = pres[j];
+      gpres[type][j] = pres[j];
       if (pres[j]) {
-        tb.relP[(size_t)type * tb.npadP + j] = rel_of(slots[j]);
+        grel[type][j] = rel_of(slots[j]);
         any = true;
       }
     }
@@ -722,14 +761,46 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
     positions(t[0], kind == 1 && a == 0, &px);
     positions(t[1], kind == 1 && a == 1, &py);
     positions(t[2], kind == 1 && a == 2, &pz);
-    const size_t first = tb.unitsP.size();
     for (int z : pz)
       for (int y : py)
-        for (int x : px) tb.unitsP.push_back(anchor(s * x, s * y, s * z));
-    if (tb.unitsP.size() == first) continue;
-    tb.typesP.push_back(type);
+        for (int x : px) {
+          if (!jumps) {
+            byType[type].push_back(anchor(s * x, s * y, s * z));
+            continue;
+          }
+          // the patch's subdomains by their cells next to the anchor; for an edge patch
+          // only those on the edge's side of the anchor along its axis
+          std::array<double, 8> key;
+          for (int o = 0; o < 8; ++o) {
+            const int oc[3] = {(o & 1) - 1, ((o >> 1) & 1) - 1, ((o >> 2) & 1) - 1};
+            key[o] = (kind == 1 && oc[a] < 0) ? 0.0 : cf.at(n, s * x + oc[0], s * y + oc[1], s * z + oc[2]);
+          }
+          const auto k = std::make_pair(type, key);
+          auto it = keyIndex.find(k);
+          if (it == keyIndex.end()) {
+            it = keyIndex.emplace(k, (int)tb.geomP.size()).first;
+            tb.geomP.push_back(type);
+            tb.keyP.push_back(key);
+            byType.emplace_back();
+          }
+          byType[it->second].push_back(anchor(s * x, s * y, s * z));
+        }
+  }
+  tb.ntypes = jumps ? (int)tb.geomP.size() : 27;
+  tb.relP.assign((size_t)tb.ntypes * tb.npadP, kGenAbsentHost);
+  tb.presentP.assign((size_t)tb.ntypes * tb.npadP, 0);
+  for (int ti = 0; ti < tb.ntypes; ++ti) {
+    const int geom = jumps ? tb.geomP[ti] : ti;
+    if (byType[ti].empty() || gpres[geom].empty()) continue;
+    for (int j = 0; j < tb.npadP; ++j) {
+      tb.relP[(size_t)ti * tb.npadP + j] = grel[geom][j];
+      tb.presentP[(size_t)ti * tb.npadP + j] = gpres[geom][j];
+    }
+    const size_t first = tb.unitsP.size();
+    tb.unitsP.insert(tb.unitsP.end(), byType[ti].begin(), byType[ti].end());
+    tb.typesP.push_back(ti);
     for (size_t u = first; u < tb.unitsP.size(); u += 64) {
-      tb.chunksP.push_back(type);
+      tb.chunksP.push_back(ti);
       tb.chunksP.push_back((int)u);
       tb.chunksP.push_back((int)std::min<size_t>(64, tb.unitsP.size() - u));
       tb.chunksP.push_back(0);
@@ -824,7 +895,7 @@ std::vector<int64_t> unknown_offsets(const Geom& g) {
 }
 
 bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
-                  std::vector<int64_t>* map, std::string* err) {
+                  std::vector<int64_t>* map, std::string* err, const CoefBoxes& cf) {
   const int n = g.n;
   // unknowns: interior edges in padded-layout order
   *map = unknown_offsets(g);
@@ -847,9 +918,15 @@ bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
   A0inv->assign((size_t)N * N, 0.0);
   double E[144];
   element_matrix(g.h, alpha, 1.0, E);
+  double Ealpha = alpha;
   for (int z = 0; z < n; ++z)
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x) {
+        const double ac = alpha * cf.at(n, x, y, z);
+        if (ac != Ealpha) {
+          Ealpha = ac;
+          element_matrix(g.h, Ealpha, 1.0, E);
+        }
         int c[3] = {x, y, z};
         int loc[12];
         for (int d = 0; d < 3; ++d)

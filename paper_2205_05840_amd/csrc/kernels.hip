@@ -110,6 +110,42 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, i
   return ah * curl + h3 * mass;
 }
 
+// The same with one alpha per cell (a coefficient with jumps, Sec. 6): the curl part sums
+// alpha_T K_T over the four cells T around the edge, so each face term of the RT0 mass
+// takes the alphas of the two cells on either side of the face.  ah = alpha h (alpha the
+// common factor), coef[(bz r + by) r + bx] the factor of each box, w = n / r cells per box.
+template <typename T>
+__device__ __forceinline__ T apply_at_coef(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
+                                           const int o[3], T ah, T h3, const double* __restrict__ coef,
+                                           int r) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const int64_t st[3] = {1, (int64_t)g.P, g.plane};
+  const int64_t sa = st[a], sb = st[b], sc = st[c];
+  const T* __restrict__ ua = u + a * g.B;
+  const T* __restrict__ ub = u + b * g.B;
+  const T* __restrict__ uc = u + c * g.B;
+  const T t6 = T(1) / T(6), t3 = T(1) / T(3), t23 = T(2) / T(3);
+  const int w = g.n / r;
+  // alpha of the cell at index o[a] along the edge and o[b] - 1 + db, o[c] - 1 + dc across
+  auto cell = [&](int db, int dc) {
+    int q[3];
+    q[a] = o[a];
+    q[b] = o[b] - 1 + db;
+    q[c] = o[c] - 1 + dc;
+    return (T)coef[((q[2] / w) * r + q[1] / w) * r + q[0] / w];
+  };
+  const T a00 = cell(0, 0), a10 = cell(1, 0), a01 = cell(0, 1), a11 = cell(1, 1);
+  auto Fb = [&](int64_t q) { return (ua[q + sc] - ua[q]) - (uc[q + sa] - uc[q]); };
+  auto Fc = [&](int64_t q) { return (ub[q + sa] - ub[q]) - (ua[q + sb] - ua[q]); };
+  // face of normal b (c) at q between the cells of alpha am (below along b (c)) and ap
+  auto Gb = [&](int64_t q, T am, T ap) { return t6 * (am * Fb(q - sb) + ap * Fb(q + sb)) + t3 * (am + ap) * Fb(q); };
+  auto Gc = [&](int64_t q, T am, T ap) { return t6 * (am * Fc(q - sc) + ap * Fc(q + sc)) + t3 * (am + ap) * Fc(q); };
+  const T curl = (Gb(p - sc, a00, a10) - Gb(p, a01, a11)) - (Gc(p - sb, a00, a01) - Gc(p, a10, a11));
+  auto row = [&](int64_t q) { return t6 * (ua[q - sc] + ua[q + sc]) + t23 * ua[q]; };
+  const T mass = t6 * (row(p - sb) + row(p + sb)) + t23 * row(p);
+  return ah * curl + h3 * mass;
+}
+
 // ---------------------------------------------------------------------------------
 // operator apply / residual (one thread per node position, small levels)
 // ---------------------------------------------------------------------------------
@@ -131,6 +167,23 @@ __device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __r
 }
 
 template <typename T, int MODE>
+__device__ __forceinline__ void apply_node_coef(const T* __restrict__ x, const T* __restrict__ b,
+                                                T* __restrict__ y, const DGeom& g, T ah, T h3,
+                                                const double* __restrict__ coef, int r, int i, int j, int k) {
+  const int64_t p = lin(g, i, j, k);
+  const int o[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T v = T(0);
+    if (is_unknown(g, d, i, j, k)) {
+      const T ax = apply_at_coef(x, g, d, p, o, ah, h3, coef, r);
+      v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
+    }
+    y[d * g.B + p] = v;
+  }
+}
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, DGeom g, Bat bt, double h, int nbx) {
   const int3 bk = xcd_grid_block();
@@ -143,7 +196,10 @@ __global__ void __launch_bounds__(64) k_apply(const T* __restrict__ x, const T* 
   y += off;
   if (MODE == 1) b += off;
   const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
-  apply_node<T, MODE>(x, b, y, g, ah, h3, i, j, k);
+  if (bt.coef)
+    apply_node_coef<T, MODE>(x, b, y, g, ah, h3, bt.coef, bt.coef_r, i, j, k);
+  else
+    apply_node<T, MODE>(x, b, y, g, ah, h3, i, j, k);
 }
 
 // The same for rows shorter than a wave (n + 1 < 64): the lanes of a block take
@@ -163,7 +219,10 @@ __global__ void __launch_bounds__(64) k_apply_plane(const T* __restrict__ x, con
   y += off;
   if (MODE == 1) b += off;
   const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
-  apply_node<T, MODE>(x, b, y, g, ah, h3, i, j, k);
+  if (bt.coef)
+    apply_node_coef<T, MODE>(x, b, y, g, ah, h3, bt.coef, bt.coef_r, i, j, k);
+  else
+    apply_node<T, MODE>(x, b, y, g, ah, h3, i, j, k);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1730,16 +1789,20 @@ __global__ void __launch_bounds__(64) k_assemble_rhs(const double* __restrict__ 
 
 __global__ void __launch_bounds__(64) k_curlcurl_form(const double* __restrict__ lam,
                                                       const double* __restrict__ u,
-                                                      double* __restrict__ part, DGeom g, double h) {
+                                                      double* __restrict__ part, DGeom g, double h,
+                                                      const double* __restrict__ coef, int coef_r) {
   __shared__ double sh[8];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
   double s = 0.0;
   if (i <= g.n) {
     const int64_t p = lin(g, i, j, k);
+    const int o[3] = {i, j, k};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      if (is_unknown(g, d, i, j, k)) s += lam[d * g.B + p] * apply_at(u, g, d, p, h, 0.0);
+      if (is_unknown(g, d, i, j, k))
+        s += lam[d * g.B + p] * (coef ? apply_at_coef(u, g, d, p, o, h, 0.0, coef, coef_r)
+                                      : apply_at(u, g, d, p, h, 0.0));
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0)
@@ -1786,7 +1849,9 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
   // plane-marching one for the 512-problem batch: 239 against 252 ms per 2048 solves; in
   // FP64 it is not, 365 against 362 ms)
   const int min_n = (sizeof(T) == 4 && bt.count >= 4) ? 32 : stencil_min_n(bt.count);
-  if (g.n > min_n && g.n <= stencil_max_n()) {
+  // the plane-marching kernel takes one alpha per problem: with a coefficient per cell the
+  // per-thread kernels below serve every size
+  if (bt.coef == nullptr && g.n > min_n && g.n <= stencil_max_n()) {
     const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, nullptr, st);
     if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
   }
@@ -2034,10 +2099,10 @@ hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStr
 }
 
 hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,
-                                double* partial, double* out, hipStream_t st) {
+                                double* partial, double* out, hipStream_t st, const double* coef, int coef_r) {
   const dim3 grid = node_grid(g, nbx64(g.n), 1);
   const int nparts = (int)(grid.x * grid.y * grid.z);
-  hipLaunchKernelGGL(k_curlcurl_form, grid, dim3(64), 0, st, lam, u, partial, dgeom(g), g.h);
+  hipLaunchKernelGGL(k_curlcurl_form, grid, dim3(64), 0, st, lam, u, partial, dgeom(g), g.h, coef, coef_r);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partial, nparts, (int64_t)0, 1, out,
                      Bat{1, 1, nullptr, nullptr});
   return hipGetLastError();

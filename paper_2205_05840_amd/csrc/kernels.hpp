@@ -33,6 +33,9 @@ struct Bat {
   int nrhs;                // consecutive pairs per problem
   const double* alpha;     // per problem (device)
   const int* act;          // per pair, 0 = skip (converged); nullptr = all active
+  const double* coef;      // coefficient boxes (device, r^3, [z][y][x]): alpha(x) = alpha *
+                           // coef[box of x]; nullptr = constant alpha (one problem only)
+  int coef_r;              // boxes per axis (r divides every level's n)
 };
 
 inline Bat single_batch(const double* d_alpha) { return Bat{1, 1, d_alpha, nullptr}; }
@@ -302,6 +305,6 @@ hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStr
 
 // out[0] = lam . (K u) for one pair of vectors (single problem), K = dA/dalpha.
 hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,
-                                double* part, double* out, hipStream_t st);
+                                double* part, double* out, hipStream_t st, const double* coef = nullptr, int coef_r = 0);
 
 }  // namespace ndmg

@@ -101,10 +101,12 @@ bool subdomain_factors(int s, double h, double alpha, std::vector<double>* ATinv
 // interface edges, t[ax] = 0 / 2 where the anchor lies on the low / high boundary plane
 // of axis ax (edges in such a plane through the anchor carry no unknown), 1 otherwise.
 // out (npad x npad, row-major) receives S^{-1} on the present slots and zeros elsewhere;
-// present[j] = 1 for the slots that hold an unknown.
+// present[j] = 1 for the slots that hold an unknown.  cell_alpha, if given, holds each
+// cell's own alpha (in the order of cells) in place of the common alpha.
 bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
                    const int t[3], int s, double h, double alpha, int npad, double* out,
-                   std::vector<char>* present, std::string* err);
+                   std::vector<char>* present, std::string* err,
+                   const std::vector<double>* cell_alpha = nullptr);
 
 // Patch types of the generic smoother.  kind 0 (vertex spaces): type = tx + 3 ty + 9 tz,
 // t = 0 / 1 / 2 for a vertex on the low boundary plane / inside / on the high plane of
@@ -123,13 +125,37 @@ std::vector<char> patch_slots_present(const std::vector<std::array<int, 3>>& cel
 constexpr int64_t kGenAbsentHost = INT64_MIN;
 
 // Device tables of one level of the generic smoother (geometry only).
+// A coefficient with jumps (Sec. 6): alpha(x) = alpha * v[(bz r + by) r + bx] on an
+// r x r x r grid of boxes tiling the cube; r = 0: constant.
+struct CoefBoxes {
+  int r = 0;
+  const double* v = nullptr;
+  // factor of cell (x, y, z) of a level with n cells per axis (r divides n): 1 without
+  // boxes, 0 outside the domain
+  double at(int n, int x, int y, int z) const {
+    if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return 0.0;
+    if (r == 0) return 1.0;
+    const int w = n / r;
+    return v[((size_t)(z / w) * r + (size_t)(y / w)) * r + (size_t)(x / w)];
+  }
+};
+
 struct GenTables {
   int kind = 0, s = 2, ntypes = 27;
+  // subdomain types: one per box of the coefficient (one without boxes), with its factor
+  int ntypesI = 1;
+  std::vector<double> boxI{1.0};
+  // patch types with a coefficient: the geometric type (0 .. 26) of each, and the factors
+  // of the 8 cells at offsets {-1, 0}^3 from the anchor node (x fastest; 0 outside the
+  // domain or the patch), one per subdomain of the patch.  Without boxes the type is the
+  // geometric type and these stay empty.
+  std::vector<int> geomP;
+  std::vector<std::array<double, 8>> keyP;
   int nI = 0, nB = 0;
   int npadI = 0, npadB = 0, npadE = 0, npadP = 0;
-  std::vector<int64_t> unitsI;         // subdomain anchors
-  std::vector<int64_t> relI;           // [npadI] interior offsets
-  std::vector<int64_t> relE;           // [npadE] interior offsets, then boundary offsets
+  std::vector<int64_t> unitsI;         // subdomain anchors, grouped by subdomain type
+  std::vector<int64_t> relI;           // [ntypesI][npadI] interior offsets
+  std::vector<int64_t> relE;           // [ntypesI][npadE] interior offsets, then boundary offsets
   std::vector<int> chunksI;            // [n][4]
   std::vector<int64_t> unitsP, relP;   // patch anchors; [ntypes][npadP] slot offsets
   std::vector<int> chunksP;
@@ -139,7 +165,8 @@ struct GenTables {
   std::vector<int> ccodes;             // [ngam][4] subdomain terms (u npadB + boundary slot)
   std::vector<int> codes;              // [ngam][4] patch results (u npadP + slot)
 };
-bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err);
+bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err,
+                      const CoefBoxes& cf = CoefBoxes{});
 
 // Padded-layout offsets of the interior edges (the unknowns) of a level, direction-major
 // and then in layout order.
@@ -148,7 +175,7 @@ std::vector<int64_t> unknown_offsets(const Geom& g);
 // Coarsest level: dense inverse of A_0 over its unknowns and the padded offset of each
 // (the order of unknown_offsets).
 bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
-                  std::vector<int64_t>* map, std::string* err);
+                  std::vector<int64_t>* map, std::string* err, const CoefBoxes& cf = CoefBoxes{});
 
 // 12 x 12 element matrix alpha K_T + M_T of a cube of side h (local edge order 4 d + a + 2 b).
 void element_matrix(double h, double alpha, double curl_scale, double* out144);

@@ -13,7 +13,9 @@ SMOOTHERS = {"vertex": 0, "edge": 1}
 
 
 def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None, dense_n=None,
-          smoother="vertex", subdomain=2):
+          smoother="vertex", subdomain=2, coef=None):
+    """ndmg_opts; with coef (an r x r x r array of box factors, [z][y][x]) also the
+    float64 copy the struct points to, which must live through the plan and setup calls."""
     o = _lib.ndmg_default_opts()
     o.smoother = SMOOTHERS[smoother]
     o.subdomain = int(subdomain)
@@ -28,6 +30,15 @@ def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=No
         o.bottom_n = int(bottom_n)
     if dense_n is not None:
         o.dense_n = int(dense_n)
+    keep = None
+    if coef is not None:
+        keep = np.ascontiguousarray(coef, dtype=np.float64)
+        r = keep.shape[0]
+        if keep.shape != (r, r, r):
+            raise ValueError("coef must be an r x r x r array of box factors")
+        o.coef_r = r
+        o.coef = keep.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_double))
+    o._keep = keep
     return o
 
 
@@ -70,18 +81,19 @@ class Solver(_Context):
     """V-cycle-preconditioned CG for curl(alpha curl u) + u = f on (0, length)^3 with
     n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace; smoother
     "vertex" (eq. Preconditioner P) or "edge" (eq. Preconditioner E) on subdomains of
-    subdomain^3 elements (2 or 4).  With
+    subdomain^3 elements (2 or 4).  coef: an r x r x r array of box factors, alpha(x) =
+    alpha * coef[z][y][x] of x's box (jumps, Sec. 6; r divides the coarsest level).  With
     nrhs > 1 every call works on nrhs vectors at once ([nrhs, vec_len] tensors), each
     right-hand side with its own CG scalars."""
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
-                 bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2):
+                 bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2, coef=None):
         self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
         if self.nrhs > 1 and levels:
             raise ValueError("levels applies to single right-hand-side solvers")
         o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n,
-                  smoother, subdomain)
+                  smoother, subdomain, coef)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:

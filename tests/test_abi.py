@@ -220,3 +220,56 @@ def test_tuning_table(lib, tmp_path):
     assert (v.value, z.value) == model
     if os.path.exists(lib.TUNING_PATH):   # leave the process as the binding set it up
         L.ndmg_tuning_load(lib.TUNING_PATH.encode())
+
+
+def _coef_opts(lib, r, values=None, **kw):
+    import numpy as np
+    o = lib.ndmg_default_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    if r:
+        arr = np.ascontiguousarray(np.full((r, r, r), 3.0) if values is None else values, dtype=np.float64)
+        o.coef_r = r
+        o.coef = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o._keep = arr
+    return o
+
+
+@pytest.mark.parametrize("n,r,kw,ok", [
+    (8, 2, {}, True), (16, 2, {"subdomain": 4}, True), (12, 3, {}, True), (40, 5, {}, True),
+    (8, 1, {"smoother": 1}, True),
+    (8, 3, {}, False),                       # 3 does not divide the coarsest level (2)
+    (16, 4, {}, False),                      # nor does 4
+    (24, 3, {"subdomain": 4}, False),        # level 6 has subdomains of 3 cells, boxes of 2
+    (8, 2, {"bottom_n": 8}, False),          # the one-launch bottom takes one alpha
+])
+def test_plan_coefficient_boxes(lib, n, r, kw, ok):
+    """A coefficient with jumps plans when its boxes hold whole elements of every level and
+    whole subdomains of every smoothed level; else it is refused with a message."""
+    o = _coef_opts(lib, r, **kw)
+    if ok:
+        ws, vl = lib.ndmg_plan(n, 1.0, 1.0, o)
+        _, vl0 = lib.ndmg_plan(n, 1.0, 1.0, _coef_opts(lib, 0, **kw))
+        assert vl == vl0 and ws > 0
+    else:
+        with pytest.raises(lib.NdmgError) as e:
+            lib.ndmg_plan(n, 1.0, 1.0, o)
+        assert e.value.code == lib.NDMG_EINVAL
+
+
+def test_plan_coefficient_rejects(lib):
+    import numpy as np
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        vals = np.ones((2, 2, 2))
+        vals[1, 0, 1] = bad
+        with pytest.raises(lib.NdmgError):
+            lib.ndmg_plan(8, 1.0, 1.0, _coef_opts(lib, 2, vals))
+    o = lib.ndmg_default_opts()
+    o.coef_r = 2                              # no array
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan(8, 1.0, 1.0, o)
+    # batches of several problems take one alpha per problem
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan_batched([8, 8], 1.0, 1, _coef_opts(lib, 2))
+    ws, tl = lib.ndmg_plan_batched([8], 1.0, 2, _coef_opts(lib, 2))
+    assert tl > 0

@@ -1,0 +1,216 @@
+"""GPU parity with a coefficient with jumps (Sec. 6): alpha(x) = alpha * coef[box of x]
+on an r x r x r grid of boxes, against the oracle's cell-by-cell assembly and its
+literal smoother on every level (``oracle.coefficient``, ``vcycle.Hierarchy(boxes=...)``).
+
+Tolerances:
+* operator apply (FP64): both sides sum the same 33-entry rows in different orders:
+  1e-14 of the largest |A||x| row sum, entrywise.
+* smoothing step and V-cycle, FP64, vertex and edge spaces: 0.03 (0.02 for the V-cycle)
+  of u kappa(A_T) kappa(S), the largest condition numbers over the oracle's local
+  matrices of the finest level: the first-order model of the constant-coefficient edge
+  tests (X_T = A_T^{-1} A_{I,dT} and S^{-1} carry relative rounding u kappa(A_T) from the
+  FP64 setup, which the patch solves amplify by up to kappa(S)).  With jumps the spread
+  between the oracle's LU and Cholesky routes understates the library's rounding (the
+  library condenses through explicit local inverses): measured 350 - 4000 times the
+  spread against 0.002 - 0.01 of the model; both are printed.  Floor 1e-13 (1e-12).
+* FP32 V-cycle: within 64 u of the FP64 oracle (constant coefficient: 12 u; the box
+  contrast of up to 1e4 raises the conditioning of the local solves that FP32 rounds).
+* PCG: relative residual of the returned solution recomputed with the oracle's matrix,
+  iterations within one of the oracle's PCG, and the solution against a sparse direct
+  solve.
+* Contraction at k = 1: exactly (8/9)^(2m) whatever the jumps (the pin of the oracle).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from layout import boundary_mask, from_padded, to_padded
+from oracle import coefficient, mesh, pcg, rhs, smoother, vcycle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def _boxes(r, seed, lo=-2.0, hi=2.0):
+    return 10.0 ** np.random.default_rng(seed).uniform(lo, hi, size=(r, r, r))
+
+
+def _solver(n, alpha, boxes, **kw):
+    from paper_2205_05840_amd import Solver
+    print(f"[case] coef n={n} alpha={alpha} r={boxes.shape[0]} {kw}", flush=True)
+    return Solver(n, alpha, coef=boxes, **kw)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _scale(lit):
+    """u kappa(A_T) kappa(S) of a literal smoother (largest over its subdomains and patches)."""
+    return U64 * max(np.linalg.cond(Ai) for _, Ai in lit.T) * max(np.linalg.cond(p[3]) for p in lit.P)
+
+
+def _matrix(n, alpha, boxes, L=1.0):
+    return coefficient.matrix_cells(n, L / n, alpha * coefficient.cell_field(n, boxes))
+
+
+@pytest.mark.parametrize("n,r,alpha", [(8, 2, 1.0), (12, 3, 0.5), (16, 2, 3.0), (40, 5, 1.0), (64, 2, 1.0)])
+def test_apply(n, r, alpha):
+    boxes = _boxes(r, n)
+    S = _solver(n, alpha, boxes)
+    A = _matrix(n, alpha, boxes)
+    x = np.random.default_rng(1).standard_normal(mesh.ndof(n))
+    y = from_padded(n, S.P, S.B, _host(S.apply(_dev(to_padded(n, S.P, S.B, x)))))
+    scale = abs(A) @ np.abs(x)
+    err = np.abs(y - A @ x).max() / scale.max()
+    print(f"apply n={n} r={r}: {err:.2e} of max |A||x|")
+    assert err <= 1e-14
+
+
+@pytest.mark.parametrize("kind,s,n,r,boundary", [
+    ("vertex", 2, 8, 2, True), ("vertex", 2, 12, 3, True), ("vertex", 2, 16, 2, False),
+    ("vertex", 4, 16, 2, True), ("edge", 2, 8, 2, True), ("edge", 2, 12, 3, False)])
+def test_smoother(kind, s, n, r, boundary):
+    boxes = _boxes(r, 10 + n)
+    S = _solver(n, 1.0, boxes, smoother=kind, subdomain=s, boundary_patches=boundary)
+    A = _matrix(n, 1.0, boxes)
+    g = np.random.default_rng(n).standard_normal(mesh.ndof(n))
+    z = _host(S.level_op(S.levels - 1, "smooth", _dev(to_padded(n, S.P, S.B, g))))
+    assert not z[boundary_mask(n, S.P, S.B)].any()
+    z = from_padded(n, S.P, S.B, z)
+    lit = smoother.LiteralSmoother(A, n, s, kind=kind, boundary=boundary)
+    ref = lit(g)
+    err = _rel(z, ref)
+    scale = _scale(lit)
+    spread = _rel(smoother.LiteralSmoother(A, n, s, kind=kind, boundary=boundary, inverse="cholesky")(g), ref)
+    print(f"{kind} s={s} n={n}: err {err:.2e}, scale {scale:.2e}, ratio {err / scale:.4f} "
+          f"(LU/Cholesky spread {spread:.2e})")
+    assert err <= max(1e-13, 0.03 * scale)
+
+
+@pytest.mark.parametrize("kind,n,r,m", [("vertex", 8, 2, 1), ("vertex", 16, 2, 2), ("vertex", 12, 3, 1),
+                                        ("edge", 8, 2, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vcycle(kind, n, r, m, precision):
+    boxes = _boxes(r, 20 + n)
+    S = _solver(n, 1.0, boxes, smoother=kind, m=m, precision=precision)
+    g = np.random.default_rng(3).standard_normal(mesh.ndof(n))
+    z = from_padded(n, S.P, S.B, _host(S.vcycle(_dev(to_padded(n, S.P, S.B, g)))))
+    H = vcycle.Hierarchy(n, 1.0, m=m, kind=kind, boxes=boxes)
+    ref = H.precondition(g)
+    err = _rel(z, ref)
+    if precision == "fp32":
+        print(f"{kind} n={n} V-cycle fp32: err {err:.2e} = {err / U32:.2f} u")
+        assert err <= 64 * U32
+    else:
+        scale = _scale(H.M[-1])
+        print(f"{kind} n={n} V-cycle fp64: err {err:.2e}, scale {scale:.2e}, ratio {err / scale:.4f}")
+        assert err <= max(1e-12, 0.02 * scale)
+
+
+@pytest.mark.parametrize("n,r,precision", [(16, 2, "fp64"), (16, 2, "fp32"), (12, 3, "fp64")])
+def test_pcg_against_oracle(n, r, precision):
+    from paper_2205_05840_amd import synth
+    boxes = _boxes(r, 30 + n, -3.0, 3.0)
+    S = _solver(n, 1.0, boxes, precision=precision)
+    h = 1.0 / n
+    f = synth.normal_samples(n, 0)
+    b_o = rhs.load_from_samples(n, h, f)
+    u, it, rel = S.solve(S.assemble_rhs(torch.from_numpy(f)), rtol=1e-10)
+    u_c = from_padded(n, S.P, S.B, _host(u))
+    A = _matrix(n, 1.0, boxes)
+    true_rel = _rel(A @ u_c, b_o)
+    H = vcycle.Hierarchy(n, 1.0, boxes=boxes)
+    _, it_o, _, _ = pcg.pcg(A, b_o, H.precondition, rtol=1e-10, flexible=(precision == "fp32"))
+    ue = spla.spsolve(A.tocsc(), b_o)
+    print(f"n={n} r={r} {precision}: {it} iterations (oracle {it_o}), relres {rel:.2e}, true {true_rel:.2e}, "
+          f"error {_rel(u_c, ue):.2e}")
+    assert rel <= 1e-10 and true_rel <= 1.5e-10
+    assert abs(it - it_o) <= 1
+    # ||u - ue|| <= ||A^-1|| ||r||: bounded through the smallest eigenvalue of A
+    lam_min = spla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    assert np.linalg.norm(u_c - ue) <= 1.5e-10 * np.linalg.norm(b_o) / lam_min
+
+
+@pytest.mark.parametrize("n,r,levels", [(64, 2, 0), (128, 4, 6)])
+def test_pcg_large(n, r, levels):
+    """Mixed precision at the full sizes with a 1e4 contrast.  CG's recursive residual
+    drifts from b - A u by rounding, by up to about k u || |A| |u| || after k iterations
+    (the large curl entries cancel in A u): with this contrast the gap is a few 1e-10 of
+    ||b||, so the true residual is checked against the recursive one plus that bound
+    (|A| assembled at 64^3; at 128^3 bounded row by row on a sample of 4000 rows and its
+    norm estimated from them).  One warm-started solve from u (ndmg_pcg_solve_warm:
+    r = b - A u recomputed) starts over from the true residual and may not end worse.
+    Sampled rows of the GPU's residual match the oracle's row-by-row apply to 1e-14 of
+    |A||u| in the row."""
+    from paper_2205_05840_amd import synth
+    boxes = _boxes(r, 40 + r)
+    S = _solver(n, 1.0, boxes, precision="fp32", levels=levels)
+    f = synth.normal_samples(n, 0)
+    b = S.assemble_rhs(torch.from_numpy(f))
+    u, it, rel = S.solve(b, rtol=1e-10)
+    res = b - S.apply(u)
+    bn = float(torch.linalg.norm(b))
+    true_rel = float(torch.linalg.norm(res)) / bn
+    u_c = from_padded(n, S.P, S.B, _host(u))
+    b_c = from_padded(n, S.P, S.B, _host(b))
+    cells = coefficient.cell_field(n, boxes)
+    rows = np.random.default_rng(5).choice(mesh.ndof(n), 4000, replace=False)
+    if n <= 64:
+        absAu = abs(_matrix(n, 1.0, boxes)) @ np.abs(u_c)
+        norm_absAu = np.linalg.norm(absAu)
+        absAu = absAu[rows]
+    else:   # |A||u| bounded row by row on the sample, its norm estimated from the sample
+        absAu = coefficient.apply_rows(n, 1.0 / n, cells, u_c, rows, absolute=True)
+        norm_absAu = np.sqrt(mesh.ndof(n) / rows.size) * np.linalg.norm(absAu)
+    gap = 4 * it * U64 * norm_absAu / bn
+    print(f"n={n} r={r}: {it} iterations, relres {rel:.2e}, true {true_rel:.2e}, drift bound {gap:.2e}")
+    assert rel <= 1e-10 and true_rel <= rel + gap
+    # rows of b - A u: both sides round the row sums of |A||u|
+    r_o = b_c[rows] - coefficient.apply_rows(n, 1.0 / n, cells, u_c, rows)
+    r_g = from_padded(n, S.P, S.B, _host(res))[rows]
+    assert np.all(np.abs(r_o - r_g) <= 1e-14 * absAu + 1e-300)
+    u2, it2, rel2 = S.solve(b, rtol=1e-10, u=u, warm=True)
+    true2 = float(torch.linalg.norm(b - S.apply(u2))) / bn
+    print(f"n={n} r={r}: warm restart {it2} iterations, relres {rel2:.2e}, true {true2:.2e}")
+    assert rel2 <= 1e-10 and true2 <= rel2 + 4 * it2 * U64 * norm_absAu / bn and true2 <= true_rel
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_contraction_k1(seed):
+    from paper_2205_05840_amd import Solver
+    boxes = _boxes(2, seed, -3.0, 3.0)
+    n = 4
+    for m in (1, 2):
+        S = Solver(n, 1.0, length=2.0, m=m, coef=boxes)
+        b = np.random.default_rng(seed).standard_normal(mesh.ndof(n))
+        c, lam_max, steps = S.contraction(_dev(to_padded(n, S.P, S.B, b)), rtol=0.0, maxit=100)
+        S.close()
+        print(f"k=1 jumps seed {seed} m={m}: {c:.12f} ({steps} steps)")
+        assert abs(c - (8.0 / 9.0) ** (2 * m)) <= 1e-8
+
+
+def test_curlcurl_form():
+    """lam^T K_c u with K_c = sum_T coef_T K_T (the derivative of A in alpha)."""
+    n, r = 16, 2
+    boxes = _boxes(r, 9)
+    S = _solver(n, 0.7, boxes)
+    rng = np.random.default_rng(2)
+    lam, u = rng.standard_normal((2, mesh.ndof(n)))
+    K = coefficient.stiffness_cells(n, 1.0 / n, coefficient.cell_field(n, boxes))
+    got = S.curlcurl_form(_dev(to_padded(n, S.P, S.B, lam)), _dev(to_padded(n, S.P, S.B, u)))
+    ref = lam @ (K @ u)
+    scale = np.abs(lam) @ (abs(K) @ np.abs(u))
+    assert abs(got - ref) <= 1e-13 * scale

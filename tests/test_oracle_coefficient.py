@@ -96,6 +96,14 @@ def test_apply_rows_and_stiffness():
     rows = np.arange(mesh.ndof(n))
     y = coefficient.apply_rows(n, h, cells, x, rows)
     assert np.abs(y - A @ x).max() <= 1e-13 * np.abs(A @ x).max()
+    # the absolute form bounds |A| |x| from above (cell terms of one entry may cancel) and
+    # equals it for the mass part alone (all entries of M_T are positive)
+    ya = coefficient.apply_rows(n, h, cells, x, rows, absolute=True)
+    assert np.all(ya >= (abs(A) @ np.abs(x)) * (1 - 1e-14))
+    zero = np.zeros_like(cells)
+    ym = coefficient.apply_rows(n, h, zero, x, rows, absolute=True)
+    Mx = abs(assemble.mass_kron(n, h)) @ np.abs(x)
+    assert np.abs(ym - Mx).max() <= 1e-14 * Mx.max()
     K = coefficient.stiffness_cells(n, h, cells)
     assert abs(K + assemble.mass_kron(n, h) - A).max() <= 1e-14 * abs(A).max()
 
