@@ -13,8 +13,10 @@ Tolerances:
   between the oracle's LU and Cholesky routes understates the library's rounding (the
   library condenses through explicit local inverses): measured 350 - 4000 times the
   spread against 0.002 - 0.01 of the model; both are printed.  Floor 1e-13 (1e-12).
-* FP32 V-cycle: within 64 u of the FP64 oracle (constant coefficient: 12 u; the box
-  contrast of up to 1e4 raises the conditioning of the local solves that FP32 rounds).
+* FP32 V-cycle: within 12 u of the FP64 oracle, the bound of the constant coefficient
+  (every local factor is built in FP64 and rounded once, and the condensation goes
+  through X_T, so the cancellation of the curl part happens in the FP64 setup); measured
+  with jumps: 1.05 - 2.46 u.
 * PCG: relative residual of the returned solution recomputed with the oracle's matrix,
   iterations within one of the oracle's PCG, and the solution against a sparse direct
   solve.
@@ -113,7 +115,7 @@ def test_vcycle(kind, n, r, m, precision):
     err = _rel(z, ref)
     if precision == "fp32":
         print(f"{kind} n={n} V-cycle fp32: err {err:.2e} = {err / U32:.2f} u")
-        assert err <= 64 * U32
+        assert err <= 12 * U32
     else:
         scale = _scale(H.M[-1])
         print(f"{kind} n={n} V-cycle fp64: err {err:.2e}, scale {scale:.2e}, ratio {err / scale:.4f}")
