@@ -193,8 +193,12 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
     Nd = 3 * nk * (nk - 1) * (nk - 1);
     if (Nd > ndmg::kDenseMaxN) return fail(NDMG_EINVAL, "dense level too large");
     // the level vectors at and below the dense level serve the build at setup (nprob x
-    // dense_K pairs); at run time only its g and z are used, by count pairs
-    C.dense_K = (int)std::max<int64_t>(C.nrhs, std::min<int64_t>(Nd, 256 / C.nprob));
+    // dense_K pairs, dense_K unit columns per problem and recursion pass); at run time only
+    // its g and z are used, by count pairs.  Classes of many problems take up to 2048
+    // columns in all per pass (at most a few hundred MB of level vectors): with 4 the
+    // 512-problem batch spent 0.6 s of its 0.7 s setup in 1108 passes of eager launches
+    const int64_t budget = C.nprob >= 16 ? 2048 : 256;
+    C.dense_K = (int)std::max<int64_t>(C.nrhs, std::min<int64_t>(Nd, budget / C.nprob));
     // many problems: one thread per row over the transposed matrix (coalesced, no
     // cross-lane sums); few: waves over rows, more workgroups per problem
     C.dense_t = C.nprob >= 8;
@@ -706,14 +710,12 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
           }
           continue;
         }
-        ndmg::LevelFactors fac;
-        if (!ndmg::build_level_factors(L.g.h, a, L.sub, bp, &fac, &err)) {
+        if (!ndmg::build_level_factors_into<T>(L.g.h, a, L.sub, bp, ATinv[k].data() + (size_t)p * L.blk_ATinv,
+                                               XT[k].data() + (size_t)p * L.blk_XT,
+                                               Sinv[k].data() + (size_t)p * L.blk_Sinv, &err)) {
           errs[t] = err;
           return;
         }
-        std::copy(fac.ATinv.begin(), fac.ATinv.end(), ATinv[k].begin() + (size_t)p * L.blk_ATinv);
-        std::copy(fac.XT.begin(), fac.XT.end(), XT[k].begin() + (size_t)p * L.blk_XT);
-        std::copy(fac.Sinv.begin(), fac.Sinv.end(), Sinv[k].begin() + (size_t)p * L.blk_Sinv);
       }
     }
   };

@@ -316,144 +316,256 @@ std::vector<double> submatrix(const LocalSystem& sys, const std::vector<int>& r,
 
 }  // namespace
 
-bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
-                         LevelFactors* out, std::string* err) {
-  const int s = sub.s;
-  // ---- subdomain interior: cells [0, s)^3 ------------------------------------------
+namespace {
+
+// The local matrices of one level, with h and alpha factored out: every element matrix
+// is alpha h K1 + h^3 M1 (K1, M1 those of the unit cube), so each block below is
+// assembled once per (s, boundary choice) from K1 and M1 and scaled per problem.
+struct TypePattern {
+  int nG = 0;                       // interface unknowns of the patch (0: no patch)
+  std::vector<int> Gslot;           // slot of each
+  std::vector<int> bstart;          // interior unknowns grouped by subdomain: block starts
+  std::vector<double> KGG, MGG;     // nG x nG
+  std::vector<double> KII, MII;     // per block b: nb x nb, stored one after another
+  std::vector<double> KIG, MIG;     // per block b: nb x nG, stored one after another
+};
+
+struct LevelPattern {
+  int nI = 0, nB = 0;
+  std::vector<double> KII, MII, KIB, MIB;   // subdomain: nI x nI, nI x nB
+  TypePattern type[27];
+};
+
+void split_km(const LocalSystem& a1, const LocalSystem& a0, const std::vector<int>& r, const std::vector<int>& c,
+              std::vector<double>* K, std::vector<double>* M) {
+  const std::vector<double> A1 = submatrix(a1, r, c), A0 = submatrix(a0, r, c);
+  K->resize(A1.size());
+  M->resize(A1.size());
+  for (size_t i = 0; i < A1.size(); ++i) {
+    (*M)[i] = A0[i];
+    (*K)[i] = A1[i] - A0[i];
+  }
+}
+
+LevelPattern make_pattern(int s, bool boundary_patches) {
+  LevelPattern P;
   {
     std::vector<std::array<int, 3>> cells;
     for (int z = 0; z < s; ++z)
       for (int y = 0; y < s; ++y)
         for (int x = 0; x < s; ++x) cells.push_back({x, y, z});
-    LocalSystem sys;
-    assemble_cells(cells, h, alpha, &sys);
-    auto dofs = interior_dofs(s);
-    std::vector<int> I;
-    for (auto& q : dofs) I.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
-    out->ATinv = submatrix(sys, I, I);
-    if (!spd_inverse(out->ATinv, (int)I.size())) {
-      *err = "subdomain matrix A_T is not positive definite";
+    LocalSystem a1, a0;
+    assemble_cells(cells, 1.0, 1.0, &a1);
+    assemble_cells(cells, 1.0, 0.0, &a0);
+    std::vector<int> I, Bd;
+    for (auto& q : interior_dofs(s)) I.push_back(a1.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+    for (auto& q : boundary_dofs(s)) Bd.push_back(a1.index.at(Key(q.d, q.dx, q.dy, q.dz)));
+    P.nI = (int)I.size();
+    P.nB = (int)Bd.size();
+    split_km(a1, a0, I, I, &P.KII, &P.MII);
+    split_km(a1, a0, I, Bd, &P.KIB, &P.MIB);
+  }
+  const std::vector<Slot> slots = vertex_slots(s);
+  for (int type = 0; type < 27; ++type) {
+    const int t[3] = {type % 3, (type / 3) % 3, type / 9};
+    const int nb = (t[0] != 1) + (t[1] != 1) + (t[2] != 1);
+    if (nb == 3 || (!boundary_patches && nb > 0)) continue;
+    int lo[3], hi[3];   // present cells [lo, hi) relative to the vertex node
+    for (int ax = 0; ax < 3; ++ax) {
+      lo[ax] = (t[ax] == 0) ? 0 : -s;
+      hi[ax] = (t[ax] == 2) ? 0 : s;
+    }
+    std::vector<std::array<int, 3>> cells;
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) cells.push_back({x, y, z});
+    LocalSystem a1, a0;
+    assemble_cells(cells, 1.0, 1.0, &a1);
+    assemble_cells(cells, 1.0, 0.0, &a0);
+    // an edge is Dirichlet if it lies in a boundary plane (node coordinate 0 along a
+    // boundary axis, for an axis other than its direction)
+    auto dirichlet = [&](const Key& k) {
+      const int d = std::get<0>(k);
+      const int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+      for (int ax = 0; ax < 3; ++ax)
+        if (ax != d && t[ax] != 1 && o[ax] == 0) return true;
+      return false;
+    };
+    auto inside_cells = [&](const Key& k) {
+      const int d = std::get<0>(k);
+      const int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax == d) {
+          if (o[ax] < lo[ax] || o[ax] >= hi[ax]) return false;
+        } else if (o[ax] < lo[ax] || o[ax] > hi[ax]) {
+          return false;
+        }
+      }
+      return true;
+    };
+    TypePattern& T = P.type[type];
+    std::vector<int> G;
+    for (size_t si = 0; si < slots.size(); ++si) {
+      const Key k(slots[si].d, slots[si].dx, slots[si].dy, slots[si].dz);
+      if (!inside_cells(k) || dirichlet(k)) continue;
+      G.push_back(a1.index.at(k));
+      T.Gslot.push_back((int)si);
+    }
+    T.nG = (int)G.size();
+    if (T.nG == 0) continue;
+    // interior unknowns of the patch, grouped by subdomain (floor(o / s) across)
+    std::map<std::array<int, 3>, std::vector<int>> blocks;
+    for (int e = 0; e < a1.N; ++e) {
+      const Key& k = a1.keys[e];
+      const int d = std::get<0>(k);
+      const int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
+      bool interior = true;
+      for (int ax = 0; ax < 3; ++ax)
+        if (ax != d && ((o[ax] % s) + s) % s == 0) interior = false;
+      if (!interior || dirichlet(k)) continue;
+      std::array<int, 3> blk;
+      for (int ax = 0; ax < 3; ++ax) blk[ax] = (o[ax] - ((o[ax] % s) + s) % s) / s;
+      blocks[blk].push_back(e);
+    }
+    split_km(a1, a0, G, G, &T.KGG, &T.MGG);
+    T.bstart.push_back(0);
+    for (auto& kv : blocks) {
+      std::vector<double> K, M;
+      split_km(a1, a0, kv.second, kv.second, &K, &M);
+      T.KII.insert(T.KII.end(), K.begin(), K.end());
+      T.MII.insert(T.MII.end(), M.begin(), M.end());
+      split_km(a1, a0, kv.second, G, &K, &M);
+      T.KIG.insert(T.KIG.end(), K.begin(), K.end());
+      T.MIG.insert(T.MIG.end(), M.begin(), M.end());
+      T.bstart.push_back(T.bstart.back() + (int)kv.second.size());
+    }
+  }
+  return P;
+}
+
+// The pattern of (s, boundary choice), built on first use (thread-safe: static locals of
+// the four possible keys are initialised once).
+const LevelPattern& level_pattern(int s, bool boundary_patches) {
+  if (s == 2) {
+    if (boundary_patches) {
+      static const LevelPattern p = make_pattern(2, true);
+      return p;
+    }
+    static const LevelPattern p = make_pattern(2, false);
+    return p;
+  }
+  if (boundary_patches) {
+    static const LevelPattern p = make_pattern(4, true);
+    return p;
+  }
+  static const LevelPattern p = make_pattern(4, false);
+  return p;
+}
+
+// out = a K + b M elementwise
+void combine(const double* K, const double* M, size_t n, double a, double b, double* out) {
+  for (size_t i = 0; i < n; ++i) out[i] = a * K[i] + b * M[i];
+}
+
+}  // namespace
+
+template <typename T>
+bool build_level_factors_into(double h, double alpha, const SubInfo& sub, bool boundary_patches, T* ATinv_out,
+                              T* XT_out, T* Sinv_out, std::string* err) {
+  const int s = sub.s;
+  if (s != 2 && s != 4) {
+    *err = "subdomain size must be 2 or 4";
+    return false;
+  }
+  const LevelPattern& P = level_pattern(s, boundary_patches);
+  const double ka = alpha * h, mb = h * h * h;   // element matrices: alpha h K1 + h^3 M1
+  // ---- subdomain interior ------------------------------------------------------------
+  const int nI = P.nI, nB = P.nB;
+  std::vector<double> ATinv((size_t)nI * nI);
+  combine(P.KII.data(), P.MII.data(), P.KII.size(), ka, mb, ATinv.data());
+  if (!spd_inverse(ATinv, nI)) {
+    *err = "subdomain matrix A_T is not positive definite";
+    return false;
+  }
+  // X_T = A_T^{-1} A_{I, dT}: maps the boundary values of T to (minus) the
+  // discrete-harmonic extension into its interior
+  std::vector<double> AIB((size_t)nI * nB), XT((size_t)nI * nB, 0.0);
+  combine(P.KIB.data(), P.MIB.data(), AIB.size(), ka, mb, AIB.data());
+  for (int i = 0; i < nI; ++i)
+    for (int k = 0; k < nI; ++k) {
+      const double a = ATinv[(size_t)i * nI + k];
+      for (int j = 0; j < nB; ++j) XT[(size_t)i * nB + j] += a * AIB[(size_t)k * nB + j];
+    }
+  for (size_t i = 0; i < ATinv.size(); ++i) ATinv_out[i] = (T)ATinv[i];
+  for (size_t i = 0; i < XT.size(); ++i) XT_out[i] = (T)XT[i];
+  // ---- vertex patches, one per type: S = A_GG - sum over subdomain blocks of
+  //      A_GI A_II^{-1} A_IG, then S^{-1}; entries of absent types and slots are left
+  //      as they are (the caller's zeros) ------------------------------------------------
+  const int np = sub.npad;
+  std::vector<double> S, AII, AIG, X;
+  for (int type = 0; type < 27; ++type) {
+    const TypePattern& Tp = P.type[type];
+    const int nG = Tp.nG;
+    if (nG == 0) continue;
+    S.resize((size_t)nG * nG);
+    combine(Tp.KGG.data(), Tp.MGG.data(), S.size(), ka, mb, S.data());
+    size_t oII = 0, oIG = 0;
+    for (size_t b = 0; b + 1 < Tp.bstart.size(); ++b) {
+      const int nb = Tp.bstart[b + 1] - Tp.bstart[b];
+      AII.resize((size_t)nb * nb);
+      AIG.resize((size_t)nb * nG);
+      combine(Tp.KII.data() + oII, Tp.MII.data() + oII, AII.size(), ka, mb, AII.data());
+      combine(Tp.KIG.data() + oIG, Tp.MIG.data() + oIG, AIG.size(), ka, mb, AIG.data());
+      oII += AII.size();
+      oIG += AIG.size();
+      if (!spd_inverse(AII, nb)) {
+        *err = "patch interior matrix is not positive definite";
+        return false;
+      }
+      // X = A_II^{-1} A_IG, S -= A_IG^T X
+      X.assign((size_t)nb * nG, 0.0);
+      for (int i = 0; i < nb; ++i)
+        for (int k = 0; k < nb; ++k) {
+          const double a = AII[(size_t)i * nb + k];
+          for (int j = 0; j < nG; ++j) X[(size_t)i * nG + j] += a * AIG[(size_t)k * nG + j];
+        }
+      for (int i = 0; i < nG; ++i)
+        for (int k = 0; k < nb; ++k) {
+          const double a = AIG[(size_t)k * nG + i];
+          if (a == 0.0) continue;
+          for (int j = 0; j < nG; ++j) S[(size_t)i * nG + j] -= a * X[(size_t)k * nG + j];
+        }
+    }
+    for (int i = 0; i < nG; ++i)     // symmetrise against rounding
+      for (int j = 0; j < i; ++j) {
+        const double v = 0.5 * (S[(size_t)i * nG + j] + S[(size_t)j * nG + i]);
+        S[(size_t)i * nG + j] = S[(size_t)j * nG + i] = v;
+      }
+    if (!spd_inverse(S, nG)) {
+      *err = "vertex Schur complement is not positive definite";
       return false;
     }
-    // X_T = A_T^{-1} A_{I, dT}: maps the boundary values of T to (minus) the
-    // discrete-harmonic extension into its interior
-    auto bd = boundary_dofs(s);
-    std::vector<int> Bd;
-    for (auto& q : bd) Bd.push_back(sys.index.at(Key(q.d, q.dx, q.dy, q.dz)));
-    std::vector<double> AIB = submatrix(sys, I, Bd);
-    const int nI = (int)I.size(), nB = (int)Bd.size();
-    out->XT.assign((size_t)nI * nB, 0.0);
-    for (int i = 0; i < nI; ++i)
-      for (int k = 0; k < nI; ++k) {
-        const double a = out->ATinv[(size_t)i * nI + k];
-        for (int j = 0; j < nB; ++j) out->XT[(size_t)i * nB + j] += a * AIB[(size_t)k * nB + j];
-      }
+    T* dst = Sinv_out + (size_t)type * np * np;
+    for (int i = 0; i < nG; ++i)
+      for (int j = 0; j < nG; ++j) dst[(size_t)Tp.Gslot[i] * np + Tp.Gslot[j]] = (T)S[(size_t)i * nG + j];
   }
-  // ---- vertex patches, one per type ---------------------------------------------------
-  const int np = sub.npad;
-  out->Sinv.assign((size_t)27 * np * np, 0.0);
-  out->S27.assign((size_t)27 * np * np, 0.0);
-  auto slots = vertex_slots(s);
-  for (int tz = 0; tz < 3; ++tz)
-    for (int ty = 0; ty < 3; ++ty)
-      for (int tx = 0; tx < 3; ++tx) {
-        int t[3] = {tx, ty, tz};
-        int nb = (tx != 1) + (ty != 1) + (tz != 1);
-        if (nb == 3) continue;
-        if (!boundary_patches && nb > 0) continue;
-        int type = tx + 3 * ty + 9 * tz;
-        int lo[3], hi[3];   // present cells [lo, hi) relative to the vertex node
-        for (int ax = 0; ax < 3; ++ax) {
-          lo[ax] = (t[ax] == 0) ? 0 : -s;
-          hi[ax] = (t[ax] == 2) ? 0 : s;
-        }
-        std::vector<std::array<int, 3>> cells;
-        for (int z = lo[2]; z < hi[2]; ++z)
-          for (int y = lo[1]; y < hi[1]; ++y)
-            for (int x = lo[0]; x < hi[0]; ++x) cells.push_back({x, y, z});
-        LocalSystem sys;
-        assemble_cells(cells, h, alpha, &sys);
-        // an edge is Dirichlet if it lies in a boundary plane (node coordinate 0 along a
-        // boundary axis, for an axis other than its direction)
-        auto dirichlet = [&](const Key& k) {
-          int d = std::get<0>(k);
-          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
-          for (int ax = 0; ax < 3; ++ax)
-            if (ax != d && t[ax] != 1 && o[ax] == 0) return true;
-          return false;
-        };
-        auto inside_cells = [&](const Key& k) {
-          int d = std::get<0>(k);
-          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
-          for (int ax = 0; ax < 3; ++ax) {
-            if (ax == d) { if (o[ax] < lo[ax] || o[ax] >= hi[ax]) return false; }
-            else { if (o[ax] < lo[ax] || o[ax] > hi[ax]) return false; }
-          }
-          return true;
-        };
-        std::vector<int> G, Gslot, I;
-        for (size_t si = 0; si < slots.size(); ++si) {
-          Key k(slots[si].d, slots[si].dx, slots[si].dy, slots[si].dz);
-          if (!inside_cells(k) || dirichlet(k)) continue;
-          G.push_back(sys.index.at(k));
-          Gslot.push_back((int)si);
-        }
-        for (int e = 0; e < sys.N; ++e) {
-          const Key& k = sys.keys[e];
-          int d = std::get<0>(k);
-          int o[3] = {std::get<1>(k), std::get<2>(k), std::get<3>(k)};
-          bool interior = true;
-          for (int ax = 0; ax < 3; ++ax)
-            if (ax != d) {
-              int r = ((o[ax] % s) + s) % s;
-              if (r == 0) interior = false;
-            }
-          if (interior && !dirichlet(k)) I.push_back(e);
-        }
-        if (G.empty()) continue;
-        const int nG = (int)G.size(), nIp = (int)I.size();
-        std::vector<double> S = submatrix(sys, G, G);
-        if (nIp > 0) {
-          std::vector<double> AII = submatrix(sys, I, I);
-          std::vector<double> AIG = submatrix(sys, I, G);
-          if (!spd_inverse(AII, nIp)) {
-            *err = "patch interior matrix is not positive definite";
-            return false;
-          }
-          // X = AII^{-1} AIG, S -= AIG^T X
-          std::vector<double> X((size_t)nIp * nG, 0.0);
-          for (int i = 0; i < nIp; ++i)
-            for (int k = 0; k < nIp; ++k) {
-              double a = AII[(size_t)i * nIp + k];
-              if (a == 0.0) continue;
-              for (int j = 0; j < nG; ++j) X[(size_t)i * nG + j] += a * AIG[(size_t)k * nG + j];
-            }
-          for (int i = 0; i < nG; ++i)
-            for (int k = 0; k < nIp; ++k) {
-              double a = AIG[(size_t)k * nG + i];
-              if (a == 0.0) continue;
-              for (int j = 0; j < nG; ++j) S[(size_t)i * nG + j] -= a * X[(size_t)k * nG + j];
-            }
-        }
-        for (int i = 0; i < nG; ++i)     // symmetrise against rounding
-          for (int j = 0; j < i; ++j) {
-            double v = 0.5 * (S[(size_t)i * nG + j] + S[(size_t)j * nG + i]);
-            S[(size_t)i * nG + j] = S[(size_t)j * nG + i] = v;
-          }
-        std::vector<double> Si = S;
-        if (!spd_inverse(Si, nG)) {
-          *err = "vertex Schur complement is not positive definite";
-          return false;
-        }
-        double* dst = &out->Sinv[(size_t)type * np * np];
-        double* dsS = &out->S27[(size_t)type * np * np];
-        for (int i = 0; i < nG; ++i)
-          for (int j = 0; j < nG; ++j) {
-            dst[(size_t)Gslot[i] * np + Gslot[j]] = Si[(size_t)i * nG + j];
-            dsS[(size_t)Gslot[i] * np + Gslot[j]] = S[(size_t)i * nG + j];
-          }
-      }
   return true;
+}
+
+template bool build_level_factors_into<double>(double, double, const SubInfo&, bool, double*, double*, double*,
+                                               std::string*);
+template bool build_level_factors_into<float>(double, double, const SubInfo&, bool, float*, float*, float*,
+                                              std::string*);
+
+bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
+                         LevelFactors* out, std::string* err) {
+  const int nI = sub.nI;
+  const int nB = 3 * (sub.s + 1) * (sub.s + 1) * sub.s - nI;
+  out->ATinv.assign((size_t)nI * nI, 0.0);
+  out->XT.assign((size_t)nI * nB, 0.0);
+  out->Sinv.assign((size_t)27 * sub.npad * sub.npad, 0.0);
+  return build_level_factors_into<double>(h, alpha, sub, boundary_patches, out->ATinv.data(), out->XT.data(),
+                                          out->Sinv.data(), err);
 }
 
 // ---------------------------------------------------------------------------------

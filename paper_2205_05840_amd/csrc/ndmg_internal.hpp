@@ -79,12 +79,18 @@ struct LevelFactors {
   std::vector<double> ATinv;   // nI x nI
   std::vector<double> XT;      // nI x nB: A_T^{-1} A_{I, boundary of T}
   std::vector<double> Sinv;    // 27 x npad x npad (zero for absent types/slots)
-  std::vector<double> S27;     // same layout, the Schur complements themselves
 };
 
 // Build the factors for a level (h, alpha, s).  Returns false and sets err on failure.
 bool build_level_factors(double h, double alpha, const SubInfo& sub, bool boundary_patches,
                          LevelFactors* out, std::string* err);
+// The same, cast to T and written straight into the caller's arrays (nI x nI, nI x nB,
+// 27 x npad x npad); entries of absent patch types and slots are not written, so Sinv
+// must hold zeros there.  The local matrices of each (s, boundary choice) are assembled
+// once per process with h and alpha factored out.
+template <typename T>
+bool build_level_factors_into(double h, double alpha, const SubInfo& sub, bool boundary_patches, T* ATinv,
+                              T* XT, T* Sinv, std::string* err);
 
 // Interface slots of the edge space of a coarse edge along axis a (Sec. 3.2.1), offsets
 // from the edge's first node (a multiple of s per axis): s (4 s - 3) edges along a, then
