@@ -19,6 +19,7 @@ implementation of what the GPU library computes, written from the paper:
   * ``contraction`` V-cycle contraction number ||E_k||_a (Sec. 4.2, eq. VCycleRecursion)
   * ``adjoint``    gradients of L = sum_k ||u_k - t_k||^2 w.r.t. b_k and alpha
   * ``coefficient`` alpha with jumps on a grid of boxes: cell-by-cell assembly (Sec. 6)
+  * ``domain``     non-box domains: unions of boxes of the grid, the cube restricted (Sec. 6)
   * ``timestep``   implicit (average-acceleration Newmark) time stepping of Maxwell's
                    equations, each step the model problem (Sec. 1, eq. Maxwell timestep)
 

@@ -38,10 +38,12 @@ class LiteralSmoother:
     """M^{-1} for kind='vertex' (eta defaults to 1/9) or kind='edge' (eta 1/13)."""
 
     def __init__(self, A, n, s=2, kind="vertex", eta=None, damp_interior=True, boundary=True,
-                 inverse="lu"):
+                 inverse="lu", keep=None):
         """inverse: 'lu' (LAPACK solves and inverses) or 'cholesky' (Cholesky solves and
         inverses); two FP64 routes to the same local matrices whose difference measures how
-        far rounding in the setup moves the result."""
+        far rounding in the setup moves the result.  keep: for a domain inside the cube
+        (``oracle.domain``), the cube's unknowns that are Omega's; A is then Omega's matrix
+        and every set is the cube's set intersected with them (empty sets are dropped)."""
         if n % s or n // s < 2:
             raise ValueError("need n divisible by s with at least 2 subdomains per axis")
         self.A, self.n, self.s, self.kind = A.tocsr(), n, s, kind
@@ -53,20 +55,31 @@ class LiteralSmoother:
             self._solve = np.linalg.solve
         self.eta = eta if eta is not None else (1.0 / 9.0 if kind == "vertex" else 1.0 / 13.0)
         self.damp_interior = damp_interior
+        if keep is None:
+            to_local = lambda ix: np.asarray(ix)
+        else:
+            pos = np.full(len(keep), -1)
+            pos[np.asarray(keep)] = np.arange(int(np.count_nonzero(keep)))
+
+            def to_local(ix):
+                q = pos[np.asarray(ix, dtype=np.int64)]
+                return q[q >= 0]
         self.T = []
         self.Iof = {}
         for t in mesh.coarse_elements(n, s):
-            I = mesh.interior_set(n, s, t)
+            I = to_local(mesh.interior_set(n, s, t))
             self.Iof[t] = I
-            self.T.append((I, self._inv(_sub(self.A, I, I))))
+            if len(I):
+                self.T.append((I, self._inv(_sub(self.A, I, I))))
         self.P = []
         if kind == "vertex":
             for v in mesh.coarse_vertices(n, s, boundary):
-                G = mesh.vertex_interface_set(n, s, v)
-                self.P.append(self._patch(G, mesh.patch_elements(n, s, v)))
+                G = to_local(mesh.vertex_interface_set(n, s, v))
+                if len(G):
+                    self.P.append(self._patch(G, mesh.patch_elements(n, s, v)))
         elif kind == "edge":
             for axis, c in mesh.coarse_edges(n, s, boundary):
-                G = mesh.edge_interface_set(n, s, axis, c)
+                G = to_local(mesh.edge_interface_set(n, s, axis, c))
                 if len(G):
                     self.P.append(self._patch(G, mesh.edge_patch_elements(n, s, axis, c)))
         else:

@@ -9,7 +9,7 @@ refined mesh (Sec. 3.1, eq. kthEq).
 import numpy as np
 import scipy.linalg as sla
 
-from . import assemble, coefficient, mesh, smoother as sm, transfer
+from . import assemble, coefficient, domain, mesh, smoother as sm, transfer
 
 
 class Hierarchy:
@@ -17,27 +17,36 @@ class Hierarchy:
 
     def __init__(self, n, alpha, L=1.0, s=2, m=1, kind="vertex", eta=None,
                  factored=None, damp_interior=True, boundary=True, inverse="lu", levels=None,
-                 boxes=None):
+                 boxes=None, active=None):
         """levels: keep only that many levels from the finest down (the coarsest kept
         level is then solved exactly, k = 0 of Fig. 1); None keeps all of them.
         boxes: alpha(x) = alpha * boxes[z][y][x] on an r x r x r grid of boxes (r divides
         the coarsest kept level), every level assembled cell by cell
-        (``oracle.coefficient``) and smoothed by the literal smoother; None: constant."""
+        (``oracle.coefficient``) and smoothed by the literal smoother; None: constant.
+        active: Omega as the boxes of an r x r x r grid that it keeps (``oracle.domain``):
+        every level restricted to Omega's unknowns, the literal smoother on its sets."""
         self.sizes = mesh.level_sizes(n)          # coarsest first
         if levels is not None:
             if not 1 <= levels <= len(self.sizes):
                 raise ValueError("levels out of range")
             self.sizes = self.sizes[len(self.sizes) - levels:]
-        self.alpha, self.L, self.m, self.boxes = alpha, L, m, boxes
-        if boxes is not None and factored:
-            raise ValueError("the factored smoother assumes one alpha for every subdomain")
-        self.A, self.M, self.P = [], [], [None]
+        self.alpha, self.L, self.m, self.boxes, self.active = alpha, L, m, boxes, active
+        if (boxes is not None or active is not None) and factored:
+            raise ValueError("the factored smoother assumes one alpha for every subdomain of the cube")
+        self.A, self.M, self.P, self.R = [], [], [None], []
         for k, nk in enumerate(self.sizes):
             h = L / nk
-            if boxes is None:
+            if boxes is None and active is None:
                 A = assemble.matrix_kron(nk, h, alpha)
             else:
-                A = coefficient.matrix_cells(nk, h, alpha * coefficient.cell_field(nk, boxes))
+                cf = np.ones((1, 1, 1)) if boxes is None else boxes
+                A = coefficient.matrix_cells(nk, h, alpha * coefficient.cell_field(nk, cf))
+            keep = None
+            if active is not None:
+                keep = domain.unknown_mask(nk, active)
+                Rk = domain.restriction(nk, active)
+                A = (Rk @ A @ Rk.T).tocsr()
+                self.R.append(Rk)
             self.A.append(A)
             if k == 0:
                 self.M.append(None)
@@ -46,13 +55,16 @@ class Hierarchy:
             sk = min(s, nk // 2)
             if nk % sk:
                 raise ValueError(f"level with {nk} elements is not divisible by {sk}")
-            use_f = (factored if factored is not None else (nk >= 24)) and boxes is None
+            use_f = (factored if factored is not None else (nk >= 24)) and boxes is None and active is None
             if kind == "vertex" and use_f and damp_interior:
                 e = 1.0 / 9.0 if eta is None else eta
                 self.M.append(sm.FactoredVertexSmoother(A, nk, sk, e, boundary, inverse))
             else:
-                self.M.append(sm.LiteralSmoother(A, nk, sk, kind, eta, damp_interior, boundary, inverse))
-            self.P.append(transfer.prolongation(self.sizes[k - 1]))
+                self.M.append(sm.LiteralSmoother(A, nk, sk, kind, eta, damp_interior, boundary, inverse, keep))
+            P = transfer.prolongation(self.sizes[k - 1])
+            if active is not None:
+                P = (self.R[k] @ P @ self.R[k - 1].T).tocsr()
+            self.P.append(P)
 
     @property
     def J(self):
