@@ -103,7 +103,17 @@ typedef struct ndmg_opts {
                            is refused.  ndmg_curlcurl_form then returns lam^T K_c u with
                            K_c = sum_T coef_T K_T, the derivative of A in alpha.          */
   const double* coef;   /* the r^3 box factors (> 0), host memory, read during ndmg_plan /
-                           ndmg_setup only (the context keeps a copy); NULL when r = 0 */
+                           ndmg_setup only (the context keeps a copy); NULL when r = 0,
+                           or all factors 1 when a domain is given                       */
+  const unsigned char* domain; /* a non-box domain (Sec. 6 names nonconvex domains as an
+                           extension): the boxes of the coef_r grid that Omega keeps
+                           (r^3 flags, nonzero = in Omega, same order as coef), for
+                           instance the cube less one octant.  The unknowns are the edges
+                           whose four cells all lie in Omega (zero tangential trace on
+                           its boundary); every vector keeps zeros at the other edges,
+                           and ndmg_layout's info[5] counts Omega's unknowns.  Same
+                           conditions as coef_r; NULL (default): the whole cube.  Read
+                           during ndmg_plan / ndmg_setup only.                          */
 } ndmg_opts;
 
 /* Fill *o with the defaults above. */

@@ -48,6 +48,7 @@ class ndmg_opts(ctypes.Structure):
         ("dense_n", ctypes.c_int),
         ("coef_r", ctypes.c_int),
         ("coef", ctypes.POINTER(ctypes.c_double)),
+        ("domain", ctypes.POINTER(ctypes.c_ubyte)),
     ]
 
 

@@ -155,12 +155,18 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
   if (o->dense_n < 0 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be in [0, 8]");
   if (o->coef_r < 0 || o->coef_r > 64) return fail(NDMG_EINVAL, "coef_r must be in [0, 64]");
+  if (o->domain && o->coef_r == 0) return fail(NDMG_EINVAL, "a domain needs the box grid: coef_r > 0");
   if (o->coef_r > 0) {
-    if (!o->coef) return fail(NDMG_EINVAL, "coef_r > 0 needs the coef array");
-    if (o->bottom_n > 0) return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) takes a constant alpha");
+    if (!o->coef && !o->domain) return fail(NDMG_EINVAL, "coef_r > 0 needs the coef array or a domain");
+    if (o->bottom_n > 0) return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) takes a constant alpha on the cube");
     const size_t nb = (size_t)o->coef_r * o->coef_r * o->coef_r;
-    for (size_t b = 0; b < nb; ++b)
-      if (!(o->coef[b] > 0.0) || !std::isfinite(o->coef[b])) return fail(NDMG_EINVAL, "coef values must be > 0");
+    size_t inside = 0;
+    for (size_t b = 0; b < nb; ++b) {
+      if (o->coef && (!(o->coef[b] > 0.0) || !std::isfinite(o->coef[b])))
+        return fail(NDMG_EINVAL, "coef values must be > 0");
+      inside += (!o->domain || o->domain[b]) ? 1 : 0;
+    }
+    if (inside == 0) return fail(NDMG_EINVAL, "the domain keeps no box");
   }
   return NDMG_OK;
 }
@@ -190,7 +196,8 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   int64_t Nd = 0;
   if (C.dense_k >= 1) {
     const int64_t nk = sizes[C.dense_k];
-    Nd = 3 * nk * (nk - 1) * (nk - 1);
+    Nd = cf.r > 0 ? (int64_t)ndmg::unknown_offsets(ndmg::make_geom((int)nk, pl.length), cf).size()
+                  : 3 * nk * (nk - 1) * (nk - 1);
     if (Nd > ndmg::kDenseMaxN) return fail(NDMG_EINVAL, "dense level too large");
     // the level vectors at and below the dense level serve the build at setup (nprob x
     // dense_K pairs, dense_K unit columns per problem and recursion pass); at run time only
@@ -215,7 +222,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
     L.o_g = take(vb);
     if (k == 0) {
       const int nc = sizes[k];
-      const int64_t N0 = 3LL * nc * (nc - 1) * (nc - 1);
+      const int64_t N0 = cf.r > 0 ? (int64_t)ndmg::unknown_offsets(L.g, cf).size() : 3LL * nc * (nc - 1) * (nc - 1);
       if (N0 > 1024)
         return fail(NDMG_EINVAL, "n = " + std::to_string(n) + ": the coarsest level (" + std::to_string(nc) +
                                      "^3, solved exactly) has " + std::to_string(N0) +
@@ -414,11 +421,17 @@ int make_plan(int nprob, const int* ns, double length, int nrhs, const ndmg_opts
   NDMG_TRY(check_opts(o_in, &pl->opts));
   pl->coef.clear();
   if (pl->opts.coef_r > 0) {
-    if (nprob != 1) return fail(NDMG_EINVAL, "a coefficient with jumps (coef_r > 0) serves a single problem");
+    if (nprob != 1) return fail(NDMG_EINVAL, "a coefficient with jumps or a domain (coef_r > 0) serves a single problem");
     const size_t nb = (size_t)pl->opts.coef_r * pl->opts.coef_r * pl->opts.coef_r;
-    pl->coef.assign(pl->opts.coef, pl->opts.coef + nb);
+    // box factors, 0 for the boxes outside the domain
+    pl->coef.assign(nb, 1.0);
+    for (size_t b = 0; b < nb; ++b) {
+      if (pl->opts.coef) pl->coef[b] = pl->opts.coef[b];
+      if (pl->opts.domain && !pl->opts.domain[b]) pl->coef[b] = 0.0;
+    }
   }
   pl->opts.coef = nullptr;
+  pl->opts.domain = nullptr;
   for (int p = 0; p < nprob; ++p) {
     if (ns[p] < 2) return fail(NDMG_EINVAL, "n must be >= 2");
     if (ns[p] > 2048) return fail(NDMG_EINVAL, "n too large");
@@ -560,16 +573,23 @@ bool build_gen_factors(const LevelHost& L, double alpha, T* xc, T* ex, T* sp, st
     ndmg::patch_type_axes(tb.kind, geom, t);
     const std::vector<ndmg::Slot> slots = tb.kind == 0 ? ndmg::vertex_slots(s) : ndmg::edge_slots(s, geom / 9);
     const std::vector<std::array<int, 3>> cells = ndmg::patch_cells(tb.kind, geom, s);
-    if (jumps) {   // each cell takes the alpha of its subdomain (offset floor(o / s) in {-1, 0})
+    std::vector<std::array<int, 3>> kept;
+    std::vector<char> pres_in;
+    if (jumps) {   // each cell takes the alpha of its subdomain (offset floor(o / s) in {-1, 0});
+                   // cells of subdomains outside the domain (factor 0) are left out
       cell_alpha.clear();
       for (const auto& c : cells) {
         int o = 0;
         for (int ax = 0; ax < 3; ++ax) o |= (c[ax] >= 0 ? 1 : 0) << ax;
+        if (!(tb.keyP[type][o] > 0.0)) continue;
+        kept.push_back(c);
         cell_alpha.push_back(alpha * tb.keyP[type][o]);
       }
+      pres_in.assign(tb.presentP.begin() + (size_t)type * tb.npadP,
+                     tb.presentP.begin() + (size_t)type * tb.npadP + slots.size());
     }
-    if (!ndmg::patch_inverse(cells, slots, t, s, L.g.h, alpha, tb.npadP, buf.data(), &present, err,
-                             jumps ? &cell_alpha : nullptr))
+    if (!ndmg::patch_inverse(jumps ? kept : cells, slots, t, s, L.g.h, alpha, tb.npadP, buf.data(), &present, err,
+                             jumps ? &cell_alpha : nullptr, jumps ? &pres_in : nullptr))
       return false;
     for (size_t j = 0; j < slots.size(); ++j)
       if (present[j] != tb.presentP[(size_t)type * tb.npadP + j]) {
@@ -751,7 +771,7 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
       NDMG_TRY(stg.put_vec(c, L.o_gcc, L.gt.ccodes));
       NDMG_TRY(stg.put_vec(c, L.o_gcodes, L.gt.codes));
       if (k == C.dense_k) {
-        L.map = ndmg::unknown_offsets(L.g);
+        L.map = ndmg::unknown_offsets(L.g, pl.boxes());
         if ((int)L.map.size() != L.Nd) return fail(NDMG_EINVAL, "internal: dense level size mismatch");
         NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
       }
@@ -1331,6 +1351,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->dense_n = 8;
   o->coef_r = 0;
   o->coef = nullptr;
+  o->domain = nullptr;
 }
 
 const char* ndmg_last_error(void) { return g_err.c_str(); }
@@ -1403,7 +1424,8 @@ int ndmg_layout(const ndmg_ctx* c, int level, int64_t info[6]) {
   info[2] = g.B;
   info[3] = g.len;
   info[4] = nl;
-  info[5] = 3LL * g.n * (g.n - 1) * (g.n - 1);
+  info[5] = c->plan.coef.empty() ? 3LL * g.n * (g.n - 1) * (g.n - 1)
+                                 : (int64_t)ndmg::unknown_offsets(g, c->plan.boxes()).size();
   return NDMG_OK;
 }
 
@@ -1484,7 +1506,8 @@ int ndmg_maxwell_step(ndmg_ctx* c, const double* f, double* u, double* v, double
   const ndmg::Geom& g = C.lv.back().g;
   const int64_t len = g.len;
   const ndmg::Bat all = class_batch(c, C, false);
-  const ndmg::Bat mass{C.count, C.nrhs, at<double>(c, C.o_alpha0), nullptr};
+  // the mass matrix: the operator at alpha = 0 (with coefficient boxes, on the same domain)
+  const ndmg::Bat mass{C.count, C.nrhs, at<double>(c, C.o_alpha0), nullptr, all.coef, all.coef_r};
   double* w = at<double>(c, C.o_tw);
   double* rhs = at<double>(c, C.o_tb);
   double* t = at<double>(c, C.o_pz);   // CG vectors, free outside the solve
@@ -1694,7 +1717,8 @@ int ndmg_assemble_rhs(ndmg_ctx* c, const double* f, double* b) {
       return s;
     }();
     for (int pr = 0; pr < C.count; ++pr)
-      NDMG_HIP(ndmg::launch_assemble_rhs(f + f0 + pr * flen, b + C.vec_off + pr * C.vlen, g, c->st));
+      NDMG_HIP(ndmg::launch_assemble_rhs(f + f0 + pr * flen, b + C.vec_off + pr * C.vlen, g, c->st,
+                                         pl.coef.empty() ? nullptr : at<double>(c, C.o_coef), pl.opts.coef_r));
   }
   return NDMG_OK;
 }

@@ -699,11 +699,15 @@ void patch_type_axes(int kind, int type, int t[3]) {
 
 bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
                    const int t[3], int s, double h, double alpha, int npad, double* out,
-                   std::vector<char>* present, std::string* err, const std::vector<double>* cell_alpha) {
+                   std::vector<char>* present, std::string* err, const std::vector<double>* cell_alpha,
+                   const std::vector<char>* present_in) {
   LocalSystem sys;
   assemble_cells(cells, h, alpha, &sys, cell_alpha);
   auto dirichlet = [&](int d, const int o[3]) { return in_boundary_plane(t, d, o); };
-  *present = patch_slots_present(cells, slots, t);
+  if (present_in)
+    *present = *present_in;
+  else
+    *present = patch_slots_present(cells, slots, t);
   std::vector<int> G, Gslot;
   for (size_t j = 0; j < slots.size(); ++j) {
     if (!(*present)[j]) continue;
@@ -808,6 +812,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
       for (int b = 0; b < nH; ++b)
         for (int a = 0; a < nH; ++a) {
           const int t = jumps ? ((s * c / w) * cf.r + s * b / w) * cf.r + s * a / w : 0;
+          if (jumps && !(cf.v[t] > 0.0)) continue;   // a box outside the domain
           byType[t].push_back(anchor(s * a, s * b, s * c));
         }
     for (int t = 0; t < tb.ntypesI; ++t) {
@@ -843,6 +848,8 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
   std::vector<std::vector<int64_t>> grel(27);
   std::vector<std::vector<int64_t>> byType;     // anchors per type
   std::map<std::pair<int, std::array<double, 8>>, int> keyIndex;
+  std::vector<std::vector<char>> presByType;   // with boxes: slots present per type
+  std::vector<char> hasSlots;
   if (!jumps) byType.assign(27, {});
   for (int type = 0; type < 27; ++type) {
     int t[3];
@@ -890,12 +897,23 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
           const auto k = std::make_pair(type, key);
           auto it = keyIndex.find(k);
           if (it == keyIndex.end()) {
+            // slots present: those of the geometric type whose edge lies in the domain
+            // (the same for every patch of the key: the edge's cells are the patch's)
+            std::vector<char> pres(tb.npadP, 0);
+            bool anyp = false;
+            for (int j = 0; j < nslots; ++j) {
+              const Slot& q = slots[j];
+              pres[j] = gpres[type][j] && cf.edge_in(n, q.d, s * x + q.dx, s * y + q.dy, s * z + q.dz);
+              anyp = anyp || pres[j];
+            }
             it = keyIndex.emplace(k, (int)tb.geomP.size()).first;
             tb.geomP.push_back(type);
             tb.keyP.push_back(key);
+            presByType.push_back(pres);
             byType.emplace_back();
+            hasSlots.push_back(anyp);
           }
-          byType[it->second].push_back(anchor(s * x, s * y, s * z));
+          if (hasSlots[it->second]) byType[it->second].push_back(anchor(s * x, s * y, s * z));
         }
   }
   tb.ntypes = jumps ? (int)tb.geomP.size() : 27;
@@ -905,8 +923,9 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
     const int geom = jumps ? tb.geomP[ti] : ti;
     if (byType[ti].empty() || gpres[geom].empty()) continue;
     for (int j = 0; j < tb.npadP; ++j) {
-      tb.relP[(size_t)ti * tb.npadP + j] = grel[geom][j];
-      tb.presentP[(size_t)ti * tb.npadP + j] = gpres[geom][j];
+      const char pr = jumps ? presByType[ti][j] : gpres[geom][j];
+      tb.relP[(size_t)ti * tb.npadP + j] = pr ? grel[geom][j] : kGenAbsentHost;
+      tb.presentP[(size_t)ti * tb.npadP + j] = pr;
     }
     const size_t first = tb.unitsP.size();
     tb.unitsP.insert(tb.unitsP.end(), byType[ti].begin(), byType[ti].end());
@@ -925,7 +944,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
   // interface unknowns (not inside a subdomain), in layout order, and the patch results
   // summed on each, in the order of the patches
   std::vector<int> gpos((size_t)g.len, -1);
-  for (int64_t e : unknown_offsets(g)) {
+  for (int64_t e : unknown_offsets(g, cf)) {
     const int d = (int)(e / g.B);
     int64_t r = e - d * g.B;
     const int z = (int)(r / g.plane);
@@ -987,7 +1006,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
   return true;
 }
 
-std::vector<int64_t> unknown_offsets(const Geom& g) {
+std::vector<int64_t> unknown_offsets(const Geom& g, const CoefBoxes& cf) {
   const int n = g.n;
   std::vector<int64_t> off;
   off.reserve((size_t)3 * n * (n - 1) * (n - 1));
@@ -1001,6 +1020,7 @@ std::vector<int64_t> unknown_offsets(const Geom& g) {
             if (ax == d) ok &= (o[ax] < n);
             else ok &= (o[ax] >= 1 && o[ax] <= n - 1);
           }
+          if (ok && cf.r > 0) ok = cf.edge_in(n, d, x, y, z);
           if (ok) off.push_back(d * g.B + (int64_t)z * g.plane + (int64_t)y * g.P + x);
         }
   return off;
@@ -1009,8 +1029,8 @@ std::vector<int64_t> unknown_offsets(const Geom& g) {
 bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
                   std::vector<int64_t>* map, std::string* err, const CoefBoxes& cf) {
   const int n = g.n;
-  // unknowns: interior edges in padded-layout order
-  *map = unknown_offsets(g);
+  // unknowns: interior edges (inside the domain) in padded-layout order
+  *map = unknown_offsets(g, cf);
   std::map<Key, int> idx;
   for (size_t u = 0; u < map->size(); ++u) {
     int64_t r = (*map)[u];
@@ -1034,7 +1054,9 @@ bool build_coarse(const Geom& g, double alpha, std::vector<double>* A0inv,
   for (int z = 0; z < n; ++z)
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x) {
-        const double ac = alpha * cf.at(n, x, y, z);
+        const double fac = cf.at(n, x, y, z);
+        if (!(fac > 0.0)) continue;   // outside the domain
+        const double ac = alpha * fac;
         if (ac != Ealpha) {
           Ealpha = ac;
           element_matrix(g.h, Ealpha, 1.0, E);

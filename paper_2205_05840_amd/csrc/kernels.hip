@@ -110,6 +110,26 @@ __device__ __forceinline__ T apply_at(const T* __restrict__ u, const DGeom& g, i
   return ah * curl + h3 * mass;
 }
 
+// With coefficient boxes, a box of factor 0 lies outside the domain (a non-box domain,
+// Sec. 6): the edge of direction d at node o is an unknown only if its (up to four)
+// cells, o[d] along d and o[b] - 1 .. o[b], o[c] - 1 .. o[c] across, all lie in boxes of
+// positive factor.  The caller has checked is_unknown (so the cells are inside the cube).
+__device__ __forceinline__ bool edge_in_domain(const double* __restrict__ coef, int r, int n, int d, const int o[3]) {
+  const int b = (d + 1) % 3, c = (d + 2) % 3, w = n / r;
+  bool in = true;
+#pragma unroll
+  for (int db = 0; db < 2; ++db)
+#pragma unroll
+    for (int dc = 0; dc < 2; ++dc) {
+      int q[3];
+      q[d] = o[d];
+      q[b] = o[b] - 1 + db;
+      q[c] = o[c] - 1 + dc;
+      in = in && coef[((q[2] / w) * r + q[1] / w) * r + q[0] / w] > 0.0;
+    }
+  return in;
+}
+
 // The same with one alpha per cell (a coefficient with jumps, Sec. 6): the curl part sums
 // alpha_T K_T over the four cells T around the edge, so each face term of the RT0 mass
 // takes the alphas of the two cells on either side of the face.  ah = alpha h (alpha the
@@ -175,7 +195,7 @@ __device__ __forceinline__ void apply_node_coef(const T* __restrict__ x, const T
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T v = T(0);
-    if (is_unknown(g, d, i, j, k)) {
+    if (is_unknown(g, d, i, j, k) && edge_in_domain(coef, r, g.n, d, o)) {
       const T ax = apply_at_coef(x, g, d, p, o, ah, h3, coef, r);
       v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
     }
@@ -231,14 +251,16 @@ __global__ void __launch_bounds__(64) k_apply_plane(const T* __restrict__ x, con
 // gc at the three edges of coarse node (I, J, K)
 template <typename T>
 __device__ __forceinline__ void restrict_node(const T* __restrict__ rf, T* __restrict__ gc, const DGeom& f,
-                                              const DGeom& c, int I, int J, int K) {
+                                              const DGeom& c, int I, int J, int K,
+                                              const double* __restrict__ coef = nullptr, int coef_r = 0) {
   const int64_t stf[3] = {1, (int64_t)f.P, f.plane};
   const int64_t pc = lin(c, I, J, K);
   const int64_t pf = lin(f, 2 * I, 2 * J, 2 * K);
+  const int oc[3] = {I, J, K};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     T v = T(0);
-    if (is_unknown(c, a, I, J, K)) {
+    if (is_unknown(c, a, I, J, K) && (coef == nullptr || edge_in_domain(coef, coef_r, c.n, a, oc))) {
       const int b = (a + 1) % 3, cc = (a + 2) % 3;
       const T* __restrict__ r = rf + a * f.B + pf;
       T acc = T(0);
@@ -263,7 +285,7 @@ __global__ void __launch_bounds__(64) k_restrict(const T* __restrict__ rf, T* __
   const int pair = bk.x / nbx;
   int I, J, K;
   if (!box_position(bk, c.n, nbx, packed, I, J, K) || inactive(bt, pair)) return;
-  restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K);
+  restrict_node(rf + (int64_t)pair * vlen(f), gc + (int64_t)pair * vlen(c), f, c, I, J, K, bt.coef, bt.coef_r);
 }
 
 // zf += I_{k-1}^k ec at the three edges of fine node (i, j, k)
@@ -1748,7 +1770,8 @@ __global__ void k_lincomb(double* y, const double* x0, double c0, const double* 
 // load vector from 2x2x2 Gauss samples
 // ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_assemble_rhs(const double* __restrict__ f, double* __restrict__ bv,
-                                                     DGeom g, double w8) {
+                                                     DGeom g, double w8, const double* __restrict__ coef,
+                                                     int coef_r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y, k = blockIdx.z;
   if (i > g.n) return;
@@ -1760,7 +1783,7 @@ __global__ void __launch_bounds__(64) k_assemble_rhs(const double* __restrict__ 
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double v = 0.0;
-    if (is_unknown(g, d, i, j, k)) {
+    if (is_unknown(g, d, i, j, k) && (coef == nullptr || edge_in_domain(coef, coef_r, g.n, d, o))) {
       const int b = (d + 1) % 3, c = (d + 2) % 3;
       // the four elements sharing the edge: cell o[d] along d, o[b]-1+eb, o[c]-1+ec across
       for (int ec = 0; ec < 2; ++ec)
@@ -1800,7 +1823,7 @@ __global__ void __launch_bounds__(64) k_curlcurl_form(const double* __restrict__
     const int o[3] = {i, j, k};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      if (is_unknown(g, d, i, j, k))
+      if (is_unknown(g, d, i, j, k) && (coef == nullptr || edge_in_domain(coef, coef_r, g.n, d, o)))
         s += lam[d * g.B + p] * (coef ? apply_at_coef(u, g, d, p, o, h, 0.0, coef, coef_r)
                                       : apply_at(u, g, d, p, h, 0.0));
   }
@@ -2092,9 +2115,11 @@ hipError_t launch_lincomb(double* y, const double* x0, double c0, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st) {
+hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st, const double* coef,
+                               int coef_r) {
   const double w8 = g.h * g.h * g.h / 8.0;
-  hipLaunchKernelGGL(k_assemble_rhs, node_grid(g, nbx64(g.n), 1), dim3(64), 0, st, f, b, dgeom(g), w8);
+  hipLaunchKernelGGL(k_assemble_rhs, node_grid(g, nbx64(g.n), 1), dim3(64), 0, st, f, b, dgeom(g), w8, coef,
+                     coef_r);
   return hipGetLastError();
 }
 

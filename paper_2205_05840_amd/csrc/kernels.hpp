@@ -34,7 +34,8 @@ struct Bat {
   const double* alpha;     // per problem (device)
   const int* act;          // per pair, 0 = skip (converged); nullptr = all active
   const double* coef;      // coefficient boxes (device, r^3, [z][y][x]): alpha(x) = alpha *
-                           // coef[box of x]; nullptr = constant alpha (one problem only)
+                           // coef[box of x], 0 for a box outside the domain; nullptr =
+                           // constant alpha on the cube (one problem only)
   int coef_r;              // boxes per axis (r divides every level's n)
 };
 
@@ -301,7 +302,8 @@ hipError_t launch_lincomb(double* y, const double* x0, double c0, const double* 
                           double c2, int64_t len, const Bat& bt, hipStream_t st);
 
 // b = load vector of f sampled at the 2x2x2 Gauss points (single problem).
-hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st);
+hipError_t launch_assemble_rhs(const double* f, double* b, const Geom& g, hipStream_t st, const double* coef = nullptr,
+                               int coef_r = 0);
 
 // out[0] = lam . (K u) for one pair of vectors (single problem), K = dA/dalpha.
 hipError_t launch_curlcurl_form(const double* lam, const double* u, const Geom& g,

@@ -108,11 +108,13 @@ bool subdomain_factors(int s, double h, double alpha, std::vector<double>* ATinv
 // of axis ax (edges in such a plane through the anchor carry no unknown), 1 otherwise.
 // out (npad x npad, row-major) receives S^{-1} on the present slots and zeros elsewhere;
 // present[j] = 1 for the slots that hold an unknown.  cell_alpha, if given, holds each
-// cell's own alpha (in the order of cells) in place of the common alpha.
+// cell's own alpha (in the order of cells) in place of the common alpha; present_in, if
+// given, names the present slots (a patch cut by the boundary of a non-box domain).
 bool patch_inverse(const std::vector<std::array<int, 3>>& cells, const std::vector<Slot>& slots,
                    const int t[3], int s, double h, double alpha, int npad, double* out,
                    std::vector<char>* present, std::string* err,
-                   const std::vector<double>* cell_alpha = nullptr);
+                   const std::vector<double>* cell_alpha = nullptr,
+                   const std::vector<char>* present_in = nullptr);
 
 // Patch types of the generic smoother.  kind 0 (vertex spaces): type = tx + 3 ty + 9 tz,
 // t = 0 / 1 / 2 for a vertex on the low boundary plane / inside / on the high plane of
@@ -143,6 +145,21 @@ struct CoefBoxes {
     if (r == 0) return 1.0;
     const int w = n / r;
     return v[((size_t)(z / w) * r + (size_t)(y / w)) * r + (size_t)(x / w)];
+  }
+  // a box of factor 0 lies outside the domain (a non-box domain): the edge of direction d
+  // at node (x, y, z) is an unknown only if its four cells lie in boxes of positive factor
+  bool edge_in(int n, int d, int x, int y, int z) const {
+    const int o[3] = {x, y, z};
+    const int b = (d + 1) % 3, c = (d + 2) % 3;
+    for (int db = 0; db < 2; ++db)
+      for (int dc = 0; dc < 2; ++dc) {
+        int q[3];
+        q[d] = o[d];
+        q[b] = o[b] - 1 + db;
+        q[c] = o[c] - 1 + dc;
+        if (!(at(n, q[0], q[1], q[2]) > 0.0)) return false;
+      }
+    return true;
   }
 };
 
@@ -175,8 +192,8 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
                       const CoefBoxes& cf = CoefBoxes{});
 
 // Padded-layout offsets of the interior edges (the unknowns) of a level, direction-major
-// and then in layout order.
-std::vector<int64_t> unknown_offsets(const Geom& g);
+// and then in layout order; with coefficient boxes only those inside the domain.
+std::vector<int64_t> unknown_offsets(const Geom& g, const CoefBoxes& cf = CoefBoxes{});
 
 // Coarsest level: dense inverse of A_0 over its unknowns and the padded offset of each
 // (the order of unknown_offsets).

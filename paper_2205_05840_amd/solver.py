@@ -13,9 +13,10 @@ SMOOTHERS = {"vertex": 0, "edge": 1}
 
 
 def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=None, dense_n=None,
-          smoother="vertex", subdomain=2, coef=None):
-    """ndmg_opts; with coef (an r x r x r array of box factors, [z][y][x]) also the
-    float64 copy the struct points to, which must live through the plan and setup calls."""
+          smoother="vertex", subdomain=2, coef=None, domain=None):
+    """ndmg_opts; with coef (an r x r x r array of box factors, [z][y][x]) or domain (an
+    r x r x r array of flags, the boxes a non-box domain keeps) also the copies the struct
+    points to, which must live through the plan and setup calls."""
     o = _lib.ndmg_default_opts()
     o.smoother = SMOOTHERS[smoother]
     o.subdomain = int(subdomain)
@@ -30,14 +31,23 @@ def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=No
         o.bottom_n = int(bottom_n)
     if dense_n is not None:
         o.dense_n = int(dense_n)
-    keep = None
+    keep = []
     if coef is not None:
-        keep = np.ascontiguousarray(coef, dtype=np.float64)
-        r = keep.shape[0]
-        if keep.shape != (r, r, r):
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        r = c.shape[0]
+        if c.shape != (r, r, r):
             raise ValueError("coef must be an r x r x r array of box factors")
         o.coef_r = r
-        o.coef = keep.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_double))
+        o.coef = c.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_double))
+        keep.append(c)
+    if domain is not None:
+        d = np.ascontiguousarray(np.asarray(domain, dtype=bool), dtype=np.uint8)
+        r = d.shape[0]
+        if d.shape != (r, r, r) or (coef is not None and o.coef_r != r):
+            raise ValueError("domain must be an r x r x r array of flags on the grid of coef")
+        o.coef_r = r
+        o.domain = d.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_ubyte))
+        keep.append(d)
     o._keep = keep
     return o
 
@@ -82,18 +92,20 @@ class Solver(_Context):
     n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace; smoother
     "vertex" (eq. Preconditioner P) or "edge" (eq. Preconditioner E) on subdomains of
     subdomain^3 elements (2 or 4).  coef: an r x r x r array of box factors, alpha(x) =
-    alpha * coef[z][y][x] of x's box (jumps, Sec. 6; r divides the coarsest level).  With
+    alpha * coef[z][y][x] of x's box (jumps, Sec. 6; r divides the coarsest level).
+    domain: an r x r x r array of flags, the boxes a non-box domain keeps (Sec. 6).  With
     nrhs > 1 every call works on nrhs vectors at once ([nrhs, vec_len] tensors), each
     right-hand side with its own CG scalars."""
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
-                 bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2, coef=None):
+                 bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2, coef=None,
+                 domain=None):
         self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
         if self.nrhs > 1 and levels:
             raise ValueError("levels applies to single right-hand-side solvers")
         o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n,
-                  smoother, subdomain, coef)
+                  smoother, subdomain, coef, domain)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:

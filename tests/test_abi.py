@@ -273,3 +273,35 @@ def test_plan_coefficient_rejects(lib):
         lib.ndmg_plan_batched([8, 8], 1.0, 1, _coef_opts(lib, 2))
     ws, tl = lib.ndmg_plan_batched([8], 1.0, 2, _coef_opts(lib, 2))
     assert tl > 0
+
+
+def _domain_opts(lib, active, coef=None):
+    import numpy as np
+    o = _coef_opts(lib, active.shape[0], coef) if coef is not None else lib.ndmg_default_opts()
+    d = np.ascontiguousarray(active.astype(np.uint8))
+    o.coef_r = active.shape[0]
+    o.domain = d.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+    o._keep_d = d
+    return o
+
+
+def test_plan_domain(lib):
+    """A non-box domain plans on the box grid (coef optional); it needs the grid, at least
+    one kept box and a single problem."""
+    import numpy as np
+    fichera = np.ones((2, 2, 2), dtype=bool)
+    fichera[1, 1, 1] = False
+    ws, vl = lib.ndmg_plan(16, 1.0, 1.0, _domain_opts(lib, fichera))
+    _, vl0 = lib.ndmg_plan(16, 1.0, 1.0, lib.ndmg_default_opts())
+    assert vl == vl0 and ws > 0
+    lib.ndmg_plan(16, 1.0, 1.0, _domain_opts(lib, fichera, np.full((2, 2, 2), 2.0)))
+    o = _domain_opts(lib, fichera)
+    o.coef_r = 0                                          # no grid
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan(16, 1.0, 1.0, o)
+    with pytest.raises(lib.NdmgError):                    # keeps nothing
+        lib.ndmg_plan(16, 1.0, 1.0, _domain_opts(lib, np.zeros((2, 2, 2), dtype=bool)))
+    with pytest.raises(lib.NdmgError):                    # 3 does not divide the coarsest level
+        lib.ndmg_plan(16, 1.0, 1.0, _domain_opts(lib, np.ones((3, 3, 3), dtype=bool)))
+    with pytest.raises(lib.NdmgError):                    # one problem only
+        lib.ndmg_plan_batched([16, 16], 1.0, 1, _domain_opts(lib, fichera))
