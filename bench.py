@@ -406,22 +406,56 @@ def cpu_baseline(f, iters_expected, gpu_solutions=None, sample_iters=3):
         for name, u in gpu_solutions.items():
             exact_ref[f"rel_error_{name}"] = float(np.linalg.norm(u[idx] - ue)) / nrm
     del ue
+    # one thread: SciPy's sparse products are single-threaded, and the BLAS pools (which
+    # the dense local products would use) are held to one thread, so that `cores` is exact
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except Exception:
+        limit = None
     t0 = time.perf_counter()
     H = vcycle.Hierarchy(N_ELEM, 1.0)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     pcg.pcg(H.A[-1], b, H.precondition, rtol=RTOL, maxit=sample_iters)
     t = time.perf_counter() - t0
+    threads_timed = blas_threads()
+    if limit is not None:
+        limit.restore_original_limits()
     per_iter = t / sample_iters
     s_solve = per_iter * iters_expected
     ndof = 3 * N_ELEM * (N_ELEM - 1) ** 2
     return {"value": ndof / s_solve, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": (f"{sample_iters} V-cycle-PCG iterations of the 128^3 alpha=1 solve "
                        f"({t:.1f} s, setup {t_setup:.1f} s untimed), scaled to "
-                       f"{iters_expected} iterations; SciPy SpMV single-threaded"),
+                       f"{iters_expected} iterations; one thread (SciPy SpMV, BLAS pools held to 1)"),
             "s_per_solve_est": s_solve,
             "affinity_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model(),
+            "blas_threads": threads_timed,
             "exact": exact_ref}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def blas_threads():
+    """Threads of the BLAS / OpenMP pools loaded in this process (threadpoolctl), per library."""
+    try:
+        import threadpoolctl
+        return {f"{p.get('internal_api')}:{os.path.basename(p.get('filepath', ''))}": p.get("num_threads")
+                for p in threadpoolctl.threadpool_info()}
+    except Exception:
+        return None
 
 
 def kernel_probe(torch, Solver, reps):
