@@ -124,8 +124,13 @@ void ndmg_default_opts(ndmg_opts* o);
  * vector length (in elements) of the padded edge layout of the finest level.
  * The domain is the box (0, box[0]) x (0, box[1]) x (0, box[2]) (Sec. 1: a box with
  * axis-parallel edges) meshed by nx x ny x nz congruent cubes (box[d] / n_d equal; the
- * uniform refinement of Sec. 3.1 keeps them cubes).  This version serves nx = ny = nz
- * = n (>= 2) only: every other box is rejected with NDMG_EINVAL.  alpha: the constant of
+ * uniform refinement of Sec. 3.1 keeps them cubes).  A cube (nx = ny = nz = n >= 2) is
+ * served directly.  Another box is served as a non-box domain (see ndmg_opts.domain)
+ * inside the cube of n = max(n_d) elements per axis and side n h, made of the boxes of
+ * gcd(nx, ny, nz) elements per axis that it covers: vectors, load samples and
+ * ndmg_layout then refer to that cube (zeros outside the box), n / gcd must divide the
+ * coarsest level, and opts may not carry coefficient boxes or a domain of their own.
+ * alpha: the constant of
  * eq. (model problem) (> 0).  levels: 0 for all levels n, n/2, ... while a level is even
  * and its half is >= 2 (Sec. 3.1, h_k = h_{k-1}/2), else the number of levels kept from
  * the finest down (1 = the exact solve alone); the coarsest is solved exactly and must

@@ -1315,9 +1315,14 @@ int setup_common(ndmg_ctx** out, int nprob, const int* ns, double length, const 
 }
 
 // The box (0, box[0]) x (0, box[1]) x (0, box[2]) with nx x ny x nz elements (Sec. 1: a
-// box with axis-parallel edges, meshed by congruent cubes): the elements must be cubes,
-// and the kernels serve nx = ny = nz.  On success *n and *length describe the cube.
-int check_box(int nx, int ny, int nz, const double* box, int* n, double* length) {
+// box with axis-parallel edges, meshed by congruent cubes): the elements must be cubes.  A
+// cube is served directly.  Another box is the domain, inside the cube of n = max(n_d)
+// elements per axis, made of the boxes of g = gcd(nx, ny, nz) elements per axis that it
+// covers (the grid of ndmg_opts.domain with r = n / g): every vector lives in that cube's
+// layout with zeros outside the box.  *opts_out then holds the caller's options with that
+// domain (pointing into *mask, which must outlive the plan or setup call).
+int check_box(int nx, int ny, int nz, const double* box, const ndmg_opts* opts, int* n, double* length,
+              ndmg_opts* opts_out, std::vector<unsigned char>* mask, const ndmg_opts** use) {
   if (!box) return fail(NDMG_EINVAL, "null box");
   if (nx < 2 || ny < 2 || nz < 2) return fail(NDMG_EINVAL, "nx, ny, nz must be >= 2");
   for (int d = 0; d < 3; ++d)
@@ -1326,10 +1331,40 @@ int check_box(int nx, int ny, int nz, const double* box, int* n, double* length)
   for (int d = 1; d < 3; ++d)
     if (std::fabs(h[d] - h[0]) > 1e-12 * h[0])
       return fail(NDMG_EINVAL, "the elements must be cubes: box[d] / n_d must be equal");
-  if (nx != ny || ny != nz)
-    return fail(NDMG_EINVAL, "only cubes are supported: nx = ny = nz (the kernels take one size per axis)");
-  *n = nx;
-  *length = box[0];
+  *use = opts;
+  const int nd[3] = {nx, ny, nz};
+  const int nmax = std::max(nx, std::max(ny, nz));
+  *n = nmax;
+  *length = h[0] * nmax;
+  if (nx == ny && ny == nz) return NDMG_OK;
+  if (opts && (opts->coef_r > 0 || opts->domain))
+    return fail(NDMG_EINVAL, "a box that is not a cube is served as a domain inside a cube and takes no "
+                             "coefficient boxes or domain of its own (give those on the embedding cube)");
+  int g = nx;
+  for (int d = 1; d < 3; ++d) {
+    int a = g, b = nd[d];
+    while (b) {
+      const int t = a % b;
+      a = b;
+      b = t;
+    }
+    g = a;
+  }
+  const int r = nmax / g;
+  if (r > 64) return fail(NDMG_EINVAL, "box too elongated: max(n_d) / gcd(n_d) must be at most 64");
+  mask->assign((size_t)r * r * r, 0);
+  for (int bz = 0; bz < r; ++bz)
+    for (int by = 0; by < r; ++by)
+      for (int bx = 0; bx < r; ++bx)
+        (*mask)[((size_t)bz * r + by) * r + bx] = (bx * g < nx && by * g < ny && bz * g < nz) ? 1 : 0;
+  if (opts)
+    *opts_out = *opts;
+  else
+    ndmg_default_opts(opts_out);
+  opts_out->coef_r = r;
+  opts_out->coef = nullptr;
+  opts_out->domain = mask->data();
+  *use = opts_out;
   return NDMG_OK;
 }
 
@@ -1360,10 +1395,13 @@ int ndmg_plan(int nx, int ny, int nz, const double box[3], double alpha, int lev
               const ndmg_opts* opts, size_t* workspace_bytes, size_t* vec_len) {
   int n = 0;
   double length = 0.0;
-  NDMG_TRY(check_box(nx, ny, nz, box, &n, &length));
+  ndmg_opts embed;
+  std::vector<unsigned char> mask;
+  const ndmg_opts* use = nullptr;
+  NDMG_TRY(check_box(nx, ny, nz, box, opts, &n, &length, &embed, &mask, &use));
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(NDMG_EINVAL, "alpha must be > 0");
   Plan pl;
-  NDMG_TRY(make_plan(1, &n, length, 1, opts, &pl, levels));
+  NDMG_TRY(make_plan(1, &n, length, 1, use, &pl, levels));
   if (workspace_bytes) *workspace_bytes = pl.bytes;
   if (vec_len) *vec_len = (size_t)pl.total_len;
   return NDMG_OK;
@@ -1375,8 +1413,11 @@ int ndmg_setup(ndmg_ctx** out, int nx, int ny, int nz, const double box[3], doub
   *out = nullptr;
   int n = 0;
   double length = 0.0;
-  NDMG_TRY(check_box(nx, ny, nz, box, &n, &length));
-  return setup_common(out, 1, &n, length, &alpha, 1, opts, d_workspace, workspace_bytes, stream, levels);
+  ndmg_opts embed;
+  std::vector<unsigned char> mask;
+  const ndmg_opts* use = nullptr;
+  NDMG_TRY(check_box(nx, ny, nz, box, opts, &n, &length, &embed, &mask, &use));
+  return setup_common(out, 1, &n, length, &alpha, 1, use, d_workspace, workspace_bytes, stream, levels);
 }
 
 int ndmg_plan_batched(int nprob, const int* n, double length, int nrhs, const ndmg_opts* opts,

@@ -89,7 +89,10 @@ class _Context:
 
 class Solver(_Context):
     """V-cycle-preconditioned CG for curl(alpha curl u) + u = f on (0, length)^3 with
-    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace; smoother
+    n^3 cubes, lowest-order Nedelec edge elements and zero tangential trace.  On a box that
+    is not a cube, n = (nx, ny, nz) and length = its three side lengths (cubic elements):
+    vectors and load samples then refer to the cube of max(n_d) elements, with zeros
+    outside the box (the library serves the box as a domain inside that cube).  Smoother
     "vertex" (eq. Preconditioner P) or "edge" (eq. Preconditioner E) on subdomains of
     subdomain^3 elements (2 or 4).  coef: an r x r x r array of box factors, alpha(x) =
     alpha * coef[z][y][x] of x's box (jumps, Sec. 6; r divides the coarsest level).
@@ -101,21 +104,33 @@ class Solver(_Context):
                  boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
                  bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2, coef=None,
                  domain=None):
-        self.n, self.alpha, self.length, self.nrhs = int(n), float(alpha), float(length), int(nrhs)
+        dims = (int(n),) * 3 if np.ndim(n) == 0 else tuple(int(v) for v in n)
+        box = (float(length),) * 3 if np.ndim(length) == 0 else tuple(float(v) for v in length)
+        if len(dims) != 3 or len(box) != 3:
+            raise ValueError("n and length: a number (cube) or three per axis (box)")
+        cube = dims[0] == dims[1] == dims[2]
+        # a box that is not a cube runs inside the cube of max(n_d) elements (zeros outside)
+        self.dims, self.box = dims, box
+        self.n = max(dims)
+        self.length = box[dims.index(self.n)]
+        self.alpha, self.nrhs = float(alpha), int(nrhs)
+        self._domain = domain
         if self.nrhs > 1 and levels:
             raise ValueError("levels applies to single right-hand-side solvers")
+        if self.nrhs > 1 and not cube:
+            raise ValueError("several right-hand sides at once need a cube")
         o = _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n, dense_n,
                   smoother, subdomain, coef, domain)
         self.opts = o
         self.precision = precision
         if self.nrhs == 1:
-            ws_bytes, self.vec_len = _lib.ndmg_plan(self.n, self.length, self.alpha, o, levels)
+            ws_bytes, self.vec_len = _lib.ndmg_plan(dims, box, self.alpha, o, levels)
         else:
             ws_bytes, tl = _lib.ndmg_plan_batched([self.n], self.length, self.nrhs, o)
             self.vec_len = tl // self.nrhs
         self._alloc(ws_bytes, device)
         if self.nrhs == 1:
-            self.ctx = _lib.ndmg_setup(self.n, self.length, self.alpha, o, self._ws_ptr, ws_bytes,
+            self.ctx = _lib.ndmg_setup(dims, box, self.alpha, o, self._ws_ptr, ws_bytes,
                                        self.stream.cuda_stream, levels)
         else:
             self.ctx = _lib.ndmg_setup_batched([self.n], self.length, [self.alpha], self.nrhs, o,
@@ -143,19 +158,33 @@ class Solver(_Context):
         return _lib.ndmg_layout(self.ctx, level)
 
     def unknown_mask(self):
-        """1.0 at the entries of the padded layout that are unknowns (interior edges), else 0."""
+        """1.0 at the entries of the padded layout that are unknowns, else 0: the edges
+        whose four cells lie inside the domain (the interior edges of the cube, or of the
+        box or union of boxes solved on)."""
         if getattr(self, "_mask", None) is None:
             n = self.n
-            r = torch.arange(n + 1, device=self.device)
-            k, j, i = torch.meshgrid(r, r, r, indexing="ij")
-            node = (r >= 1) & (r <= n - 1)
-            cell = r < n
+            # cell flags, [z][y][x], with a layer of outside cells around the cube
+            c = torch.zeros(n + 2, n + 2, n + 2, dtype=torch.bool, device=self.device)
+            c[1:n + 1, 1:n + 1, 1:n + 1] = self._cells_inside()
             m = torch.zeros(3, n + 1, n + 1, self.P, dtype=torch.float64, device=self.device)
-            m[0, :, :, :n + 1] = (cell[i] & node[j] & node[k]).double()
-            m[1, :, :, :n + 1] = (node[i] & cell[j] & node[k]).double()
-            m[2, :, :, :n + 1] = (node[i] & node[j] & cell[k]).double()
+            # an x edge (cell i, nodes j, k) touches cells (i, j-1..j, k-1..k); likewise y, z
+            m[0, :, :, :n] = (c[:-1, :-1, 1:-1] & c[:-1, 1:, 1:-1] & c[1:, :-1, 1:-1] & c[1:, 1:, 1:-1]).double()
+            m[1, :, :n, :n + 1] = (c[:-1, 1:-1, :-1] & c[:-1, 1:-1, 1:] & c[1:, 1:-1, :-1] & c[1:, 1:-1, 1:]).double()
+            m[2, :n, :, :n + 1] = (c[1:-1, :-1, :-1] & c[1:-1, :-1, 1:] & c[1:-1, 1:, :-1] & c[1:-1, 1:, 1:]).double()
             self._mask = m.reshape(-1)
         return self._mask
+
+    def _cells_inside(self):
+        """[n, n, n] flags ([z][y][x]) of the cells of the cube that belong to the domain."""
+        n = self.n
+        if self._domain is not None:
+            flags = torch.as_tensor(np.asarray(self._domain, dtype=bool), device=self.device)
+            w = n // flags.shape[0]
+            return flags.repeat_interleave(w, 0).repeat_interleave(w, 1).repeat_interleave(w, 2)
+        inside = torch.zeros(n, n, n, dtype=torch.bool, device=self.device)
+        nx, ny, nz = self.dims
+        inside[:nz, :ny, :nx] = True
+        return inside
 
     # ---- operations -----------------------------------------------------------------
 

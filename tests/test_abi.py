@@ -125,15 +125,15 @@ def test_batched_null_arguments(lib):
     assert L.ndmg_pcg_solve_batched(None, None, None, 1e-10, 10, None, None) == lib.NDMG_EINVAL
 
 
-@pytest.mark.parametrize("dims,box,msg", [((8, 8, 16), (1.0, 1.0, 2.0), b"only cubes"),
-                                          ((8, 16, 16), (1.0, 2.0, 2.0), b"only cubes"),
-                                          ((8, 8, 8), (1.0, 1.0, 1.5), b"must be cubes"),
+@pytest.mark.parametrize("dims,box,msg", [((8, 8, 8), (1.0, 1.0, 1.5), b"must be cubes"),
                                           ((8, 8, 8), (1.0, -1.0, 1.0), b"box lengths"),
-                                          ((8, 8, 1), (1.0, 1.0, 0.125), b">= 2")])
+                                          ((8, 8, 1), (1.0, 1.0, 0.125), b">= 2"),
+                                          ((16, 12, 8), (4.0, 3.0, 2.0), b"must divide the coarsest"),
+                                          ((256, 2, 2), (128.0, 1.0, 1.0), b"too elongated")])
 def test_plan_box_rejections(lib, dims, box, msg):
     """The boundary takes a box (Sec. 1) with nx x ny x nz elements; the elements must be
-    cubes, and this version serves cubes nx = ny = nz only: anything else is refused with
-    a message (no silent fallback)."""
+    cubes, and a box that is not a cube must fit the embedding cube's level hierarchy:
+    anything else is refused with a message (no silent fallback)."""
     o = lib.ndmg_default_opts()
     with pytest.raises(lib.NdmgError) as e:
         lib.ndmg_plan(dims, box, 1.0, o)
@@ -144,6 +144,21 @@ def test_plan_box_rejections(lib, dims, box, msg):
 def test_plan_box_cube_equals_scalar_form(lib):
     o = lib.ndmg_default_opts()
     assert lib.ndmg_plan((16, 16, 16), (2.0, 2.0, 2.0), 1.0, o) == lib.ndmg_plan(16, 2.0, 1.0, o)
+
+
+@pytest.mark.parametrize("dims,box", [((16, 8, 8), (2.0, 1.0, 1.0)), ((8, 16, 16), (1.0, 2.0, 2.0)),
+                                      ((32, 16, 16), (2.0, 1.0, 1.0))])
+def test_plan_box_embedded(lib, dims, box):
+    """A box that is not a cube plans in the layout of the cube of max(n_d) elements (the
+    same vector length as that cube), and refuses coefficient boxes of its own."""
+    import numpy as np
+    o = lib.ndmg_default_opts()
+    n = max(dims)
+    ws, vl = lib.ndmg_plan(dims, box, 1.0, o)
+    _, vl_c = lib.ndmg_plan(n, max(box), 1.0, o)
+    assert vl == vl_c and ws > 0
+    with pytest.raises(lib.NdmgError):
+        lib.ndmg_plan(dims, box, 1.0, _coef_opts(lib, 2))
 
 
 @pytest.mark.parametrize("n,levels,ok", [(32, 1, False), (32, 2, False), (32, 3, False), (32, 4, True),

@@ -100,6 +100,7 @@ def test_apply_and_rhs(name, n):
     W = Omega(S, n, active)
     A = domain.matrix(n, 1.0 / n, 0.8 * np.ones((n, n, n)), active)
     assert S.ndof == A.shape[0]
+    assert np.array_equal(_host(S.unknown_mask()), to_padded(n, S.P, S.B, W.keep.astype(np.float64)))
     x = np.random.default_rng(n).standard_normal(A.shape[0])
     y = W.host(S.apply(W.dev(x)))
     err = np.abs(y - A @ x).max() / (abs(A) @ np.abs(x)).max()
@@ -200,3 +201,35 @@ def test_pcg_fichera_large(n):
     absAu = coefficient.apply_rows(n, 1.0 / n, cells, full, rows, absolute=True)
     r_g = from_padded(n, S.P, S.B, _host(res))[rows]
     assert np.all(np.abs(r_o - r_g) <= 1e-14 * absAu + 1e-300)
+
+
+@pytest.mark.parametrize("dims,box", [((16, 8, 8), (2.0, 1.0, 1.0)), ((8, 16, 8), (1.0, 2.0, 1.0)),
+                                      ((12, 12, 8), (3.0, 3.0, 2.0))])
+def test_box_not_a_cube(dims, box):
+    """A box that is not a cube (Sec. 1), served inside the cube of max(n_d) elements: the
+    unknown count against its closed form nx (ny-1)(nz-1) + (nx-1) ny (nz-1) + (nx-1)(ny-1) nz,
+    zeros outside the box, and PCG against the oracle on the same union of boxes."""
+    from paper_2205_05840_amd import Solver, synth
+    nx, ny, nz = dims
+    n = max(dims)
+    L = box[dims.index(n)]
+    g = int(np.gcd.reduce(dims))
+    r = n // g
+    active = np.zeros((r, r, r), dtype=bool)
+    active[: nz // g, : ny // g, : nx // g] = True
+    print(f"[case] box {dims} {box}", flush=True)
+    S = Solver(dims, 1.0, length=box)
+    assert (S.n, S.ndof) == (n, nx * (ny - 1) * (nz - 1) + (nx - 1) * ny * (nz - 1) + (nx - 1) * (ny - 1) * nz)
+    W = Omega(S, n, active)
+    want = to_padded(n, S.P, S.B, W.keep.astype(np.float64))
+    assert np.array_equal(_host(S.unknown_mask()), want)
+    h = L / n
+    f = synth.normal_samples(n, 3)
+    b_o = rhs.load_from_samples(n, h, f)[W.keep]
+    u, it, rel = S.solve(S.assemble_rhs(torch.from_numpy(f)), rtol=1e-10)
+    u_c = W.host(u)
+    H = vcycle.Hierarchy(n, 1.0, L=L, active=active)
+    A = H.A[-1]
+    _, it_o, _, _ = pcg.pcg(A, b_o, H.precondition, rtol=1e-10)
+    print(f"box {dims}: {it} iterations (oracle {it_o}), relres {rel:.2e}, true {_rel(A @ u_c, b_o):.2e}")
+    assert rel <= 1e-10 and _rel(A @ u_c, b_o) <= 1.5e-10 and abs(it - it_o) <= 1
