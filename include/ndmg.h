@@ -86,7 +86,9 @@ typedef struct ndmg_opts {
                            as one dense matrix per problem, built at setup by the
                            recursive V-cycle on unit vectors (the same map, rounded
                            differently; the matrices take nprob N_k^2 scalars of the
-                           workspace).  Default 8; 0: the recursion all the way down. */
+                           workspace).  0: the recursion all the way down.  -1
+                           (default): 8 for a size class of fewer than 16 problems, 4
+                           for larger classes (the build costs nprob N_k V-cycles). */
   int coef_r;           /* a coefficient with jumps (Sec. 6, the first extension the
                            paper names): alpha(x) = alpha * coef[(bz r + by) r + bx] on
                            the r x r x r grid of equal boxes tiling the cube (x fastest),

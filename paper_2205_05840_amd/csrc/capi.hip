@@ -153,7 +153,7 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
   if (o->bottom_n > 0 && (o->smoother == NDMG_SMOOTHER_EDGE || o->subdomain != 2))
     return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) serves the vertex smoother with subdomain 2 only");
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
-  if (o->dense_n < 0 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be in [0, 8]");
+  if (o->dense_n < -1 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be -1 or in [0, 8]");
   if (o->coef_r < 0 || o->coef_r > 64) return fail(NDMG_EINVAL, "coef_r must be in [0, 64]");
   if (o->domain && o->coef_r == 0) return fail(NDMG_EINVAL, "a domain needs the box grid: coef_r > 0");
   if (o->coef_r > 0) {
@@ -189,10 +189,14 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
   if (cf.r > 0 && sizes[0] % cf.r)
     return fail(NDMG_EINVAL, "coef_r = " + std::to_string(cf.r) + " must divide the coarsest level's n (" +
                                  std::to_string(sizes[0]) + "), so that every element of every level lies in one box");
-  // dense bottom: the finest level with n_k <= dense_n, if above the coarsest
+  // dense bottom: the finest level with n_k <= dense_n, if above the coarsest.  -1: 8 for
+  // classes of fewer than 16 problems, 4 for larger ones (whose build, nprob N_k V-cycles
+  // on unit vectors, then costs 0.01 instead of 0.2 s for 512 problems, and whose solves
+  // measured as fast: the bottom levels of many problems share each launch)
+  const int dense_n = pl.opts.dense_n >= 0 ? pl.opts.dense_n : (C.nprob >= 16 ? 4 : 8);
   C.dense_k = -1;
   for (size_t k = 1; k < sizes.size(); ++k)
-    if (sizes[k] <= pl.opts.dense_n) C.dense_k = (int)k;
+    if (sizes[k] <= dense_n) C.dense_k = (int)k;
   int64_t Nd = 0;
   if (C.dense_k >= 1) {
     const int64_t nk = sizes[C.dense_k];
@@ -204,6 +208,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
     // its g and z are used, by count pairs.  Classes of many problems take up to 2048
     // columns in all per pass (at most a few hundred MB of level vectors): with 4 the
     // 512-problem batch spent 0.6 s of its 0.7 s setup in 1108 passes of eager launches
+    // (16384 columns per pass measured no faster than 2048)
     const int64_t budget = C.nprob >= 16 ? 2048 : 256;
     C.dense_K = (int)std::max<int64_t>(C.nrhs, std::min<int64_t>(Nd, budget / C.nprob));
     // many problems: one thread per row over the transposed matrix (coalesced, no
@@ -522,8 +527,25 @@ ndmg::Bat class_batch(ndmg_ctx* c, const Cls& C, bool masked) {
 }
 
 // Host staging of everything uploaded at setup; freed after the stream has synchronised.
+// A host array left uninitialised at allocation: the threads that fill it touch (and
+// zero) their own parts first, so that the page faults and the zeroing of the large
+// factor arrays run in parallel.
+template <typename T>
+struct HostArray {
+  std::unique_ptr<T[]> p;
+  size_t n = 0;
+  void alloc(size_t count) {
+    p.reset(count ? new T[count] : nullptr);
+    n = count;
+  }
+  T* data() { return p.get(); }
+};
+
+// Host-to-device uploads on the context's stream; the sources stay alive until the
+// caller synchronises the stream and drops the staging.
 struct Staging {
   std::vector<std::vector<char>> keep;
+  std::vector<std::shared_ptr<void>> owned;
   int put(ndmg_ctx* c, size_t off, const void* src, size_t bytes) {
     if (bytes == 0) return NDMG_OK;
     keep.emplace_back((const char*)src, (const char*)src + bytes);
@@ -533,6 +555,16 @@ struct Staging {
   template <typename V>
   int put_vec(ndmg_ctx* c, size_t off, const V& v) {
     return put(c, off, v.data(), v.size() * sizeof(typename V::value_type));
+  }
+  // uploads a large array without copying it: the staging takes it over
+  template <typename T>
+  int put_owned(ndmg_ctx* c, size_t off, HostArray<T>& a) {
+    if (a.n == 0) return NDMG_OK;
+    T* raw = a.p.release();
+    owned.emplace_back(raw, [](void* q) { delete[] static_cast<T*>(q); });
+    NDMG_HIP(hipMemcpyAsync(c->ws + off, raw, a.n * sizeof(T), hipMemcpyHostToDevice, c->st));
+    a.n = 0;
+    return NDMG_OK;
   }
 };
 
@@ -685,20 +717,23 @@ template <typename T>
 int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
   Plan& pl = c->plan;
   const int nl = (int)C.lv.size();
-  std::vector<std::vector<T>> ATinv(nl), XT(nl), Sinv(nl), A0(nl);
+  // per level, problem p's blocks at p * blk of each array (zeroed by the thread that
+  // builds problem p, then filled)
+  std::vector<HostArray<T>> ATinv(nl), XT(nl), Sinv(nl), A0(nl);
+  std::vector<size_t> bE(nl, 0), bX(nl, 0), bS(nl, 0), b0(nl, 0);
   for (int k = 0; k < nl; ++k) {
     LevelHost& L = C.lv[k];
     if (L.gen) {
-      ATinv[k].assign(L.blk_gE * C.nprob, T(0));
-      XT[k].assign(L.blk_gX * C.nprob, T(0));
-      Sinv[k].assign(L.blk_gS * C.nprob, T(0));
+      bE[k] = L.blk_gE, bX[k] = L.blk_gX, bS[k] = L.blk_gS;
     } else if (L.smoothed) {
-      ATinv[k].assign(L.blk_ATinv * C.nprob, T(0));
-      XT[k].assign(L.blk_XT * C.nprob, T(0));
-      Sinv[k].assign(L.blk_Sinv * C.nprob, T(0));
+      bE[k] = L.blk_ATinv, bX[k] = L.blk_XT, bS[k] = L.blk_Sinv;
     } else {
-      A0[k].assign(L.blk_A0 * C.nprob, T(0));
+      b0[k] = L.blk_A0;
     }
+    ATinv[k].alloc(bE[k] * C.nprob);
+    XT[k].alloc(bX[k] * C.nprob);
+    Sinv[k].alloc(bS[k] * C.nprob);
+    A0[k].alloc(b0[k] * C.nprob);
   }
   const bool bp = pl.opts.boundary_patches != 0;
   unsigned hw = std::thread::hardware_concurrency();
@@ -709,6 +744,12 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
     for (int p = t; p < C.nprob; p += nth) {
       const double a = C.alpha[p];
       for (int k = 0; k < nl; ++k) {
+        std::fill_n(ATinv[k].data() + p * bE[k], bE[k], T(0));
+        std::fill_n(XT[k].data() + p * bX[k], bX[k], T(0));
+        std::fill_n(Sinv[k].data() + p * bS[k], bS[k], T(0));
+        std::fill_n(A0[k].data() + p * b0[k], b0[k], T(0));
+      }
+      for (int k = 0; k < nl; ++k) {
         LevelHost& L = C.lv[k];
         std::string err;
         if (!L.smoothed) {
@@ -718,7 +759,7 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
             errs[t] = err;
             return;
           }
-          std::copy(inv.begin(), inv.end(), A0[k].begin() + (size_t)p * L.blk_A0);
+              std::copy(inv.begin(), inv.end(), A0[k].data() + (size_t)p * L.blk_A0);
           if (maps[t].empty()) maps[t] = map;
           continue;
         }
@@ -752,14 +793,14 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
     LevelHost& L = C.lv[k];
     if (!L.smoothed) {
       L.map = maps[0];
-      NDMG_TRY(stg.put_vec(c, L.o_A0, A0[k]));
+      NDMG_TRY(stg.put_owned(c, L.o_A0, A0[k]));
       NDMG_TRY(stg.put_vec(c, L.o_map, L.map));
       continue;
     }
     if (L.gen) {
-      NDMG_TRY(stg.put_vec(c, L.o_gE, ATinv[k]));
-      NDMG_TRY(stg.put_vec(c, L.o_gX, XT[k]));
-      NDMG_TRY(stg.put_vec(c, L.o_gS, Sinv[k]));
+      NDMG_TRY(stg.put_owned(c, L.o_gE, ATinv[k]));
+      NDMG_TRY(stg.put_owned(c, L.o_gX, XT[k]));
+      NDMG_TRY(stg.put_owned(c, L.o_gS, Sinv[k]));
       NDMG_TRY(stg.put_vec(c, L.o_guI, L.gt.unitsI));
       NDMG_TRY(stg.put_vec(c, L.o_grI, L.gt.relI));
       NDMG_TRY(stg.put_vec(c, L.o_grE, L.gt.relE));
@@ -777,9 +818,9 @@ int build_class_factors(ndmg_ctx* c, Cls& C, Staging& stg) {
       }
       continue;
     }
-    NDMG_TRY(stg.put_vec(c, L.o_ATinv, ATinv[k]));
-    NDMG_TRY(stg.put_vec(c, L.o_XT, XT[k]));
-    NDMG_TRY(stg.put_vec(c, L.o_Sinv, Sinv[k]));
+    NDMG_TRY(stg.put_owned(c, L.o_ATinv, ATinv[k]));
+    NDMG_TRY(stg.put_owned(c, L.o_XT, XT[k]));
+    NDMG_TRY(stg.put_owned(c, L.o_Sinv, Sinv[k]));
     {
       std::vector<int64_t> bo;
       for (auto& q : ndmg::boundary_dofs(L.sub.s))
@@ -1383,7 +1424,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->flexible = -1;
   o->use_graphs = 1;
   o->bottom_n = 0;
-  o->dense_n = 8;
+  o->dense_n = -1;
   o->coef_r = 0;
   o->coef = nullptr;
   o->domain = nullptr;

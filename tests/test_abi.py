@@ -61,11 +61,28 @@ def test_plan_rejects(lib, args, code):
 
 
 def test_plan_rejects_bad_options(lib):
-    for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5), ("subdomain", 8)):
+    for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5), ("subdomain", 8),
+                       ("dense_n", -2), ("dense_n", 9)):
         o = lib.ndmg_default_opts()
         setattr(o, field, val)
         with pytest.raises(lib.NdmgError):
             lib.ndmg_plan(8, 1.0, 1.0, o)
+
+
+def test_dense_default_by_class_size(lib):
+    """dense_n = -1 (the default): the dense bottom from the 8^3 level for a single problem,
+    from 4^3 for a class of 16 or more problems (workspace equal to dense_n 8, resp. 4)."""
+    o = lib.ndmg_default_opts()
+    assert o.dense_n == -1
+
+    def ws(ns, dense):
+        q = lib.ndmg_default_opts()
+        q.dense_n = dense
+        return lib.ndmg_plan_batched(ns, 1.0, 2, q)[0]
+
+    assert ws([16], -1) == ws([16], 8) != ws([16], 4)
+    assert ws([16] * 16, -1) == ws([16] * 16, 4) != ws([16] * 16, 8)
+    assert ws([16] * 15, -1) == ws([16] * 15, 8)
 
 
 def test_null_arguments(lib):
