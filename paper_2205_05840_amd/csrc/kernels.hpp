@@ -132,8 +132,8 @@ bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz);
 // 16-vertex groups per wave of the patch kernel for a level with `groups` groups in all
 // (summed over the segments and the pairs of a class): the fewest that let the whole grid
 // be resident at once, given the workgroups per CU that the kernel's registers allow
-// (4 in FP32, 3 in FP64 on a 256-CU MI355X), at most 8.
-inline int64_t patch_resident_blocks(size_t elem) { return (elem == 4 ? 4 : 3) * 256; }
+// (6 in FP32 with buffer addressing, 3 in FP64 on a 256-CU MI355X), at most 8.
+inline int64_t patch_resident_blocks(size_t elem) { return (elem == 4 ? 6 : 3) * 256; }
 inline int patch_groups(int64_t groups, size_t elem) {
   const int64_t resident = patch_resident_blocks(elem) * 4;   // waves
   const int64_t g = (groups + resident - 1) / resident;
