@@ -22,6 +22,7 @@
 
 #include "kernels.hpp"
 #include "reduce.hpp"
+#include "tuning.hpp"
 
 namespace ndmg {
 
@@ -2016,11 +2017,14 @@ hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, 
 }
 
 // the patch products, with buffer addressing when a pair's vector and Y rows fit the
-// descriptors' 31-bit ranges (offsets of 2^31 must lie past both)
+// descriptors' 31-bit ranges (offsets of 2^31 must lie past both), unless the table asks
+// for 64-bit addresses at this size (which also lets a test compare the two forms)
 template <typename T>
 void launch_sm_patch(const LevelPtrs<T>& L, const DSub& sub, const DGeom& dg, const Bat& bt, hipStream_t st) {
   constexpr int64_t NPAD = (6 * 2 * (4 * 2 - 3) + 15) / 16 * 16;
-  const bool buf = 3 * dg.B * (int64_t)sizeof(T) < 0x7fffffffLL &&
+  int bits = 32, unused = 0;
+  tune_lookup(kTunePatchAddr, dg.n, (int)sizeof(T), 0, bt.count, &bits, &unused);
+  const bool buf = bits == 32 && 3 * dg.B * (int64_t)sizeof(T) < 0x7fffffffLL &&
                    y_row_len(sub.nH) * NPAD * (int64_t)sizeof(T) < 0x7fffffffLL;
   const dim3 grid((unsigned)sub.nchunks, (unsigned)bt.count);
   if (buf)

@@ -32,8 +32,10 @@ bool parse_entry(const std::string& line, Key* k, std::pair<int, int>* v, std::s
   int kd = -1;
   if (kind == "stencil") kd = kTuneStencil;
   else if (kind == "patch") kd = kTunePatch;
+  else if (kind == "patchaddr") kd = kTunePatchAddr;
   const int elem = prec == "fp64" ? 8 : (prec == "fp32" ? 4 : 0);
-  if (kd < 0 || elem == 0 || n < 2 || cls < 0 || cls > 4 || p0 < 0 || p1 < 1) {
+  if (kd < 0 || elem == 0 || n < 2 || cls < 0 || cls > 4 || p0 < 0 || p1 < 1 ||
+      (kd == kTunePatchAddr && p0 != 32 && p0 != 64)) {
     *err = "bad tuning entry: " + line;
     return false;
   }

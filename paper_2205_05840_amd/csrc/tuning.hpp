@@ -11,6 +11,8 @@ enum TuneKind : int {
   kTuneStencil = 0,   // plane-marching operator kernel: p0 = variant index, p1 = planes per workgroup
   kTunePatch = 1,     // vertex patch products: p0 = groups per wave (interior segment),
                       // p1 = groups per wave (segments on the faces and edges of the box)
+  kTunePatchAddr = 2, // vertex patch products' addressing: p0 = 64 for 64-bit addresses,
+                      // 32 for 32-bit buffer offsets where the vectors allow them (p1 unused)
 };
 
 // Pairs per launch, in classes: 1, 2-3, 4-15, 16-63, 64 and more.
@@ -27,8 +29,8 @@ bool tune_forced_stencil(int* variant, int* kz);
 
 const char* source_key();
 
-// Table text: "key <source key>", then lines "<stencil|patch> <n> <fp32|fp64> <mode>
-// <pair class> <p0> <p1>"; '#' starts a comment.
+// Table text: "key <source key>", then lines "<stencil|patch|patchaddr> <n> <fp32|fp64>
+// <mode> <pair class> <p0> <p1>"; '#' starts a comment.
 bool tune_load(const std::string& path, std::string* err);
 bool tune_set_line(const std::string& line, std::string* err);
 void tune_clear();

@@ -247,6 +247,10 @@ def test_tuning_table(lib, tmp_path):
     assert (v.value, z.value) == (2, 16)             # unchanged
     assert L.ndmg_tuning_set(b"stencil 96 fp64") == lib.NDMG_EINVAL
     assert L.ndmg_tuning_set(b"warp 96 fp64 0 0 1 1") == lib.NDMG_EINVAL
+    # the patch products' addressing: 64-bit addresses or 32-bit buffer offsets only
+    assert L.ndmg_tuning_set(b"patchaddr 64 fp32 0 0 64 1") == 0
+    assert L.ndmg_tuning_set(b"patchaddr 64 fp64 0 0 32 1") == 0
+    assert L.ndmg_tuning_set(b"patchaddr 64 fp32 0 0 48 1") == lib.NDMG_EINVAL
     L.ndmg_tuning_clear()
     L.ndmg_stencil_shape(96, 0, 0, 1, ctypes.byref(v), ctypes.byref(z))
     assert (v.value, z.value) == model

@@ -119,6 +119,40 @@ def test_smoother_after_small_level_kernel(boundary):
     assert _rel(from_padded(n, S.P, S.B, z), ref) <= max(1e-13, C64 * _rel(alt, ref))
 
 
+@pytest.mark.parametrize("precision,n,nrhs", [("fp32", 64, 1), ("fp64", 64, 1), ("fp32", 32, 4),
+                                               ("fp64", 24, 4)])
+def test_patch_addressing_forms_agree(precision, n, nrhs):
+    """The vertex patch products address their gathers and stores either through buffer
+    descriptors with 32-bit byte offsets (an absent slot's offset lies past the range and
+    reads zero) or with 64-bit addresses (the form for vectors of 2 GB or more, selected
+    here by table entries "patchaddr" for every level).  The V-cycle must come out the same
+    bit for bit; several right-hand sides take the waves that serve one pair each."""
+    import os
+    from paper_2205_05840_amd import _lib
+    L = _lib.lib()
+    cls = 0 if nrhs == 1 else 2
+    S = _solver(n, 0.8, precision=precision, nrhs=nrhs)
+    rng = np.random.default_rng(n)
+    g = (torch.from_numpy(rng.standard_normal((nrhs, S.vec_len))).cuda() * S.unknown_mask()).contiguous()
+    if nrhs == 1:
+        g = g[0].contiguous()
+    z32 = _host(S.vcycle(g))
+    try:
+        k = n
+        while k >= 4:
+            _lib.check(L.ndmg_tuning_set(f"patchaddr {k} {precision} 0 {cls} 64 1".encode()))
+            k //= 2
+        S64 = _solver(n, 0.8, precision=precision, nrhs=nrhs)
+        z64 = _host(S64.vcycle(g))
+    finally:
+        L.ndmg_tuning_clear()
+        if os.path.exists(_lib.TUNING_PATH):
+            L.ndmg_tuning_load(_lib.TUNING_PATH.encode())
+    print(f"{precision} n={n} nrhs={nrhs}: max |z| {np.abs(z32).max():.3e}, "
+          f"differing entries {int((z32 != z64).sum())}")
+    assert np.array_equal(z32, z64)
+
+
 def test_exported_factors_match_patch_matrices():
     n, alpha = 8, 0.7
     S = _solver(n, alpha)
