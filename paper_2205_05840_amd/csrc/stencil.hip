@@ -162,7 +162,7 @@ struct Unroll<U, U> {
   __device__ __forceinline__ static void run(F&, int) {}
 };
 
-template <typename T, int R, int NW, int D, int MODE>
+template <typename T, int R, int NW, int D, int MODE, int SYNC>
 __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, const T* __restrict__ bv,
                                                      T* __restrict__ y, DGeom g, Bat bt, double h,
                                                      int KZ, int ntj, int ntiles,
@@ -186,9 +186,15 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   __shared__ __attribute__((aligned(16))) unsigned char ring1[NW * CH];
   __shared__ __attribute__((aligned(16))) unsigned char ring2[NW * CH];
   __shared__ __attribute__((aligned(16))) unsigned char ring3[D == 4 ? NW * CH : 16];
-  // y-neighbour exchange: F_y, G_z, G_x, T_z x, T_x z of the current step
+  // y-neighbour exchange: F_y, G_z, G_x, T_z x, T_x z of the current step.  SYNC = 1:
+  // two copies used by step parity, and one barrier per step (see the step); SYNC = 2:
+  // one copy, and a second barrier per step before it is overwritten.
   typedef typename RowVec<T, R>::type V;
-  __shared__ V sB[5][NW][64];
+  constexpr bool kOneBarrier = SYNC == 1;
+  static_assert(SYNC == 1 || SYNC == 2, "one or two barriers per step");
+  static_assert(!kOneBarrier || D * NW * CH + 2 * 5 * NW * 64 * (int)sizeof(V) + 1024 <= 160 * 1024,
+                "two copies of the exchange area must fit the LDS");
+  __shared__ V sBuf[kOneBarrier ? 2 : 1][5][NW][64];
 
   const int pair = blockIdx.y;
   if (bt.act != nullptr && bt.act[pair] == 0) return;
@@ -286,9 +292,17 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
     constexpr int sl_cur = ph % D;              // plane s
     constexpr int sl_next = (ph + 1) % D;       // plane s + 1
     T bcur[3][R];   // b of the output plane s - 1 (residual mode)
+    // this step's copy of the exchange area
+    V(*sB)[NW][64] = sBuf[kOneBarrier ? (s & 1) : 0];
     if constexpr (compute) {
       wait_vm_lds<NWAIT>();
-      wg_barrier();   // plane s + 1 is in the ring; every wave is done with step s - 1
+      // plane s + 1 is in the ring; every wave is done with step s - 1.  With two copies
+      // of the exchange area only the first step needs this barrier: afterwards the
+      // barrier in the middle of step s - 1 already orders what it would (every wave had
+      // waited for its loads of plane s and finished reading plane s - 1 from the ring,
+      // whose slot this step refills, and a wave can only reach this step's exchange
+      // writes after every wave has finished reading the copy of step s - 2)
+      if (!kOneBarrier || s == kstart - 1) wg_barrier();
       if constexpr (MODE == 1) {
         // b rows of plane s - 1, before its slot is refilled
         const unsigned char* prev = slot_base(std::integral_constant<int, sl_prev>()) + wave * CH;
@@ -479,23 +493,26 @@ Tiling tiling(int n, int NW, int KZ) {
   return t;
 }
 
-template <typename T, int R, int NW, int D, int MODE>
+template <typename T, int R, int NW, int D, int MODE, int SYNC = 2>
 hipError_t launch_m(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int KZ, double* part,
                     int64_t pstride, double* dot, hipStream_t st) {
   const Tiling tl = tiling(g.n, NW, KZ);
   if (MODE == 2 && (part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tl.nblocks, (unsigned)bt.count);
-  hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g), bt,
+  hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g), bt,
                      g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
   if (MODE == 2 && dot != nullptr) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
   return hipGetLastError();
 }
 
-// Launch variants: waves per workgroup and ring depth, each fitting the 160 KB of LDS
-// of a compute unit with one workgroup per unit (the residual mode carries b in the
-// ring, twice the bytes per slot).
+// Launch variants: waves per workgroup, ring depth and barriers per step (2, or 1 with
+// two copies of the exchange area where they fit), each fitting the 160 KB of LDS of a
+// compute unit with one workgroup per unit (the residual mode carries b in the ring,
+// twice the bytes per slot).  One barrier measured faster at 64^3 (FP32 residual 10.1 ->
+// 9.0 us, FP64 apply 11.1 -> 10.5 us) and slower for the FP64 apply at 128^3 (29.3 ->
+// 31.8 us): the tuner's table picks per size.
 struct Variant {
-  int nw, d;
+  int nw, d, sync;
 };
 
 int compute_units() {
@@ -535,19 +552,19 @@ Choice choose_kz(int n, int count, Variant v) {
 // Candidate variants per precision, row length and mode (index 0 or 1 of the
 // instantiated pair below); returns the chosen one and its KZ.
 template <typename T, int R>
-void variants(int mode, Variant (&vs)[3], int* nv) {
+void variants(int mode, Variant (&vs)[4], int* nv) {
   constexpr bool f64 = std::is_same<T, double>::value;
   if (R == 2) {
     if (f64) {
-      if (mode == 1) { vs[0] = {6, 3}; *nv = 1; }
-      else { vs[0] = {10, 3}; vs[1] = {8, 4}; vs[2] = {6, 4}; *nv = 3; }
+      if (mode == 1) { vs[0] = {6, 3, 2}; *nv = 1; }
+      else { vs[0] = {10, 3, 2}; vs[1] = {8, 4, 2}; vs[2] = {6, 4, 2}; vs[3] = {6, 4, 1}; *nv = 4; }
     } else {
-      if (mode == 1) { vs[0] = {10, 3}; vs[1] = {8, 4}; *nv = 2; }
-      else { vs[0] = {10, 4}; vs[1] = {8, 4}; *nv = 2; }
+      if (mode == 1) { vs[0] = {10, 3, 2}; vs[1] = {8, 4, 2}; vs[2] = {10, 3, 1}; vs[3] = {8, 4, 1}; *nv = 4; }
+      else { vs[0] = {10, 4, 2}; vs[1] = {8, 4, 2}; vs[2] = {10, 4, 1}; vs[3] = {8, 4, 1}; *nv = 4; }
     }
   } else {
     if (f64 && mode == 1) { *nv = 0; }   // does not fit: the caller falls back
-    else { vs[0] = {4, 4}; *nv = 1; }
+    else { vs[0] = {4, 4, 2}; *nv = 1; }
   }
 }
 
@@ -555,7 +572,7 @@ void variants(int mode, Variant (&vs)[3], int* nv) {
 // table's entry, else the cost model.
 template <typename T, int R>
 bool pick(int n, int count, int mode, int* which, int* kz, Variant* var) {
-  Variant vs[3];
+  Variant vs[4];
   int nv = 0;
   variants<T, R>(mode, vs, &nv);
   if (nv == 0) return false;
@@ -594,15 +611,20 @@ hipError_t launch_mode(const T* x, const T* b, T* y, const Geom& g, const Bat& b
     if constexpr (f64 && MODE != 1) {
       if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
       if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
-      return launch_m<T, R, 6, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 6, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 6, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
     if constexpr (!f64 && MODE == 1) {
       if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 10, 3, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
     if constexpr (!f64 && MODE != 1) {
       if (which == 0) return launch_m<T, R, 10, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
-      return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 10, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
     }
   } else {
     if constexpr (!(f64 && MODE == 1)) return launch_m<T, R, 4, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
@@ -654,7 +676,7 @@ bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz) 
 }
 
 int stencil_variant_count(int elem, int mode, int n) {
-  Variant vs[3];
+  Variant vs[4];
   int nv = 0;
   if (n <= 128) {
     if (elem == 8) variants<double, 2>(mode, vs, &nv);

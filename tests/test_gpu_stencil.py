@@ -115,3 +115,41 @@ def test_pcg_bench_size_mixed():
     print(f"128^3 mixed: {it} iterations, relres {rel:.2e}, |u - u_exact| / |u_exact| "
           f"{err / np.linalg.norm(ue):.2e}")
     assert err <= 3e-10 * np.linalg.norm(b_o) / ev_min
+
+
+# (precision, mode, n, planes per workgroup, [(two-barrier variant, one-barrier variant)])
+SYNC_CASES = [("fp64", 0, 64, 4, [(2, 3)]), ("fp64", 0, 128, 16, [(2, 3)]),
+              ("fp32", 1, 64, 3, [(0, 2), (1, 3)]), ("fp32", 1, 128, 12, [(0, 2), (1, 3)])]
+
+
+@pytest.mark.parametrize("prec,mode,n,kz,pairs", SYNC_CASES)
+def test_one_barrier_form_agrees(prec, mode, n, kz, pairs):
+    """The operator kernel's form with one barrier per step (two copies of the y-exchange
+    area, used by step parity) against the form with two, at the same tiling: the FP64
+    apply (mode 0) and the FP32 V-cycle whose level-n residuals use mode 1 must agree bit
+    for bit, on every one of repeated launches (an ordering fault would show as a change
+    between launches)."""
+    import os
+    from paper_2205_05840_amd import _lib
+    L = _lib.lib()
+    S = _solver(n, 0.9, precision=prec)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n + mode)
+    x = (torch.randn(S.vec_len, generator=g, dtype=torch.float64, device="cuda") * S.unknown_mask()).contiguous()
+    run = (lambda: S.apply(x)) if mode == 0 else (lambda: S.vcycle(x))
+    try:
+        for two, one in pairs:
+            outs = {}
+            for v in (two, one):
+                L.ndmg_tuning_clear()
+                _lib.check(L.ndmg_tuning_set(f"stencil {n} {prec} {mode} 0 {v} {kz}".encode()))
+                ref = _host(run())
+                same = all(np.array_equal(_host(run()), ref) for _ in range(10))
+                outs[v] = ref
+                print(f"{prec} mode {mode} n={n} variant {v} kz {kz}: repeats identical {same}")
+                assert same
+            assert np.array_equal(outs[two], outs[one])
+    finally:
+        L.ndmg_tuning_clear()
+        if os.path.exists(_lib.TUNING_PATH):
+            L.ndmg_tuning_load(_lib.TUNING_PATH.encode())
