@@ -1016,9 +1016,11 @@ double* part_region(ndmg_ctx* c, const Cls& C, int region) {
 }
 int64_t part_stride(const Cls& C) { return 3 * C.pstride; }
 
-// q = A p with partial sums of p^T q, then (reducing them) u += a p, r -= a q
-// (a = s[num] / p^T q) with partial sums of r . r (and the FP32 copy of r when mixed).
-int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt, hipStream_t st) {
+// q = A p with partial sums of p^T q, then (reducing them) r -= a q (a = s[num] / p^T q)
+// with partial sums of r . r (and the FP32 copy of r when mixed).  u += a p is left
+// pending (a in s[kS_AL]): the next direction kernel applies it while it reads p, or
+// finish_solution at the end of the solve.
+int cg_apply_update(ndmg_ctx* c, Cls& C, int num, const ndmg::Bat& bt, hipStream_t st) {
   const ndmg::Geom& g = C.lv.back().g;
   const int64_t len = g.len;
   double* r = at<double>(c, C.o_pr);
@@ -1036,7 +1038,7 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, double* u, int num, const ndmg::Bat& bt
     NDMG_HIP(ndmg::launch_dot<double>(p, q, nullptr, pq_part, ps, nullptr, len, bt, st));
     pq_n = ndmg::dot_parts(len, bt.count);
   }
-  NDMG_HIP(ndmg::launch_cg_update(u, r, p, q, sc, num, pq_part, pq_n, r32_of(c, C), part_region(c, C, 2), ps,
+  NDMG_HIP(ndmg::launch_cg_update(nullptr, r, p, q, sc, num, pq_part, pq_n, r32_of(c, C), part_region(c, C, 2), ps,
                                   len, bt, st));
   return NDMG_OK;
 }
@@ -1087,7 +1089,7 @@ int pcg_prologue(ndmg_ctx* c, size_t ci, const double* b, double* u, double rtol
     NDMG_HIP(ndmg::launch_dot<double>(z, r, nullptr, part, ps, sc + kS_RZA, len, act, st));
     NDMG_HIP(ndmg::launch_copy(z, p, len, act, st));
   }
-  NDMG_TRY(cg_apply_update(c, C, u, kS_RZA, act, st));
+  NDMG_TRY(cg_apply_update(c, C, kS_RZA, act, st));
   return pcg_check(c, ci, kS_RZA, 0, st);
 }
 
@@ -1112,14 +1114,14 @@ int pcg_body(ndmg_ctx* c, size_t ci, double* u, int cur, int nxt, hipStream_t st
   if (mixed(c->plan)) {
     const float* zf = at<float>(c, C.lv.back().o_z);
     NDMG_HIP(ndmg::launch_dot<float>(zf, r, flex ? q : nullptr, part, ps, nullptr, len, act, st));
-    NDMG_HIP(ndmg::launch_cg_direction<float>(p, zf, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part, nd, ps,
-                                              len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<float>(p, zf, u, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part, nd,
+                                              ps, len, act, st));
   } else {
     NDMG_HIP(ndmg::launch_dot<double>(z, r, flex ? q : nullptr, part, ps, nullptr, len, act, st));
-    NDMG_HIP(ndmg::launch_cg_direction<double>(p, z, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part, nd,
-                                               ps, len, act, st));
+    NDMG_HIP(ndmg::launch_cg_direction<double>(p, z, u, sc, nxt, cur, flex ? 1 : 0, nxt + 1, cur, kS_PQ, part,
+                                               nd, ps, len, act, st));
   }
-  NDMG_TRY(cg_apply_update(c, C, u, nxt, act, st));
+  NDMG_TRY(cg_apply_update(c, C, nxt, act, st));
   return pcg_check(c, ci, nxt, cur == kS_RZA ? 1 : 0, st);
 }
 
@@ -1225,6 +1227,13 @@ int pcg_all(ndmg_ctx* c, const double* b, double* u, double rtol, int maxit, int
     NDMG_TRY(active_pairs(c, set, &nact));
     if (!launch || nact == 0) break;
   }
+  // the last update's u += a p of every pair
+  NDMG_TRY(for_classes(c, [&](size_t ci, hipStream_t st) {
+    Cls& C = pl.cls[ci];
+    NDMG_HIP(ndmg::launch_cg_finish(u + C.vec_off, at<double>(c, C.o_pp), at<double>(c, C.o_scal), C.vlen,
+                                    class_batch(c, C, false), st));
+    return NDMG_OK;
+  }));
   // per-pair results
   int nbroken = 0, nrun = 0, first_bad = -1;
   for (const Cls& C : pl.cls) {

@@ -1632,7 +1632,9 @@ __global__ void __launch_bounds__(256) k_final(const double* __restrict__ part, 
 }
 
 // u += a p, r -= a q (a = s[i_num] / s[i_den]), partial sums of r . r; with r32 the new
-// residual is also written in FP32 (input of the next mixed-precision V-cycle)
+// residual is also written in FP32 (input of the next mixed-precision V-cycle).  DEFER:
+// u is not touched; a goes to s[kS_AL] and the update is marked pending.
+template <bool DEFER>
 __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, double* __restrict__ r,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ q,
@@ -1644,7 +1646,7 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   const int pair = blockIdx.y;
   if (inactive(bt, pair)) return;
   const int64_t off = (int64_t)pair * len;
-  u += off;
+  if (!DEFER) u += off;
   r += off;
   p += off;
   q += off;
@@ -1655,28 +1657,34 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   // read (index clamped, no branch), so the two latencies overlap
   const int64_t n4 = len >> 2, step = (int64_t)gridDim.x * blockDim.x;
   const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double u0[4], r0[4], p0[4], q0[4];
+  double u0[4] = {0.0, 0.0, 0.0, 0.0}, r0[4], p0[4], q0[4];
   {
     const int64_t ec = 4 * (e0 < n4 ? e0 : 0);
-    Quad<double>::load(u + ec, u0);
+    if (!DEFER) Quad<double>::load(u + ec, u0);
     Quad<double>::load(r + ec, r0);
-    Quad<double>::load(p + ec, p0);
+    if (!DEFER) Quad<double>::load(p + ec, p0);
     Quad<double>::load(q + ec, q0);
   }
   // p^T A p from the partials of the operator kernel (every block the same value)
   const double pq = reduce_partials(pq_part + (int64_t)pair * pstride, pq_n, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0) scal[kS_PQ] = pq;
   const double alpha = scal[i_num] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[kS_PQ] = pq;
+    if (DEFER) {
+      scal[kS_AL] = alpha;
+      scal[kS_PEND] = 1.0;
+    }
+  }
   double s = 0.0;
   auto update = [&](int64_t e, double (&uv)[4], double (&rv)[4], const double (&pv)[4],
                     const double (&qv)[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      uv[k] += alpha * pv[k];
+      if (!DEFER) uv[k] += alpha * pv[k];
       rv[k] -= alpha * qv[k];
       s += rv[k] * rv[k];
     }
-    Quad<double>::store(u + 4 * e, uv);
+    if (!DEFER) Quad<double>::store(u + 4 * e, uv);
     Quad<double>::store(r + 4 * e, rv);
     if (r32) {
       float rf[4];
@@ -1688,10 +1696,10 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   if (e0 < n4) update(e0, u0, r0, p0, q0);
 #pragma unroll 2
   for (int64_t e = e0 + step; e < n4; e += step) {
-    double uv[4], rv[4], pv[4], qv[4];
-    Quad<double>::load(u + 4 * e, uv);
+    double uv[4] = {0.0, 0.0, 0.0, 0.0}, rv[4], pv[4], qv[4];
+    if (!DEFER) Quad<double>::load(u + 4 * e, uv);
     Quad<double>::load(r + 4 * e, rv);
-    Quad<double>::load(p + 4 * e, pv);
+    if (!DEFER) Quad<double>::load(p + 4 * e, pv);
     Quad<double>::load(q + 4 * e, qv);
     update(e, uv, rv, pv, qv);
   }
@@ -1699,26 +1707,33 @@ __global__ void __launch_bounds__(256) k_cg_update(double* __restrict__ u, doubl
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-template <typename TZ>
+template <typename TZ, bool WITHU>
 __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, const TZ* __restrict__ z,
-                                                      double* __restrict__ scal, int i_num,
-                                                      int i_den, int flexible, int i_zq, int i_an,
-                                                      int i_ad, const double* __restrict__ dot_part,
-                                                      int dot_n, int64_t pstride, int64_t len, Bat bt) {
+                                                      double* __restrict__ u, double* __restrict__ scal,
+                                                      int i_num, int i_den, int flexible, int i_zq, int i_an,
+                                                      int i_ad, const double* __restrict__ dot_part, int dot_n,
+                                                      int64_t pstride, int64_t len, Bat bt) {
   __shared__ double sh[17];
   const int pair = blockIdx.y;
   if (inactive(bt, pair)) return;
   p += (int64_t)pair * len;
   z += (int64_t)pair * len;
+  if (WITHU) u += (int64_t)pair * len;
   scal += (int64_t)pair * kScalStride;
-  // this lane's first quads of z and p do not depend on beta: their loads go out before
-  // the partial sums are read, so the two latencies overlap (index clamped, no branch)
+  // this lane's first quads of z, p (and u) do not depend on beta: their loads go out
+  // before the partial sums are read, so the two latencies overlap (index clamped, no
+  // branch)
   const int64_t n4 = len >> 2, step = (int64_t)gridDim.x * blockDim.x;
   const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   TZ z0[4];
-  double p0[4];
+  double p0[4], u0[4];
   Quad<TZ>::load(z + 4 * (e0 < n4 ? e0 : 0), z0);
   Quad<double>::load(p + 4 * (e0 < n4 ? e0 : 0), p0);
+  if (WITHU) Quad<double>::load(u + 4 * (e0 < n4 ? e0 : 0), u0);
+  // the pending update's alpha: an active pair always has one here (the update of the
+  // previous iteration, or of the first step), and the update that follows in this
+  // iteration marks its own as pending again
+  const double al = WITHU ? scal[kS_AL] : 0.0;
   // r . z (and z . q) from the partials of the dot kernel; block 0 keeps them
   const double* dp = dot_part + (int64_t)pair * pstride;
   const double rz = reduce_partials(dp, dot_n, sh);
@@ -1731,6 +1746,11 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
   if (flexible) beta = -(scal[i_an] / scal[i_ad]) * zq / scal[i_den];
   else beta = rz / scal[i_den];
   if (e0 < n4) {
+    if (WITHU) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u0[k] += al * p0[k];
+      Quad<double>::store(u + 4 * e0, u0);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) p0[k] = (double)z0[k] + beta * p0[k];
     Quad<double>::store(p + 4 * e0, p0);
@@ -1738,13 +1758,45 @@ __global__ void __launch_bounds__(256) k_cg_direction(double* __restrict__ p, co
 #pragma unroll 2
   for (int64_t e = e0 + step; e < n4; e += step) {
     TZ zv[4];
-    double pv[4];
+    double pv[4], uv[4];
     Quad<TZ>::load(z + 4 * e, zv);
     Quad<double>::load(p + 4 * e, pv);
+    if (WITHU) {
+      Quad<double>::load(u + 4 * e, uv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) uv[k] += al * pv[k];
+      Quad<double>::store(u + 4 * e, uv);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) pv[k] = (double)zv[k] + beta * pv[k];
     Quad<double>::store(p + 4 * e, pv);
   }
+}
+
+// u += s[kS_AL] p where an update is pending; clears the flag
+__global__ void __launch_bounds__(256) k_cg_finish(double* __restrict__ u, const double* __restrict__ p,
+                                                   double* __restrict__ scal, int64_t len, Bat bt) {
+  const int pair = blockIdx.y;
+  if (inactive(bt, pair)) return;
+  double* s = scal + (int64_t)pair * kScalStride;
+  if (s[kS_PEND] == 0.0) return;
+  const double al = s[kS_AL];
+  u += (int64_t)pair * len;
+  p += (int64_t)pair * len;
+  const int64_t n4 = len >> 2, step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += step) {
+    double uv[4], pv[4];
+    Quad<double>::load(u + 4 * e, uv);
+    Quad<double>::load(p + 4 * e, pv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) uv[k] += al * pv[k];
+    Quad<double>::store(u + 4 * e, uv);
+  }
+}
+
+// clears the pending flags once every block of k_cg_finish has read them
+__global__ void k_cg_finish_clear(double* __restrict__ scal, int count) {
+  for (int p = threadIdx.x; p < count; p += blockDim.x) scal[(int64_t)p * kScalStride + kS_PEND] = 0.0;
 }
 
 __global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, int* __restrict__ act,
@@ -1755,6 +1807,7 @@ __global__ void __launch_bounds__(1024) k_pcg_init(double* __restrict__ scal, in
     const double bb = s[kS_BB];
     s[kS_TOL] = rtol;
     s[kS_REL] = 0.0;
+    s[kS_PEND] = 0.0;
     iters[p] = 0;
     if (!isfinite(bb)) {
       act[p] = 0;
@@ -2161,23 +2214,40 @@ hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nou
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
                             int i_num, const double* pq_part, int pq_n, float* r32, double* part,
                             int64_t pstride, int64_t len, const Bat& bt, hipStream_t st) {
-  if (!quad_ok(len, u) || !quad_ok(len, r) || !quad_ok(len, p) || !quad_ok(len, q) || (r32 && !quad_ok(len, r32)))
+  if ((u && !quad_ok(len, u)) || !quad_ok(len, r) || !quad_ok(len, p) || !quad_ok(len, q) ||
+      (r32 && !quad_ok(len, r32)))
     return hipErrorInvalidValue;
   const unsigned nb = vec_blocks(len, bt.count, kRedBlocks);
   if ((int64_t)nb > pstride || pq_n > pstride) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_update, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal, i_num,
-                     pq_part, pq_n, r32, part, pstride, len, bt);
+  if (u)
+    hipLaunchKernelGGL(k_cg_update<false>, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal,
+                       i_num, pq_part, pq_n, r32, part, pstride, len, bt);
+  else
+    hipLaunchKernelGGL(k_cg_update<true>, dim3(nb, (unsigned)bt.count), dim3(256), 0, st, u, r, p, q, scal,
+                       i_num, pq_part, pq_n, r32, part, pstride, len, bt);
   return hipGetLastError();
 }
 
 template <typename TZ>
-hipError_t launch_cg_direction(double* p, const TZ* z, double* scal, int i_num, int i_den, int flexible,
-                               int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n, int64_t pstride,
-                               int64_t len, const Bat& bt, hipStream_t st) {
-  if (!quad_ok(len, p) || !quad_ok(len, z)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_cg_direction<TZ>), dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count),
-                     dim3(256), 0, st, p, z, scal, i_num, i_den, flexible, i_zq, i_an, i_ad, dot_part, dot_n,
-                     pstride, len, bt);
+hipError_t launch_cg_direction(double* p, const TZ* z, double* u, double* scal, int i_num, int i_den,
+                               int flexible, int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n,
+                               int64_t pstride, int64_t len, const Bat& bt, hipStream_t st) {
+  if (!quad_ok(len, p) || !quad_ok(len, z) || (u && !quad_ok(len, u))) return hipErrorInvalidValue;
+  const dim3 grid(vec_blocks(len, bt.count, 2048), (unsigned)bt.count);
+  if (u)
+    hipLaunchKernelGGL((k_cg_direction<TZ, true>), grid, dim3(256), 0, st, p, z, u, scal, i_num, i_den, flexible,
+                       i_zq, i_an, i_ad, dot_part, dot_n, pstride, len, bt);
+  else
+    hipLaunchKernelGGL((k_cg_direction<TZ, false>), grid, dim3(256), 0, st, p, z, u, scal, i_num, i_den,
+                       flexible, i_zq, i_an, i_ad, dot_part, dot_n, pstride, len, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(double* u, const double* p, double* scal, int64_t len, const Bat& bt, hipStream_t st) {
+  if (!quad_ok(len, u) || !quad_ok(len, p)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_finish, dim3(vec_blocks(len, bt.count, 2048), (unsigned)bt.count), dim3(256), 0, st, u,
+                     p, scal, len, bt);
+  hipLaunchKernelGGL(k_cg_finish_clear, dim3(1), dim3(1024), 0, st, scal, bt.count);
   return hipGetLastError();
 }
 
@@ -2185,10 +2255,10 @@ template hipError_t launch_dot<double>(const double*, const double*, const doubl
                                        double*, int64_t, const Bat&, hipStream_t);
 template hipError_t launch_dot<float>(const float*, const double*, const double*, double*, int64_t,
                                       double*, int64_t, const Bat&, hipStream_t);
-template hipError_t launch_cg_direction<double>(double*, const double*, double*, int, int, int, int, int, int,
-                                                const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
-template hipError_t launch_cg_direction<float>(double*, const float*, double*, int, int, int, int, int, int,
-                                               const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<double>(double*, const double*, double*, double*, int, int, int, int, int,
+                                                int, const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
+template hipError_t launch_cg_direction<float>(double*, const float*, double*, double*, int, int, int, int, int,
+                                               int, const double*, int, int64_t, int64_t, const Bat&, hipStream_t);
 
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
                            hipStream_t st) {

@@ -254,6 +254,9 @@ enum : int {
   kS_TOL = 7,   // relative tolerance
   kS_REL = 8,   // ||r|| / ||b|| after the last iteration
   kS_CC = 9,    // curl-curl form
+  kS_AL = 10,   // alpha of the last update, whose u += alpha p is still pending
+  kS_PEND = 11, // 1 once an update has left its u += alpha p pending (the next direction
+                // kernel applies it, or launch_cg_finish at the end of a solve)
 };
 // per-pair PCG state
 enum : int { kPairRun = 0, kPairDone = 1, kPairBroken = 2 };
@@ -274,15 +277,22 @@ hipError_t launch_final(const double* part, int nparts, int64_t pstride, int nou
 // alpha = s[i_num] / pq; u += alpha p; r -= alpha q; partial sums of r . r at
 // part[pair * pstride + blk] (dot_parts(len, count) of them); r32 (may be null) receives
 // r in FP32
+// With u == nullptr the u += a p of this update is left pending: a is kept in s[kS_AL]
+// and s[kS_PEND] = 1, and the next direction kernel (or launch_cg_finish) applies it
+// while it reads p anyway, which saves the update one vector read.
 hipError_t launch_cg_update(double* u, double* r, const double* p, const double* q, double* scal,
                             int i_num, const double* pq_part, int pq_n, float* r32, double* part,
                             int64_t pstride, int64_t len, const Bat& bt, hipStream_t st);
 // rz (and zq when flexible) = sums of the dot partials (kept in s[i_num], s[i_zq]);
-// beta = rz / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) zq / s[i_den]); p = z + beta p
+// beta = rz / s[i_den] (flexible: beta = -(s[i_an] / s[i_ad]) zq / s[i_den]); with
+// u != nullptr first the pending u += s[kS_AL] p (old p), then p = z + beta p
 template <typename TZ>
-hipError_t launch_cg_direction(double* p, const TZ* z, double* scal, int i_num, int i_den, int flexible,
-                               int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n, int64_t pstride,
-                               int64_t len, const Bat& bt, hipStream_t st);
+hipError_t launch_cg_direction(double* p, const TZ* z, double* u, double* scal, int i_num, int i_den,
+                               int flexible, int i_zq, int i_an, int i_ad, const double* dot_part, int dot_n,
+                               int64_t pstride, int64_t len, const Bat& bt, hipStream_t st);
+// u += s[kS_AL] p for every pair of bt whose update is pending (s[kS_PEND] != 0), then
+// s[kS_PEND] = 0: the end of a solve.
+hipError_t launch_cg_finish(double* u, const double* p, double* scal, int64_t len, const Bat& bt, hipStream_t st);
 // Start of a solve: s[kS_TOL] = rtol, iters = 0; pairs with b = 0 are done, pairs with a
 // non-finite b . b broken, all others active.
 hipError_t launch_pcg_init(double* scal, int* act, int* iters, int* status, int count, double rtol,
