@@ -73,8 +73,13 @@ typedef struct ndmg_opts {
                            the boundary, cut to the domain (default; reproduces
                            Table 2); 0: interior coarse vertices (edges) only         */
   int flexible;         /* 1: Polak-Ribiere beta in PCG (default for FP32)          */
-  int use_graphs;       /* 1 (default): replay each CG iteration from a captured HIP
-                           graph when the stream is not the null stream; 0: eager   */
+  int use_graphs;       /* 1: replay each CG iteration from a captured HIP graph when
+                           the stream is not the null stream; 0: eager launches;
+                           -1 (default): graphs unless the context holds one size
+                           class whose finest level has n >= 80 (there the host
+                           queues an iteration's launches faster than the device
+                           runs them, and eager launches measured 1-4 % faster;
+                           below, graphs 8-9 % faster)                               */
   int bottom_n;         /* levels with n_k <= bottom_n (at most 64) and the coarsest
                            solve run as one launch with one workgroup per (problem,
                            right-hand side); 0 (default): every level launches its

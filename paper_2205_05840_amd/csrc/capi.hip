@@ -154,6 +154,7 @@ int check_opts(const ndmg_opts* o_in, ndmg_opts* o) {
     return fail(NDMG_EINVAL, "the one-launch bottom (bottom_n) serves the vertex smoother with subdomain 2 only");
   if (o->bottom_n < 0 || o->bottom_n > 64) return fail(NDMG_EINVAL, "bottom_n must be in [0, 64]");
   if (o->dense_n < -1 || o->dense_n > 8) return fail(NDMG_EINVAL, "dense_n must be -1 or in [0, 8]");
+  if (o->use_graphs < -1 || o->use_graphs > 1) return fail(NDMG_EINVAL, "use_graphs must be -1, 0 or 1");
   if (o->coef_r < 0 || o->coef_r > 64) return fail(NDMG_EINVAL, "coef_r must be in [0, 64]");
   if (o->domain && o->coef_r == 0) return fail(NDMG_EINVAL, "a domain needs the box grid: coef_r > 0");
   if (o->coef_r > 0) {
@@ -1160,8 +1161,16 @@ void drop_graphs(ndmg_ctx* c) {
   c->graph_u = nullptr;
 }
 
+// Graphs for the CG iterations: as asked, or (use_graphs -1) unless one size class with a
+// finest level of n >= 80 makes each iteration long enough for eager launches to keep
+// ahead of the device.
+bool use_graphs(const Plan& pl) {
+  if (pl.opts.use_graphs >= 0) return pl.opts.use_graphs != 0;
+  return !(pl.cls.size() == 1 && pl.cls[0].lv.back().g.n >= 80);
+}
+
 int body_all(ndmg_ctx* c, double* u, int cur, int nxt) {
-  if (!c->plan.opts.use_graphs || c->st == nullptr) return body_all_eager(c, u, cur, nxt);
+  if (!use_graphs(c->plan) || c->st == nullptr) return body_all_eager(c, u, cur, nxt);
   if (c->graph_u != u) drop_graphs(c);
   const int par = (cur == kS_RZA) ? 0 : 1;
   if (!c->gexec[par]) {
@@ -1431,7 +1440,7 @@ void ndmg_default_opts(ndmg_opts* o) {
   o->subdomain = 2;
   o->boundary_patches = 1;
   o->flexible = -1;
-  o->use_graphs = 1;
+  o->use_graphs = -1;
   o->bottom_n = 0;
   o->dense_n = -1;
   o->coef_r = 0;

@@ -26,7 +26,8 @@ def _opts(m, eta, precision, boundary_patches, flexible, use_graphs, bottom_n=No
     o.precision = PRECISIONS[precision]
     o.boundary_patches = 1 if boundary_patches else 0
     o.flexible = -1 if flexible is None else int(bool(flexible))
-    o.use_graphs = 1 if use_graphs else 0
+    if use_graphs is not None:   # None: the library's choice by problem size
+        o.use_graphs = 1 if use_graphs else 0
     if bottom_n is not None:
         o.bottom_n = int(bottom_n)
     if dense_n is not None:
@@ -101,7 +102,7 @@ class Solver(_Context):
     right-hand side with its own CG scalars."""
 
     def __init__(self, n, alpha, length=1.0, m=1, eta=None, precision="fp64",
-                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0", nrhs=1,
+                 boundary_patches=True, flexible=None, use_graphs=None, device="cuda:0", nrhs=1,
                  bottom_n=None, dense_n=None, levels=0, smoother="vertex", subdomain=2, coef=None,
                  domain=None):
         dims = (int(n),) * 3 if np.ndim(n) == 0 else tuple(int(v) for v in n)
@@ -277,7 +278,7 @@ class BatchedSolver(_Context):
     CG scalars and stops on its own.  Vectors are batch vectors (see `offset`)."""
 
     def __init__(self, ns, alphas, nrhs=1, length=1.0, m=1, eta=None, precision="fp32",
-                 boundary_patches=True, flexible=None, use_graphs=True, device="cuda:0",
+                 boundary_patches=True, flexible=None, use_graphs=None, device="cuda:0",
                  bottom_n=None, dense_n=None, smoother="vertex", subdomain=2):
         self.ns = [int(v) for v in ns]
         self.alphas = [float(v) for v in alphas]

@@ -62,7 +62,7 @@ def test_plan_rejects(lib, args, code):
 
 def test_plan_rejects_bad_options(lib):
     for field, val in (("m", 0), ("precision", 7), ("subdomain", 3), ("smoother", 5), ("subdomain", 8),
-                       ("dense_n", -2), ("dense_n", 9)):
+                       ("dense_n", -2), ("dense_n", 9), ("use_graphs", 2), ("use_graphs", -2)):
         o = lib.ndmg_default_opts()
         setattr(o, field, val)
         with pytest.raises(lib.NdmgError):
@@ -73,7 +73,7 @@ def test_dense_default_by_class_size(lib):
     """dense_n = -1 (the default): the dense bottom from the 8^3 level for a single problem,
     from 4^3 for a class of 16 or more problems (workspace equal to dense_n 8, resp. 4)."""
     o = lib.ndmg_default_opts()
-    assert o.dense_n == -1
+    assert o.dense_n == -1 and o.use_graphs == -1
 
     def ws(ns, dense):
         q = lib.ndmg_default_opts()
