@@ -964,7 +964,11 @@ __device__ __forceinline__ void stage_lds(T* __restrict__ dst, const T* __restri
   stage_store(dst, v, n);
 }
 
-template <typename T>
+// BUF (the pair's vector below 2 GB): the residual loads go through a buffer descriptor,
+// a per-lane byte offset of the subdomain's node plus a uniform offset per slot, with no
+// 64-bit address arithmetic (FP64 measured 58.5 -> 53.8 us for condensation and
+// pull/extend at 128^3, FP32 unchanged; results bit for bit the same).
+template <typename T, bool BUF>
 __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* __restrict__ gg,
                                                     const T* __restrict__ XT, DGeom g, int nH, Bat bt, int nbx,
                                                     int packed) {
@@ -989,22 +993,50 @@ __global__ void __launch_bounds__(64) k_sm_condense(const T* __restrict__ r, T* 
   // interior residuals of T - q (q = bits x, y, z; not all three: never needed), from a
   // clamped subdomain where T - q leaves the domain (those values are never used)
   T rI[8][6];
-#pragma unroll
-  for (int qq = 0; qq < 7; ++qq) {
-    const int sa = max(a - (qq & 1), 0), sb = max(b - ((qq >> 1) & 1), 0), sc = max(c - (qq >> 2), 0);
-    int64_t off[6];
-    interior_offsets_s2(g, lin(g, 2 * sa, 2 * sb, 2 * sc), off);
-#pragma unroll
-    for (int t = 0; t < 6; ++t) rI[qq][t] = r[off[t]];
-  }
   const int64_t base = lin(g, 2 * a, 2 * b, 2 * c);
   // every owned slot is read and written (its node lies inside the grid); a slot on the
   // domain boundary gets 0, which keeps the zero there.  No branch around a load or
   // store: predicated memory operations make the compiler's wait counters conservative.
   T rO[18];
+  if constexpr (BUF) {
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)r, (short)0, (int)(vlen(g) * (int64_t)sizeof(T)), kBufferFlags);
+    auto ld = [&](unsigned voff, int soff) -> T {
+      if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rr, (int)voff, soff, 0));
+      else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rr, (int)voff, soff, 0));
+    };
+    // byte offsets of the interior unknowns from a subdomain's lower node (the order of
+    // interior_offsets_s2), uniform
+    const int es = (int)sizeof(T);
+    const int io[6] = {(int)((g.P + g.plane) * es),         (int)((1 + g.P + g.plane) * es),
+                       (int)((g.B + 1 + g.plane) * es),     (int)((g.B + 1 + g.P + g.plane) * es),
+                       (int)((2 * g.B + 1 + g.P) * es),     (int)((2 * g.B + 1 + g.P + g.plane) * es)};
 #pragma unroll
-  for (int k = 0; k < 18; ++k)
-    rO[k] = r[kOI.d[k] * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2])];
+    for (int qq = 0; qq < 7; ++qq) {
+      const int sa = max(a - (qq & 1), 0), sb = max(b - ((qq >> 1) & 1), 0), sc = max(c - (qq >> 2), 0);
+      const unsigned vb = (unsigned)(lin(g, 2 * sa, 2 * sb, 2 * sc) * es);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) rI[qq][t] = ld(vb, io[t]);
+    }
+    const unsigned vb = (unsigned)(base * es);
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+      rO[k] = ld(vb, (int)((kOI.d[k] * g.B + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2])) * es));
+  } else {
+#pragma unroll
+    for (int qq = 0; qq < 7; ++qq) {
+      const int sa = max(a - (qq & 1), 0), sb = max(b - ((qq >> 1) & 1), 0), sc = max(c - (qq >> 2), 0);
+      int64_t off[6];
+      interior_offsets_s2(g, lin(g, 2 * sa, 2 * sb, 2 * sc), off);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) rI[qq][t] = r[off[t]];
+    }
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+      rO[k] = r[kOI.d[k] * g.B + base + lin(g, kOI.o[k][0], kOI.o[k][1], kOI.o[k][2])];
+  }
   stage_store(sX, xv, 6 * NB);
   __syncthreads();
   if (!valid) return;
@@ -2069,16 +2101,21 @@ hipError_t launch_prolong_add(const T* ec, T* zf, const Geom& f, const Geom& c, 
   return hipGetLastError();
 }
 
-// the patch products, with buffer addressing when a pair's vector and Y rows fit the
-// descriptors' 31-bit ranges (offsets of 2^31 must lie past both), unless the table asks
-// for 64-bit addresses at this size (which also lets a test compare the two forms)
-template <typename T>
-void launch_sm_patch(const LevelPtrs<T>& L, const DSub& sub, const DGeom& dg, const Bat& bt, hipStream_t st) {
+// Buffer addressing for the smoother's condensation and patch products when a pair's
+// vector and Y rows fit the descriptors' 31-bit ranges (offsets of 2^31 must lie past
+// both), unless the table asks for 64-bit addresses at this size (which also lets a test
+// compare the two forms).
+bool smoother_buffers(const DGeom& dg, const DSub& sub, const Bat& bt, size_t elem) {
   constexpr int64_t NPAD = (6 * 2 * (4 * 2 - 3) + 15) / 16 * 16;
   int bits = 32, unused = 0;
-  tune_lookup(kTunePatchAddr, dg.n, (int)sizeof(T), 0, bt.count, &bits, &unused);
-  const bool buf = bits == 32 && 3 * dg.B * (int64_t)sizeof(T) < 0x7fffffffLL &&
-                   y_row_len(sub.nH) * NPAD * (int64_t)sizeof(T) < 0x7fffffffLL;
+  tune_lookup(kTunePatchAddr, dg.n, (int)elem, 0, bt.count, &bits, &unused);
+  return bits == 32 && 3 * dg.B * (int64_t)elem < 0x7fffffffLL &&
+         y_row_len(sub.nH) * NPAD * (int64_t)elem < 0x7fffffffLL;
+}
+
+template <typename T>
+void launch_sm_patch(const LevelPtrs<T>& L, const DSub& sub, const DGeom& dg, const Bat& bt, hipStream_t st) {
+  const bool buf = smoother_buffers(dg, sub, bt, sizeof(T));
   const dim3 grid((unsigned)sub.nchunks, (unsigned)bt.count);
   if (buf)
     hipLaunchKernelGGL((k_sm_patch<T, 2, true>), grid, dim3(256), 0, st, L.gg, L.Y, L.Sinv, dg, sub, bt);
@@ -2096,7 +2133,10 @@ hipError_t launch_smooth(const T* r, T* z, const LevelPtrs<T>& L, const DSub& su
   const int packed = (sub.nH < 64) ? 1 : 0;
   const int nbs = packed ? (sub.nH * sub.nH + 63) / 64 : (sub.nH + 63) / 64;
   const dim3 eg((unsigned)(nbs * bt.count), (unsigned)sub.nH, packed ? 1u : (unsigned)sub.nH);
-  hipLaunchKernelGGL((k_sm_condense<T>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs, packed);
+  if (smoother_buffers(dg, sub, bt, sizeof(T)))
+    hipLaunchKernelGGL((k_sm_condense<T, true>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs, packed);
+  else
+    hipLaunchKernelGGL((k_sm_condense<T, false>), eg, dim3(64), 0, st, r, L.gg, L.XT, dg, sub.nH, bt, nbs, packed);
   if (sub.nchunks > 0) launch_sm_patch<T>(L, sub, dg, bt, st);
   hipLaunchKernelGGL((k_sm_pull_extend<T>), eg, dim3(64), 0, st, L.Y, r, z, L.XT, L.ATinv, dg, sub, (T)eta, assign,
                      bt, nbs, packed);

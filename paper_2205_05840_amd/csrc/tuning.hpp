@@ -11,8 +11,9 @@ enum TuneKind : int {
   kTuneStencil = 0,   // plane-marching operator kernel: p0 = variant index, p1 = planes per workgroup
   kTunePatch = 1,     // vertex patch products: p0 = groups per wave (interior segment),
                       // p1 = groups per wave (segments on the faces and edges of the box)
-  kTunePatchAddr = 2, // vertex patch products' addressing: p0 = 64 for 64-bit addresses,
-                      // 32 for 32-bit buffer offsets where the vectors allow them (p1 unused)
+  kTunePatchAddr = 2, // addressing of the smoother's condensation and patch products: p0 =
+                      // 64 for 64-bit addresses, 32 for 32-bit buffer offsets where the
+                      // vectors allow them (p1 unused)
 };
 
 // Pairs per launch, in classes: 1, 2-3, 4-15, 16-63, 64 and more.

@@ -122,11 +122,12 @@ def test_smoother_after_small_level_kernel(boundary):
 @pytest.mark.parametrize("precision,n,nrhs", [("fp32", 64, 1), ("fp64", 64, 1), ("fp32", 32, 4),
                                                ("fp64", 24, 4)])
 def test_patch_addressing_forms_agree(precision, n, nrhs):
-    """The vertex patch products address their gathers and stores either through buffer
-    descriptors with 32-bit byte offsets (an absent slot's offset lies past the range and
-    reads zero) or with 64-bit addresses (the form for vectors of 2 GB or more, selected
-    here by table entries "patchaddr" for every level).  The V-cycle must come out the same
-    bit for bit; several right-hand sides take the waves that serve one pair each."""
+    """The smoother's condensation and vertex patch products address their loads and
+    stores either through buffer descriptors with 32-bit byte offsets (in the patch
+    products an absent slot's offset lies past the range and reads zero) or with 64-bit
+    addresses (the form for vectors of 2 GB or more, selected here by table entries
+    "patchaddr" for every level).  The V-cycle must come out the same bit for bit; several
+    right-hand sides take the waves that serve one pair each."""
     import os
     from paper_2205_05840_amd import _lib
     L = _lib.lib()
