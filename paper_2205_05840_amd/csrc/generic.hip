@@ -28,54 +28,90 @@ __device__ __forceinline__ bool pair_inactive(const Bat& bt, int pair) { return 
 
 // Units of 64 per block along x (a chunk of one patch type, or of subdomains), blocks of
 // 64 result rows: wave w of the block takes rows rb 64 + 16 w .. + 15 for the 64 units
-// (lane = unit).  M is stored k-major, so the 16 rows of a wave at one k are 16
-// consecutive values, the same for every lane (scalar loads).
+// (lane = unit).  The k dimension goes in chunks of 32: the block stages the gathered
+// inputs (32 x 64 units) and the chunk of M for its 64 rows (32 x 64, k-major, coalesced
+// rows of M) in LDS, every load issued before any is waited for (an absent slot reads the
+// unit's own anchor and is zeroed after the load, so no load sits behind a branch); the
+// next chunk's loads are in flight while the current one is multiplied.  Each lane then
+// reads its 16 rows of M at one k as a broadcast from LDS and accumulates in k order,
+// acc[q] += M[k][r0 + q] x[k] (the order of the sum does not depend on the shape).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
+  constexpr int KC = 32;               // k per chunk
+  constexpr int VX = KC * 64 / 256;    // gathered inputs per thread and chunk (8)
+  constexpr int VM = KC * 64 / 256;    // values of M per thread and chunk (8)
   const int pair = blockIdx.y;
   if (pair_inactive(bt, pair)) return;
   const int chunk = blockIdx.x / a.nrb, rb = blockIdx.x - chunk * a.nrb;
   const int type = a.chunks[4 * chunk], u0 = a.chunks[4 * chunk + 1], cnt = a.chunks[4 * chunk + 2];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool valid = lane < cnt;
   const int64_t base = a.units[u0 + (valid ? lane : 0)];
   const T* __restrict__ x = a.x + (int64_t)pair * a.vlen;
   const T* __restrict__ x2 = a.x2 + (int64_t)pair * a.vlen;
   const T* __restrict__ M = a.M + (int64_t)(pair / bt.nrhs) * a.mstride + (int64_t)type * a.npadK * a.npadR;
   const int64_t* __restrict__ rin = a.relIn + (int64_t)type * a.npadK;
-  __shared__ T Xs[32][64];
+  __shared__ T Xs[KC][64];
+  __shared__ __attribute__((aligned(16))) T Ms[KC][64];
+  // M staging: thread tid copies rows mr0 .. mr0 + 7 of k-row mk (8 consecutive values)
+  const int mk = tid >> 3, mr0 = (tid & 7) * 8;
+  const int rowb = rb * 64;
+  const int nrows = min(64, a.npadR - rowb);   // a multiple of 16
+  T xr[VX], mrg[VM];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < VX; ++i) {
+      const int j = k0 + wave * VX + i;                 // uniform
+      const int jj = j < a.npadK ? j : 0;
+      const int64_t ro = rin[jj];
+      const bool ok = j < a.npadK && ro != kGenAbsent;
+      const T* __restrict__ src = j < a.ksplit ? x : x2;
+      const T v = src[base + (ok ? ro : 0)];
+      xr[i] = ok ? v : T(0);
+    }
+    const int k = k0 + mk;
+    const bool mok = k < a.npadK && mr0 < nrows;
+    const T* __restrict__ mp = M + (int64_t)(mok ? k : 0) * a.npadR + rowb + (mok ? mr0 : 0);
+#pragma unroll
+    for (int i = 0; i < VM; ++i) mrg[i] = mp[i];
+#pragma unroll
+    for (int i = 0; i < VM; ++i) mrg[i] = mok ? mrg[i] : T(0);
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < VX; ++i) Xs[wave * VX + i][lane] = xr[i];
+#pragma unroll
+    for (int i = 0; i < VM; ++i) Ms[mk][mr0 + i] = mrg[i];
+  };
   T acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = T(0);
-  const int r0 = rb * 64 + wave * 16;
-  const bool rows_ok = r0 < a.npadR;   // npadR is a multiple of 16
-  for (int k0 = 0; k0 < a.npadK; k0 += 32) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int j = k0 + wave * 8 + i;
-      T v = T(0);
-      if (j < a.npadK) {
-        const int64_t ro = rin[j];
-        if (ro != kGenAbsent) v = (j < a.ksplit ? x : x2)[base + ro];
-      }
-      Xs[wave * 8 + i][lane] = v;
-    }
+  const int r0 = wave * 16;   // within the block's rows
+  const bool rows_ok = r0 < nrows;
+  load_chunk(0);
+  for (int k0 = 0; k0 < a.npadK; k0 += KC) {
+    store_chunk();
     __syncthreads();
+    if (k0 + KC < a.npadK) load_chunk(k0 + KC);   // in flight during the products
     if (rows_ok) {
-      const int kmax = min(32, a.npadK - k0);
+      const int kmax = min(KC, a.npadK - k0);
       for (int kk = 0; kk < kmax; ++kk) {
         const T xv = Xs[kk][lane];
-        const T* __restrict__ mr = M + (int64_t)(k0 + kk) * a.npadR + r0;
+        T m[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += mr[q] * xv;
+        for (int q = 0; q < 16; ++q) m[q] = Ms[kk][r0 + q];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += m[q] * xv;
       }
     }
     __syncthreads();
   }
   if (!rows_ok || !valid) return;
+  const int rg = rowb + r0;
   if (MODE == kGemmToY) {
-    T* __restrict__ y = a.out + (int64_t)pair * a.ylen + (int64_t)(u0 + lane) * a.npadR + r0;
+    T* __restrict__ y = a.out + (int64_t)pair * a.ylen + (int64_t)(u0 + lane) * a.npadR + rg;
 #pragma unroll
     for (int q = 0; q < 16; ++q) y[q] = acc[q];
   } else {
@@ -84,7 +120,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
     const T sc = a.scale;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int64_t ro = rout[r0 + q];
+      const int64_t ro = rout[rg + q];
       if (ro == kGenAbsent) continue;
       const T v = sc * acc[q];
       o[base + ro] = a.assign ? v : o[base + ro] + v;
