@@ -40,6 +40,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
   constexpr int KC = 32;               // k per chunk
   constexpr int VX = KC * 64 / 256;    // gathered inputs per thread and chunk (8)
   constexpr int VM = KC * 64 / 256;    // values of M per thread and chunk (8)
+  static_assert(KC == 256 / 8 && VM == 8, "M staging: 8 threads of 8 values per k-row of 64 rows");
   const int pair = blockIdx.y;
   if (pair_inactive(bt, pair)) return;
   const int chunk = blockIdx.x / a.nrb, rb = blockIdx.x - chunk * a.nrb;
