@@ -26,15 +26,38 @@ namespace {
 
 __device__ __forceinline__ bool pair_inactive(const Bat& bt, int pair) { return bt.act && bt.act[pair] == 0; }
 
+// 16 x 16 x 4 MFMA: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result register
+// q of lane l holds D[row(l / 16, q)][l % 16] (row = 4 q + l / 16 for the f64 instruction,
+// 4 (l / 16) + q for f32, as the vertex patch kernel measured on gfx950).
+template <typename T>
+struct GMfma;
+template <>
+struct GMfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * q + lk; }
+};
+template <>
+struct GMfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
+};
+
 // Units of 64 per block along x (a chunk of one patch type, or of subdomains), blocks of
 // 64 result rows: wave w of the block takes rows rb 64 + 16 w .. + 15 for the 64 units
 // (lane = unit).  The k dimension goes in chunks of 32: the block stages the gathered
 // inputs (32 x 64 units) and the chunk of M for its 64 rows (32 x 64, k-major, coalesced
 // rows of M) in LDS, every load issued before any is waited for (an absent slot reads the
 // unit's own anchor and is zeroed after the load, so no load sits behind a branch); the
-// next chunk's loads are in flight while the current one is multiplied.  Each lane then
-// reads its 16 rows of M at one k as a broadcast from LDS and accumulates in k order,
-// acc[q] += M[k][r0 + q] x[k] (the order of the sum does not depend on the shape).
+// next chunk's loads are in flight while the current one is multiplied, as 16 x 16 x 4
+// MFMA tiles (A from the staged M, B from the staged inputs), accumulated in k order (the
+// order of the sum does not depend on the launch shape; measured bit for bit equal to
+// sequential fused multiply-adds in k order, in FP64 and FP32).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
   constexpr int KC = 32;               // k per chunk
@@ -86,9 +109,11 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
 #pragma unroll
     for (int i = 0; i < VM; ++i) Ms[mk][mr0 + i] = mrg[i];
   };
-  T acc[16];
+  // wave w: 4 MFMA tiles of rows r0 .. r0 + 15 against units 16 t .. 16 t + 15
+  const int lr = lane & 15, lk = lane >> 4;
+  typename GMfma<T>::v4 acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = T(0);
+  for (int t = 0; t < 4; ++t) acc[t] = {T(0), T(0), T(0), T(0)};
   const int r0 = wave * 16;   // within the block's rows
   const bool rows_ok = r0 < nrows;
   load_chunk(0);
@@ -97,34 +122,34 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
     __syncthreads();
     if (k0 + KC < a.npadK) load_chunk(k0 + KC);   // in flight during the products
     if (rows_ok) {
-      const int kmax = min(KC, a.npadK - k0);
-      for (int kk = 0; kk < kmax; ++kk) {
-        const T xv = Xs[kk][lane];
-        T m[16];
+      const int nks = min(KC, a.npadK - k0) / 4;   // npadK is a multiple of 16
+      for (int ks = 0; ks < nks; ++ks) {
+        const T av = Ms[4 * ks + lk][r0 + lr];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) m[q] = Ms[kk][r0 + q];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += m[q] * xv;
+        for (int t = 0; t < 4; ++t) acc[t] = GMfma<T>::mma(av, Xs[4 * ks + lk][16 * t + lr], acc[t]);
       }
     }
     __syncthreads();
   }
-  if (!rows_ok || !valid) return;
+  if (!rows_ok) return;
   const int rg = rowb + r0;
-  if (MODE == kGemmToY) {
-    T* __restrict__ y = a.out + (int64_t)pair * a.ylen + (int64_t)(u0 + lane) * a.npadR + rg;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) y[q] = acc[q];
-  } else {
-    T* __restrict__ o = a.out + (int64_t)pair * a.vlen;
-    const int64_t* __restrict__ rout = a.relOut + (int64_t)type * a.npadR;
-    const T sc = a.scale;
+  for (int t = 0; t < 4; ++t) {
+    const int unit = 16 * t + lr;
+    if (unit >= cnt) continue;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t ro = rout[rg + q];
-      if (ro == kGenAbsent) continue;
-      const T v = sc * acc[q];
-      o[base + ro] = a.assign ? v : o[base + ro] + v;
+    for (int q = 0; q < 4; ++q) {
+      const int row = GMfma<T>::row(lk, q);
+      const T val = acc[t][q];   // copied out before use as a scalar
+      if (MODE == kGemmToY) {
+        a.out[(int64_t)pair * a.ylen + (int64_t)(u0 + unit) * a.npadR + rg + row] = val;
+      } else {
+        const int64_t ro = a.relOut[(int64_t)type * a.npadR + rg + row];
+        if (ro == kGenAbsent) continue;
+        T* __restrict__ o = a.out + (int64_t)pair * a.vlen + a.units[u0 + unit] + ro;
+        const T v = a.scale * val;
+        *o = a.assign ? v : *o + v;
+      }
     }
   }
 }
