@@ -941,22 +941,42 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
     *err = "level too large for the patch result indices";
     return false;
   }
-  // interface unknowns (not inside a subdomain), in layout order, and the patch results
-  // summed on each, in the order of the patches
+  // interface unknowns (not inside a subdomain), grouped by blocks of 16^3 nodes (layout
+  // order inside a block), and the patch results summed on each, in the order of the
+  // patches.  The kernels that pull per unknown then find the patch results and
+  // subdomain terms of one block in cache: a patch's row of results is consumed by
+  // unknowns of at most a few neighbouring blocks.  (The order of each unknown's own sum
+  // does not depend on this order.)
   std::vector<int> gpos((size_t)g.len, -1);
-  for (int64_t e : unknown_offsets(g, cf)) {
-    const int d = (int)(e / g.B);
-    int64_t r = e - d * g.B;
-    const int z = (int)(r / g.plane);
-    r -= (int64_t)z * g.plane;
-    const int y = (int)(r / g.P), x = (int)(r - (int64_t)y * g.P);
-    const int o[3] = {x, y, z};
-    bool interior = true;
-    for (int ax = 0; ax < 3; ++ax)
-      if (ax != d && o[ax] % s == 0) interior = false;
-    if (interior) continue;
-    gpos[(size_t)e] = (int)tb.gamma.size();
-    tb.gamma.push_back(e);
+  {
+    constexpr int kBlk = 16;
+    const int nbk = (g.n + 1 + kBlk - 1) / kBlk;
+    std::vector<int64_t> list;
+    std::vector<int> blk;
+    for (int64_t e : unknown_offsets(g, cf)) {
+      const int d = (int)(e / g.B);
+      int64_t r = e - d * g.B;
+      const int z = (int)(r / g.plane);
+      r -= (int64_t)z * g.plane;
+      const int y = (int)(r / g.P), x = (int)(r - (int64_t)y * g.P);
+      const int o[3] = {x, y, z};
+      bool interior = true;
+      for (int ax = 0; ax < 3; ++ax)
+        if (ax != d && o[ax] % s == 0) interior = false;
+      if (interior) continue;
+      list.push_back(e);
+      blk.push_back(((z / kBlk) * nbk + y / kBlk) * nbk + x / kBlk);
+    }
+    // stable counting sort by block
+    std::vector<int64_t> start((size_t)nbk * nbk * nbk + 1, 0);
+    for (int b : blk) ++start[(size_t)b + 1];
+    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+    tb.gamma.assign(list.size(), 0);
+    for (size_t i = 0; i < list.size(); ++i) {
+      const int64_t k = start[(size_t)blk[i]]++;
+      tb.gamma[(size_t)k] = list[i];
+      gpos[(size_t)list[i]] = (int)k;
+    }
   }
   // subdomain terms of the condensation on each interface unknown
   tb.ccodes.assign(tb.gamma.size() * 4, -1);
