@@ -658,6 +658,7 @@ ndmg::GenLevel<T> gen_level(ndmg_ctx* c, const LevelHost& L) {
   Cd.npadR = tb.npadB;
   Cd.nrb = (tb.npadB + 63) / 64;
   Cd.ylen = L.clenG;
+  Cd.nunits = (int64_t)tb.unitsI.size();
   auto& Ex = G.ext;    // z_I = eta [A_T^{-1} | -X_T] [r_I ; w_dT]
   common(Ex);
   Ex.M = at<T>(c, L.o_gE);
@@ -686,6 +687,7 @@ ndmg::GenLevel<T> gen_level(ndmg_ctx* c, const LevelHost& L) {
   P.npadR = tb.npadP;
   P.nrb = (tb.npadP + 63) / 64;
   P.ylen = L.ylenG;
+  P.nunits = (int64_t)tb.unitsP.size();
   G.C = at<T>(c, L.o_C);
   G.gg = at<T>(c, L.o_gg);
   G.Y = at<T>(c, L.o_Y);

@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> a, Bat bt) {
       const int row = GMfma<T>::row(lk, q);
       const T val = acc[t][q];   // copied out before use as a scalar
       if (MODE == kGemmToY) {
-        a.out[(int64_t)pair * a.ylen + (int64_t)(u0 + unit) * a.npadR + rg + row] = val;
+        a.out[(int64_t)pair * a.ylen + (int64_t)(rg + row) * a.nunits + u0 + unit] = val;
       } else {
         const int64_t ro = a.relOut[(int64_t)type * a.npadR + rg + row];
         if (ro == kGenAbsent) continue;

@@ -37,6 +37,7 @@ struct GemmArgs {
   int nrb;              // ceil(npadR / 64)
   int64_t vlen;         // vector length per pair
   int64_t ylen;         // Y length per pair
+  int64_t nunits;       // units of the level (Y is row-major over them: row r of unit u at r * nunits + u)
   T scale;
   int assign;
 };

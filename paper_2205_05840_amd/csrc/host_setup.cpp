@@ -999,7 +999,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
           *err = "internal: more than 4 subdomains hold an interface unknown";
           return false;
         }
-        tb.ccodes[(size_t)k * 4 + cfill[k]++] = (int)u * tb.npadB + b;
+        tb.ccodes[(size_t)k * 4 + cfill[k]++] = b * (int)tb.unitsI.size() + (int)u;
       }
   }
   tb.codes.assign(tb.gamma.size() * 4, -1);
@@ -1020,7 +1020,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
           *err = "internal: more than 4 patches hold an interface unknown";
           return false;
         }
-        tb.codes[(size_t)k * 4 + fill[k]++] = u * tb.npadP + j;
+        tb.codes[(size_t)k * 4 + fill[k]++] = j * (int)tb.unitsP.size() + u;
       }
   }
   return true;

@@ -185,8 +185,8 @@ struct GenTables {
   std::vector<char> presentP;          // [ntypes][npadP]
   std::vector<int> typesP;             // the types that have patches
   std::vector<int64_t> gamma;          // interface unknowns
-  std::vector<int> ccodes;             // [ngam][4] subdomain terms (u npadB + boundary slot)
-  std::vector<int> codes;              // [ngam][4] patch results (u npadP + slot)
+  std::vector<int> ccodes;             // [ngam][4] subdomain terms (boundary slot * units + u)
+  std::vector<int> codes;              // [ngam][4] patch results (slot * units + u)
 };
 bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* out, std::string* err,
                       const CoefBoxes& cf = CoefBoxes{});
