@@ -135,10 +135,11 @@ __device__ __forceinline__ bool edge_in_domain(const double* __restrict__ coef, 
 // alpha_T K_T over the four cells T around the edge, so each face term of the RT0 mass
 // takes the alphas of the two cells on either side of the face.  ah = alpha h (alpha the
 // common factor), coef[(bz r + by) r + bx] the factor of each box, w = n / r cells per box.
+// a00 .. a11: the factors of the cells at index o[a] along the edge and o[b] - 1 + db,
+// o[c] - 1 + dc across (a_{db dc}).
 template <typename T>
-__device__ __forceinline__ T apply_at_coef(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
-                                           const int o[3], T ah, T h3, const double* __restrict__ coef,
-                                           int r) {
+__device__ __forceinline__ T apply_at_cells(const T* __restrict__ u, const DGeom& g, int a, int64_t p, T ah, T h3,
+                                            T a00, T a10, T a01, T a11) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const int64_t st[3] = {1, (int64_t)g.P, g.plane};
   const int64_t sa = st[a], sb = st[b], sc = st[c];
@@ -146,16 +147,6 @@ __device__ __forceinline__ T apply_at_coef(const T* __restrict__ u, const DGeom&
   const T* __restrict__ ub = u + b * g.B;
   const T* __restrict__ uc = u + c * g.B;
   const T t6 = T(1) / T(6), t3 = T(1) / T(3), t23 = T(2) / T(3);
-  const int w = g.n / r;
-  // alpha of the cell at index o[a] along the edge and o[b] - 1 + db, o[c] - 1 + dc across
-  auto cell = [&](int db, int dc) {
-    int q[3];
-    q[a] = o[a];
-    q[b] = o[b] - 1 + db;
-    q[c] = o[c] - 1 + dc;
-    return (T)coef[((q[2] / w) * r + q[1] / w) * r + q[0] / w];
-  };
-  const T a00 = cell(0, 0), a10 = cell(1, 0), a01 = cell(0, 1), a11 = cell(1, 1);
   auto Fb = [&](int64_t q) { return (ua[q + sc] - ua[q]) - (uc[q + sa] - uc[q]); };
   auto Fc = [&](int64_t q) { return (ub[q + sa] - ub[q]) - (ua[q + sb] - ua[q]); };
   // face of normal b (c) at q between the cells of alpha am (below along b (c)) and ap
@@ -165,6 +156,22 @@ __device__ __forceinline__ T apply_at_coef(const T* __restrict__ u, const DGeom&
   auto row = [&](int64_t q) { return t6 * (ua[q - sc] + ua[q + sc]) + t23 * ua[q]; };
   const T mass = t6 * (row(p - sb) + row(p + sb)) + t23 * row(p);
   return ah * curl + h3 * mass;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_at_coef(const T* __restrict__ u, const DGeom& g, int a, int64_t p,
+                                           const int o[3], T ah, T h3, const double* __restrict__ coef,
+                                           int r) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const int w = g.n / r;
+  auto cell = [&](int db, int dc) {
+    int q[3];
+    q[a] = o[a];
+    q[b] = o[b] - 1 + db;
+    q[c] = o[c] - 1 + dc;
+    return (T)coef[((q[2] / w) * r + q[1] / w) * r + q[0] / w];
+  };
+  return apply_at_cells(u, g, a, p, ah, h3, cell(0, 0), cell(1, 0), cell(0, 1), cell(1, 1));
 }
 
 // ---------------------------------------------------------------------------------
@@ -187,17 +194,43 @@ __device__ __forceinline__ void apply_node(const T* __restrict__ x, const T* __r
   }
 }
 
+// The three edges of a node share the 8 cells around it (o - 1 and o on each axis): their
+// factors are looked up once (6 divisions by the box width instead of 3 per cell and
+// edge).  Cells outside the cube are clamped into it; they belong to no unknown's edge.
 template <typename T, int MODE>
 __device__ __forceinline__ void apply_node_coef(const T* __restrict__ x, const T* __restrict__ b,
                                                 T* __restrict__ y, const DGeom& g, T ah, T h3,
                                                 const double* __restrict__ coef, int r, int i, int j, int k) {
   const int64_t p = lin(g, i, j, k);
   const int o[3] = {i, j, k};
+  const int w = g.n / r;
+  int bq[3][2];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) bq[ax][s] = min(max(o[ax] - 1 + s, 0), g.n - 1) / w;
+  double cf[2][2][2];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) cf[dz][dy][dx] = coef[(bq[2][dz] * r + bq[1][dy]) * r + bq[0][dx]];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    const int bb = (d + 1) % 3, cc = (d + 2) % 3;
+    // the cell at o[d] along the edge and o[bb] - 1 + db, o[cc] - 1 + dc across
+    auto cell = [&](int db, int dc) {
+      int s[3];
+      s[d] = 1;
+      s[bb] = db;
+      s[cc] = dc;
+      return cf[s[2]][s[1]][s[0]];
+    };
+    const double c00 = cell(0, 0), c10 = cell(1, 0), c01 = cell(0, 1), c11 = cell(1, 1);
     T v = T(0);
-    if (is_unknown(g, d, i, j, k) && edge_in_domain(coef, r, g.n, d, o)) {
-      const T ax = apply_at_coef(x, g, d, p, o, ah, h3, coef, r);
+    if (is_unknown(g, d, i, j, k) && c00 > 0.0 && c10 > 0.0 && c01 > 0.0 && c11 > 0.0) {
+      const T ax = apply_at_cells(x, g, d, p, ah, h3, (T)c00, (T)c10, (T)c01, (T)c11);
       v = (MODE == 1) ? b[d * g.B + p] - ax : ax;
     }
     y[d * g.B + p] = v;
