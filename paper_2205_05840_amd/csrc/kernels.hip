@@ -2081,10 +2081,10 @@ inline unsigned vec_blocks(int64_t len, int count, unsigned cap) {
 template <typename T>
 hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                         hipStream_t st) {
-  // FP32 batches: the per-thread kernel up to n = 32 (measured faster there than the
-  // plane-marching one for the 512-problem batch: 239 against 252 ms per 2048 solves; in
-  // FP64 it is not, 365 against 362 ms)
-  const int min_n = (sizeof(T) == 4 && bt.count >= 4) ? 32 : stencil_min_n(bt.count);
+  // batches of four or more pairs take the plane-marching kernel from n = 17 in both
+  // precisions (one position per lane up to n = 64: for the 512-problem batch FP32 165.6
+  // against 182.7 ms per 2048 solves with the per-thread kernel at n = 24, 32)
+  const int min_n = stencil_min_n(bt.count);
   // the plane-marching kernel takes one alpha per problem: with a coefficient per cell the
   // per-thread kernels below serve every size
   if (bt.coef == nullptr && g.n > min_n && g.n <= stencil_max_n()) {

@@ -554,7 +554,17 @@ Choice choose_kz(int n, int count, Variant v) {
 template <typename T, int R>
 void variants(int mode, Variant (&vs)[4], int* nv) {
   constexpr bool f64 = std::is_same<T, double>::value;
-  if (R == 2) {
+  if (R == 1) {
+    // rows of 64 positions: half the ring bytes of R = 2, so the FP64 residual fits more
+    // waves and a deeper ring
+    if (f64) {
+      if (mode == 1) { vs[0] = {6, 3, 2}; vs[1] = {10, 3, 2}; vs[2] = {8, 4, 2}; vs[3] = {8, 4, 1}; *nv = 4; }
+      else { vs[0] = {10, 3, 2}; vs[1] = {8, 4, 2}; vs[2] = {6, 4, 2}; vs[3] = {6, 4, 1}; *nv = 4; }
+    } else {
+      if (mode == 1) { vs[0] = {10, 3, 2}; vs[1] = {8, 4, 2}; vs[2] = {10, 3, 1}; vs[3] = {8, 4, 1}; *nv = 4; }
+      else { vs[0] = {10, 4, 2}; vs[1] = {8, 4, 2}; vs[2] = {10, 4, 1}; vs[3] = {8, 4, 1}; *nv = 4; }
+    }
+  } else if (R == 2) {
     if (f64) {
       if (mode == 1) { vs[0] = {6, 3, 2}; *nv = 1; }
       else { vs[0] = {10, 3, 2}; vs[1] = {8, 4, 2}; vs[2] = {6, 4, 2}; vs[3] = {6, 4, 1}; *nv = 4; }
@@ -606,7 +616,32 @@ hipError_t launch_mode(const T* x, const T* b, T* y, const Geom& g, const Bat& b
   int which = 0, kz = 8;
   Variant var{};
   if (!pick<T, R>(g.n, bt.count, MODE, &which, &kz, &var)) return hipErrorNotSupported;
-  if constexpr (R == 2) {
+  if constexpr (R == 1) {
+    if constexpr (f64 && MODE == 1) {
+      if (which == 0) return launch_m<T, R, 6, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+    }
+    if constexpr (f64 && MODE != 1) {
+      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 6, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 6, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+    }
+    if constexpr (!f64 && MODE == 1) {
+      if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 10, 3, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+    }
+    if constexpr (!f64 && MODE != 1) {
+      if (which == 0) return launch_m<T, R, 10, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 1) return launch_m<T, R, 8, 4, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      if (which == 2) return launch_m<T, R, 10, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+      return launch_m<T, R, 8, 4, MODE, 1>(x, b, y, g, bt, kz, part, pstride, dot, st);
+    }
+  } else if constexpr (R == 2) {
     if constexpr (f64 && MODE == 1) return launch_m<T, R, 6, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
     if constexpr (f64 && MODE != 1) {
       if (which == 0) return launch_m<T, R, 10, 3, MODE>(x, b, y, g, bt, kz, part, pstride, dot, st);
@@ -653,8 +688,9 @@ int stencil_blocks(const Geom& g, int count) {
   if (g.n <= stencil_min_n(count) || g.n > stencil_max_n()) return 0;
   int which = 0, kz = 8;
   Variant var{};
-  const bool ok = (g.n <= 128) ? pick<double, 2>(g.n, count, 2, &which, &kz, &var)
-                               : pick<double, 4>(g.n, count, 2, &which, &kz, &var);
+  const bool ok = (g.n <= 64)    ? pick<double, 1>(g.n, count, 2, &which, &kz, &var)
+                  : (g.n <= 128) ? pick<double, 2>(g.n, count, 2, &which, &kz, &var)
+                                 : pick<double, 4>(g.n, count, 2, &which, &kz, &var);
   return ok ? tiling(g.n, var.nw, kz).ntiles : 0;
 }
 
@@ -667,6 +703,10 @@ int stencil_max_blocks(const Geom& g) {
 
 bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz) {
   Variant var{};
+  if (n <= 64) {
+    if (elem == 8) return pick<double, 1>(n, count, mode, variant, kz, &var);
+    return pick<float, 1>(n, count, mode, variant, kz, &var);
+  }
   if (n <= 128) {
     if (elem == 8) return pick<double, 2>(n, count, mode, variant, kz, &var);
     return pick<float, 2>(n, count, mode, variant, kz, &var);
@@ -678,7 +718,10 @@ bool stencil_shape(int n, int elem, int mode, int count, int* variant, int* kz) 
 int stencil_variant_count(int elem, int mode, int n) {
   Variant vs[4];
   int nv = 0;
-  if (n <= 128) {
+  if (n <= 64) {
+    if (elem == 8) variants<double, 1>(mode, vs, &nv);
+    else variants<float, 1>(mode, vs, &nv);
+  } else if (n <= 128) {
     if (elem == 8) variants<double, 2>(mode, vs, &nv);
     else variants<float, 2>(mode, vs, &nv);
   } else {
@@ -691,8 +734,10 @@ int stencil_variant_count(int elem, int mode, int n) {
 template <typename T>
 hipError_t launch_stencil(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, int mode,
                           double* part, int64_t pstride, double* dot, hipStream_t st) {
-  // rows span 64 R positions: R = 2 up to n = 128, R = 4 up to 256
+  // rows span 64 R positions: R = 1 up to n = 64 (the position i = n of a row of 65 is
+  // written separately), R = 2 up to 128, R = 4 up to 256
   if (g.n <= stencil_min_n(bt.count)) return hipErrorInvalidValue;
+  if (g.n <= 64) return launch_r<T, 1>(x, b, y, g, bt, mode, part, pstride, dot, st);
   if (g.n <= 128) return launch_r<T, 2>(x, b, y, g, bt, mode, part, pstride, dot, st);
   if (g.n <= 256) return launch_r<T, 4>(x, b, y, g, bt, mode, part, pstride, dot, st);
   return hipErrorInvalidValue;

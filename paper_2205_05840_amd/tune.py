@@ -36,10 +36,13 @@ def _stencil_cases(quick):
             for mode in modes:
                 yield n, prec, mode, 1
     if not quick:
-        # batched classes of the uneven-size form (FP64 operator from n > 16 at >= 4 pairs)
+        # batched classes of the uneven-size form (the operator kernel from n > 16 at >= 4
+        # pairs)
         for n in (24, 32):
             for mode in (0, 1, 2):
                 yield n, "fp64", mode, 400
+            for mode in (0, 1):
+                yield n, "fp32", mode, 400
 
 
 def _time_stencil(torch, n, prec, mode, count, variant, kz, bufs):

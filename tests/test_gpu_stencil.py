@@ -1,5 +1,5 @@
-"""GPU parity of the plane-marching operator kernel (meshes with 64 < n <= 128) against
-the FP64 oracle: the apply on sampled rows (element definition, up to the 128^3 bench
+"""GPU parity of the plane-marching operator kernel (one position per lane up to n = 64,
+two up to 128) against the FP64 oracle: the apply on sampled rows (element definition, up to the 128^3 bench
 size), the FP64 V-cycle (its residuals use the kernel's residual mode), and PCG (its
 p^T A p uses the dot mode) in FP64 and mixed precision against the exact discrete
 solution.  n = 80 and 112 give tile counts that leave padding workgroups."""
@@ -119,6 +119,7 @@ def test_pcg_bench_size_mixed():
 
 # (precision, mode, n, planes per workgroup, [(two-barrier variant, one-barrier variant)])
 SYNC_CASES = [("fp64", 0, 64, 4, [(2, 3)]), ("fp64", 0, 128, 16, [(2, 3)]),
+              ("fp64", 1, 64, 4, [(2, 3)]),
               ("fp32", 1, 64, 3, [(0, 2), (1, 3)]), ("fp32", 1, 128, 12, [(0, 2), (1, 3)])]
 
 
@@ -153,3 +154,40 @@ def test_one_barrier_form_agrees(prec, mode, n, kz, pairs):
         L.ndmg_tuning_clear()
         if os.path.exists(_lib.TUNING_PATH):
             L.ndmg_tuning_load(_lib.TUNING_PATH.encode())
+
+
+@pytest.mark.parametrize("n", [40, 64])
+def test_one_position_per_lane_shapes(n):
+    """Up to n = 64 the operator kernel gives each lane one position of a row (n = 64: the
+    position i = n is written apart).  Every launch variant and several plane counts per
+    workgroup must give the same apply bit for bit, and it must match the element
+    definition on sampled rows (random, and next to tile edges in y and z)."""
+    import os
+    from paper_2205_05840_amd import _lib
+    L = _lib.lib()
+    S = _solver(n, 2.5)
+    h = 1.0 / n
+    x = np.random.default_rng(n + 7).standard_normal(mesh.ndof(n))
+    xd = torch.from_numpy(to_padded(n, S.P, S.B, x)).cuda()
+    outs = []
+    try:
+        for v in range(4):
+            for kz in (2, 5, n):
+                L.ndmg_tuning_clear()
+                _lib.check(L.ndmg_tuning_set(f"stencil {n} fp64 0 0 {v} {kz}".encode()))
+                outs.append(((v, kz), _host(S.apply(xd))))
+    finally:
+        L.ndmg_tuning_clear()
+        if os.path.exists(_lib.TUNING_PATH):
+            L.ndmg_tuning_load(_lib.TUNING_PATH.encode())
+    ref_shape, y = outs[0]
+    for shape, o in outs[1:]:
+        assert np.array_equal(o, y), (shape, ref_shape)
+    rng = np.random.default_rng(2)
+    d, p = mesh.edge_coords(n)
+    edge = np.nonzero((p[:, 1] % 8 <= 1) | (p[:, 1] % 8 == 7) | (p[:, 2] % 5 <= 1))[0]
+    rows = np.unique(np.concatenate([rng.choice(mesh.ndof(n), 8000, replace=False),
+                                     rng.choice(edge, 8000, replace=False)]))
+    ref = assemble.apply_rows(n, h, 2.5, x, rows)
+    assert _rel(from_padded(n, S.P, S.B, y)[rows], ref) <= 1e-14
+    assert np.all(y[boundary_mask(n, S.P, S.B)] == 0.0)
