@@ -97,6 +97,37 @@ def test_batched_apply_and_vcycle_equal_single(precision):
             assert np.array_equal(Z[sl], _host(S.vcycle(x))), (p, r)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_operator_kernel_classes(precision):
+    """Classes of 24^3 and 32^3 with four pairs each run the plane-marching operator
+    kernel with one position per lane (a single problem of these sizes takes the
+    per-thread kernel): the batched apply against the assembled matrix for every pair,
+    and the batched PCG (whose V-cycle residuals use the same kernel, in FP32 for the
+    mixed form) against the exact discrete solution."""
+    ns, alphas, nrhs = [24, 32, 24, 32], [0.3, 2.0, 45.0, 0.01], 2
+    BS = _batch(ns, alphas, nrhs, precision)
+    rng = np.random.default_rng(24)
+    blocks = [rng.standard_normal((nrhs, mesh.ndof(n))) for n in ns]
+    Y = _unpack(BS, BS.apply(_pack(BS, blocks)))
+    for p, n in enumerate(ns):
+        A = assemble.matrix_kron(n, 1.0 / n, alphas[p])
+        for r in range(nrhs):
+            assert _rel(Y[p][r], A @ blocks[p][r]) <= 1e-14, (p, r)
+    b = _loads(ns, nrhs, 240)
+    U, it, rel = BS.solve(_pack(BS, b), rtol=1e-10)
+    u = _unpack(BS, U)
+    assert (rel <= 1e-10).all()
+    for p, n in enumerate(ns):
+        h = 1.0 / n
+        A = assemble.matrix_kron(n, h, alphas[p])
+        ev = exact.eigenvalues(n, h, alphas[p])
+        ue = exact.solve_fft(n, h, alphas[p], b[p])
+        for r in range(nrhs):
+            bn = np.linalg.norm(b[p][r])
+            assert _true_residual_ok(A, b[p][r], u[p][r], 1e-10), (p, r)
+            assert np.linalg.norm(u[p][r] - ue[r]) <= 2e-10 * bn / ev.min(), (p, r)
+
+
 def test_batched_pcg_fp64_matches_oracle():
     ns = [8, 12, 16, 6, 8, 12]
     alphas = [0.01, 2.5, 0.3, 100.0, 17.0, 1.0]
