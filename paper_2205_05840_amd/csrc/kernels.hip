@@ -2085,9 +2085,9 @@ hipError_t launch_apply(const T* x, const T* b, T* y, const Geom& g, const Bat& 
   // precisions (one position per lane up to n = 64: for the 512-problem batch FP32 165.6
   // against 182.7 ms per 2048 solves with the per-thread kernel at n = 24, 32)
   const int min_n = stencil_min_n(bt.count);
-  // the plane-marching kernel takes one alpha per problem: with a coefficient per cell the
-  // per-thread kernels below serve every size
-  if (bt.coef == nullptr && g.n > min_n && g.n <= stencil_max_n()) {
+  // with a coefficient per cell the plane-marching kernel takes box grids of up to 8^3
+  // (its factors in LDS); others, and the smaller levels, take the per-thread kernels
+  if (g.n > min_n && g.n <= stencil_max_n()) {
     const hipError_t e = launch_stencil<T>(x, b, y, g, bt, mode, nullptr, 0, nullptr, st);
     if (e != hipErrorNotSupported) return e;   // else: the per-thread kernel below
   }

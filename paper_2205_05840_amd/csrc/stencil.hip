@@ -162,7 +162,13 @@ struct Unroll<U, U> {
   __device__ __forceinline__ static void run(F&, int) {}
 };
 
-template <typename T, int R, int NW, int D, int MODE, int SYNC>
+// COEF: alpha per cell from the r^3 box factors (bt.coef, r <= kCoefMaxR): each face's
+// term of the RT0 mass takes the factors of the two cells on either side (the per-cell
+// form of the per-thread kernels), and an edge is written only where its four cells
+// have a positive factor (a domain inside the cube).  The factors sit in LDS.
+constexpr int kCoefMaxR = 8;
+
+template <typename T, int R, int NW, int D, int MODE, int SYNC, bool COEF>
 __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, const T* __restrict__ bv,
                                                      T* __restrict__ y, DGeom g, Bat bt, double h,
                                                      int KZ, int ntj, int ntiles,
@@ -194,7 +200,13 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   static_assert(SYNC == 1 || SYNC == 2, "one or two barriers per step");
   static_assert(!kOneBarrier || D * NW * CH + 2 * 5 * NW * 64 * (int)sizeof(V) + 1024 <= 160 * 1024,
                 "two copies of the exchange area must fit the LDS");
+  static_assert(!COEF || MODE != 2, "the per-cell form has no dot mode");
+  constexpr int kCoefN = COEF ? kCoefMaxR * kCoefMaxR * kCoefMaxR : 1;
+  static_assert(!COEF || D * NW * CH + (kOneBarrier ? 2 : 1) * 5 * NW * 64 * (int)sizeof(V) +
+                                 kCoefN * (int)sizeof(T) + 1024 <= 160 * 1024,
+                "the box factors must fit the LDS beside the ring");
   __shared__ V sBuf[kOneBarrier ? 2 : 1][5][NW][64];
+  __shared__ T sCoef[kCoefN];
 
   const int pair = blockIdx.y;
   if (bt.act != nullptr && bt.act[pair] == 0) return;
@@ -205,6 +217,12 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
     if (MODE == 1) bv += off;
   }
   const T ah = (T)(bt.alpha[pair / bt.nrhs] * h), h3 = (T)(h * h * h);
+  // box factors into LDS (read from the first computing step on, which starts with a
+  // barrier)
+  const int rc = COEF ? bt.coef_r : 1;
+  if constexpr (COEF) {
+    for (int e = threadIdx.x; e < rc * rc * rc; e += blockDim.x) sCoef[e] = (T)bt.coef[e];
+  }
   // XCD-aware tile order: blocks b, b + 8, b + 16, ... run on one XCD, so give them
   // consecutive tiles (neighbouring j-tiles share halo rows in that XCD's L2).
   const int nb = gridDim.x;
@@ -230,7 +248,17 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   const bool zero_row = (wave == NW - 1 && j == g.n);
   const bool out_row = active && j <= g.n && ((wave >= 1 && wave <= TJ) || zero_row);
   const bool row_ok = (j >= 0 && j < g.n);
-  const T t6 = T(1) / T(6), t23 = T(2) / T(3);
+  const T t6 = T(1) / T(6), t23 = T(2) / T(3), t3 = T(1) / T(3);
+  // COEF: box of a cell index (clamped into the cube: a clamped cell only meets faces
+  // whose flux is zero and edges that are not written), boxes of cells i0 - 1 + q along
+  // the row and of cells j - 1, j across it
+  const int cwid = COEF ? g.n / rc : 1;
+  auto cbox = [&](int c) { return min(max(c, 0), g.n - 1) / cwid; };
+  int bxq[R + 1];
+#pragma unroll
+  for (int q = 0; q <= R; ++q) bxq[q] = COEF ? cbox(i0 - 1 + q) : 0;
+  const int byl = COEF ? cbox(j - 1) : 0, by0 = COEF ? cbox(j) : 0;
+  auto cf = [&](int bx, int by, int bz) -> T { return sCoef[(bz * rc + by) * rc + bx]; };
 
   // ring loads of this lane: source (x rows 0-2, b rows 3-5; direction block + clamped
   // position) of the 16 bytes it copies in each of the NQ loads of a chunk; lanes past
@@ -338,12 +366,32 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
         Fy[r] = (xp[3][r] - xp[2][r]) - (zi1[r] - zp[1][r]);
         Fz[r] = (yi1[r] - yp[2][r]) - (xj[r] - xp[2][r]);
       }
+      // COEF: boxes of the cell planes s - 2, s - 1 and s
+      const int bz2 = COEF ? cbox(s - 2) : 0, bz1 = COEF ? cbox(s - 1) : 0, bz0 = COEF ? cbox(s) : 0;
       T Gx[R];
-      tri_x<T, R>(Fx, Gx);
+      if constexpr (COEF) {
+        // x-faces of plane s between cells i - 1 and i (row j)
+        T Fm[R], Fp[R];
+        shr1<T, R>(Fx, Fm);
+        shl1<T, R>(Fx, Fp);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T am = cf(bxq[r], by0, bz0), a0 = cf(bxq[r + 1], by0, bz0);
+          Gx[r] = t6 * (am * Fm[r] + a0 * Fp[r]) + t3 * (am + a0) * Fx[r];
+        }
+      } else {
+        tri_x<T, R>(Fx, Gx);
+      }
       T Gz1[R], Tzx[R], Tzy[R];   // at plane s-1
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        Gz1[r] = t6 * (fz[0][r] + Fz[r]) + t23 * fz[1][r];
+        if constexpr (COEF) {
+          // z-face at plane s - 1 between cells s - 2 and s - 1
+          const T a2 = cf(bxq[r + 1], by0, bz2), a1 = cf(bxq[r + 1], by0, bz1);
+          Gz1[r] = t6 * (a2 * fz[0][r] + a1 * Fz[r]) + t3 * (a2 + a1) * fz[1][r];
+        } else {
+          Gz1[r] = t6 * (fz[0][r] + Fz[r]) + t23 * fz[1][r];
+        }
         Tzx[r] = t6 * (xp[0][r] + xp[2][r]) + t23 * xp[1][r];
         Tzy[r] = t6 * (yp[0][r] + yp[2][r]) + t23 * yp[1][r];
       }
@@ -375,7 +423,15 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
       {
         const V fyl = sB[0][wl][lane], fyh = sB[0][wh][lane];
 #pragma unroll
-        for (int r = 0; r < R; ++r) Gy[r] = t6 * (fyl[r] + fyh[r]) + t23 * Fy[r];
+        for (int r = 0; r < R; ++r) {
+          if constexpr (COEF) {
+            // y-face of row j between cells j - 1 and j (plane s)
+            const T al = cf(bxq[r + 1], byl, bz0), a0 = cf(bxq[r + 1], by0, bz0);
+            Gy[r] = t6 * (al * fyl[r] + a0 * fyh[r]) + t3 * (al + a0) * Fy[r];
+          } else {
+            Gy[r] = t6 * (fyl[r] + fyh[r]) + t23 * Fy[r];
+          }
+        }
       }
       const int ko = s - 1;   // output plane
       // a lane stores its R positions when they lie inside the row (positions > n of the
@@ -415,9 +471,18 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
           // unknown masks: x-edge: i < n, 1 <= j,k <= n-1; y-edge: j < n, 1 <= i,k <= n-1; ...
           const bool iin = (i >= 1 && i <= g.n - 1), jin = (j >= 1 && j <= g.n - 1),
                      kin = (ko >= 1 && ko <= g.n - 1);
-          const bool ux = (i < g.n) && jin && kin;
-          const bool uy = iin && (j < g.n) && kin;
-          const bool uz = iin && jin && (ko < g.n);
+          bool ux = (i < g.n) && jin && kin;
+          bool uy = iin && (j < g.n) && kin;
+          bool uz = iin && jin && (ko < g.n);
+          if constexpr (COEF) {
+            // the four cells of each edge (planes ko - 1 = s - 2 and ko = s - 1)
+            const T p00 = cf(bxq[r + 1], byl, bz2), p01 = cf(bxq[r + 1], byl, bz1),
+                    p10 = cf(bxq[r + 1], by0, bz2), p11 = cf(bxq[r + 1], by0, bz1);
+            const T m10 = cf(bxq[r], by0, bz2), m11 = cf(bxq[r], by0, bz1), m01 = cf(bxq[r], byl, bz1);
+            ux = ux && p00 > T(0) && p01 > T(0) && p10 > T(0) && p11 > T(0);
+            uy = uy && m10 > T(0) && m11 > T(0) && p10 > T(0) && p11 > T(0);
+            uz = uz && m01 > T(0) && m11 > T(0) && p01 > T(0) && p11 > T(0);
+          }
           if (MODE == 1) {
             ox = ux ? bcur[0][r] - ox : T(0);
             oy = uy ? bcur[1][r] - oy : T(0);
@@ -499,8 +564,18 @@ hipError_t launch_m(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, 
   const Tiling tl = tiling(g.n, NW, KZ);
   if (MODE == 2 && (part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tl.nblocks, (unsigned)bt.count);
-  hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g), bt,
-                     g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
+  if (bt.coef != nullptr) {
+    if constexpr (MODE == 2) {
+      return hipErrorNotSupported;
+    } else {
+      if (bt.coef_r < 1 || bt.coef_r > kCoefMaxR || g.n % bt.coef_r) return hipErrorNotSupported;
+      hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC, true>), grid, dim3(64 * NW), 0, st, x, b, y,
+                         dgeom(g), bt, g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC, false>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g),
+                     bt, g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
   if (MODE == 2 && dot != nullptr) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
   return hipGetLastError();
 }

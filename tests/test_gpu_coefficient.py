@@ -68,7 +68,8 @@ def _matrix(n, alpha, boxes, L=1.0):
     return coefficient.matrix_cells(n, L / n, alpha * coefficient.cell_field(n, boxes))
 
 
-@pytest.mark.parametrize("n,r,alpha", [(8, 2, 1.0), (12, 3, 0.5), (16, 2, 3.0), (40, 5, 1.0), (64, 2, 1.0)])
+@pytest.mark.parametrize("n,r,alpha", [(8, 2, 1.0), (12, 3, 0.5), (16, 2, 3.0), (40, 5, 1.0), (64, 2, 1.0),
+                                     (80, 5, 0.3)])
 def test_apply(n, r, alpha):
     boxes = _boxes(r, n)
     S = _solver(n, alpha, boxes)
