@@ -269,7 +269,7 @@ int plan_class(Cls& C, const Plan& pl, Take&& take) {
         L.o_guP = take(std::max<size_t>(1, L.gt.unitsP.size()) * sizeof(int64_t));
         L.o_grP = take(L.gt.relP.size() * sizeof(int64_t));
         L.o_gcP = take(std::max<size_t>(1, L.gt.chunksP.size()) * sizeof(int));
-        L.o_ggam = take(std::max<size_t>(1, L.gt.gamma.size()) * sizeof(int64_t));
+        L.o_ggam = take(std::max<size_t>(1, L.gt.gamma.size()) * sizeof(int));
         L.o_gcc = take(std::max<size_t>(1, L.gt.ccodes.size()) * sizeof(int));
         L.o_gcodes = take(std::max<size_t>(1, L.gt.codes.size()) * sizeof(int));
         if ((int)k == C.dense_k) {
@@ -692,7 +692,7 @@ ndmg::GenLevel<T> gen_level(ndmg_ctx* c, const LevelHost& L) {
   G.gg = at<T>(c, L.o_gg);
   G.Y = at<T>(c, L.o_Y);
   G.w = at<T>(c, L.o_w);
-  G.gamma = at<int64_t>(c, L.o_ggam);
+  G.gamma = at<int>(c, L.o_ggam);
   G.ccodes = at<int>(c, L.o_gcc);
   G.codes = at<int>(c, L.o_gcodes);
   G.ngam = (int64_t)tb.gamma.size();
@@ -1033,13 +1033,19 @@ int cg_apply_update(ndmg_ctx* c, Cls& C, int num, const ndmg::Bat& bt, hipStream
   double* pq_part = part_region(c, C, 1);
   const int64_t ps = part_stride(C);
   int pq_n = 0;
-  if (bt.coef == nullptr && g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n()) {
-    NDMG_HIP(ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, pq_part, ps, nullptr, st));
+  // q = A p with the partials of p^T A p from the operator kernel, else (small meshes,
+  // box grids beyond what the kernel's per-cell form holds) apply then dot
+  hipError_t e = hipErrorNotSupported;
+  if (g.n > ndmg::stencil_min_n(bt.count) && g.n <= ndmg::stencil_max_n())
+    e = ndmg::launch_stencil<double>(p, nullptr, q, g, bt, 2, pq_part, ps, nullptr, st);
+  if (e == hipSuccess) {
     pq_n = ndmg::stencil_blocks(g, bt.count);
-  } else {
+  } else if (e == hipErrorNotSupported) {
     NDMG_HIP(ndmg::launch_apply<double>(p, nullptr, q, g, bt, 0, st));
     NDMG_HIP(ndmg::launch_dot<double>(p, q, nullptr, pq_part, ps, nullptr, len, bt, st));
     pq_n = ndmg::dot_parts(len, bt.count);
+  } else {
+    NDMG_HIP(e);
   }
   NDMG_HIP(ndmg::launch_cg_update(nullptr, r, p, q, sc, num, pq_part, pq_n, r32_of(c, C), part_region(c, C, 2), ps,
                                   len, bt, st));

@@ -168,7 +168,7 @@ __device__ __forceinline__ T pull4(const T* __restrict__ src, const int4 c) {
 // g_Gamma = r_Gamma - sum_T C_T on every interface unknown.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_condense(const T* __restrict__ C, const T* __restrict__ r,
-                                                      const int64_t* __restrict__ gamma, const int4* __restrict__ codes,
+                                                      const int* __restrict__ gamma, const int4* __restrict__ codes,
                                                       int64_t ngam, T* __restrict__ gg, int64_t vlen, int64_t clen,
                                                       Bat bt) {
   const int pair = blockIdx.y;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) k_gen_condense(const T* __restrict__ C, c
 
 // w = sum_P R_P^T y_P on every interface unknown, and z (=, +=) eta w there.
 template <typename T>
-__global__ void __launch_bounds__(256) k_gen_pull(const T* __restrict__ Y, const int64_t* __restrict__ gamma,
+__global__ void __launch_bounds__(256) k_gen_pull(const T* __restrict__ Y, const int* __restrict__ gamma,
                                                   const int4* __restrict__ codes, int64_t ngam, T* __restrict__ w,
                                                   T* __restrict__ z, T eta, int assign, int64_t vlen, int64_t ylen,
                                                   Bat bt) {

@@ -48,7 +48,7 @@ struct GenLevel {
   GemmArgs<T> patch;      // y_P = S_P^{-1} g|Gamma_P over the patches
   GemmArgs<T> ext;        // z_I = eta [A_T^{-1} | -X_T] [r_I ; w_dT] over the subdomains
   T *C, *gg, *Y, *w;
-  const int64_t* gamma;   // interface unknowns (padded offsets)
+  const int* gamma;       // interface unknowns (padded offsets)
   const int* ccodes;      // [ngam][4] indices into C of the subdomain terms at each (-1: none)
   const int* codes;       // [ngam][4] indices into Y of the patch results at each (-1: none)
   int64_t ngam;

@@ -948,6 +948,10 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
   // unknowns of at most a few neighbouring blocks.  (The order of each unknown's own sum
   // does not depend on this order.)
   std::vector<int> gpos((size_t)g.len, -1);
+  if (g.len >= (int64_t)1 << 31) {
+    *err = "level too large for the interface offsets";
+    return false;
+  }
   {
     constexpr int kBlk = 16;
     const int nbk = (g.n + 1 + kBlk - 1) / kBlk;
@@ -974,7 +978,7 @@ bool build_gen_tables(const Geom& g, int s, int kind, bool boundary, GenTables* 
     tb.gamma.assign(list.size(), 0);
     for (size_t i = 0; i < list.size(); ++i) {
       const int64_t k = start[(size_t)blk[i]]++;
-      tb.gamma[(size_t)k] = list[i];
+      tb.gamma[(size_t)k] = (int)list[i];
       gpos[(size_t)list[i]] = (int)k;
     }
   }

@@ -184,7 +184,7 @@ struct GenTables {
   std::vector<int> chunksP;
   std::vector<char> presentP;          // [ntypes][npadP]
   std::vector<int> typesP;             // the types that have patches
-  std::vector<int64_t> gamma;          // interface unknowns
+  std::vector<int> gamma;              // interface unknowns (offsets below 2^31)
   std::vector<int> ccodes;             // [ngam][4] subdomain terms (boundary slot * units + u)
   std::vector<int> codes;              // [ngam][4] patch results (slot * units + u)
 };

@@ -165,7 +165,8 @@ struct Unroll<U, U> {
 // COEF: alpha per cell from the r^3 box factors (bt.coef, r <= kCoefMaxR): each face's
 // term of the RT0 mass takes the factors of the two cells on either side (the per-cell
 // form of the per-thread kernels), and an edge is written only where its four cells
-// have a positive factor (a domain inside the cube).  The factors sit in LDS.
+// have a positive factor (a domain inside the cube).  The factors sit in LDS.  Every
+// mode, the dot mode's p^T A p included, takes the per-cell form.
 constexpr int kCoefMaxR = 8;
 
 template <typename T, int R, int NW, int D, int MODE, int SYNC, bool COEF>
@@ -200,7 +201,6 @@ __global__ void __launch_bounds__(64 * NW) k_stencil(const T* __restrict__ x, co
   static_assert(SYNC == 1 || SYNC == 2, "one or two barriers per step");
   static_assert(!kOneBarrier || D * NW * CH + 2 * 5 * NW * 64 * (int)sizeof(V) + 1024 <= 160 * 1024,
                 "two copies of the exchange area must fit the LDS");
-  static_assert(!COEF || MODE != 2, "the per-cell form has no dot mode");
   constexpr int kCoefN = COEF ? kCoefMaxR * kCoefMaxR * kCoefMaxR : 1;
   static_assert(!COEF || D * NW * CH + (kOneBarrier ? 2 : 1) * 5 * NW * 64 * (int)sizeof(V) +
                                  kCoefN * (int)sizeof(T) + 1024 <= 160 * 1024,
@@ -565,14 +565,11 @@ hipError_t launch_m(const T* x, const T* b, T* y, const Geom& g, const Bat& bt, 
   if (MODE == 2 && (part == nullptr || tl.ntiles > pstride)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tl.nblocks, (unsigned)bt.count);
   if (bt.coef != nullptr) {
-    if constexpr (MODE == 2) {
-      return hipErrorNotSupported;
-    } else {
-      if (bt.coef_r < 1 || bt.coef_r > kCoefMaxR || g.n % bt.coef_r) return hipErrorNotSupported;
-      hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC, true>), grid, dim3(64 * NW), 0, st, x, b, y,
-                         dgeom(g), bt, g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
-      return hipGetLastError();
-    }
+    if (bt.coef_r < 1 || bt.coef_r > kCoefMaxR || g.n % bt.coef_r) return hipErrorNotSupported;
+    hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC, true>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g),
+                       bt, g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
+    if (MODE == 2 && dot != nullptr) return launch_final(part, tl.ntiles, pstride, 1, dot, bt, st);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((k_stencil<T, R, NW, D, MODE, SYNC, false>), grid, dim3(64 * NW), 0, st, x, b, y, dgeom(g),
                      bt, g.h, tl.KZ, tl.ntj, tl.ntiles, part, pstride, 0);
